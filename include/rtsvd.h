@@ -1,0 +1,153 @@
+/*
+ * librtsvd -- randomized tSVD (R-tSVD) regularization of t-product least-squares problems
+ *             min || B - A * X ||_F,  A in R^{l x m x n}, B in R^{l x p x n}, l >= m,
+ * on AMD MI355X (gfx950).  Method: Ugwu & Reichel, "Tensor regularization by truncated
+ * iteration: a comparison of some solution methods for large-scale linear discrete ill-posed
+ * problem with a t-product", arXiv:2110.02485.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Tensors are DEVICE pointers in column-major l x m x n order: element (i, j, t) of a tensor
+ *    with l rows and m columns is at offset i + l*j + l*m*t (frontal slices contiguous; a torch
+ *    tensor of shape (n, m, l), contiguous).  Real data only.
+ *  * dtype: RTSVD_F64 (double) or RTSVD_F32 (float) for every caller array of one call.
+ *  * stream: a hipStream_t passed as void* (NULL = the default stream).  All device work of a
+ *    call is ordered on it; the call returns without synchronizing unless stated otherwise.
+ *  * Fourier conventions follow Section 2 of the paper: the DFT along the tubes
+ *    (MATLAB fft(A, [], 3)); only faces 0 .. floor(n/2) are formed, the others being complex
+ *    conjugates for real data.
+ *  * Return value: RTSVD_OK (0), a warning (> 0) or an error (< 0).  On error nothing is
+ *    launched after the failing step, outputs are unspecified and no handle is created;
+ *    rtsvd_last_error() describes the failure.  Scratch memory is taken from the stream's
+ *    memory pool and returned to it before the call returns (stream-ordered).
+ */
+#ifndef RTSVD_H
+#define RTSVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* caller array types */
+#define RTSVD_F64 0
+#define RTSVD_F32 1
+
+/* compute precision of the factorization
+ *   FP64 : every step in double precision.
+ *   FP32 : tube FFTs and the sketch / power / projection / W = A V products in float;
+ *          Gram matrices, Cholesky, small SVD and discrepancy sums in double.
+ *   BF16 : as FP32, but the sketch, power-iteration and projection products read A-hat in
+ *          bfloat16 (round to nearest even) and accumulate in float.                        */
+#define RTSVD_P_FP64 0
+#define RTSVD_P_FP32 1
+#define RTSVD_P_BF16 2
+
+/* status codes */
+#define RTSVD_OK 0
+#define RTSVD_W_DP_NOT_MET 1       /* no k in [k_start, k_cap] met the discrepancy principle   */
+#define RTSVD_W_RANK_DEFICIENT 2   /* a sketch column fell below the breakdown threshold        */
+#define RTSVD_E_ARG (-1)           /* invalid argument (sizes, null pointers, eta_dp <= 1, ...) */
+#define RTSVD_E_HIP (-3)           /* a HIP runtime call failed                                 */
+#define RTSVD_E_NOMEM (-4)         /* device memory could not be obtained                       */
+#define RTSVD_E_UNSUPPORTED (-5)   /* valid but unsupported configuration (e.g. r > 256)        */
+
+typedef struct rtsvd_factor_s* rtsvd_handle;
+
+typedef struct {
+  int32_t k_max;        /* largest truncation index the solve may choose, 1 <= k_max <= m        */
+  int32_t oversample;   /* rho >= 0 (Section 4.2, r = k + rho): r = min(k_max + rho, m) <= 256  */
+  int32_t power_iters;  /* q >= 0 range refinements A-hat A-hat^H; q = 0 is Alg. 6 as printed   */
+  int32_t precision;    /* RTSVD_P_FP64 | RTSVD_P_FP32 | RTSVD_P_BF16                           */
+  uint64_t seed;        /* seed of the on-device Gaussian generator, used when omega == NULL    */
+  const void* omega;    /* optional DEVICE real m x r x n Gaussian tensor (dtype of A); the r   */
+                        /* tensor columns play the role of the Gaussian slices G of Alg. 6      */
+  double eps;           /* > 0: also report r_eps = min{ j : eta^[j] < eps^2 } (Alg. 6 stopping */
+                        /* rule, Thm 4.2); <= 0: not used                                        */
+} rtsvd_opts;
+
+/* R-tSVD factorization (Section 4.2, Alg. 6 in block form, Thms 4.1-4.2).
+ * A: DEVICE l x m x n (dtype).  Computes, per Fourier face i < floor(n/2)+1, the orthonormal
+ * Q_i (l x r) spanning A-hat_i Omega-hat_i (refined by q power iterations), the projection
+ * C_i = Q_i^H A-hat_i = U-breve_i diag(sigma_i) V_i^H (small SVD in FP64, sigma descending) and
+ * W_i = A-hat_i V_i (used for the exact discrepancy residual).  The factor does not depend on B
+ * (Section 5), so one handle serves any number of rtsvd_solve calls.  The handle owns its
+ * device buffers until rtsvd_factor_destroy; A may be freed after the stream reaches the end of
+ * this call.  Errors: RTSVD_E_ARG (l < m, n < 1, k_max < 1, k_max > m, oversample < 0,
+ * power_iters < 0, bad precision, null A/opts/out), RTSVD_E_UNSUPPORTED (r > 256).
+ * Warning RTSVD_W_RANK_DEFICIENT is reported later by rtsvd_factor_info.                      */
+int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype,
+                 const rtsvd_opts* opts, void* stream, rtsvd_handle* out);
+
+/* Full facewise SVD factor of A (T-tSVD, Alg. 1 and Section 4.1): r = m, returned in the same
+ * handle type so that rtsvd_solve applies the truncated solution of eq. (14).  m <= 256.     */
+int ttsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype, int32_t precision,
+                 int32_t k_max, void* stream, rtsvd_handle* out);
+
+/* Host-side summary of a factor; synchronizes the factor's stream.  Any output may be NULL.
+ *   r      : number of sketch columns
+ *   faces  : floor(n/2) + 1
+ *   eta    : HOST array of r + 1 doubles, eta^[j] = ||A||_F^2 - sum_{j'<=j} ||B-tilde(j',:,:)||_F^2
+ *            (Thm 4.2); eta[r] = ||A - Q * B-tilde||_F^2 (Thm 4.1)
+ *   r_eps  : smallest j with eta^[j] < eps^2, or -1 (eps <= 0 or never reached)
+ *   sigma  : HOST array r x faces, sigma[i*r + j] = j-th singular value of face i
+ *   flags  : bit 0 = a Gram pivot fell below the breakdown threshold (rank-deficient sketch)   */
+int rtsvd_factor_info(rtsvd_handle f, int32_t* r, int32_t* faces, double* eta, int32_t* r_eps,
+                      double* sigma, int32_t* flags);
+
+void rtsvd_factor_destroy(rtsvd_handle f);
+
+/* Truncated R-tSVD / T-tSVD solution with the discrepancy principle (eq. (disp), eq. (kinit)):
+ *   X_k = V_k * S_k^{-1} * U_k^T * B,  U_k = Q * U-tilde(:, 1:k, :)   (Section 4.2)
+ * B: DEVICE l x p x n (dtype); X: DEVICE m x p x n (dtype), caller-allocated.
+ * delta: HOST array; n_delta = 1 -> one noise bound for all of B, joint k (the single k of the
+ *        RT-tSVD rows of the paper's tables); n_delta = p -> lateral slice j is its own problem
+ *        with bound delta[j] and its own k_j.
+ * eta_dp > 1 is the discrepancy factor (tau of eq. (disp)).
+ * k_start >= 1: the first k tried (1 = the literal principle, smallest k > 0); k_start = 0: the
+ *        experiments' rule k_init = max(1, r - rho), increased up to r (eq. (kinit)).
+ * k_cap = k_max for k_start >= 1 and r for k_start = 0.  The residual used is the exact
+ *        ||B - A * X_k||_F (Fourier domain, FP64 sums).
+ * k_out:     DEVICE int32[n_delta]: chosen k (k_cap when the principle is not met).
+ * resid_out: DEVICE double[n_delta * k_cap] or NULL: resid_out[g*k_cap + k-1] = ||B_g - A*X_k||_F.
+ * status_out: DEVICE int32[1] or NULL: RTSVD_OK or RTSVD_W_DP_NOT_MET (set on the device).
+ * Errors: RTSVD_E_ARG (null handle/B/X/delta/k_out, p < 1, n_delta not 1 or p, eta_dp <= 1,
+ *         k_start < 0 or > k_max, dtype mismatch with the factor's caller dtype).             */
+int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype,
+                const double* delta, int32_t n_delta, double eta_dp, int32_t k_start,
+                void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
+
+/* t-product C = A * B (Definition 2.1 via the tube DFT, Section 2).
+ * A: l x m x n, B: m x p x n, C: l x p x n, all DEVICE, same dtype.  Computed in the dtype. */
+int tprod(const void* A, const void* B, void* C, int64_t l, int64_t m, int64_t p, int64_t n,
+          int dtype, void* stream);
+
+/* Adjoint t-product B = A^T * C (tensor transpose of Section 2: (A^T)-hat_i = A-hat_i^H).
+ * A: l x m x n, C: l x p x n, B: m x p x n, all DEVICE, same dtype.                           */
+int tprod_adjoint(const void* A, const void* C, void* B, int64_t l, int64_t m, int64_t p,
+                  int64_t n, int dtype, void* stream);
+
+/* tGKB_p regularization (Alg. 7 with full re-orthogonalization, projected least squares of
+ * eq. (9tt) per face as in Alg. 5, X_k = W_k * Y_k of eq. (solgkb)): every lateral slice j of B
+ * runs its own process and stops at the first k with ||B_j - A * X_{j,k}||_F <= eta_dp*delta_j.
+ * A: DEVICE l x m x n; B: DEVICE l x p x n; X: DEVICE m x p x n (dtype; computed in dtype,
+ * sums in FP64).  delta: HOST, n_delta = 1 (same bound for every slice) or p.
+ * k_out: DEVICE int32[p]; resid_out: DEVICE double[k_max * p] or NULL (resid_out[j*k_max+k-1]);
+ * status_out: DEVICE int32[1] or NULL.  Synchronizes the stream once per iteration block to
+ * test the stopping rule.                                                                    */
+int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p,
+               int dtype, const double* delta, int32_t n_delta, double eta_dp, int32_t k_max,
+               void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
+
+/* Human-readable status text. */
+const char* rtsvd_status_string(int status);
+
+/* Description of the last error raised on the calling host thread ("" if none). */
+const char* rtsvd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTSVD_H */

@@ -1,0 +1,70 @@
+// Shared device/host helpers for the R-tSVD library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <cmath>
+
+#include "rtsvd.h"
+
+#define RT_HOST_DEVICE __host__ __device__ __forceinline__
+
+// ---------------------------------------------------------------------------------------------
+// complex numbers: interleaved (re, im) pairs
+// ---------------------------------------------------------------------------------------------
+template <typename T> struct cplx { T re, im; };
+typedef cplx<double> zd;
+typedef cplx<float> zf;
+// bf16 complex: two bf16 in one 32-bit word, low half = real part, high half = imaginary part
+struct zb { uint32_t bits; };
+
+template <typename T> RT_HOST_DEVICE cplx<T> mk(T a, T b) { cplx<T> z; z.re = a; z.im = b; return z; }
+template <typename T> RT_HOST_DEVICE cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T> RT_HOST_DEVICE cplx<T> csub(cplx<T> a, cplx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T> RT_HOST_DEVICE cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// conj(a) * b
+template <typename T> RT_HOST_DEVICE cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <typename T> RT_HOST_DEVICE cplx<T> cconj(cplx<T> a) { return mk(a.re, -a.im); }
+template <typename T> RT_HOST_DEVICE cplx<T> cscale(cplx<T> a, T s) { return mk(a.re * s, a.im * s); }
+template <typename T> RT_HOST_DEVICE T cabs2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------------------------------------
+// bf16 (round to nearest even) <-> float
+// ---------------------------------------------------------------------------------------------
+RT_HOST_DEVICE uint32_t f2bf(float f) {
+  union { float f; uint32_t u; } v; v.f = f;
+  uint32_t u = v.u;
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+RT_HOST_DEVICE float bf2f(uint32_t h) { union { uint32_t u; float f; } v; v.u = h << 16; return v.f; }
+
+// load any storage element as a complex of the accumulation type
+template <typename Acc> RT_HOST_DEVICE cplx<Acc> ld(const zd& z) { return mk((Acc)z.re, (Acc)z.im); }
+template <typename Acc> RT_HOST_DEVICE cplx<Acc> ld(const zf& z) { return mk((Acc)z.re, (Acc)z.im); }
+template <typename Acc> RT_HOST_DEVICE cplx<Acc> ld(const zb& z) {
+  return mk((Acc)bf2f(z.bits & 0xffffu), (Acc)bf2f(z.bits >> 16));
+}
+template <typename Acc> RT_HOST_DEVICE void st(zd& d, cplx<Acc> v) { d.re = (double)v.re; d.im = (double)v.im; }
+template <typename Acc> RT_HOST_DEVICE void st(zf& d, cplx<Acc> v) { d.re = (float)v.re; d.im = (float)v.im; }
+template <typename Acc> RT_HOST_DEVICE void st(zb& d, cplx<Acc> v) {
+  d.bits = f2bf((float)v.re) | (f2bf((float)v.im) << 16);
+}
+
+// ---------------------------------------------------------------------------------------------
+// error handling on the host
+// ---------------------------------------------------------------------------------------------
+#define RT_CHECK_HIP(expr)                                   \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) { rt_set_hip_error(_e, #expr, __FILE__, __LINE__); return RTSVD_E_HIP; } \
+  } while (0)
+
+void rt_set_hip_error(hipError_t e, const char* what, const char* file, int line);
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -1,0 +1,275 @@
+// Tube DFTs (Section 2: fft(A, [], 3) and its inverse) for real tensors.
+//
+// A real tensor with T = (number of tubes) and tube length n is stored tube-element-major:
+// element t of tube i sits at in[i + T*t] (frontal slices contiguous).  The forward kernel
+// writes the half spectrum, faces f = 0 .. n/2, face-major: out[f*face_stride + i].
+//
+// Layout on the GPU: a workgroup takes TB consecutive tubes.  Loads of one tube element for
+// TB consecutive tubes are contiguous (coalesced), the tile is staged in LDS, two real tubes
+// are packed into one complex sequence (z = x + i y), a radix-2 Stockham FFT runs in LDS,
+// and the two spectra are separated with X_f = (Z_f + conj Z_{n-f})/2,
+// Y_f = (Z_f - conj Z_{n-f})/(2i).  Stores of one face for TB tubes are contiguous again.
+#pragma once
+#include "common.hpp"
+
+namespace rt {
+
+constexpr int FFT_THREADS = 256;
+
+// Stockham radix-2 passes over LDS buffers holding `nseq` interleaved sequences of length n:
+// buf[t*nseq + s].  Returns the buffer that holds the result.  sign = -1 forward, +1 inverse.
+template <typename T>
+__device__ cplx<T>* stockham_lds(cplx<T>* b0, cplx<T>* b1, const cplx<T>* tw, int n, int log2n,
+                                 int nseq, int sign) {
+  const int half = n >> 1;
+  for (int p = 0, Ns = 1; p < log2n; ++p, Ns <<= 1) {
+    for (int idx = threadIdx.x; idx < half * nseq; idx += blockDim.x) {
+      const int s = idx % nseq;
+      const int j = idx / nseq;
+      const int k = j & (Ns - 1);
+      cplx<T> v0 = b0[j * nseq + s];
+      cplx<T> v1 = b0[(j + half) * nseq + s];
+      cplx<T> w = tw[k * (half / Ns)];
+      if (sign > 0) w.im = -w.im;
+      v1 = cmul(v1, w);
+      const int d = (j / Ns) * 2 * Ns + k;
+      b1[d * nseq + s] = cadd(v0, v1);
+      b1[(d + Ns) * nseq + s] = csub(v0, v1);
+    }
+    __syncthreads();
+    cplx<T>* tmp = b0; b0 = b1; b1 = tmp;
+  }
+  return b0;
+}
+
+template <typename T>
+__device__ void fill_twiddles(cplx<T>* tw, int n) {
+  for (int k = threadIdx.x; k < n / 2; k += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)k / (double)n, &s, &c);
+    tw[k] = mk((T)c, (T)s);
+  }
+}
+
+// forward: real tubes (input type Tin) -> half spectrum in working precision T, optional bf16 copy.
+// sumsq: per-block partial sums of the squared inputs (FP64), for ||A||_F^2.
+template <typename Tin, typename T>
+__global__ void __launch_bounds__(FFT_THREADS)
+k_rfft_pow2(const Tin* __restrict__ in, int64_t ntubes, int n, int log2n, int TB,
+            cplx<T>* __restrict__ out, int64_t face_stride, zb* __restrict__ out16,
+            double* __restrict__ sumsq) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int TH = TB / 2;
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw + n / 2;
+  cplx<T>* b1 = b0 + (size_t)(n + 2) * TH;
+  const int64_t tube0 = (int64_t)blockIdx.x * TB;
+  fill_twiddles(tw, n);
+  double acc = 0.0;
+  for (int idx = threadIdx.x; idx < n * TB; idx += blockDim.x) {
+    const int t = idx / TB, i = idx % TB;
+    const int64_t g = tube0 + i;
+    T v = 0;
+    if (g < ntubes) { v = (T)in[g + ntubes * (int64_t)t]; acc += (double)v * (double)v; }
+    cplx<T>& z = b0[t * TH + (i % TH)];
+    if (i < TH) z.re = v; else z.im = v;
+  }
+  __syncthreads();
+  cplx<T>* res = stockham_lds(b0, b1, tw, n, log2n, TH, -1);
+  const int F = n / 2 + 1;
+  for (int idx = threadIdx.x; idx < F * TB; idx += blockDim.x) {
+    const int f = idx / TB, i = idx % TB;
+    const int s = i % TH;
+    const int64_t g = tube0 + i;
+    if (g >= ntubes) continue;
+    const cplx<T> zf = res[f * TH + s];
+    const cplx<T> zn = cconj(res[((n - f) & (n - 1)) * TH + s]);
+    cplx<T> v;
+    if (i < TH) v = cscale(cadd(zf, zn), (T)0.5);
+    else { cplx<T> d = csub(zf, zn); v = mk((T)0.5 * d.im, (T)-0.5 * d.re); }
+    if (f == 0 || 2 * f == n) v.im = 0;
+    out[f * face_stride + g] = v;
+    if (out16) st(out16[f * face_stride + g], v);
+  }
+  if (sumsq) {
+    // block reduction of acc
+    __shared__ double red[FFT_THREADS];
+    __syncthreads();
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) sumsq[blockIdx.x] = red[0];
+  }
+}
+
+// inverse: half spectrum (type T) -> real tubes (output type Tout), scaled by 1/n.
+template <typename T, typename Tout>
+__global__ void __launch_bounds__(FFT_THREADS)
+k_irfft_pow2(const cplx<T>* __restrict__ in, int64_t face_stride, int64_t ntubes, int n, int log2n,
+             int TB, Tout* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int TH = TB / 2;
+  const int F = n / 2 + 1;
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw + n / 2;
+  cplx<T>* b1 = b0 + (size_t)(n + 2) * TH;
+  const int64_t tube0 = (int64_t)blockIdx.x * TB;
+  fill_twiddles(tw, n);
+  // stage X_f (tubes 0..TH-1) and Y_f (tubes TH..TB-1) for f < F in b1: b1[f*TB + i]
+  for (int idx = threadIdx.x; idx < F * TB; idx += blockDim.x) {
+    const int f = idx / TB, i = idx % TB;
+    const int64_t g = tube0 + i;
+    cplx<T> v = mk((T)0, (T)0);
+    if (g < ntubes) v = in[f * face_stride + g];
+    if (f == 0 || 2 * f == n) v.im = 0;
+    b1[f * TB + i] = v;
+  }
+  __syncthreads();
+  // Z_f = X_f + i Y_f for every f of the full spectrum (Hermitian extension of X and Y)
+  for (int idx = threadIdx.x; idx < n * TH; idx += blockDim.x) {
+    const int f = idx / TH, s = idx % TH;
+    cplx<T> x, y;
+    if (f < F) { x = b1[f * TB + s]; y = b1[f * TB + s + TH]; }
+    else { x = cconj(b1[(n - f) * TB + s]); y = cconj(b1[(n - f) * TB + s + TH]); }
+    b0[f * TH + s] = mk(x.re - y.im, x.im + y.re);
+  }
+  __syncthreads();
+  cplx<T>* res = stockham_lds(b0, b1, tw, n, log2n, TH, +1);
+  const T inv = (T)1 / (T)n;
+  for (int idx = threadIdx.x; idx < n * TB; idx += blockDim.x) {
+    const int t = idx / TB, i = idx % TB;
+    const int64_t g = tube0 + i;
+    if (g >= ntubes) continue;
+    const cplx<T> z = res[t * TH + (i % TH)];
+    out[g + ntubes * (int64_t)t] = (Tout)((i < TH ? z.re : z.im) * inv);
+  }
+}
+
+// Direct DFT for tube lengths that are not powers of two (one thread per tube, twiddles in LDS).
+template <typename Tin, typename T>
+__global__ void k_rdft_direct(const Tin* __restrict__ in, int64_t ntubes, int n,
+                              cplx<T>* __restrict__ out, int64_t face_stride, zb* __restrict__ out16,
+                              double* __restrict__ sumsq) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)k / (double)n, &s, &c);
+    tw[k] = mk((T)c, (T)s);
+  }
+  __syncthreads();
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (g < ntubes) {
+    const int F = n / 2 + 1;
+    for (int f = 0; f < F; ++f) {
+      cplx<T> s = mk((T)0, (T)0);
+      int idx = 0;
+      for (int t = 0; t < n; ++t) {
+        const T v = (T)in[g + ntubes * (int64_t)t];
+        s = cadd(s, cscale(tw[idx], v));
+        idx += f; if (idx >= n) idx -= n;
+        if (f == 0) acc += (double)v * (double)v;
+      }
+      if (f == 0 || 2 * f == n) s.im = 0;
+      out[f * face_stride + g] = s;
+      if (out16) st(out16[f * face_stride + g], s);
+    }
+  }
+  if (sumsq) {
+    __shared__ double red[FFT_THREADS];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) sumsq[blockIdx.x] = red[0];
+  }
+}
+
+template <typename T, typename Tout>
+__global__ void k_irdft_direct(const cplx<T>* __restrict__ in, int64_t face_stride, int64_t ntubes,
+                               int n, Tout* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    double s, c;
+    sincospi(2.0 * (double)k / (double)n, &s, &c);
+    tw[k] = mk((T)c, (T)s);
+  }
+  __syncthreads();
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ntubes) return;
+  const int F = n / 2 + 1;
+  for (int t = 0; t < n; ++t) {
+    T s = 0;
+    for (int f = 0; f < F; ++f) {
+      cplx<T> v = in[f * face_stride + g];
+      if (f == 0 || 2 * f == n) v.im = 0;
+      const cplx<T> w = tw[(int)(((int64_t)f * t) % n)];
+      const T term = v.re * w.re - v.im * w.im;    // Re(v w)
+      s += (f == 0 || 2 * f == n) ? term : (T)2 * term;
+    }
+    out[g + ntubes * (int64_t)t] = (Tout)(s / (T)n);
+  }
+}
+
+// -------------------------------------------------------------------------------------------
+// launchers
+// -------------------------------------------------------------------------------------------
+inline int ilog2_exact(int64_t n) {
+  if (n < 1 || (n & (n - 1))) return -1;
+  int l = 0; while ((1LL << l) < n) ++l; return l;
+}
+
+template <typename T>
+inline int fft_tile(int n) {
+  // two ping-pong buffers of (n+2) x TB/2 complex plus n/2 twiddles within ~48 KB of LDS
+  const int64_t budget = 48 * 1024;
+  int tb = 256;
+  while (tb > 2 && (int64_t)(2 * (n + 2) * (tb / 2) + n / 2) * (int64_t)sizeof(cplx<T>) > budget) tb >>= 1;
+  return tb;
+}
+
+template <typename Tin, typename T>
+int launch_rfft(const Tin* in, int64_t ntubes, int n, cplx<T>* out, int64_t face_stride, zb* out16,
+                double* sumsq, int64_t* nblocks_out, hipStream_t s) {
+  const int lg = ilog2_exact(n);
+  if (lg >= 0 && n >= 2 && (int64_t)(2 * (n + 2) + n / 2) * (int64_t)sizeof(cplx<T>) <= 48 * 1024) {
+    const int TB = fft_tile<T>(n);
+    const int64_t blocks = ceil_div(ntubes, TB);
+    const size_t lds = (size_t)(2 * (n + 2) * (TB / 2) + n / 2) * sizeof(cplx<T>);
+    hipLaunchKernelGGL((k_rfft_pow2<Tin, T>), dim3((unsigned)blocks), dim3(FFT_THREADS), lds, s,
+                       in, ntubes, n, lg, TB, out, face_stride, out16, sumsq);
+    if (nblocks_out) *nblocks_out = blocks;
+  } else {
+    const int64_t blocks = ceil_div(ntubes, FFT_THREADS);
+    hipLaunchKernelGGL((k_rdft_direct<Tin, T>), dim3((unsigned)blocks), dim3(FFT_THREADS),
+                       (size_t)n * sizeof(cplx<T>), s, in, ntubes, n, out, face_stride, out16, sumsq);
+    if (nblocks_out) *nblocks_out = blocks;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T, typename Tout>
+int launch_irfft(const cplx<T>* in, int64_t face_stride, int64_t ntubes, int n, Tout* out, hipStream_t s) {
+  const int lg = ilog2_exact(n);
+  if (lg >= 0 && n >= 2 && (int64_t)(2 * (n + 2) + n / 2) * (int64_t)sizeof(cplx<T>) <= 48 * 1024) {
+    const int TB = fft_tile<T>(n);
+    const int64_t blocks = ceil_div(ntubes, TB);
+    const size_t lds = (size_t)(2 * (n + 2) * (TB / 2) + n / 2) * sizeof(cplx<T>);
+    hipLaunchKernelGGL((k_irfft_pow2<T, Tout>), dim3((unsigned)blocks), dim3(FFT_THREADS), lds, s,
+                       in, face_stride, ntubes, n, lg, TB, out);
+  } else {
+    const int64_t blocks = ceil_div(ntubes, FFT_THREADS);
+    hipLaunchKernelGGL((k_irdft_direct<T, Tout>), dim3((unsigned)blocks), dim3(FFT_THREADS),
+                       (size_t)n * sizeof(cplx<T>), s, in, face_stride, ntubes, n, out);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace rt

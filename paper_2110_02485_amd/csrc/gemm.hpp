@@ -1,0 +1,110 @@
+// Batched complex GEMM over Fourier faces: C_f = alpha * op(A_f) op(B_f) (+ C_f).
+//
+// op(A) is A (M x K, column-major, A[i + k*lda]) or A^H (A stored K x M: op(A)[i][k] =
+// conj(A[k + i*lda])); op(B) likewise with B (K x N) or B^H (stored N x K).  Storage types of A,
+// B and C are any of zd / zf / zb (double, float, bf16 complex); products accumulate in Acc.
+// Every face f uses A + f*strideA etc.  Generic LDS-tiled kernel for the small and medium
+// products of the path (Gram matrices, triangular factors, solve-side products); the big
+// passes over A-hat use the MFMA kernels in mfma_gemm.hpp.
+#pragma once
+#include "common.hpp"
+
+namespace rt {
+
+template <int BM, int BN, int BK, typename TA, typename TB, typename TC, typename Acc, bool CA, bool CB>
+__global__ void __launch_bounds__(256)
+k_cgemm(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
+        const TB* __restrict__ B, int64_t ldb, int64_t sB, TC* __restrict__ C, int64_t ldc, int64_t sC,
+        Acc alpha, int accumulate) {
+  constexpr int TM = BM / 16, TN = BN / 16;
+  __shared__ cplx<Acc> As[BK][BM + 1];
+  __shared__ cplx<Acc> Bs[BK][BN + 1];
+  const int f = blockIdx.z;
+  A += f * sA; B += f * sB; C += f * sC;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  cplx<Acc> acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = mk((Acc)0, (Acc)0);
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    // A tile: BM x BK
+    for (int idx = threadIdx.x; idx < BM * BK; idx += 256) {
+      int i, k;
+      if (!CA) { i = idx % BM; k = idx / BM; } else { k = idx % BK; i = idx / BK; }
+      const int gi = m0 + i, gk = k0 + k;
+      cplx<Acc> v = mk((Acc)0, (Acc)0);
+      if (gi < M && gk < K) {
+        if (!CA) v = ld<Acc>(A[gi + (int64_t)gk * lda]);
+        else v = cconj(ld<Acc>(A[gk + (int64_t)gi * lda]));
+      }
+      As[k][i] = v;
+    }
+    for (int idx = threadIdx.x; idx < BN * BK; idx += 256) {
+      int j, k;
+      if (!CB) { k = idx % BK; j = idx / BK; } else { j = idx % BN; k = idx / BN; }
+      const int gj = n0 + j, gk = k0 + k;
+      cplx<Acc> v = mk((Acc)0, (Acc)0);
+      if (gj < N && gk < K) {
+        if (!CB) v = ld<Acc>(B[gk + (int64_t)gj * ldb]);
+        else v = cconj(ld<Acc>(B[gj + (int64_t)gk * ldb]));
+      }
+      Bs[k][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BK; ++k) {
+      cplx<Acc> av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[k][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[k][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          acc[a][b].re += av[a].re * bv[b].re - av[a].im * bv[b].im;
+          acc[a][b].im += av[a].re * bv[b].im + av[a].im * bv[b].re;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int gi = m0 + tx + 16 * a, gj = n0 + ty + 16 * b;
+      if (gi < M && gj < N) {
+        cplx<Acc> v = cscale(acc[a][b], alpha);
+        TC& dst = C[gi + (int64_t)gj * ldc];
+        if (accumulate) v = cadd(v, ld<Acc>(dst));
+        st(dst, v);
+      }
+    }
+}
+
+template <typename TA, typename TB, typename TC, typename Acc>
+int cgemm(bool conjA, bool conjB, int M, int N, int K, const TA* A, int64_t lda, int64_t sA,
+          const TB* B, int64_t ldb, int64_t sB, TC* C, int64_t ldc, int64_t sC, int batch,
+          Acc alpha, bool accumulate, hipStream_t s) {
+  if (M <= 0 || N <= 0 || batch <= 0) return 0;
+  constexpr int BM = 64, BN = 64, BK = 8;
+  dim3 grid((unsigned)ceil_div(M, BM), (unsigned)ceil_div(N, BN), (unsigned)batch);
+  if (!conjA && !conjB)
+    hipLaunchKernelGGL((k_cgemm<BM, BN, BK, TA, TB, TC, Acc, false, false>), grid, dim3(256), 0, s,
+                       M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate);
+  else if (conjA && !conjB)
+    hipLaunchKernelGGL((k_cgemm<BM, BN, BK, TA, TB, TC, Acc, true, false>), grid, dim3(256), 0, s,
+                       M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate);
+  else if (!conjA && conjB)
+    hipLaunchKernelGGL((k_cgemm<BM, BN, BK, TA, TB, TC, Acc, false, true>), grid, dim3(256), 0, s,
+                       M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate);
+  else
+    hipLaunchKernelGGL((k_cgemm<BM, BN, BK, TA, TB, TC, Acc, true, true>), grid, dim3(256), 0, s,
+                       M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace rt

@@ -1,0 +1,483 @@
+// C ABI of librtsvd (declared in include/rtsvd.h): argument checks, scratch management and the
+// launch sequences of the R-tSVD factor / solve, the T-tSVD comparator, t-products and tGKB.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "fft.hpp"
+#include "gemm.hpp"
+#include "mfma_gemm.hpp"
+#include "small.hpp"
+#include "solve.hpp"
+
+using namespace rt;
+
+// ---------------------------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void rt_set_hip_error(hipError_t e, const char* what, const char* file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  g_last_error = buf;
+}
+
+static int fail(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define RT_TRY(expr)                                                        \
+  do {                                                                      \
+    int _rc = (expr);                                                       \
+    if (_rc != 0) {                                                         \
+      if (g_last_error.empty()) g_last_error = "launch failed: " #expr;     \
+      return _rc < 0 ? _rc : RTSVD_E_HIP;                                   \
+    }                                                                       \
+  } while (0)
+
+#define RT_LAUNCH_OK() RT_CHECK_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------------------------
+// stream-ordered scratch from the device's default memory pool (kept allocated between calls)
+// ---------------------------------------------------------------------------------------------
+static void ensure_pool_keeps_memory() {
+  static std::once_flag once[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::call_once(once[dev], [dev]() {
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
+}
+
+struct Scratch {
+  hipStream_t s;
+  std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t st) : s(st) { ensure_pool_keeps_memory(); }
+  ~Scratch() { for (void* p : ptrs) (void)hipFreeAsync(p, s); }
+  template <typename T> T* get(int64_t count) {
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    if (hipMallocAsync(&p, (size_t)count * sizeof(T), s) != hipSuccess || !p) return nullptr;
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <typename T> T* release(T* p) {  // ownership passes to the caller
+    ptrs.erase(std::remove(ptrs.begin(), ptrs.end(), (void*)p), ptrs.end());
+    return p;
+  }
+};
+
+#define RT_ALLOC(var, type, count, sc)                                             \
+  type* var = (sc).template get<type>(count);                                      \
+  if (!var) return fail(RTSVD_E_NOMEM, "device allocation failed: " #var)
+
+static inline unsigned nblocks(int64_t total, int threads = 256) { return (unsigned)ceil_div(total, threads); }
+
+template <typename TI, typename TO>
+__global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) st(out[i], ld<double>(in[i]));
+}
+
+// ---------------------------------------------------------------------------------------------
+// factor handle
+// ---------------------------------------------------------------------------------------------
+struct rtsvd_factor_s {
+  int64_t l = 0, m = 0, n = 0, F = 0, r = 0;
+  int dtype = RTSVD_F64;       // caller dtype
+  int precision = RTSVD_P_FP64;
+  int kind = 0;                // 0 = R-tSVD, 1 = T-tSVD
+  int k_max = 0, oversample = 0;
+  double eps = 0.0;
+  hipStream_t stream = nullptr;
+  void* Q = nullptr;           // F x l x r, work type; T-tSVD: the left singular vectors U
+  zd* Ub = nullptr;            // F x r x r (R-tSVD only)
+  double* sigma = nullptr;     // F x r
+  zd* V = nullptr;             // F x m x r
+  void* W = nullptr;           // F x l x r, work type (A-hat V)
+  double* eta = nullptr;       // r + 1
+  int* flags = nullptr;        // 1
+  std::vector<void*> owned;
+};
+
+static bool work_is_double(int precision) { return precision == RTSVD_P_FP64; }
+
+// ---------------------------------------------------------------------------------------------
+// CholeskyQR: Y (F x rows x r) <- Y R^{-1} with R^H R = Y^H Y (FP64 Gram + Cholesky), `passes`
+// times (2 = CholeskyQR2, orthonormal to working precision).
+// ---------------------------------------------------------------------------------------------
+template <typename TY>
+static int orthonormalize(TY* Y, int64_t rows, int64_t r, int64_t F, int passes, zd* G, zd* Rinv, TY* tmp,
+                          int* flags, hipStream_t s) {
+  for (int pass = 0; pass < passes; ++pass) {
+    RT_TRY((cgemm<TY, TY, zd, double>(true, false, (int)r, (int)r, (int)rows, Y, rows, rows * r, Y, rows, rows * r,
+                                     G, r, r * r, (int)F, 1.0, false, s)));
+    hipLaunchKernelGGL(k_chol_inv, dim3((unsigned)F), dim3(256), 0, s, G, Rinv, (int)r, 1e-13, flags);
+    RT_LAUNCH_OK();
+    RT_CHECK_HIP(hipMemcpyAsync(tmp, Y, sizeof(TY) * F * rows * r, hipMemcpyDeviceToDevice, s));
+    RT_TRY((cgemm<TY, zd, TY, double>(false, false, (int)rows, (int)r, (int)r, tmp, rows, rows * r, Rinv, r, r * r,
+                                     Y, rows, rows * r, (int)F, 1.0, false, s)));
+  }
+  return 0;
+}
+
+// products over A-hat: Y = A-hat X (conjA = false, Y is l x r) or Y = A-hat^H X (Y is m x r)
+template <typename TA, typename TX, typename TY, typename Acc>
+static int big_gemm(bool conjA, const TA* Ah, int64_t l, int64_t m, const TX* X, int64_t r, TY* Y, int64_t F,
+                    hipStream_t s) {
+  if (!conjA)
+    return big_cgemm<TA, TX, TY, Acc>(false, (int)l, (int)r, (int)m, Ah, l, l * m, X, m, m * r, Y, l, l * r,
+                                      (int)F, s);
+  return big_cgemm<TA, TX, TY, Acc>(true, (int)m, (int)r, (int)l, Ah, l, l * m, X, l, l * r, Y, m, m * r, (int)F, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// R-tSVD factor (Alg. 6, block form) and the T-tSVD comparator (Alg. 1)
+// ---------------------------------------------------------------------------------------------
+template <typename Tin, typename Tw>
+static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int64_t n, int64_t r, int precision,
+                       int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd_mode) {
+  typedef cplx<Tw> zw;
+  const int64_t F = n / 2 + 1;
+  const bool bf16 = (precision == RTSVD_P_BF16);
+  Scratch sc(s);
+  // tube DFT of A (half spectrum), ||A||_F^2 partial sums on the way
+  RT_ALLOC(Ah, zw, F * l * m, sc);
+  zb* Ah16 = nullptr;
+  if (bf16) {
+    Ah16 = sc.get<zb>(F * l * m);
+    if (!Ah16) return fail(RTSVD_E_NOMEM, "device allocation failed: Ah16");
+  }
+  RT_ALLOC(sumsq, double, ceil_div(l * m, 2) + 1, sc);
+  int64_t nblk = 0;
+  RT_TRY((launch_rfft<Tin, Tw>(A, l * m, (int)n, Ah, l * m, Ah16, sumsq, &nblk, s)));
+
+  // outputs owned by the handle
+  RT_ALLOC(Qo, zw, F * l * r, sc);
+  RT_ALLOC(sigma, double, F * r, sc);
+  RT_ALLOC(V, zd, F * m * r, sc);
+  RT_ALLOC(Wo, zw, F * l * r, sc);
+  RT_ALLOC(eta, double, r + 1, sc);
+  RT_ALLOC(flags, int, 1, sc);
+  RT_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
+  zd* Ub = nullptr;
+
+  RT_ALLOC(G, zd, F * r * r, sc);
+  RT_ALLOC(lam, double, F * r, sc);
+  const double eig_tol = 4.0 * (double)r * 2.220446049250313e-16;
+
+  if (!tsvd_mode) {
+    Ub = sc.get<zd>(F * r * r);
+    if (!Ub) return fail(RTSVD_E_NOMEM, "device allocation failed: Ub");
+    RT_ALLOC(Rinv, zd, F * r * r, sc);
+    RT_ALLOC(Omh, zw, F * std::max(l, m) * r, sc);
+    RT_ALLOC(Y, zw, F * std::max(l, m) * r, sc);
+    RT_ALLOC(tmp, zw, F * std::max(l, m) * r, sc);
+    RT_ALLOC(Ch, zd, F * m * r, sc);  // C^H = A-hat^H Q, m x r per face (C = Q^H A-hat)
+    RT_ALLOC(rown, double, F * r, sc);
+    RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+    // sketch Y = A-hat Omega-hat, then Q = orth(Y) (q power iterations in between)
+    if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
+    else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
+    RT_TRY(orthonormalize<zw>(Y, l, r, F, q == 0 ? 2 : 1, G, Rinv, tmp, flags, s));
+    for (int it = 0; it < q; ++it) {
+      if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(true, Ah16, l, m, Y, r, Omh, F, s)));
+      else RT_TRY((big_gemm<zw, zw, zw, Tw>(true, Ah, l, m, Y, r, Omh, F, s)));
+      RT_TRY(orthonormalize<zw>(Omh, m, r, F, 1, G, Rinv, tmp, flags, s));
+      if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
+      else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
+      RT_TRY(orthonormalize<zw>(Y, l, r, F, it == q - 1 ? 2 : 1, G, Rinv, tmp, flags, s));
+    }
+    RT_CHECK_HIP(hipMemcpyAsync(Qo, Y, sizeof(zw) * F * l * r, hipMemcpyDeviceToDevice, s));
+    // projection C^H = A-hat^H Q
+    if (bf16) RT_TRY((big_gemm<zb, zw, zd, float>(true, Ah16, l, m, Qo, r, Ch, F, s)));
+    else RT_TRY((big_gemm<zw, zw, zd, Tw>(true, Ah, l, m, Qo, r, Ch, F, s)));
+    // error indicator eta^[j] (Thm 4.2)
+    hipLaunchKernelGGL((k_colnorms<zd>), dim3((unsigned)r, (unsigned)F), dim3(256), 0, s, Ch, (int)m, (int)r, rown);
+    RT_LAUNCH_OK();
+    hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, rown, (int)F, (int)r, (int)n, eta);
+    RT_LAUNCH_OK();
+    // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
+    RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)m, Ch, m, m * r, Ch, m, m * r, G, r, r * r,
+                                     (int)F, 1.0, false, s)));
+    hipLaunchKernelGGL(k_jacobi_eig, dim3((unsigned)F), dim3(SMALL_THREADS), 0, s, G, Ub, lam, (int)r, 60);
+    RT_LAUNCH_OK();
+    hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
+    RT_LAUNCH_OK();
+    // V = C^H U-breve diag(1/sigma)
+    RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)r, (int)r, Ch, m, m * r, Ub, r, r * r, V, m, m * r,
+                                     (int)F, 1.0, false, s)));
+    hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * m * r)), dim3(256), 0, s, V, V, sigma, (int)m,
+                       (int)r, (int)F);
+    RT_LAUNCH_OK();
+    // W = A-hat V: exact residuals of the discrepancy principle
+    RT_TRY((big_gemm<zw, zd, zw, Tw>(false, Ah, l, m, V, r, Wo, F, s)));
+  } else {
+    // full facewise SVD through G = A-hat^H A-hat = V diag(sigma^2) V^H; W = A-hat V; U = W diag(1/sigma)
+    RT_TRY((cgemm<zw, zw, zd, double>(true, false, (int)m, (int)m, (int)l, Ah, l, l * m, Ah, l, l * m, G, m, m * m,
+                                     (int)F, 1.0, false, s)));
+    hipLaunchKernelGGL(k_jacobi_eig, dim3((unsigned)F), dim3(SMALL_THREADS), 0, s, G, V, lam, (int)m, 60);
+    RT_LAUNCH_OK();
+    hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
+    RT_LAUNCH_OK();
+    hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, lam, (int)F, (int)r, (int)n, eta);
+    RT_LAUNCH_OK();
+    RT_TRY((big_gemm<zw, zd, zw, Tw>(false, Ah, l, m, V, r, Wo, F, s)));
+    hipLaunchKernelGGL((k_scale_cols<zw, zw>), dim3(nblocks(F * l * r)), dim3(256), 0, s, Wo, Qo, sigma, (int)l,
+                       (int)r, (int)F);
+    RT_LAUNCH_OK();
+  }
+  h->Q = sc.release(Qo);
+  h->Ub = Ub ? sc.release(Ub) : nullptr;
+  h->sigma = sc.release(sigma);
+  h->V = sc.release(V);
+  h->W = sc.release(Wo);
+  h->eta = sc.release(eta);
+  h->flags = sc.release(flags);
+  h->owned = {h->Q, h->sigma, h->V, h->W, h->eta, h->flags};
+  if (h->Ub) h->owned.push_back(h->Ub);
+  return 0;
+}
+
+static void free_handle(rtsvd_factor_s* h) {
+  if (!h) return;
+  for (void* p : h->owned) (void)hipFreeAsync(p, h->stream);
+  delete h;
+}
+
+static int dispatch_factor(const void* A, const void* omega, int dtype, int64_t l, int64_t m, int64_t n, int64_t r,
+                           int precision, int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd) {
+  if (dtype == RTSVD_F64) {
+    if (work_is_double(precision))
+      return factor_impl<double, double>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd);
+    return factor_impl<double, float>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd);
+  }
+  if (work_is_double(precision))
+    return factor_impl<float, double>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd);
+  return factor_impl<float, float>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd);
+}
+
+extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype, const rtsvd_opts* opts,
+                            void* stream, rtsvd_handle* out) {
+  g_last_error.clear();
+  if (!A || !opts || !out) return fail(RTSVD_E_ARG, "rtsvd_factor: null argument");
+  *out = nullptr;
+  if (dtype != RTSVD_F64 && dtype != RTSVD_F32) return fail(RTSVD_E_ARG, "rtsvd_factor: bad dtype");
+  if (l < 1 || m < 1 || n < 1 || l < m) return fail(RTSVD_E_ARG, "rtsvd_factor: need l >= m >= 1 and n >= 1");
+  const rtsvd_opts o = *opts;
+  if (o.k_max < 1 || o.k_max > m || o.oversample < 0 || o.power_iters < 0)
+    return fail(RTSVD_E_ARG, "rtsvd_factor: need 1 <= k_max <= m, oversample >= 0, power_iters >= 0");
+  if (o.precision != RTSVD_P_FP64 && o.precision != RTSVD_P_FP32 && o.precision != RTSVD_P_BF16)
+    return fail(RTSVD_E_ARG, "rtsvd_factor: bad precision");
+  const int64_t r = std::min<int64_t>((int64_t)o.k_max + o.oversample, m);
+  if (r > 256) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_factor: r = min(k_max + oversample, m) must be <= 256");
+  if (!o.omega) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_factor: omega must be supplied");
+  hipStream_t s = (hipStream_t)stream;
+  rtsvd_factor_s* h = new rtsvd_factor_s();
+  h->l = l; h->m = m; h->n = n; h->F = n / 2 + 1; h->r = r; h->dtype = dtype; h->precision = o.precision;
+  h->kind = 0; h->k_max = o.k_max; h->oversample = o.oversample; h->eps = o.eps; h->stream = s;
+  const int rc = dispatch_factor(A, o.omega, dtype, l, m, n, r, o.precision, o.power_iters, h, s, false);
+  if (rc != 0) { delete h; return rc; }
+  *out = h;
+  return RTSVD_OK;
+}
+
+extern "C" int ttsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype, int32_t precision,
+                            int32_t k_max, void* stream, rtsvd_handle* out) {
+  g_last_error.clear();
+  if (!A || !out) return fail(RTSVD_E_ARG, "ttsvd_factor: null argument");
+  *out = nullptr;
+  if (dtype != RTSVD_F64 && dtype != RTSVD_F32) return fail(RTSVD_E_ARG, "ttsvd_factor: bad dtype");
+  if (l < 1 || m < 1 || n < 1 || l < m) return fail(RTSVD_E_ARG, "ttsvd_factor: need l >= m >= 1 and n >= 1");
+  if (k_max < 1 || k_max > m) return fail(RTSVD_E_ARG, "ttsvd_factor: need 1 <= k_max <= m");
+  if (precision != RTSVD_P_FP64 && precision != RTSVD_P_FP32)
+    return fail(RTSVD_E_ARG, "ttsvd_factor: precision must be FP64 or FP32");
+  if (m > 256) return fail(RTSVD_E_UNSUPPORTED, "ttsvd_factor: m must be <= 256");
+  hipStream_t s = (hipStream_t)stream;
+  rtsvd_factor_s* h = new rtsvd_factor_s();
+  h->l = l; h->m = m; h->n = n; h->F = n / 2 + 1; h->r = m; h->dtype = dtype; h->precision = precision;
+  h->kind = 1; h->k_max = k_max; h->oversample = 0; h->stream = s;
+  const int rc = dispatch_factor(A, nullptr, dtype, l, m, n, m, precision, 0, h, s, true);
+  if (rc != 0) { delete h; return rc; }
+  *out = h;
+  return RTSVD_OK;
+}
+
+extern "C" void rtsvd_factor_destroy(rtsvd_handle f) { free_handle(f); }
+
+extern "C" int rtsvd_factor_info(rtsvd_handle f, int32_t* r, int32_t* faces, double* eta, int32_t* r_eps,
+                                 double* sigma, int32_t* flags) {
+  g_last_error.clear();
+  if (!f) return fail(RTSVD_E_ARG, "rtsvd_factor_info: null handle");
+  if (r) *r = (int32_t)f->r;
+  if (faces) *faces = (int32_t)f->F;
+  std::vector<double> e(f->r + 1);
+  RT_CHECK_HIP(hipMemcpyAsync(e.data(), f->eta, sizeof(double) * (f->r + 1), hipMemcpyDeviceToHost, f->stream));
+  int fl = 0;
+  RT_CHECK_HIP(hipMemcpyAsync(&fl, f->flags, sizeof(int), hipMemcpyDeviceToHost, f->stream));
+  if (sigma)
+    RT_CHECK_HIP(hipMemcpyAsync(sigma, f->sigma, sizeof(double) * f->r * f->F, hipMemcpyDeviceToHost, f->stream));
+  RT_CHECK_HIP(hipStreamSynchronize(f->stream));
+  if (eta) std::copy(e.begin(), e.end(), eta);
+  if (flags) *flags = fl;
+  if (r_eps) {
+    *r_eps = -1;
+    if (f->eps > 0.0)
+      for (int64_t j = 0; j <= f->r; ++j)
+        if (e[j] < f->eps * f->eps) { *r_eps = (int32_t)j; break; }
+  }
+  return RTSVD_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// solve: coefficients, discrepancy principle, truncated solution, inverse DFT
+// ---------------------------------------------------------------------------------------------
+template <typename Tio, typename Tw>
+static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vector<double>& bounds, int k_start,
+                      int kcap, Tio* X, int* k_out, double* resid_out, int* status_out, hipStream_t s) {
+  typedef cplx<Tw> zw;
+  const int64_t l = h->l, m = h->m, n = h->n, F = h->F, r = h->r;
+  const int groups = (int)bounds.size();
+  Scratch sc(s);
+  RT_ALLOC(Bh, zw, F * l * p, sc);
+  RT_TRY((launch_rfft<Tio, Tw>(B, l * p, (int)n, Bh, l * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  RT_ALLOC(D, zd, F * r * p, sc);
+  RT_ALLOC(T, zd, F * r * p, sc);
+  // D = Q^H B-hat (T-tSVD: U^H B-hat); T = U-breve^H D
+  RT_TRY((cgemm<zw, zw, zd, double>(true, false, (int)r, (int)p, (int)l, (const zw*)h->Q, l, l * r, Bh, l, l * p,
+                                   h->Ub ? D : T, r, r * p, (int)F, 1.0, false, s)));
+  if (h->Ub)
+    RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)p, (int)r, h->Ub, r, r * r, D, r, r * p, T, r, r * p,
+                                     (int)F, 1.0, false, s)));
+  hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(F * r * p)), dim3(256), 0, s, T, h->sigma, (int)r, (int)p, (int)F);
+  RT_LAUNCH_OK();
+  // residual norms for k = 1..kcap, then the first k meeting the principle
+  const int tiles = (int)ceil_div(l, DP_ROWS);
+  RT_ALLOC(partial, double, F * tiles * p * kcap, sc);
+  hipLaunchKernelGGL((k_dp_partial<zw, zw>), dim3((unsigned)tiles, (unsigned)p, (unsigned)F), dim3(DP_ROWS), 0, s,
+                     Bh, (const zw*)h->W, T, (int)l, (int)p, (int)r, kcap, partial);
+  RT_LAUNCH_OK();
+  RT_ALLOC(bnd, double, groups, sc);
+  RT_ALLOC(rho_tmp, double, (int64_t)groups * kcap, sc);
+  RT_CHECK_HIP(hipMemcpyAsync(bnd, bounds.data(), sizeof(double) * groups, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(256), 0, s, partial, (int)F, tiles, (int)p, kcap, (int)n, groups, bnd,
+                     k_start, k_out, resid_out, status_out, rho_tmp);
+  RT_LAUNCH_OK();
+  // X-hat = V T', T' = T with rows >= k zeroed; X = inverse DFT
+  hipLaunchKernelGGL(k_mask_coeffs, dim3(nblocks(F * r * p)), dim3(256), 0, s, T, D, k_out, groups, (int)r, (int)p,
+                     (int)F);
+  RT_LAUNCH_OK();
+  RT_ALLOC(Xh, zd, F * m * p, sc);
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)p, (int)r, h->V, m, m * r, D, r, r * p, Xh, m, m * p,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((launch_irfft<double, Tio>(Xh, m * p, m * p, (int)n, X, s)));
+  return 0;
+}
+
+extern "C" int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype, const double* delta, int32_t n_delta,
+                           double eta_dp, int32_t k_start, void* X, int32_t* k_out, double* resid_out,
+                           int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  if (!f || !B || !X || !delta || !k_out) return fail(RTSVD_E_ARG, "rtsvd_solve: null argument");
+  if (p < 1) return fail(RTSVD_E_ARG, "rtsvd_solve: p must be >= 1");
+  if (dtype != f->dtype) return fail(RTSVD_E_ARG, "rtsvd_solve: dtype differs from the factor's");
+  if (n_delta != 1 && n_delta != p) return fail(RTSVD_E_ARG, "rtsvd_solve: n_delta must be 1 or p");
+  if (!(eta_dp > 1.0)) return fail(RTSVD_E_ARG, "rtsvd_solve: eta_dp must be > 1");
+  if (k_start < 0 || k_start > f->k_max) return fail(RTSVD_E_ARG, "rtsvd_solve: need 0 <= k_start <= k_max");
+  for (int i = 0; i < n_delta; ++i)
+    if (!(delta[i] >= 0.0)) return fail(RTSVD_E_ARG, "rtsvd_solve: delta must be >= 0");
+  int ks = k_start, kcap = std::min<int>(f->k_max, (int)f->r);
+  if (k_start == 0) {
+    ks = std::max<int>(1, (int)f->r - f->oversample);
+    kcap = (int)f->r;
+  }
+  std::vector<double> bounds(n_delta);
+  for (int i = 0; i < n_delta; ++i) bounds[i] = eta_dp * delta[i];
+  hipStream_t s = (hipStream_t)stream;
+  if (f->dtype == RTSVD_F64) {
+    if (work_is_double(f->precision))
+      return solve_impl<double, double>(f, (const double*)B, p, bounds, ks, kcap, (double*)X, k_out, resid_out,
+                                        status_out, s);
+    return solve_impl<double, float>(f, (const double*)B, p, bounds, ks, kcap, (double*)X, k_out, resid_out,
+                                     status_out, s);
+  }
+  if (work_is_double(f->precision))
+    return solve_impl<float, double>(f, (const float*)B, p, bounds, ks, kcap, (float*)X, k_out, resid_out, status_out,
+                                     s);
+  return solve_impl<float, float>(f, (const float*)B, p, bounds, ks, kcap, (float*)X, k_out, resid_out, status_out, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// t-products
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+static int tprod_impl(const T* A, const T* Bin, T* Out, int64_t l, int64_t m, int64_t p, int64_t n, bool adjoint,
+                      hipStream_t s) {
+  typedef cplx<T> zt;
+  const int64_t F = n / 2 + 1;
+  Scratch sc(s);
+  RT_ALLOC(Ah, zt, F * l * m, sc);
+  RT_TRY((launch_rfft<T, T>(A, l * m, (int)n, Ah, l * m, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  const int64_t rin = adjoint ? l : m, rout = adjoint ? m : l;
+  RT_ALLOC(Bh, zt, F * rin * p, sc);
+  RT_ALLOC(Ch, zt, F * rout * p, sc);
+  RT_TRY((launch_rfft<T, T>(Bin, rin * p, (int)n, Bh, rin * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  if (!adjoint)
+    RT_TRY((cgemm<zt, zt, zt, T>(false, false, (int)l, (int)p, (int)m, Ah, l, l * m, Bh, m, m * p, Ch, l, l * p,
+                                 (int)F, (T)1, false, s)));
+  else
+    RT_TRY((cgemm<zt, zt, zt, T>(true, false, (int)m, (int)p, (int)l, Ah, l, l * m, Bh, l, l * p, Ch, m, m * p,
+                                 (int)F, (T)1, false, s)));
+  RT_TRY((launch_irfft<T, T>(Ch, rout * p, rout * p, (int)n, Out, s)));
+  return 0;
+}
+
+extern "C" int tprod(const void* A, const void* B, void* C, int64_t l, int64_t m, int64_t p, int64_t n, int dtype,
+                     void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !C) return fail(RTSVD_E_ARG, "tprod: null argument");
+  if (l < 1 || m < 1 || p < 1 || n < 1) return fail(RTSVD_E_ARG, "tprod: sizes must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RTSVD_F64) return tprod_impl<double>((const double*)A, (const double*)B, (double*)C, l, m, p, n, false, s);
+  if (dtype == RTSVD_F32) return tprod_impl<float>((const float*)A, (const float*)B, (float*)C, l, m, p, n, false, s);
+  return fail(RTSVD_E_ARG, "tprod: bad dtype");
+}
+
+extern "C" int tprod_adjoint(const void* A, const void* C, void* B, int64_t l, int64_t m, int64_t p, int64_t n,
+                             int dtype, void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !C) return fail(RTSVD_E_ARG, "tprod_adjoint: null argument");
+  if (l < 1 || m < 1 || p < 1 || n < 1) return fail(RTSVD_E_ARG, "tprod_adjoint: sizes must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RTSVD_F64) return tprod_impl<double>((const double*)A, (const double*)C, (double*)B, l, m, p, n, true, s);
+  if (dtype == RTSVD_F32) return tprod_impl<float>((const float*)A, (const float*)C, (float*)B, l, m, p, n, true, s);
+  return fail(RTSVD_E_ARG, "tprod_adjoint: bad dtype");
+}
+
+// ---------------------------------------------------------------------------------------------
+extern "C" const char* rtsvd_status_string(int status) {
+  switch (status) {
+    case RTSVD_OK: return "ok";
+    case RTSVD_W_DP_NOT_MET: return "warning: discrepancy principle not met within k_cap";
+    case RTSVD_W_RANK_DEFICIENT: return "warning: rank-deficient sketch (breakdown threshold reached)";
+    case RTSVD_E_ARG: return "error: invalid argument";
+    case RTSVD_E_HIP: return "error: HIP runtime failure";
+    case RTSVD_E_NOMEM: return "error: out of device memory";
+    case RTSVD_E_UNSUPPORTED: return "error: unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* rtsvd_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,173 @@
+// Truncated pseudo-inverse coefficients and the discrepancy principle (eq. (disp), eq. (kinit)).
+//
+// Per face f: T_f = diag(1/sigma_f) U-breve_f^H Q_f^H B-hat_f (r x p, FP64).  The residual of
+// the k-term solution is, by Parseval over the half spectrum,
+//     rho_k^2 = (1/n) sum_f w_f || B-hat_f - W_f[:, :k] T_f[:k, :] ||_F^2,   W_f = A-hat_f V_f,
+// with w_f = 1 for the self-conjugate faces (0 and n/2) and 2 otherwise -- the exact
+// ||B - A * X_k||_F^2 (no approximation of A).  k_dp_partial forms the per-face, per-row-tile
+// sums for every k in one pass (the residual is updated one rank-1 term at a time), k_dp_select
+// reduces them over faces in a fixed order (deterministic) and picks the first k >= k_start
+// with rho_k <= eta * delta.
+#pragma once
+#include "common.hpp"
+
+namespace rt {
+
+constexpr int DP_ROWS = 256;
+
+// T = diag(1/sigma) E, zero where sigma <= 0 (dependent columns excluded from the pseudo-inverse)
+__global__ void k_scale_rows(zd* __restrict__ T, const double* __restrict__ sigma, int r, int p, int F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)F * r * p;
+  if (idx >= total) return;
+  const int j = (int)(idx % r);
+  const int64_t f = idx / ((int64_t)r * p);
+  const double s = sigma[f * r + j];
+  T[idx] = s > 0.0 ? cscale(T[idx], 1.0 / s) : mk(0.0, 0.0);
+}
+
+// partial[((f * tiles + tile) * p + c) * kcap + (k-1)] = sum over the tile's rows of
+// |B-hat - W[:, :k] T[:k, c]|^2, FP64.  Block = DP_ROWS threads = one row tile of one column.
+template <typename TBh, typename TW>
+__global__ void __launch_bounds__(DP_ROWS)
+k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __restrict__ T,
+             int l, int p, int r, int kcap, double* __restrict__ partial) {
+  const int tile = blockIdx.x, c = blockIdx.y, f = blockIdx.z;
+  const int tiles = gridDim.x;
+  const int row = tile * DP_ROWS + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double wsum[DP_ROWS / 64][256];
+  zd R = mk(0.0, 0.0);
+  const bool on = row < l;
+  if (on) R = ld<double>(Bh[(int64_t)f * l * p + (int64_t)c * l + row]);
+  const TW* wf = W + (int64_t)f * l * r;
+  const zd* tf = T + (int64_t)f * r * p + (int64_t)c * r;
+  for (int k = 1; k <= kcap; ++k) {
+    if (on) R = csub(R, cmul(ld<double>(wf[(int64_t)(k - 1) * l + row]), tf[k - 1]));
+    double v = on ? cabs2(R) : 0.0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) wsum[wave][k - 1] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kcap; k += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < DP_ROWS / 64; ++w) s += wsum[w][k];
+    partial[(((int64_t)f * tiles + tile) * p + c) * kcap + k] = s;
+  }
+}
+
+// One block.  groups = 1 (joint) or p (per slice).  k_start >= 1.
+__global__ void k_dp_select(const double* __restrict__ partial, int F, int tiles, int p, int kcap, int n,
+                            int groups, const double* __restrict__ bound /* eta*delta per group */,
+                            int k_start, int* __restrict__ k_out, double* __restrict__ resid_out,
+                            int* __restrict__ status_out, double* __restrict__ rho_tmp) {
+  // rho_tmp: groups * kcap doubles of scratch
+  for (int idx = threadIdx.x; idx < groups * kcap; idx += blockDim.x) {
+    const int g = idx / kcap, k = idx % kcap;
+    const int c0 = groups == 1 ? 0 : g, c1 = groups == 1 ? p : g + 1;
+    double tot = 0.0;
+    for (int f = 0; f < F; ++f) {
+      const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
+      double s = 0.0;
+      for (int t = 0; t < tiles; ++t)
+        for (int c = c0; c < c1; ++c) s += partial[(((int64_t)f * tiles + t) * p + c) * kcap + k];
+      tot += w * s;
+    }
+    const double rho = sqrt(fmax(tot / (double)n, 0.0));
+    rho_tmp[idx] = rho;
+    if (resid_out) resid_out[idx] = rho;
+  }
+  __syncthreads();
+  __shared__ int any_fail;
+  if (threadIdx.x == 0) any_fail = 0;
+  __syncthreads();
+  for (int g = threadIdx.x; g < groups; g += blockDim.x) {
+    int kk = -1;
+    for (int k = k_start; k <= kcap; ++k)
+      if (rho_tmp[g * kcap + k - 1] <= bound[g]) { kk = k; break; }
+    if (kk < 0) { kk = kcap; atomicOr(&any_fail, 1); }
+    k_out[g] = kk;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && status_out) *status_out = any_fail ? RTSVD_W_DP_NOT_MET : RTSVD_OK;
+}
+
+// T'[f][j][c] = T[f][j][c] if j < k of column c's group, else 0
+__global__ void k_mask_coeffs(const zd* __restrict__ T, zd* __restrict__ Tm, const int* __restrict__ k_of,
+                              int groups, int r, int p, int F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)F * r * p;
+  if (idx >= total) return;
+  const int j = (int)(idx % r);
+  const int c = (int)((idx / r) % p);
+  const int k = k_of[groups == 1 ? 0 : c];
+  Tm[idx] = j < k ? T[idx] : mk(0.0, 0.0);
+}
+
+// Column sums of |C^H|^2 per face: rown[f*r + j] = ||C_f(j, :)||^2 (C^H stored m x r).
+template <typename TC>
+__global__ void k_colnorms(const TC* __restrict__ Ch, int m, int r, double* __restrict__ rown) {
+  const int j = blockIdx.x, f = blockIdx.y;
+  const TC* col = Ch + (int64_t)f * m * r + (int64_t)j * m;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) s += cabs2(ld<double>(col[i]));
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rown[(int64_t)f * r + j] = red[0];
+}
+
+// eta[j] = ||A||^2 - (1/n) sum_f w_f sum_{j' < j} rown[f][j'],  j = 0..r  (one block)
+__global__ void k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __restrict__ rown,
+                             int F, int r, int n, double* __restrict__ eta) {
+  __shared__ double red[256];
+  __shared__ double rows[257];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nsumsq; i += blockDim.x) s += sumsq[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+    double t = 0.0;
+    for (int f = 0; f < F; ++f) t += ((f == 0 || 2 * f == n) ? 1.0 : 2.0) * rown[(int64_t)f * r + j];
+    rows[j] = t / (double)n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = red[0];
+    eta[0] = e;
+    for (int j = 0; j < r; ++j) { e -= rows[j]; eta[j + 1] = e; }
+  }
+}
+
+// Out_f[:, j] = In_f[:, j] / sigma_f[j]  (zero column when sigma is zero); In and Out may alias
+template <typename TI, typename TO>
+__global__ void k_scale_cols(const TI* In, TO* Out, const double* __restrict__ sigma,
+                             int rows, int r, int F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)F * rows * r;
+  if (idx >= total) return;
+  const int j = (int)((idx / rows) % r);
+  const int64_t f = idx / ((int64_t)rows * r);
+  const double s = sigma[f * r + j];
+  st(Out[idx], s > 0.0 ? cscale(ld<double>(In[idx]), 1.0 / s) : mk(0.0, 0.0));
+}
+
+// sigma = sqrt(max(lambda, 0)), with eigenvalues at or below tol_rel * lambda_max set to zero
+__global__ void k_sqrt_eigs(const double* __restrict__ lam, double* __restrict__ sigma, int r, int F, double tol_rel) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)F * r) return;
+  const int64_t f = idx / r;
+  const double lmax = lam[f * r];
+  const double l = lam[idx];
+  sigma[idx] = (l > tol_rel * lmax && l > 0.0) ? sqrt(l) : 0.0;
+}
+
+}  // namespace rt

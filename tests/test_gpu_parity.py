@@ -1,0 +1,136 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on identical seeded inputs.
+
+Tolerances: FP64 path 1e-12 (relative, Frobenius), FP32 path 1e-5, truncation indices equal.
+"""
+import numpy as np
+import pytest
+
+from oracle import tproduct as tp
+from oracle import factor as fa
+from oracle import solve as so
+from paper_2110_02485_amd import workloads as wl
+from tests.problems import blur_problem, random_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype="float64"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=getattr(torch, dtype))
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ---------------------------------------------------------------------------------------------
+# t-products
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("l,m,p,n", [(5, 3, 2, 8), (37, 29, 3, 16), (64, 64, 1, 1), (33, 17, 4, 7),
+                                     (130, 70, 5, 12), (300, 260, 2, 64), (8, 8, 1, 2)])
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 2e-5)])
+def test_tprod_and_adjoint(l, m, p, n, dtype, tol):
+    from paper_2110_02485_amd import rtsvd as rt
+    rng = np.random.default_rng(l * 1000 + m * 10 + n)
+    A = rng.standard_normal((n, m, l))
+    X = rng.standard_normal((n, p, m))
+    Y = rng.standard_normal((n, p, l))
+    C = _np(rt.tprod(_t(A, dtype), _t(X, dtype)))
+    ref = wl.to_storage(tp.tprod(wl.to_math(A), wl.to_math(X)))
+    assert _rel(C, ref) <= tol
+    Bt = _np(rt.tprod_adjoint(_t(A, dtype), _t(Y, dtype)))
+    ref = wl.to_storage(tp.tprod(tp.ttranspose(wl.to_math(A)), wl.to_math(Y)))
+    assert _rel(Bt, ref) <= tol
+
+
+# ---------------------------------------------------------------------------------------------
+# R-tSVD restorations
+# ---------------------------------------------------------------------------------------------
+def _oracle_rtsvd(A, B, Om, delta, eta, k_max, q, k_start=1, per_slice=False, rho=None):
+    return so.rtsvd_restore(wl.to_math(A), wl.to_math(B), wl.to_math(Om), delta, eta, k_max, q, k_start,
+                            per_slice, rho)
+
+
+def _gpu_rtsvd(A, B, Om, delta, eta, k_max, rho, q, precision, dtype, k_start=1):
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    f = rt.factor(_t(A, dtype), k_max, rho, q, precision, _t(Om, dtype))
+    res = f.solve(_t(B, dtype), delta, eta, k_start)
+    torch.cuda.synchronize()
+    return f, res
+
+
+def test_rtsvd_fp64_blur64():
+    # the 64 x 64 x 16 FP64 workload: sigma 2, band 6, 5 blobs, noise 1e-2, k <= 20, rho = 10
+    w = wl.WORKLOADS["blur64"]
+    A, X, B, Om, delta = blur_problem(w.size, w.n, w.sigma, w.band, 1, w.noise, w.k_max, w.oversample)
+    orc = _oracle_rtsvd(A, B, Om, delta, w.eta, w.k_max, 0)
+    f, res = _gpu_rtsvd(A, B, Om, delta, w.eta, w.k_max, w.oversample, 0, "fp64", "float64")
+    assert int(res.k[0]) == orc["k"] and int(res.status[0]) == orc["status"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-12
+    np.testing.assert_allclose(_np(res.resid)[0], orc["res"][:, 0], rtol=1e-12)
+    r, faces, eta, r_eps, sig, flags = f.info()
+    np.testing.assert_allclose(sig, orc["factor"]["s"][:, :faces].T, rtol=1e-12, atol=1e-14 * sig.max())
+    np.testing.assert_allclose(eta, fa.eta_prefix(wl.to_math(A), orc["factor"]["C"]), rtol=0,
+                               atol=1e-12 * eta[0])
+    assert flags == 0
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_rtsvd_fp64_random_ragged(q):
+    # ragged sizes (not multiples of any tile), non-power-of-two tube length, several RHS
+    l, m, n, p, k_max, rho = 45, 38, 6, 3, 9, 4
+    A, B, Om = random_problem(l, m, n, p, k_max + rho, seed=q)
+    delta = 0.6 * np.linalg.norm(B)
+    orc = _oracle_rtsvd(A, B, Om, delta, 1.05, k_max, q)
+    f, res = _gpu_rtsvd(A, B, Om, delta, 1.05, k_max, rho, q, "fp64", "float64")
+    assert int(res.k[0]) == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-11
+    np.testing.assert_allclose(_np(res.resid)[0], orc["res"][:, 0], rtol=1e-11)
+
+
+def test_rtsvd_per_slice_and_paper_mode():
+    w = wl.WORKLOADS["blur64"]
+    A, X, B, Om, delta = blur_problem(48, 10, 2.0, 6, 3, 1e-2, 12, 6, seed=3, video=True)
+    Bm = wl.to_math(B)
+    deltas = [0.01 * np.linalg.norm(Bm[:, j]) for j in range(3)]
+    orc = _oracle_rtsvd(A, B, Om, deltas, 1.01, 12, 0, per_slice=True)
+    f, res = _gpu_rtsvd(A, B, Om, deltas, 1.01, 12, 6, 0, "fp64", "float64")
+    assert [int(v) for v in res.k.cpu()] == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-11
+    # experiments' rule: start at r - rho, search up to r
+    orc = _oracle_rtsvd(A, B, Om, delta, 1.01, 12, 0, k_start=0, rho=6)
+    res = f.solve(_t(B), delta, 1.01, 0)
+    assert int(res.k[0]) == orc["k"] and int(res.k[0]) >= 12
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-11
+
+
+def test_rtsvd_dp_not_met_status():
+    A, X, B, Om, delta = blur_problem(40, 8, 2.0, 6, 1, 1e-2, 8, 4, seed=4)
+    f, res = _gpu_rtsvd(A, B, Om, 1e-12, 1.01, 8, 4, 0, "fp64", "float64")
+    assert int(res.k[0]) == 8 and int(res.status[0]) == 1
+
+
+def test_rtsvd_fp32_blur():
+    A, X, B, Om, delta = blur_problem(96, 32, 3.0, 10, 2, 1e-2, 24, 8, seed=5, video=True)
+    orc = _oracle_rtsvd(A, B, Om, delta, 1.01, 24, 0)
+    f, res = _gpu_rtsvd(A, B, Om, delta, 1.01, 24, 8, 0, "fp32", "float32")
+    assert abs(int(res.k[0]) - orc["k"]) <= 0 or True
+    assert int(res.k[0]) == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-5
+
+
+def test_ttsvd_fp64():
+    A, X, B, Om, delta = blur_problem(40, 12, 2.0, 6, 1, 1e-2, 20, 0, seed=6)
+    orc = so.tsvd_restore(wl.to_math(A), wl.to_math(B), delta, 1.01, 20)
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    f = rt.ttsvd_factor(_t(A), 20, "fp64")
+    res = f.solve(_t(B), delta, 1.01, 1)
+    torch.cuda.synchronize()
+    assert int(res.k[0]) == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-10
