@@ -1,0 +1,417 @@
+// Hermitian eigensolver and Cholesky inverse for the r x r per-face matrices, FP64, one
+// workgroup (1024 threads) per Fourier face.  The Hermitian matrix is held as a packed lower
+// triangle (column-major: column j holds rows j..r-1 at offset j*r - j*(j-1)/2) in LDS when it
+// fits, else in a global scratch slice; both are addressed through one generic pointer.
+//
+// k_heev:  G = Q_H T Q_H^H by Householder reflections (T real symmetric tridiagonal), eigenvalues
+//          of T by multisection of Sturm counts (8 lanes per eigenvalue), eigenvectors of T by
+//          inverse iteration with LU and partial pivoting (clusters re-orthogonalized by modified
+//          Gram-Schmidt), eigenvectors of G = Q_H z.  Output sorted by descending eigenvalue.
+//          Applied to G = C C^H it gives the small SVD C = U-breve diag(sigma) V^H of Alg. 6.
+// k_cholinv: G = L L^H (right-looking Cholesky), in-place L^{-1}, output Rinv = L^{-H}: for
+//          G = Y^H Y, Y Rinv has orthonormal columns and R = L^H has a real positive diagonal
+//          (the per-face QR that Alg. 6 builds by normalization and re-orthogonalization).  A
+//          pivot at or below tol_rel * max diag marks a dependent column: its row and column of
+//          Rinv are zero and the face is flagged (Alg. 3's breakdown).
+#pragma once
+#include "common.hpp"
+
+namespace rt {
+
+constexpr int HEEV_THREADS = 1024;
+constexpr int HEEV_RMAX = 256;
+
+RT_HOST_DEVICE int64_t pk_off(int j, int r) { return (int64_t)j * r - ((int64_t)j * (j - 1)) / 2; }
+RT_HOST_DEVICE int64_t packed_size(int r) { return (int64_t)r * (r + 1) / 2; }
+
+// element (i, j) of the Hermitian matrix from its packed lower triangle
+__device__ __forceinline__ zd pk_get(const zd* S, int i, int j, int r) {
+  if (i >= j) return S[pk_off(j, r) + (i - j)];
+  return cconj(S[pk_off(i, r) + (j - i)]);
+}
+
+// reduce `v` over the 8 aligned lanes of a group
+__device__ __forceinline__ double grp8_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
+}
+
+// block-wide sum (all threads get the result); red has >= 17 doubles
+__device__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    red[16] = s;
+  }
+  __syncthreads();
+  return red[16];
+}
+
+// number of eigenvalues of the tridiagonal (d, e) strictly below x (Sturm sequence)
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int r, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += (q < 0.0);
+  for (int i = 1; i < r; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+  }
+  return cnt;
+}
+
+struct HeevLds {
+  double d[HEEV_RMAX], e[HEEV_RMAX], e2[HEEV_RMAX], lam[HEEV_RMAX];
+  zd tau[HEEV_RMAX], v[HEEV_RMAX], p[HEEV_RMAX];
+  double red[32];
+  zd sc;       // 1 / (alpha - beta)
+  int flag;
+};
+
+inline size_t heev_lds_bytes(int r, bool packed_in_lds) {
+  return sizeof(HeevLds) + (packed_in_lds ? (size_t)packed_size(r) * sizeof(zd) : 0);
+}
+
+// G: F x r x r (full, column-major, only the lower triangle is read); U: F x r x r out;
+// lam: F x r out (descending).  gpk: F x packed_size(r) global scratch (used when !in_lds);
+// zs: F x r x r doubles (eigenvectors of T); lu: F x r x 5r doubles (LU of T - lambda I).
+__global__ void __launch_bounds__(HEEV_THREADS)
+k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restrict__ lamout,
+       zd* __restrict__ gpk, double* __restrict__ zs, double* __restrict__ lu, int in_lds) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  HeevLds& L = *reinterpret_cast<HeevLds*>(smem_raw);
+  const int f = blockIdx.x;
+  zd* S = in_lds ? reinterpret_cast<zd*>(smem_raw + sizeof(HeevLds)) : gpk + (int64_t)f * packed_size(r);
+  const zd* G = Gin + (int64_t)f * r * r;
+  zd* U = Uout + (int64_t)f * r * r;
+  double* Z = zs + (int64_t)f * r * r;
+  const int tid = threadIdx.x;
+
+  // ---- load the lower triangle -----------------------------------------------------------
+  for (int j = 0; j < r; ++j)
+    for (int i = j + tid; i < r; i += blockDim.x) S[pk_off(j, r) + (i - j)] = G[i + (int64_t)j * r];
+  __syncthreads();
+
+  // ---- Householder tridiagonalization ----------------------------------------------------
+  for (int k = 0; k < r - 1; ++k) {
+    double xn = 0.0;
+    for (int i = k + 2 + tid; i < r; i += blockDim.x) xn += cabs2(S[pk_off(k, r) + (i - k)]);
+    xn = block_sum(xn, L.red);
+    if (tid == 0) {
+      const zd alpha = S[pk_off(k, r) + 1];
+      zd tau = mk(0.0, 0.0);
+      double beta = alpha.re;
+      if (xn > 0.0 || alpha.im != 0.0) {
+        const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn);
+        beta = alpha.re >= 0.0 ? -nrm : nrm;
+        tau = mk((beta - alpha.re) / beta, -alpha.im / beta);
+        const zd den = mk(alpha.re - beta, alpha.im);      // 1 / (alpha - beta)
+        const double dd = cabs2(den);
+        L.sc = mk(den.re / dd, -den.im / dd);
+        L.flag = 1;
+      } else {
+        L.flag = 0;
+      }
+      L.e[k] = beta;
+      L.tau[k] = tau;
+    }
+    __syncthreads();
+    const int active = L.flag;
+    const int n2 = r - k - 1;
+    // v (v[k+1] = 1), kept in S's column k as well (needed by the back-transformation)
+    if (active) {
+      const zd sc = L.sc;
+      for (int i = k + 1 + tid; i < r; i += blockDim.x) {
+        zd vi = (i == k + 1) ? mk(1.0, 0.0) : cmul(S[pk_off(k, r) + (i - k)], sc);
+        S[pk_off(k, r) + (i - k)] = vi;
+        L.v[i] = vi;
+      }
+    } else {
+      for (int i = k + 1 + tid; i < r; i += blockDim.x) {
+        zd vi = (i == k + 1) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+        S[pk_off(k, r) + (i - k)] = vi;
+        L.v[i] = vi;
+      }
+    }
+    __syncthreads();
+    if (active) {
+      const zd tau = L.tau[k];
+      // p = tau * A22 v ; 8 lanes per row
+      for (int base = 0; base < n2; base += (int)blockDim.x / 8) {
+        const int row = base + tid / 8, sub = tid % 8;
+        zd s = mk(0.0, 0.0);
+        if (row < n2) {
+          const int i = k + 1 + row;
+          for (int jj = sub; jj < n2; jj += 8) {
+            const int j = k + 1 + jj;
+            s = cadd(s, cmul(pk_get(S, i, j, r), L.v[j]));
+          }
+        }
+        s.re = grp8_sum(s.re);
+        s.im = grp8_sum(s.im);
+        if (row < n2 && sub == 0) L.p[k + 1 + row] = cmul(tau, s);
+      }
+      __syncthreads();
+      // alpha2 = -1/2 tau (p^H v);  w = p + alpha2 v  (stored in p)
+      double dre = 0.0, dim = 0.0;
+      for (int i = k + 1 + tid; i < r; i += blockDim.x) {
+        const zd c = cmulc(L.p[i], L.v[i]);
+        dre += c.re; dim += c.im;
+      }
+      dre = block_sum(dre, L.red);
+      dim = block_sum(dim, L.red);
+      const zd a2 = cscale(cmul(tau, mk(dre, dim)), -0.5);
+      for (int i = k + 1 + tid; i < r; i += blockDim.x) L.p[i] = cadd(L.p[i], cmul(a2, L.v[i]));
+      __syncthreads();
+      // A22 -= v w^H + w v^H (lower triangle); one wave per column
+      const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+      for (int c = k + 1 + wave; c < r; c += nw) {
+        const zd vc = cconj(L.v[c]), wc = cconj(L.p[c]);
+        for (int i = c + lane; i < r; i += 64) {
+          zd& a = S[pk_off(c, r) + (i - c)];
+          a = csub(a, cadd(cmul(L.v[i], wc), cmul(L.p[i], vc)));
+        }
+      }
+    }
+    if (tid == 0) L.d[k] = S[pk_off(k, r)].re;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    L.d[r - 1] = S[pk_off(r - 1, r)].re;
+    if (r >= 1) L.e[r - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += blockDim.x) L.e2[i] = L.e[i] * L.e[i];
+  __syncthreads();
+
+  // ---- eigenvalues of T: multisection, 8 lanes per eigenvalue ------------------------------
+  double gl = 1e308, gu = -1e308, emax2 = 0.0;
+  for (int i = 0; i < r; ++i) {
+    const double off = fabs(L.e[i]) + (i > 0 ? fabs(L.e[i - 1]) : 0.0);
+    gl = fmin(gl, L.d[i] - off);
+    gu = fmax(gu, L.d[i] + off);
+    emax2 = fmax(emax2, L.e2[i]);
+  }
+  const double tnorm = fmax(fabs(gl), fabs(gu));
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  const double atol = 2.0 * eps * tnorm + 4.0 * pivmin;
+  gl -= 2.0 * eps * tnorm + pivmin;
+  gu += 2.0 * eps * tnorm + pivmin;
+  for (int base = 0; base < r; base += (int)blockDim.x / 8) {
+    const int j = base + tid / 8, sub = tid % 8;  // j-th largest eigenvalue
+    const bool on = j < r;
+    const int a = r - 1 - (on ? j : 0);           // ascending index
+    double lo = gl, hi = gu;
+    for (int it = 0; it < 200; ++it) {
+      if (hi - lo <= atol + 2.0 * eps * fmax(fabs(lo), fabs(hi))) break;
+      const double x = lo + (hi - lo) * (double)(sub + 1) / 9.0;
+      const int cnt = on ? sturm_count(L.d, L.e2, r, x, pivmin) : 0;
+      double nlo = (cnt <= a) ? x : -1e308;
+      double nhi = (cnt > a) ? x : 1e308;
+      for (int o = 1; o < 8; o <<= 1) {
+        nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
+        nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
+      }
+      if (nlo > lo) lo = nlo;
+      if (nhi < hi) hi = nhi;
+    }
+    if (on && sub == 0) L.lam[j] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+
+  // ---- eigenvectors of T: inverse iteration, clusters re-orthogonalized ------------------------
+  const double ortol = 1e-3 * tnorm;
+  for (int j0 = tid; j0 < r; j0 += blockDim.x) {
+    if (j0 > 0 && L.lam[j0 - 1] - L.lam[j0] <= ortol) continue;  // not the first of its cluster
+    int j1 = j0 + 1;
+    while (j1 < r && L.lam[j1 - 1] - L.lam[j1] <= ortol) ++j1;
+    double* ud = lu + ((int64_t)f * r + j0) * 5 * r;
+    double* us1 = ud + r;
+    double* us2 = us1 + r;
+    double* ml = us2 + r;
+    double* sw = ml + r;
+    for (int j = j0; j < j1; ++j) {
+      const double lam = L.lam[j];
+      // LU with partial pivoting of T - lam I
+      double a = L.d[0] - lam, b = r > 1 ? L.e[0] : 0.0;
+      for (int k = 0; k < r - 1; ++k) {
+        const double c = L.e[k];              // sub-diagonal entry of row k+1
+        const double anext = L.d[k + 1] - lam;
+        const double bnext = (k + 1 < r - 1) ? L.e[k + 1] : 0.0;
+        if (fabs(a) >= fabs(c)) {
+          const double mlt = (a != 0.0) ? c / a : 0.0;
+          ud[k] = a; us1[k] = b; us2[k] = 0.0; ml[k] = mlt; sw[k] = 0.0;
+          a = anext - mlt * b;
+          b = bnext;
+        } else {
+          const double mlt = a / c;
+          ud[k] = c; us1[k] = anext; us2[k] = bnext; ml[k] = mlt; sw[k] = 1.0;
+          a = b - mlt * anext;
+          b = -mlt * bnext;
+        }
+      }
+      ud[r - 1] = a;
+      const double pert = eps * tnorm > 0.0 ? eps * tnorm : 1e-300;
+      for (int k = 0; k < r; ++k)
+        if (fabs(ud[k]) < pert) ud[k] = ud[k] < 0.0 ? -pert : pert;
+      // start vector: deterministic, not aligned with any structure
+      double* z = Z + (int64_t)j * r;
+      uint32_t st = 0x9E3779B9u ^ (uint32_t)(j * 2654435761u);
+      for (int i = 0; i < r; ++i) {
+        st = st * 1664525u + 1013904223u;
+        z[i] = ((double)(st >> 8) / 16777216.0) - 0.5;
+      }
+      for (int iter = 0; iter < 3; ++iter) {
+        // forward: apply the row swaps and multipliers
+        for (int k = 0; k < r - 1; ++k) {
+          if (sw[k] != 0.0) { const double t = z[k]; z[k] = z[k + 1]; z[k + 1] = t - ml[k] * z[k + 1]; }
+          else z[k + 1] -= ml[k] * z[k];
+        }
+        // back substitution with the three diagonals of U
+        for (int k = r - 1; k >= 0; --k) {
+          double s = z[k];
+          if (k + 1 < r) s -= us1[k] * z[k + 1];
+          if (k + 2 < r) s -= us2[k] * z[k + 2];
+          z[k] = s / ud[k];
+        }
+        // re-orthogonalize against the previous members of the cluster, normalize
+        for (int q = j0; q < j; ++q) {
+          const double* zq = Z + (int64_t)q * r;
+          double dt = 0.0;
+          for (int i = 0; i < r; ++i) dt += zq[i] * z[i];
+          for (int i = 0; i < r; ++i) z[i] -= dt * zq[i];
+        }
+        double nn = 0.0;
+        for (int i = 0; i < r; ++i) nn += z[i] * z[i];
+        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int i = 0; i < r; ++i) z[i] *= inv;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- back-transformation U = Q_H Z, 8 lanes per column ---------------------------------------
+  for (int base = 0; base < r; base += (int)blockDim.x / 8) {
+    const int c = base + tid / 8, sub = tid % 8;
+    const bool on = c < r;
+    // each lane owns the rows i = sub (mod 8) of its column for the whole loop
+    zd* u = U + (int64_t)(on ? c : 0) * r;
+    if (on)
+      for (int i = sub; i < r; i += 8) u[i] = mk(Z[(int64_t)c * r + i], 0.0);
+    for (int k = r - 2; k >= 0; --k) {
+      const zd tau = L.tau[k];
+      if (tau.re == 0.0 && tau.im == 0.0) continue;
+      zd s = mk(0.0, 0.0);
+      if (on)
+        for (int i = sub; i < r; i += 8)
+          if (i > k) s = cadd(s, cmulc(S[pk_off(k, r) + (i - k)], u[i]));
+      s.re = grp8_sum(s.re);
+      s.im = grp8_sum(s.im);
+      s = cmul(tau, s);
+      if (on)
+        for (int i = sub; i < r; i += 8)
+          if (i > k) u[i] = csub(u[i], cmul(S[pk_off(k, r) + (i - k)], s));
+    }
+    if (on && sub == 0) lamout[(int64_t)f * r + c] = L.lam[c];
+  }
+}
+
+// -------------------------------------------------------------------------------------------
+// Cholesky and triangular inverse: Rinv = L^{-H}
+// -------------------------------------------------------------------------------------------
+struct CholLds {
+  zd x[HEEV_RMAX], t[HEEV_RMAX];
+  double piv, tol;
+  int bad;
+};
+
+inline size_t chol_lds_bytes(int r, bool packed_in_lds) {
+  return sizeof(CholLds) + (packed_in_lds ? (size_t)packed_size(r) * sizeof(zd) : 0);
+}
+
+__global__ void __launch_bounds__(HEEV_THREADS)
+k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_rel, int* __restrict__ flags,
+          zd* __restrict__ gpk, int in_lds) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  CholLds& L = *reinterpret_cast<CholLds*>(smem_raw);
+  const int f = blockIdx.x;
+  zd* S = in_lds ? reinterpret_cast<zd*>(smem_raw + sizeof(CholLds)) : gpk + (int64_t)f * packed_size(r);
+  const zd* G = Gin + (int64_t)f * r * r;
+  zd* R = Rinv + (int64_t)f * r * r;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+  for (int j = 0; j < r; ++j)
+    for (int i = j + tid; i < r; i += blockDim.x) S[pk_off(j, r) + (i - j)] = G[i + (int64_t)j * r];
+  if (tid == 0) { L.bad = 0; }
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int j = 0; j < r; ++j) mx = fmax(mx, S[pk_off(j, r)].re);
+    L.tol = tol_rel * mx;
+  }
+  __syncthreads();
+  // right-looking Cholesky
+  for (int j = 0; j < r; ++j) {
+    if (tid == 0) {
+      const double d = S[pk_off(j, r)].re;
+      double pv = 0.0;
+      if (d > L.tol && d > 0.0) pv = sqrt(d); else L.bad = 1;
+      L.piv = pv;
+      S[pk_off(j, r)] = mk(pv, 0.0);
+    }
+    __syncthreads();
+    const double pv = L.piv;
+    const double ipv = pv > 0.0 ? 1.0 / pv : 0.0;
+    for (int i = j + 1 + tid; i < r; i += blockDim.x) {
+      zd& a = S[pk_off(j, r) + (i - j)];
+      a = cscale(a, ipv);
+      L.x[i] = a;
+    }
+    __syncthreads();
+    for (int c = j + 1 + wave; c < r; c += nw) {
+      const zd lc = cconj(L.x[c]);
+      for (int i = c + lane; i < r; i += 64) {
+        zd& a = S[pk_off(c, r) + (i - c)];
+        a = csub(a, cmul(L.x[i], lc));
+      }
+    }
+    __syncthreads();
+  }
+  // in-place inverse of the lower triangular L (columns from the last to the first)
+  for (int j = r - 1; j >= 0; --j) {
+    const double ljj = S[pk_off(j, r)].re;
+    const double ajj = ljj > 0.0 ? 1.0 / ljj : 0.0;
+    for (int i = j + 1 + tid; i < r; i += blockDim.x) L.x[i] = S[pk_off(j, r) + (i - j)];
+    __syncthreads();
+    // t_i = sum_{k=j+1..i} Linv(i,k) x_k, 8 lanes per row
+    for (int base = j + 1; base < r; base += (int)blockDim.x / 8) {
+      const int i = base + tid / 8, sub = tid % 8;
+      zd s = mk(0.0, 0.0);
+      if (i < r)
+        for (int k = j + 1 + sub; k <= i; k += 8) s = cadd(s, cmul(S[pk_off(k, r) + (i - k)], L.x[k]));
+      s.re = grp8_sum(s.re);
+      s.im = grp8_sum(s.im);
+      if (i < r && sub == 0) L.t[i] = s;
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < r; i += blockDim.x) S[pk_off(j, r) + (i - j)] = cscale(L.t[i], -ajj);
+    if (tid == 0) S[pk_off(j, r)] = mk(ajj, 0.0);
+    __syncthreads();
+  }
+  // Rinv(i, j) = conj(Linv(j, i)) for i <= j, zero below the diagonal
+  for (int idx = tid; idx < r * r; idx += blockDim.x) {
+    const int i = idx % r, j = idx / r;
+    R[idx] = (i <= j) ? cconj(S[pk_off(i, r) + (j - i)]) : mk(0.0, 0.0);
+  }
+  if (tid == 0 && flags && L.bad) atomicOr(flags, 1);
+}
+
+}  // namespace rt

@@ -13,7 +13,7 @@
 #include "fft.hpp"
 #include "gemm.hpp"
 #include "mfma_gemm.hpp"
-#include "small.hpp"
+#include "heev.hpp"
 #include "solve.hpp"
 
 using namespace rt;
@@ -115,17 +115,64 @@ struct rtsvd_factor_s {
 static bool work_is_double(int precision) { return precision == RTSVD_P_FP64; }
 
 // ---------------------------------------------------------------------------------------------
+// launchers of the per-face r x r kernels (packed matrix in LDS when it fits)
+// ---------------------------------------------------------------------------------------------
+static int max_lds_per_block() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (!cached[dev]) {
+    int v = 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
+static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratch& sc, hipStream_t s) {
+  const size_t full = heev_lds_bytes(r, true);
+  const bool in_lds = (int64_t)full <= (int64_t)max_lds_per_block();
+  const size_t bytes = in_lds ? full : heev_lds_bytes(r, false);
+  zd* gpk = nullptr;
+  if (!in_lds) {
+    gpk = sc.get<zd>(F * packed_size(r));
+    if (!gpk) return fail(RTSVD_E_NOMEM, "device allocation failed: heev packed scratch");
+  }
+  double* zs = sc.get<double>(F * r * r);
+  double* lu = sc.get<double>(F * r * 5 * (int64_t)r);
+  if (!zs || !lu) return fail(RTSVD_E_NOMEM, "device allocation failed: heev scratch");
+  if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)k_heev, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  hipLaunchKernelGGL(k_heev, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu, (int)in_lds);
+  RT_LAUNCH_OK();
+  return 0;
+}
+
+static int launch_cholinv(const zd* G, int r, int64_t F, zd* Rinv, int* flags, Scratch& sc, hipStream_t s) {
+  const size_t full = chol_lds_bytes(r, true);
+  const bool in_lds = (int64_t)full <= (int64_t)max_lds_per_block();
+  const size_t bytes = in_lds ? full : chol_lds_bytes(r, false);
+  zd* gpk = nullptr;
+  if (!in_lds) {
+    gpk = sc.get<zd>(F * packed_size(r));
+    if (!gpk) return fail(RTSVD_E_NOMEM, "device allocation failed: cholinv packed scratch");
+  }
+  if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)k_cholinv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  hipLaunchKernelGGL(k_cholinv, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, Rinv, 1e-13, flags, gpk, (int)in_lds);
+  RT_LAUNCH_OK();
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------------------
 // CholeskyQR: Y (F x rows x r) <- Y R^{-1} with R^H R = Y^H Y (FP64 Gram + Cholesky), `passes`
 // times (2 = CholeskyQR2, orthonormal to working precision).
 // ---------------------------------------------------------------------------------------------
 template <typename TY>
 static int orthonormalize(TY* Y, int64_t rows, int64_t r, int64_t F, int passes, zd* G, zd* Rinv, TY* tmp,
-                          int* flags, hipStream_t s) {
+                          int* flags, Scratch& sc, hipStream_t s) {
   for (int pass = 0; pass < passes; ++pass) {
     RT_TRY((cgemm<TY, TY, zd, double>(true, false, (int)r, (int)r, (int)rows, Y, rows, rows * r, Y, rows, rows * r,
                                      G, r, r * r, (int)F, 1.0, false, s)));
-    hipLaunchKernelGGL(k_chol_inv, dim3((unsigned)F), dim3(256), 0, s, G, Rinv, (int)r, 1e-13, flags);
-    RT_LAUNCH_OK();
+    RT_TRY(launch_cholinv(G, (int)r, F, Rinv, flags, sc, s));
     RT_CHECK_HIP(hipMemcpyAsync(tmp, Y, sizeof(TY) * F * rows * r, hipMemcpyDeviceToDevice, s));
     RT_TRY((cgemm<TY, zd, TY, double>(false, false, (int)rows, (int)r, (int)r, tmp, rows, rows * r, Rinv, r, r * r,
                                      Y, rows, rows * r, (int)F, 1.0, false, s)));
@@ -191,14 +238,14 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     // sketch Y = A-hat Omega-hat, then Q = orth(Y) (q power iterations in between)
     if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
     else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
-    RT_TRY(orthonormalize<zw>(Y, l, r, F, q == 0 ? 2 : 1, G, Rinv, tmp, flags, s));
+    RT_TRY(orthonormalize<zw>(Y, l, r, F, q == 0 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
     for (int it = 0; it < q; ++it) {
       if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(true, Ah16, l, m, Y, r, Omh, F, s)));
       else RT_TRY((big_gemm<zw, zw, zw, Tw>(true, Ah, l, m, Y, r, Omh, F, s)));
-      RT_TRY(orthonormalize<zw>(Omh, m, r, F, 1, G, Rinv, tmp, flags, s));
+      RT_TRY(orthonormalize<zw>(Omh, m, r, F, 1, G, Rinv, tmp, flags, sc, s));
       if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
       else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
-      RT_TRY(orthonormalize<zw>(Y, l, r, F, it == q - 1 ? 2 : 1, G, Rinv, tmp, flags, s));
+      RT_TRY(orthonormalize<zw>(Y, l, r, F, it == q - 1 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
     }
     RT_CHECK_HIP(hipMemcpyAsync(Qo, Y, sizeof(zw) * F * l * r, hipMemcpyDeviceToDevice, s));
     // projection C^H = A-hat^H Q
@@ -212,8 +259,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
     RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)m, Ch, m, m * r, Ch, m, m * r, G, r, r * r,
                                      (int)F, 1.0, false, s)));
-    hipLaunchKernelGGL(k_jacobi_eig, dim3((unsigned)F), dim3(SMALL_THREADS), 0, s, G, Ub, lam, (int)r, 60);
-    RT_LAUNCH_OK();
+    RT_TRY(launch_heev(G, (int)r, F, Ub, lam, sc, s));
     hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
     RT_LAUNCH_OK();
     // V = C^H U-breve diag(1/sigma)
@@ -228,8 +274,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     // full facewise SVD through G = A-hat^H A-hat = V diag(sigma^2) V^H; W = A-hat V; U = W diag(1/sigma)
     RT_TRY((cgemm<zw, zw, zd, double>(true, false, (int)m, (int)m, (int)l, Ah, l, l * m, Ah, l, l * m, G, m, m * m,
                                      (int)F, 1.0, false, s)));
-    hipLaunchKernelGGL(k_jacobi_eig, dim3((unsigned)F), dim3(SMALL_THREADS), 0, s, G, V, lam, (int)m, 60);
-    RT_LAUNCH_OK();
+    RT_TRY(launch_heev(G, (int)m, F, V, lam, sc, s));
     hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
     RT_LAUNCH_OK();
     hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, lam, (int)F, (int)r, (int)n, eta);
