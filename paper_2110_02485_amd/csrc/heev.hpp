@@ -25,9 +25,9 @@ RT_HOST_DEVICE int64_t pk_off(int j, int r) { return (int64_t)j * r - ((int64_t)
 RT_HOST_DEVICE int64_t packed_size(int r) { return (int64_t)r * (r + 1) / 2; }
 
 // element (i, j) of the Hermitian matrix from its packed lower triangle
-__device__ __forceinline__ zd pk_get(const zd* S, int i, int j, int r) {
-  if (i >= j) return S[pk_off(j, r) + (i - j)];
-  return cconj(S[pk_off(i, r) + (j - i)]);
+__device__ __forceinline__ zd pk_get(const zd* S, const int* cb, int i, int j) {
+  if (i >= j) return S[cb[j] + (i - j)];
+  return cconj(S[cb[i] + (j - i)]);
 }
 
 // reduce `v` over the 8 aligned lanes of a group
@@ -72,6 +72,9 @@ struct HeevLds {
   double d[HEEV_RMAX], e[HEEV_RMAX], e2[HEEV_RMAX], lam[HEEV_RMAX];
   zd tau[HEEV_RMAX], v[HEEV_RMAX], p[HEEV_RMAX];
   double red[32];
+  int cb[HEEV_RMAX + 1];      // packed column offsets
+  int cstart[HEEV_RMAX + 1];  // cluster starts (eigenvalues closer than the cluster tolerance)
+  int ncl;
   zd sc;       // 1 / (alpha - beta)
   int flag;
 };
@@ -81,8 +84,9 @@ inline size_t heev_lds_bytes(int r, bool packed_in_lds) {
 }
 
 // G: F x r x r (full, column-major, only the lower triangle is read); U: F x r x r out;
-// lam: F x r out (descending).  gpk: F x packed_size(r) global scratch (used when !in_lds);
-// zs: F x r x r doubles (eigenvectors of T); lu: F x r x 5r doubles (LU of T - lambda I).
+// lam: F x r out (descending).  gpk: F x packed_size(r) global scratch (the reflectors; also the
+// working matrix when !in_lds); zs: F x r x (r+1) doubles (eigenvectors of T when !in_lds);
+// lu: F x r x 5r doubles (LU factors of T - lambda I).
 __global__ void __launch_bounds__(HEEV_THREADS)
 k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restrict__ lamout,
        zd* __restrict__ gpk, double* __restrict__ zs, double* __restrict__ lu, int in_lds) {
@@ -92,9 +96,10 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   zd* S = in_lds ? reinterpret_cast<zd*>(smem_raw + sizeof(HeevLds)) : gpk + (int64_t)f * packed_size(r);
   const zd* G = Gin + (int64_t)f * r * r;
   zd* U = Uout + (int64_t)f * r * r;
-  double* Z = zs + (int64_t)f * r * r;
+  double* Z = zs + (int64_t)f * r * (r + 1);
   const int tid = threadIdx.x;
 
+  for (int j = tid; j <= r; j += blockDim.x) L.cb[j] = (int)pk_off(j, r);
   // ---- load the lower triangle -----------------------------------------------------------
   for (int j = 0; j < r; ++j)
     for (int i = j + tid; i < r; i += blockDim.x) S[pk_off(j, r) + (i - j)] = G[i + (int64_t)j * r];
@@ -103,10 +108,10 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   // ---- Householder tridiagonalization ----------------------------------------------------
   for (int k = 0; k < r - 1; ++k) {
     double xn = 0.0;
-    for (int i = k + 2 + tid; i < r; i += blockDim.x) xn += cabs2(S[pk_off(k, r) + (i - k)]);
+    for (int i = k + 2 + tid; i < r; i += blockDim.x) xn += cabs2(S[L.cb[k] + (i - k)]);
     xn = block_sum(xn, L.red);
     if (tid == 0) {
-      const zd alpha = S[pk_off(k, r) + 1];
+      const zd alpha = S[L.cb[k] + 1];
       zd tau = mk(0.0, 0.0);
       double beta = alpha.re;
       if (xn > 0.0 || alpha.im != 0.0) {
@@ -130,14 +135,14 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
     if (active) {
       const zd sc = L.sc;
       for (int i = k + 1 + tid; i < r; i += blockDim.x) {
-        zd vi = (i == k + 1) ? mk(1.0, 0.0) : cmul(S[pk_off(k, r) + (i - k)], sc);
-        S[pk_off(k, r) + (i - k)] = vi;
+        zd vi = (i == k + 1) ? mk(1.0, 0.0) : cmul(S[L.cb[k] + (i - k)], sc);
+        S[L.cb[k] + (i - k)] = vi;
         L.v[i] = vi;
       }
     } else {
       for (int i = k + 1 + tid; i < r; i += blockDim.x) {
         zd vi = (i == k + 1) ? mk(1.0, 0.0) : mk(0.0, 0.0);
-        S[pk_off(k, r) + (i - k)] = vi;
+        S[L.cb[k] + (i - k)] = vi;
         L.v[i] = vi;
       }
     }
@@ -152,7 +157,7 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
           const int i = k + 1 + row;
           for (int jj = sub; jj < n2; jj += 8) {
             const int j = k + 1 + jj;
-            s = cadd(s, cmul(pk_get(S, i, j, r), L.v[j]));
+            s = cadd(s, cmul(pk_get(S, L.cb, i, j), L.v[j]));
           }
         }
         s.re = grp8_sum(s.re);
@@ -176,16 +181,16 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
       for (int c = k + 1 + wave; c < r; c += nw) {
         const zd vc = cconj(L.v[c]), wc = cconj(L.p[c]);
         for (int i = c + lane; i < r; i += 64) {
-          zd& a = S[pk_off(c, r) + (i - c)];
+          zd& a = S[L.cb[c] + (i - c)];
           a = csub(a, cadd(cmul(L.v[i], wc), cmul(L.p[i], vc)));
         }
       }
     }
-    if (tid == 0) L.d[k] = S[pk_off(k, r)].re;
+    if (tid == 0) L.d[k] = S[L.cb[k]].re;
     __syncthreads();
   }
   if (tid == 0) {
-    L.d[r - 1] = S[pk_off(r - 1, r)].re;
+    L.d[r - 1] = S[L.cb[r - 1]].re;
     if (r >= 1) L.e[r - 1] = 0.0;
   }
   __syncthreads();
@@ -228,73 +233,102 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   }
   __syncthreads();
 
-  // ---- eigenvectors of T: inverse iteration, clusters re-orthogonalized ------------------------
-  const double ortol = 1e-3 * tnorm;
-  for (int j0 = tid; j0 < r; j0 += blockDim.x) {
-    if (j0 > 0 && L.lam[j0 - 1] - L.lam[j0] <= ortol) continue;  // not the first of its cluster
-    int j1 = j0 + 1;
-    while (j1 < r && L.lam[j1 - 1] - L.lam[j1] <= ortol) ++j1;
-    double* ud = lu + ((int64_t)f * r + j0) * 5 * r;
+  // ---- the reflectors move to global memory; LDS (or the global slice) then holds Z ------------
+  // Z column j (stride zst = r + 1 doubles) = eigenvector of T for lam[j]
+  zd* Sg = gpk + (int64_t)f * packed_size(r);
+  if (in_lds) {
+    for (int64_t i = tid; i < packed_size(r); i += blockDim.x) Sg[i] = S[i];
+    __syncthreads();
+  }
+  const int zst = r + 1;
+  double* Zp = in_lds ? reinterpret_cast<double*>(smem_raw + sizeof(HeevLds)) : Z;
+
+  // ---- eigenvectors of T: inverse iteration, one thread per eigenvalue ---------------------------
+  for (int j = tid; j < r; j += blockDim.x) {
+    const double lam = L.lam[j];
+    double* ud = lu + ((int64_t)f * r + j) * 5 * r;
     double* us1 = ud + r;
     double* us2 = us1 + r;
     double* ml = us2 + r;
     double* sw = ml + r;
-    for (int j = j0; j < j1; ++j) {
-      const double lam = L.lam[j];
-      // LU with partial pivoting of T - lam I
-      double a = L.d[0] - lam, b = r > 1 ? L.e[0] : 0.0;
+    // LU with partial pivoting of T - lam I
+    double a = L.d[0] - lam, b = r > 1 ? L.e[0] : 0.0;
+    for (int k = 0; k < r - 1; ++k) {
+      const double c = L.e[k];              // sub-diagonal entry of row k+1
+      const double anext = L.d[k + 1] - lam;
+      const double bnext = (k + 1 < r - 1) ? L.e[k + 1] : 0.0;
+      if (fabs(a) >= fabs(c)) {
+        const double mlt = (a != 0.0) ? c / a : 0.0;
+        ud[k] = a; us1[k] = b; us2[k] = 0.0; ml[k] = mlt; sw[k] = 0.0;
+        a = anext - mlt * b;
+        b = bnext;
+      } else {
+        const double mlt = a / c;
+        ud[k] = c; us1[k] = anext; us2[k] = bnext; ml[k] = mlt; sw[k] = 1.0;
+        a = b - mlt * anext;
+        b = -mlt * bnext;
+      }
+    }
+    ud[r - 1] = a;
+    const double pert = eps * tnorm > 0.0 ? eps * tnorm : 1e-300;
+    for (int k = 0; k < r; ++k)
+      if (fabs(ud[k]) < pert) ud[k] = ud[k] < 0.0 ? -pert : pert;
+    // start vector: deterministic, not aligned with any structure
+    double* z = Zp + (int64_t)j * zst;
+    uint32_t st = 0x9E3779B9u ^ (uint32_t)(j * 2654435761u);
+    for (int i = 0; i < r; ++i) {
+      st = st * 1664525u + 1013904223u;
+      z[i] = ((double)(st >> 8) / 16777216.0) - 0.5;
+    }
+    for (int iter = 0; iter < 2; ++iter) {
       for (int k = 0; k < r - 1; ++k) {
-        const double c = L.e[k];              // sub-diagonal entry of row k+1
-        const double anext = L.d[k + 1] - lam;
-        const double bnext = (k + 1 < r - 1) ? L.e[k + 1] : 0.0;
-        if (fabs(a) >= fabs(c)) {
-          const double mlt = (a != 0.0) ? c / a : 0.0;
-          ud[k] = a; us1[k] = b; us2[k] = 0.0; ml[k] = mlt; sw[k] = 0.0;
-          a = anext - mlt * b;
-          b = bnext;
-        } else {
-          const double mlt = a / c;
-          ud[k] = c; us1[k] = anext; us2[k] = bnext; ml[k] = mlt; sw[k] = 1.0;
-          a = b - mlt * anext;
-          b = -mlt * bnext;
-        }
+        if (sw[k] != 0.0) { const double t = z[k]; z[k] = z[k + 1]; z[k + 1] = t - ml[k] * z[k + 1]; }
+        else z[k + 1] -= ml[k] * z[k];
       }
-      ud[r - 1] = a;
-      const double pert = eps * tnorm > 0.0 ? eps * tnorm : 1e-300;
-      for (int k = 0; k < r; ++k)
-        if (fabs(ud[k]) < pert) ud[k] = ud[k] < 0.0 ? -pert : pert;
-      // start vector: deterministic, not aligned with any structure
-      double* z = Z + (int64_t)j * r;
-      uint32_t st = 0x9E3779B9u ^ (uint32_t)(j * 2654435761u);
-      for (int i = 0; i < r; ++i) {
-        st = st * 1664525u + 1013904223u;
-        z[i] = ((double)(st >> 8) / 16777216.0) - 0.5;
+      for (int k = r - 1; k >= 0; --k) {
+        double sacc = z[k];
+        if (k + 1 < r) sacc -= us1[k] * z[k + 1];
+        if (k + 2 < r) sacc -= us2[k] * z[k + 2];
+        z[k] = sacc / ud[k];
       }
-      for (int iter = 0; iter < 3; ++iter) {
-        // forward: apply the row swaps and multipliers
-        for (int k = 0; k < r - 1; ++k) {
-          if (sw[k] != 0.0) { const double t = z[k]; z[k] = z[k + 1]; z[k + 1] = t - ml[k] * z[k + 1]; }
-          else z[k + 1] -= ml[k] * z[k];
+      double nn = 0.0;
+      for (int i = 0; i < r; ++i) nn += z[i] * z[i];
+      const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+      for (int i = 0; i < r; ++i) z[i] *= inv;
+    }
+  }
+  // clusters: maximal runs of eigenvalues with consecutive gaps <= ortol
+  const double ortol = 1e-3 * tnorm;
+  if (tid == 0) {
+    int nc = 0;
+    for (int j = 0; j < r; ++j)
+      if (j == 0 || L.lam[j - 1] - L.lam[j] > ortol) L.cstart[nc++] = j;
+    L.cstart[nc] = r;
+    L.ncl = nc;
+  }
+  __syncthreads();
+  // modified Gram-Schmidt inside every cluster (twice), one wave per cluster
+  {
+    const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+    for (int c = wave; c < L.ncl; c += nw) {
+      const int j0 = L.cstart[c], j1 = L.cstart[c + 1];
+      if (j1 - j0 < 2) continue;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i = j0; i < j1; ++i) {
+          double* zi = Zp + (int64_t)i * zst;
+          for (int q = j0; q < i; ++q) {
+            const double* zq = Zp + (int64_t)q * zst;
+            double dt = 0.0;
+            for (int x = lane; x < r; x += 64) dt += zq[x] * zi[x];
+            for (int o = 32; o > 0; o >>= 1) dt += __shfl_xor(dt, o, 64);
+            for (int x = lane; x < r; x += 64) zi[x] -= dt * zq[x];
+          }
+          double nn = 0.0;
+          for (int x = lane; x < r; x += 64) nn += zi[x] * zi[x];
+          for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
+          const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+          for (int x = lane; x < r; x += 64) zi[x] *= inv;
         }
-        // back substitution with the three diagonals of U
-        for (int k = r - 1; k >= 0; --k) {
-          double s = z[k];
-          if (k + 1 < r) s -= us1[k] * z[k + 1];
-          if (k + 2 < r) s -= us2[k] * z[k + 2];
-          z[k] = s / ud[k];
-        }
-        // re-orthogonalize against the previous members of the cluster, normalize
-        for (int q = j0; q < j; ++q) {
-          const double* zq = Z + (int64_t)q * r;
-          double dt = 0.0;
-          for (int i = 0; i < r; ++i) dt += zq[i] * z[i];
-          for (int i = 0; i < r; ++i) z[i] -= dt * zq[i];
-        }
-        double nn = 0.0;
-        for (int i = 0; i < r; ++i) nn += z[i] * z[i];
-        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-        for (int i = 0; i < r; ++i) z[i] *= inv;
-      }
     }
   }
   __syncthreads();
@@ -306,20 +340,21 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
     // each lane owns the rows i = sub (mod 8) of its column for the whole loop
     zd* u = U + (int64_t)(on ? c : 0) * r;
     if (on)
-      for (int i = sub; i < r; i += 8) u[i] = mk(Z[(int64_t)c * r + i], 0.0);
+      for (int i = sub; i < r; i += 8) u[i] = mk(Zp[(int64_t)c * zst + i], 0.0);
     for (int k = r - 2; k >= 0; --k) {
       const zd tau = L.tau[k];
       if (tau.re == 0.0 && tau.im == 0.0) continue;
-      zd s = mk(0.0, 0.0);
+      const zd* vk = Sg + L.cb[k] - k;   // vk[i] = v_k(i) for i > k
+      zd sacc = mk(0.0, 0.0);
       if (on)
         for (int i = sub; i < r; i += 8)
-          if (i > k) s = cadd(s, cmulc(S[pk_off(k, r) + (i - k)], u[i]));
-      s.re = grp8_sum(s.re);
-      s.im = grp8_sum(s.im);
-      s = cmul(tau, s);
+          if (i > k) sacc = cadd(sacc, cmulc(vk[i], u[i]));
+      sacc.re = grp8_sum(sacc.re);
+      sacc.im = grp8_sum(sacc.im);
+      sacc = cmul(tau, sacc);
       if (on)
         for (int i = sub; i < r; i += 8)
-          if (i > k) u[i] = csub(u[i], cmul(S[pk_off(k, r) + (i - k)], s));
+          if (i > k) u[i] = csub(u[i], cmul(vk[i], sacc));
     }
     if (on && sub == 0) lamout[(int64_t)f * r + c] = L.lam[c];
   }
@@ -330,6 +365,7 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
 // -------------------------------------------------------------------------------------------
 struct CholLds {
   zd x[HEEV_RMAX], t[HEEV_RMAX];
+  int cb[HEEV_RMAX + 1];
   double piv, tol;
   int bad;
 };
@@ -348,30 +384,31 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
   const zd* G = Gin + (int64_t)f * r * r;
   zd* R = Rinv + (int64_t)f * r * r;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+  for (int j = tid; j <= r; j += blockDim.x) L.cb[j] = (int)pk_off(j, r);
   for (int j = 0; j < r; ++j)
     for (int i = j + tid; i < r; i += blockDim.x) S[pk_off(j, r) + (i - j)] = G[i + (int64_t)j * r];
   if (tid == 0) { L.bad = 0; }
   __syncthreads();
   if (tid == 0) {
     double mx = 0.0;
-    for (int j = 0; j < r; ++j) mx = fmax(mx, S[pk_off(j, r)].re);
+    for (int j = 0; j < r; ++j) mx = fmax(mx, S[L.cb[j]].re);
     L.tol = tol_rel * mx;
   }
   __syncthreads();
   // right-looking Cholesky
   for (int j = 0; j < r; ++j) {
     if (tid == 0) {
-      const double d = S[pk_off(j, r)].re;
+      const double d = S[L.cb[j]].re;
       double pv = 0.0;
       if (d > L.tol && d > 0.0) pv = sqrt(d); else L.bad = 1;
       L.piv = pv;
-      S[pk_off(j, r)] = mk(pv, 0.0);
+      S[L.cb[j]] = mk(pv, 0.0);
     }
     __syncthreads();
     const double pv = L.piv;
     const double ipv = pv > 0.0 ? 1.0 / pv : 0.0;
     for (int i = j + 1 + tid; i < r; i += blockDim.x) {
-      zd& a = S[pk_off(j, r) + (i - j)];
+      zd& a = S[L.cb[j] + (i - j)];
       a = cscale(a, ipv);
       L.x[i] = a;
     }
@@ -379,7 +416,7 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
     for (int c = j + 1 + wave; c < r; c += nw) {
       const zd lc = cconj(L.x[c]);
       for (int i = c + lane; i < r; i += 64) {
-        zd& a = S[pk_off(c, r) + (i - c)];
+        zd& a = S[L.cb[c] + (i - c)];
         a = csub(a, cmul(L.x[i], lc));
       }
     }
@@ -387,29 +424,29 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
   }
   // in-place inverse of the lower triangular L (columns from the last to the first)
   for (int j = r - 1; j >= 0; --j) {
-    const double ljj = S[pk_off(j, r)].re;
+    const double ljj = S[L.cb[j]].re;
     const double ajj = ljj > 0.0 ? 1.0 / ljj : 0.0;
-    for (int i = j + 1 + tid; i < r; i += blockDim.x) L.x[i] = S[pk_off(j, r) + (i - j)];
+    for (int i = j + 1 + tid; i < r; i += blockDim.x) L.x[i] = S[L.cb[j] + (i - j)];
     __syncthreads();
     // t_i = sum_{k=j+1..i} Linv(i,k) x_k, 8 lanes per row
     for (int base = j + 1; base < r; base += (int)blockDim.x / 8) {
       const int i = base + tid / 8, sub = tid % 8;
       zd s = mk(0.0, 0.0);
       if (i < r)
-        for (int k = j + 1 + sub; k <= i; k += 8) s = cadd(s, cmul(S[pk_off(k, r) + (i - k)], L.x[k]));
+        for (int k = j + 1 + sub; k <= i; k += 8) s = cadd(s, cmul(S[L.cb[k] + (i - k)], L.x[k]));
       s.re = grp8_sum(s.re);
       s.im = grp8_sum(s.im);
       if (i < r && sub == 0) L.t[i] = s;
     }
     __syncthreads();
-    for (int i = j + 1 + tid; i < r; i += blockDim.x) S[pk_off(j, r) + (i - j)] = cscale(L.t[i], -ajj);
-    if (tid == 0) S[pk_off(j, r)] = mk(ajj, 0.0);
+    for (int i = j + 1 + tid; i < r; i += blockDim.x) S[L.cb[j] + (i - j)] = cscale(L.t[i], -ajj);
+    if (tid == 0) S[L.cb[j]] = mk(ajj, 0.0);
     __syncthreads();
   }
   // Rinv(i, j) = conj(Linv(j, i)) for i <= j, zero below the diagonal
   for (int idx = tid; idx < r * r; idx += blockDim.x) {
     const int i = idx % r, j = idx / r;
-    R[idx] = (i <= j) ? cconj(S[pk_off(i, r) + (j - i)]) : mk(0.0, 0.0);
+    R[idx] = (i <= j) ? cconj(S[L.cb[i] + (j - i)]) : mk(0.0, 0.0);
   }
   if (tid == 0 && flags && L.bad) atomicOr(flags, 1);
 }

@@ -133,12 +133,9 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
   const size_t full = heev_lds_bytes(r, true);
   const bool in_lds = (int64_t)full <= (int64_t)max_lds_per_block();
   const size_t bytes = in_lds ? full : heev_lds_bytes(r, false);
-  zd* gpk = nullptr;
-  if (!in_lds) {
-    gpk = sc.get<zd>(F * packed_size(r));
-    if (!gpk) return fail(RTSVD_E_NOMEM, "device allocation failed: heev packed scratch");
-  }
-  double* zs = sc.get<double>(F * r * r);
+  zd* gpk = sc.get<zd>(F * packed_size(r));
+  if (!gpk) return fail(RTSVD_E_NOMEM, "device allocation failed: heev packed scratch");
+  double* zs = sc.get<double>(in_lds ? 1 : F * r * (int64_t)(r + 1));
   double* lu = sc.get<double>(F * r * 5 * (int64_t)r);
   if (!zs || !lu) return fail(RTSVD_E_NOMEM, "device allocation failed: heev scratch");
   if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)k_heev, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
@@ -162,6 +159,15 @@ static int launch_cholinv(const zd* G, int r, int64_t F, zd* Rinv, int* flags, S
   return 0;
 }
 
+// number of K splits of a Gram product so that the grid has about 1000 blocks
+static int gram_splits(int64_t rows, int64_t r, int64_t F) {
+  const int64_t t = ceil_div(r, 64);
+  const int64_t tiles = F * t * (t + 1) / 2;
+  int64_t ks = ceil_div(1024, std::max<int64_t>(tiles, 1));
+  ks = std::min<int64_t>(ks, std::max<int64_t>(1, rows / 64));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ks, 16));
+}
+
 // ---------------------------------------------------------------------------------------------
 // CholeskyQR: Y (F x rows x r) <- Y R^{-1} with R^H R = Y^H Y (FP64 Gram + Cholesky), `passes`
 // times (2 = CholeskyQR2, orthonormal to working precision).
@@ -169,13 +175,15 @@ static int launch_cholinv(const zd* G, int r, int64_t F, zd* Rinv, int* flags, S
 template <typename TY>
 static int orthonormalize(TY* Y, int64_t rows, int64_t r, int64_t F, int passes, zd* G, zd* Rinv, TY* tmp,
                           int* flags, Scratch& sc, hipStream_t s) {
+  const int ksplit = gram_splits(rows, r, F);
+  zd* part = sc.get<zd>(F * ksplit * r * r);
+  if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
   for (int pass = 0; pass < passes; ++pass) {
-    RT_TRY((cgemm<TY, TY, zd, double>(true, false, (int)r, (int)r, (int)rows, Y, rows, rows * r, Y, rows, rows * r,
-                                     G, r, r * r, (int)F, 1.0, false, s)));
+    RT_TRY(gram_fp64<TY>(Y, rows, (int)r, rows * r, (int)F, part, ksplit, G, s));
     RT_TRY(launch_cholinv(G, (int)r, F, Rinv, flags, sc, s));
     RT_CHECK_HIP(hipMemcpyAsync(tmp, Y, sizeof(TY) * F * rows * r, hipMemcpyDeviceToDevice, s));
-    RT_TRY((cgemm<TY, zd, TY, double>(false, false, (int)rows, (int)r, (int)r, tmp, rows, rows * r, Rinv, r, r * r,
-                                     Y, rows, rows * r, (int)F, 1.0, false, s)));
+    RT_TRY((small_k_cgemm<TY, zd, TY>((int)rows, (int)r, (int)r, tmp, rows, rows * r, Rinv, r, r * r, Y, rows,
+                                      rows * r, (int)F, s)));
   }
   return 0;
 }
@@ -257,14 +265,17 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, rown, (int)F, (int)r, (int)n, eta);
     RT_LAUNCH_OK();
     // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
-    RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)m, Ch, m, m * r, Ch, m, m * r, G, r, r * r,
-                                     (int)F, 1.0, false, s)));
+    {
+      const int ks = gram_splits(m, r, F);
+      zd* part = sc.get<zd>(F * ks * r * r);
+      if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
+      RT_TRY(gram_fp64<zd>(Ch, m, (int)r, m * r, (int)F, part, ks, G, s));
+    }
     RT_TRY(launch_heev(G, (int)r, F, Ub, lam, sc, s));
     hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
     RT_LAUNCH_OK();
     // V = C^H U-breve diag(1/sigma)
-    RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)r, (int)r, Ch, m, m * r, Ub, r, r * r, V, m, m * r,
-                                     (int)F, 1.0, false, s)));
+    RT_TRY((small_k_cgemm<zd, zd, zd>((int)m, (int)r, (int)r, Ch, m, m * r, Ub, r, r * r, V, m, m * r, (int)F, s)));
     hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * m * r)), dim3(256), 0, s, V, V, sigma, (int)m,
                        (int)r, (int)F);
     RT_LAUNCH_OK();
@@ -272,8 +283,12 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     RT_TRY((big_gemm<zw, zd, zw, Tw>(false, Ah, l, m, V, r, Wo, F, s)));
   } else {
     // full facewise SVD through G = A-hat^H A-hat = V diag(sigma^2) V^H; W = A-hat V; U = W diag(1/sigma)
-    RT_TRY((cgemm<zw, zw, zd, double>(true, false, (int)m, (int)m, (int)l, Ah, l, l * m, Ah, l, l * m, G, m, m * m,
-                                     (int)F, 1.0, false, s)));
+    {
+      const int ks = gram_splits(l, m, F);
+      zd* part = sc.get<zd>(F * ks * m * m);
+      if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
+      RT_TRY(gram_fp64<zw>(Ah, l, (int)m, l * m, (int)F, part, ks, G, s));
+    }
     RT_TRY(launch_heev(G, (int)m, F, V, lam, sc, s));
     hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
     RT_LAUNCH_OK();
