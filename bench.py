@@ -28,7 +28,53 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+
+TAGS = {1: "fft_A", 2: "fft_omega", 3: "sketch", 4: "power", 5: "project", 6: "W", 7: "gram", 8: "chol",
+        9: "qmul", 10: "heev", 11: "svd_aux", 12: "solve"}
+
+
+def stage_model(w, precision):
+    """Algorithmic work per launch of each timed stage: (flops, bytes, bound, compute precision)."""
+    l = m = w.size
+    n, F, r, p = w.n, w.faces, w.r, max(w.p, 1)
+    s_in = 8 if precision == "fp64" else 4
+    cw = 16 if precision == "fp64" else 8                   # complex working precision
+    ca = {"fp64": 16, "fp32": 8}.get(precision, 4)         # complex A-hat operand of the big passes
+    gp = {"fp64": "fp64", "fp32": "fp32"}.get(precision, "bf16")
+    big = 8.0 * l * m * r * F
+    mdl = {
+        "fft_A": (0.0, l * m * n * s_in + F * l * m * cw + (F * l * m * 4 if ca == 4 else 0), "hbm", None),
+        "fft_omega": (0.0, m * r * n * s_in + F * m * r * cw, "hbm", None),
+        "sketch": (big, F * l * m * ca + F * (m + l) * r * cw, None, gp),
+        "power": (big, F * l * m * ca + F * (m + l) * r * cw, None, gp),
+        "project": (big, F * l * m * ca + F * l * r * cw + F * m * r * 16, None, gp),
+        "W": (big, F * l * m * cw + F * m * r * 16 + F * l * r * cw, None, "fp64" if precision == "fp64" else "fp32"),
+        "gram": (4.0 * l * r * r * F, F * l * r * cw + F * r * r * 16, None, "fp64"),
+        "chol": (F * (8.0 / 3.0) * r ** 3, F * 2 * r * r * 16, "alu", "fp64"),
+        "qmul": (4.0 * l * r * r * F, 2 * F * l * r * cw + F * r * r * 16, None, "fp64" if precision == "fp64" else "fp32"),
+        "heev": (F * (16.0 / 3.0 + 8.0) * r ** 3, F * 2 * r * r * 16, "alu", "fp64"),
+        "svd_aux": (F * (4.0 * m * r * r + 8.0 * m * r * r), F * m * r * 16 * 3, None, "fp64"),
+        "solve": (8.0 * F * (2 * l * r * p + m * r * p + r * r * p + l * r * p),
+                  l * p * n * s_in + F * l * p * cw + F * (2 * l * r + m * r) * cw + m * p * n * s_in, "hbm", None),
+    }
+    return mdl
+
+
+def roofline_of(name, ms, launches, w, precision):
+    flops, byts, bound, prec = stage_model(w, precision)[name]
+    per = ms / max(launches, 1) / 1e3            # seconds per launch
+    if bound is None:                              # by arithmetic intensity against the ridge point
+        ridge = PEAK_TFLOPS[prec] * 1e12 / (HBM_PEAK_GBS * 1e9)
+        bound = "mfma" if flops / byts >= ridge else "hbm"
+    if bound == "hbm":
+        ach = byts / per / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "algorithmic_bytes": byts}
+    ach = flops / per / 1e12
+    pk = PEAK_TFLOPS[prec]
+    return {"bound": bound, "achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk,
+            "algorithmic_flops": flops, "precision": prec}
 
 
 def parse():
@@ -69,11 +115,14 @@ def run_once(rt, prob, w, precision):
     return f, res
 
 
-def time_steps(torch, rt, prob, w, precision, steps, warmup):
+def time_steps(torch, rt, prob, w, precision, steps, warmup, timers=False):
+    lib = rt.load()
     for _ in range(warmup):
         f, res = run_once(rt, prob, w, precision)
         f.close()
     torch.cuda.synchronize()
+    if timers:
+        lib.rtsvd_timer_enable(1)
     t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -91,6 +140,18 @@ def time_steps(torch, rt, prob, w, precision, steps, warmup):
     ev_ms = start.elapsed_time(end)
     out = {"X": res.X, "k": int(res.k[0]), "status": int(res.status[0])}
     last.close()
+    if timers:
+        import ctypes
+        stages = {}
+        for tag, name in TAGS.items():
+            tot, cnt = ctypes.c_double(), ctypes.c_int32()
+            lib.rtsvd_timer_read(tag, ctypes.byref(tot), ctypes.byref(cnt))
+            if cnt.value:
+                stages[name] = {"ms_per_step": tot.value / steps, "launches_per_step": cnt.value / steps,
+                                "avg_launch_us": 1e3 * tot.value / cnt.value,
+                                **roofline_of(name, tot.value / steps, cnt.value / steps, w, precision)}
+        lib.rtsvd_timer_enable(0)
+        out["stages"] = stages
     return ev_ms / steps, wall, out
 
 
@@ -151,7 +212,7 @@ def main():
     dev = torch.device("cuda:0")
     prob = make_problem(w, dev, torch, rt, wl)
     print(f"[bench] inputs ready: {w.name} l=m={w.size} n={w.n} r={w.r}", file=sys.stderr, flush=True)
-    ms, wall, out = time_steps(torch, rt, prob, w, precision, args.steps, args.warmup)
+    ms, wall, out = time_steps(torch, rt, prob, w, precision, args.steps, args.warmup, timers=True)
     x_true = prob["X64"]
     err = float(torch.linalg.norm(out["X"].double() - x_true) / torch.linalg.norm(x_true))
     result = {
@@ -165,6 +226,15 @@ def main():
                    "precision": precision, "noise": w.noise, "eta": w.eta},
         "k": out["k"], "dp_status": out["status"], "rel_error": err,
     }
+    stages = out.get("stages", {})
+    if stages:
+        dom = max(stages, key=lambda k: stages[k]["ms_per_step"])
+        st = stages[dom]
+        result["roofline"] = {"kernel": dom, "bound": st["bound"], "achieved": st["achieved"], "peak": st["peak"],
+                              "unit": st["unit"], "frac": st["frac"], "traffic": None,
+                              "avg_launch_us": st["avg_launch_us"]}
+        result["stages"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                            for k, v in stages.items()}
     if not args.no_fp64 and precision != "fp64":
         ms64, _, out64 = time_steps(torch, rt, prob, w, "fp64", args.fp64_steps, 1)
         err64 = float(torch.linalg.norm(out64["X"] - x_true) / torch.linalg.norm(x_true))

@@ -140,6 +140,26 @@ int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, in
                int dtype, const double* delta, int32_t n_delta, double eta_dp, int32_t k_max,
                void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
 
+/* Stage timers (for benchmarks and profiling).  While enabled, every tagged stage of every call
+ * is bracketed by a pair of HIP events recorded on the call's stream; rtsvd_timer_read
+ * synchronizes on the recorded events of one tag and returns the summed elapsed time and the
+ * number of bracketed launches.  rtsvd_timer_enable(0 or 1) also clears the record.         */
+#define RTSVD_T_FFT_A 1      /* tube DFT of A (and ||A||_F partial sums)                     */
+#define RTSVD_T_FFT_OMEGA 2  /* tube DFT of the Gaussian tensor                              */
+#define RTSVD_T_SKETCH 3     /* Y = A-hat Omega-hat                                          */
+#define RTSVD_T_POWER 4      /* power iteration products A-hat^H Q and A-hat Q_z             */
+#define RTSVD_T_PROJECT 5    /* C^H = A-hat^H Q                                              */
+#define RTSVD_T_W 6          /* W = A-hat V                                                  */
+#define RTSVD_T_GRAM 7       /* FP64 Gram matrices of CholeskyQR                             */
+#define RTSVD_T_CHOL 8       /* Cholesky + triangular inverse                                */
+#define RTSVD_T_QMUL 9       /* Q = Y R^{-1}                                                 */
+#define RTSVD_T_HEEV 10      /* Hermitian eigensolver of C C^H                               */
+#define RTSVD_T_SVDAUX 11    /* Gram C C^H, V = C^H U-breve diag(1/sigma), error indicator    */
+#define RTSVD_T_SOLVE 12     /* whole rtsvd_solve                                            */
+#define RTSVD_T_TGKB 13      /* whole tgkb_solve                                             */
+int rtsvd_timer_enable(int on);
+int rtsvd_timer_read(int tag, double* total_ms, int32_t* launches);
+
 /* Human-readable status text. */
 const char* rtsvd_status_string(int status);
 

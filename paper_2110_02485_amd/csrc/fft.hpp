@@ -11,6 +11,9 @@
 // Y_f = (Z_f - conj Z_{n-f})/(2i).  Stores of one face for TB tubes are contiguous again.
 #pragma once
 #include "common.hpp"
+#include <map>
+#include <mutex>
+#include <algorithm>
 
 namespace rt {
 
@@ -42,13 +45,20 @@ __device__ cplx<T>* stockham_lds(cplx<T>* b0, cplx<T>* b1, const cplx<T>* tw, in
   return b0;
 }
 
+// twiddle table in global memory: tw[k] = exp(-2 pi i k / n), k < n/2, computed in FP64
 template <typename T>
-__device__ void fill_twiddles(cplx<T>* tw, int n) {
-  for (int k = threadIdx.x; k < n / 2; k += blockDim.x) {
+__global__ void k_twiddle_table(cplx<T>* tw, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n / 2) {
     double s, c;
     sincospi(-2.0 * (double)k / (double)n, &s, &c);
     tw[k] = mk((T)c, (T)s);
   }
+}
+
+template <typename T>
+__device__ void fill_twiddles(cplx<T>* tw, const cplx<T>* __restrict__ gtw, int n) {
+  for (int k = threadIdx.x; k < n / 2; k += blockDim.x) tw[k] = gtw[k];
 }
 
 // forward: real tubes (input type Tin) -> half spectrum in working precision T, optional bf16 copy.
@@ -57,14 +67,14 @@ template <typename Tin, typename T>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_rfft_pow2(const Tin* __restrict__ in, int64_t ntubes, int n, int log2n, int TB,
             cplx<T>* __restrict__ out, int64_t face_stride, zb* __restrict__ out16,
-            double* __restrict__ sumsq) {
+            double* __restrict__ sumsq, const cplx<T>* __restrict__ gtw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int TH = TB / 2;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* b0 = tw + n / 2;
   cplx<T>* b1 = b0 + (size_t)(n + 2) * TH;
   const int64_t tube0 = (int64_t)blockIdx.x * TB;
-  fill_twiddles(tw, n);
+  fill_twiddles(tw, gtw, n);
   double acc = 0.0;
   for (int idx = threadIdx.x; idx < n * TB; idx += blockDim.x) {
     const int t = idx / TB, i = idx % TB;
@@ -109,7 +119,7 @@ k_rfft_pow2(const Tin* __restrict__ in, int64_t ntubes, int n, int log2n, int TB
 template <typename T, typename Tout>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_irfft_pow2(const cplx<T>* __restrict__ in, int64_t face_stride, int64_t ntubes, int n, int log2n,
-             int TB, Tout* __restrict__ out) {
+             int TB, Tout* __restrict__ out, const cplx<T>* __restrict__ gtw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int TH = TB / 2;
   const int F = n / 2 + 1;
@@ -117,7 +127,7 @@ k_irfft_pow2(const cplx<T>* __restrict__ in, int64_t face_stride, int64_t ntubes
   cplx<T>* b0 = tw + n / 2;
   cplx<T>* b1 = b0 + (size_t)(n + 2) * TH;
   const int64_t tube0 = (int64_t)blockIdx.x * TB;
-  fill_twiddles(tw, n);
+  fill_twiddles(tw, gtw, n);
   // stage X_f (tubes 0..TH-1) and Y_f (tubes TH..TB-1) for f < F in b1: b1[f*TB + i]
   for (int idx = threadIdx.x; idx < F * TB; idx += blockDim.x) {
     const int f = idx / TB, i = idx % TB;
@@ -226,6 +236,24 @@ inline int ilog2_exact(int64_t n) {
   int l = 0; while ((1LL << l) < n) ++l; return l;
 }
 
+// per-device cache of twiddle tables (kept for the life of the process; a few KB each)
+template <typename T>
+const cplx<T>* twiddles(int n, hipStream_t s) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, cplx<T>*> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_pair(dev, n);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  cplx<T>* tw = nullptr;
+  if (hipMalloc(&tw, sizeof(cplx<T>) * (size_t)std::max(1, n / 2)) != hipSuccess) return nullptr;
+  hipLaunchKernelGGL((k_twiddle_table<T>), dim3((unsigned)((n / 2 + 255) / 256 + 1)), dim3(256), 0, s, tw, n);
+  cache[key] = tw;
+  return tw;
+}
+
 template <typename T>
 inline int fft_tile(int n) {
   // two ping-pong buffers of (n+2) x TB/2 complex plus n/2 twiddles within ~48 KB of LDS
@@ -243,8 +271,10 @@ int launch_rfft(const Tin* in, int64_t ntubes, int n, cplx<T>* out, int64_t face
     const int TB = fft_tile<T>(n);
     const int64_t blocks = ceil_div(ntubes, TB);
     const size_t lds = (size_t)(2 * (n + 2) * (TB / 2) + n / 2) * sizeof(cplx<T>);
+    const cplx<T>* tw = twiddles<T>(n, s);
+    if (!tw) return -1;
     hipLaunchKernelGGL((k_rfft_pow2<Tin, T>), dim3((unsigned)blocks), dim3(FFT_THREADS), lds, s,
-                       in, ntubes, n, lg, TB, out, face_stride, out16, sumsq);
+                       in, ntubes, n, lg, TB, out, face_stride, out16, sumsq, tw);
     if (nblocks_out) *nblocks_out = blocks;
   } else {
     const int64_t blocks = ceil_div(ntubes, FFT_THREADS);
@@ -262,8 +292,10 @@ int launch_irfft(const cplx<T>* in, int64_t face_stride, int64_t ntubes, int n, 
     const int TB = fft_tile<T>(n);
     const int64_t blocks = ceil_div(ntubes, TB);
     const size_t lds = (size_t)(2 * (n + 2) * (TB / 2) + n / 2) * sizeof(cplx<T>);
+    const cplx<T>* tw = twiddles<T>(n, s);
+    if (!tw) return -1;
     hipLaunchKernelGGL((k_irfft_pow2<T, Tout>), dim3((unsigned)blocks), dim3(FFT_THREADS), lds, s,
-                       in, face_stride, ntubes, n, lg, TB, out);
+                       in, face_stride, ntubes, n, lg, TB, out, tw);
   } else {
     const int64_t blocks = ceil_div(ntubes, FFT_THREADS);
     hipLaunchKernelGGL((k_irdft_direct<T, Tout>), dim3((unsigned)blocks), dim3(FFT_THREADS),

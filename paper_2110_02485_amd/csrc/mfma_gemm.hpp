@@ -68,23 +68,35 @@ struct PB16 {
   static __device__ __forceinline__ int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-// read a storage element as (re, im) doubles -- bf16 storage is read exactly
-__device__ __forceinline__ void ld2(const zd& z, double& a, double& b) { a = z.re; b = z.im; }
-__device__ __forceinline__ void ld2(const zf& z, double& a, double& b) { a = z.re; b = z.im; }
-__device__ __forceinline__ void ld2(const zb& z, double& a, double& b) { a = bf2f(z.bits & 0xffffu); b = bf2f(z.bits >> 16); }
+// read a storage element as (re, im) in the staging type -- bf16 storage is read exactly
+template <typename T> __device__ __forceinline__ void ld2(const zd& z, T& a, T& b) { a = (T)z.re; b = (T)z.im; }
+template <typename T> __device__ __forceinline__ void ld2(const zf& z, T& a, T& b) { a = (T)z.re; b = (T)z.im; }
+template <typename T> __device__ __forceinline__ void ld2(const zb& z, T& a, T& b) {
+  a = (T)bf2f(z.bits & 0xffffu); b = (T)bf2f(z.bits >> 16);
+}
+// staging arithmetic type: double for the FP64 MFMA, float otherwise
+template <class P> struct StageT { typedef float T; };
+template <> struct StageT<P64> { typedef double T; };
 
 // Grid: x = batch * mtiles * ntiles (XCD-aware order), y = k splits.  Block = 256 threads.
 // Output: C + f*sC + split*sCsplit (split partials summed by k_gram_reduce when ksplit > 1).
 // lower_only: skip tiles strictly above the diagonal (Hermitian Gram).
-template <class P, bool CA, bool CB, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WM, int WN>
+// Operand staging: every thread moves chunks of CH consecutive k of one row of op(A) (one column
+// of B) from global memory into registers for the next k-step while the MFMAs of the current
+// k-step run, then converts them and writes them to LDS after the barrier.
+template <class P, bool CA, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(256)
 k_mfma_cgemm(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA, const TB* __restrict__ B,
              int64_t ldb, int64_t sB, TC* __restrict__ C, int64_t ldc, int64_t sC, int batch, int mtiles, int ntiles,
              int kchunk, int64_t sCsplit, int lower_only) {
   typedef typename P::E E;
   typedef typename P::V V;
+  typedef typename StageT<P>::T ST;
   constexpr int BKP = BK + P::PAD;
   constexpr int TMW = BM / WM / 16, TNW = BN / WN / 16;
+  constexpr int CH = (P::KPER == 8) ? 8 : 4;               // k elements per staging chunk
+  constexpr int ACH = BM * BK / CH / 256, BCH = BN * BK / CH / 256;
+  static_assert(ACH >= 1 && BCH >= 1 && BM * BK % (CH * 256) == 0 && BN * BK % (CH * 256) == 0, "tile/chunk mismatch");
   __shared__ __align__(16) E As[2][BM][BKP];
   __shared__ __align__(16) E Bs[2][BN][BKP];
 
@@ -95,8 +107,7 @@ k_mfma_cgemm(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t
   int f, t;
   if (nb % 8 == 0 && batch >= 8) {
     const int xcd = b % 8, slot = b / 8;
-    const int per_xcd = nb / 8;               // blocks per XCD
-    const int faces_per_xcd = per_xcd / tiles;
+    const int faces_per_xcd = (nb / 8) / tiles;
     const int fl = slot / tiles;
     t = slot % tiles;
     f = fl * 8 + xcd;
@@ -120,6 +131,71 @@ k_mfma_cgemm(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t
   const int wm = wave % WM, wn = wave / WM;
   const int lr = lane & 15, lk = (lane >> 4) * P::KPER;
 
+  // chunk coordinates: A chunk q -> (row ai, k offset ak); B chunk q -> (column bj, k offset bk)
+  int ai[ACH], ak[ACH], bj[BCH], bk[BCH];
+#pragma unroll
+  for (int q = 0; q < ACH; ++q) {
+    const int c = tid + 256 * q;
+    if (!CA) { ai[q] = c % BM; ak[q] = (c / BM) * CH; }   // rows contiguous in global: coalesce along rows
+    else { ak[q] = (c % (BK / CH)) * CH; ai[q] = c / (BK / CH); }
+  }
+#pragma unroll
+  for (int q = 0; q < BCH; ++q) {
+    const int c = tid + 256 * q;
+    bk[q] = (c % (BK / CH)) * CH; bj[q] = c / (BK / CH);
+  }
+  ST ra[ACH][CH][2], rb[BCH][CH][2];
+
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < ACH; ++q) {
+      const int gi = m0 + ai[q];
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        const int gk = k0 + ak[q] + e;
+        ST re = 0, im = 0;
+        if (gi < M && gk < kend) {
+          if (!CA) ld2<ST>(A[gi + (int64_t)gk * lda], re, im);
+          else { ld2<ST>(A[gk + (int64_t)gi * lda], re, im); im = -im; }
+        }
+        ra[q][e][0] = re; ra[q][e][1] = im;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BCH; ++q) {
+      const int gj = n0 + bj[q];
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        const int gk = k0 + bk[q] + e;
+        ST re = 0, im = 0;
+        if (gj < N && gk < kend) ld2<ST>(B[gk + (int64_t)gj * ldb], re, im);
+        rb[q][e][0] = re; rb[q][e][1] = im;
+      }
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int q = 0; q < ACH; ++q)
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        E tmp[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) tmp[e] = P::cvt(ra[q][e][pl]);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) As[pl][ai[q]][ak[q] + e] = tmp[e];
+      }
+#pragma unroll
+    for (int q = 0; q < BCH; ++q)
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        E tmp[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) tmp[e] = P::cvt(rb[q][e][pl]);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) Bs[pl][bj[q]][bk[q] + e] = tmp[e];
+      }
+  };
+
   V accr[TMW][TNW], acci[TMW][TNW];
 #pragma unroll
   for (int i = 0; i < TMW; ++i)
@@ -129,60 +205,43 @@ k_mfma_cgemm(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t
       for (int v = 0; v < 4; ++v) { accr[i][j][v] = 0; acci[i][j][v] = 0; }
     }
 
+  if (kbeg < kend) {
+    load_tiles(kbeg);
+    store_tiles();
+  }
+  __syncthreads();
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // ---- stage op(A) tile (BM x BK) and op(B) tile (BK x BN) as real/imag planes ----
-    for (int idx = tid; idx < BM * BK; idx += 256) {
-      int i, k;
-      if (!CA) { i = idx % BM; k = idx / BM; } else { k = idx % BK; i = idx / BK; }
-      const int gi = m0 + i, gk = k0 + k;
-      double re = 0.0, im = 0.0;
-      if (gi < M && gk < kend) {
-        if (!CA) ld2(A[gi + (int64_t)gk * lda], re, im);
-        else { ld2(A[gk + (int64_t)gi * lda], re, im); im = -im; }
-      }
-      As[0][i][k] = P::cvt(re);
-      As[1][i][k] = P::cvt(im);
-    }
-    for (int idx = tid; idx < BN * BK; idx += 256) {
-      int j, k;
-      if (!CB) { k = idx % BK; j = idx / BK; } else { j = idx % BN; k = idx / BN; }
-      const int gj = n0 + j, gk = k0 + k;
-      double re = 0.0, im = 0.0;
-      if (gj < N && gk < kend) {
-        if (!CB) ld2(B[gk + (int64_t)gj * ldb], re, im);
-        else { ld2(B[gj + (int64_t)gk * ldb], re, im); im = -im; }
-      }
-      Bs[0][j][k] = P::cvt(re);
-      Bs[1][j][k] = P::cvt(im);
-    }
-    __syncthreads();
+    const bool more = k0 + BK < kend;
+    if (more) load_tiles(k0 + BK);     // global loads in flight during the MFMAs below
 #pragma unroll
     for (int ks = 0; ks < BK; ks += P::KM) {
-      typename P::Frag ar[TMW], ai[TMW], br[TNW], bi[TNW], bn[TNW];
+      typename P::Frag ar[TMW], aim[TMW];
 #pragma unroll
       for (int i = 0; i < TMW; ++i) {
         const int row = wm * (BM / WM) + i * 16 + lr;
         ar[i] = P::frag(&As[0][row][ks + lk]);
-        ai[i] = P::frag(&As[1][row][ks + lk]);
+        aim[i] = P::frag(&As[1][row][ks + lk]);
       }
 #pragma unroll
       for (int j = 0; j < TNW; ++j) {
         const int col = wn * (BN / WN) + j * 16 + lr;
-        br[j] = P::frag(&Bs[0][col][ks + lk]);
-        bi[j] = P::frag(&Bs[1][col][ks + lk]);
-        bn[j] = P::neg(bi[j]);
-      }
+        const typename P::Frag br = P::frag(&Bs[0][col][ks + lk]);
+        const typename P::Frag bi = P::frag(&Bs[1][col][ks + lk]);
+        const typename P::Frag bn = P::neg(bi);
 #pragma unroll
-      for (int i = 0; i < TMW; ++i)
-#pragma unroll
-        for (int j = 0; j < TNW; ++j) {
-          accr[i][j] = P::mma(ar[i], br[j], accr[i][j]);
-          accr[i][j] = P::mma(ai[i], bn[j], accr[i][j]);
-          acci[i][j] = P::mma(ar[i], bi[j], acci[i][j]);
-          acci[i][j] = P::mma(ai[i], br[j], acci[i][j]);
+        for (int i = 0; i < TMW; ++i) {
+          accr[i][j] = P::mma(ar[i], br, accr[i][j]);
+          accr[i][j] = P::mma(aim[i], bn, accr[i][j]);
+          acci[i][j] = P::mma(ar[i], bi, acci[i][j]);
+          acci[i][j] = P::mma(aim[i], br, acci[i][j]);
         }
+      }
     }
     __syncthreads();
+    if (more) {
+      store_tiles();
+      __syncthreads();
+    }
   }
   // ---- store ----
 #pragma unroll
@@ -215,7 +274,7 @@ __global__ void k_gram_reduce(const zd* __restrict__ part, int r, int ksplit, in
 // ---------------------------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------------------------
-template <class P, bool CA, bool CB, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WM, int WN>
+template <class P, bool CA, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WM, int WN>
 int launch_mfma(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const TB* B, int64_t ldb, int64_t sB,
                 TC* C, int64_t ldc, int64_t sC, int batch, int ksplit, int64_t sCsplit, bool lower_only, hipStream_t s) {
   const int mtiles = (int)ceil_div(M, BM), ntiles = (int)ceil_div(N, BN);
@@ -223,7 +282,7 @@ int launch_mfma(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const
   int64_t nblk = (int64_t)batch * tiles;
   if (batch >= 8) nblk = ceil_div(batch, 8) * 8 * (int64_t)tiles;  // XCD-aware decode needs a multiple of 8
   int kchunk = (int)ceil_div(ceil_div(K, ksplit), BK) * BK;
-  hipLaunchKernelGGL((k_mfma_cgemm<P, CA, CB, TA, TB, TC, BM, BN, BK, WM, WN>), dim3((unsigned)nblk, (unsigned)ksplit),
+  hipLaunchKernelGGL((k_mfma_cgemm<P, CA, TA, TB, TC, BM, BN, BK, WM, WN>), dim3((unsigned)nblk, (unsigned)ksplit),
                      dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, batch, mtiles, ntiles, kchunk,
                      sCsplit, (int)lower_only);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -241,14 +300,14 @@ int big_cgemm(bool conjA, int M, int N, int K, const TA* A, int64_t lda, int64_t
               int64_t sX, TY* Y, int64_t ldy, int64_t sY, int batch, hipStream_t s) {
   typedef typename BigP<TA, Acc>::P P;
   if constexpr (std::is_same<P, P64>::value) {
-    if (!conjA) return launch_mfma<P, false, false, TA, TX, TY, 64, 128, 16, 1, 4>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
-    return launch_mfma<P, true, false, TA, TX, TY, 64, 128, 16, 1, 4>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
+    if (!conjA) return launch_mfma<P, false, TA, TX, TY, 64, 128, 16, 1, 4>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
+    return launch_mfma<P, true, TA, TX, TY, 64, 128, 16, 1, 4>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
   } else if constexpr (std::is_same<P, P32>::value) {
-    if (!conjA) return launch_mfma<P, false, false, TA, TX, TY, 128, 128, 16, 2, 2>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
-    return launch_mfma<P, true, false, TA, TX, TY, 128, 128, 16, 2, 2>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
+    if (!conjA) return launch_mfma<P, false, TA, TX, TY, 128, 128, 16, 2, 2>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
+    return launch_mfma<P, true, TA, TX, TY, 128, 128, 16, 2, 2>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
   } else {
-    if (!conjA) return launch_mfma<P, false, false, TA, TX, TY, 128, 128, 32, 2, 2>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
-    return launch_mfma<P, true, false, TA, TX, TY, 128, 128, 32, 2, 2>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
+    if (!conjA) return launch_mfma<P, false, TA, TX, TY, 128, 128, 32, 2, 2>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
+    return launch_mfma<P, true, TA, TX, TY, 128, 128, 32, 2, 2>(M, N, K, A, lda, sA, X, ldx, sX, Y, ldy, sY, batch, 1, 0, false, s);
   }
 }
 
@@ -257,9 +316,9 @@ template <typename TX, typename TR, typename TY>
 int small_k_cgemm(int M, int N, int K, const TX* X, int64_t ldx, int64_t sX, const TR* R, int64_t ldr, int64_t sR,
                   TY* Y, int64_t ldy, int64_t sY, int batch, hipStream_t s) {
   if constexpr (std::is_same<TY, zd>::value)
-    return launch_mfma<P64, false, false, TX, TR, TY, 64, 128, 16, 1, 4>(M, N, K, X, ldx, sX, R, ldr, sR, Y, ldy, sY, batch, 1, 0, false, s);
+    return launch_mfma<P64, false, TX, TR, TY, 64, 128, 16, 1, 4>(M, N, K, X, ldx, sX, R, ldr, sR, Y, ldy, sY, batch, 1, 0, false, s);
   else
-    return launch_mfma<P32, false, false, TX, TR, TY, 128, 128, 16, 2, 2>(M, N, K, X, ldx, sX, R, ldr, sR, Y, ldy, sY, batch, 1, 0, false, s);
+    return launch_mfma<P32, false, TX, TR, TY, 128, 128, 16, 2, 2>(M, N, K, X, ldx, sX, R, ldr, sR, Y, ldy, sY, batch, 1, 0, false, s);
 }
 
 // FP64 Gram G_f = Y_f^H Y_f (r x r), Y_f rows x r of any storage type; split-K partials in `part`
@@ -267,7 +326,7 @@ int small_k_cgemm(int M, int N, int K, const TX* X, int64_t ldx, int64_t sX, con
 template <typename TY>
 int gram_fp64(const TY* Y, int64_t rows, int r, int64_t sY, int batch, zd* part, int ksplit, zd* G, hipStream_t s) {
   const int64_t sPart = (int64_t)r * r;
-  int rc = launch_mfma<P64, true, false, TY, TY, zd, 64, 64, 16, 2, 2>(r, r, (int)rows, Y, rows, sY, Y, rows, sY, part,
+  int rc = launch_mfma<P64, true, TY, TY, zd, 64, 64, 16, 2, 2>(r, r, (int)rows, Y, rows, sY, Y, rows, sY, part,
                                                                        r, (int64_t)ksplit * sPart, batch, ksplit, sPart,
                                                                        true, s);
   if (rc) return rc;

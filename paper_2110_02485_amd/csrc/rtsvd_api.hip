@@ -115,6 +115,71 @@ struct rtsvd_factor_s {
 static bool work_is_double(int precision) { return precision == RTSVD_P_FP64; }
 
 // ---------------------------------------------------------------------------------------------
+// stage timers: HIP events around tagged launch sequences, on the stream they are launched on
+// ---------------------------------------------------------------------------------------------
+struct TimerState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> rec;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+static TimerState g_timer;
+
+struct TimerScope {
+  int tag;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimerScope(int t, hipStream_t st) : tag(t), s(st) {
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    if (!g_timer.on) return;
+    a = g_timer.get();
+    b = g_timer.get();
+    (void)hipEventRecord(a, s);
+  }
+  ~TimerScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    g_timer.rec.push_back({tag, {a, b}});
+  }
+};
+#define RT_CAT2(a, b) a##b
+#define RT_CAT(a, b) RT_CAT2(a, b)
+#define RT_TIMED(tag) TimerScope RT_CAT(_timer_scope_, __LINE__)(tag, s)
+
+extern "C" int rtsvd_timer_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  for (auto& r : g_timer.rec) { g_timer.pool.push_back(r.second.first); g_timer.pool.push_back(r.second.second); }
+  g_timer.rec.clear();
+  g_timer.on = on != 0;
+  return RTSVD_OK;
+}
+
+extern "C" int rtsvd_timer_read(int tag, double* total_ms, int32_t* launches) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  double tot = 0.0;
+  int cnt = 0;
+  for (auto& r : g_timer.rec) {
+    if (r.first != tag) continue;
+    if (hipEventSynchronize(r.second.second) != hipSuccess) return fail(RTSVD_E_HIP, "rtsvd_timer_read: event");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.second.first, r.second.second) != hipSuccess)
+      return fail(RTSVD_E_HIP, "rtsvd_timer_read: elapsed");
+    tot += ms;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return RTSVD_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
 // launchers of the per-face r x r kernels (packed matrix in LDS when it fits)
 // ---------------------------------------------------------------------------------------------
 static int max_lds_per_block() {
@@ -179,8 +244,15 @@ static int orthonormalize(TY* Y, int64_t rows, int64_t r, int64_t F, int passes,
   zd* part = sc.get<zd>(F * ksplit * r * r);
   if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
   for (int pass = 0; pass < passes; ++pass) {
-    RT_TRY(gram_fp64<TY>(Y, rows, (int)r, rows * r, (int)F, part, ksplit, G, s));
-    RT_TRY(launch_cholinv(G, (int)r, F, Rinv, flags, sc, s));
+    {
+      RT_TIMED(RTSVD_T_GRAM);
+      RT_TRY(gram_fp64<TY>(Y, rows, (int)r, rows * r, (int)F, part, ksplit, G, s));
+    }
+    {
+      RT_TIMED(RTSVD_T_CHOL);
+      RT_TRY(launch_cholinv(G, (int)r, F, Rinv, flags, sc, s));
+    }
+    RT_TIMED(RTSVD_T_QMUL);
     RT_CHECK_HIP(hipMemcpyAsync(tmp, Y, sizeof(TY) * F * rows * r, hipMemcpyDeviceToDevice, s));
     RT_TRY((small_k_cgemm<TY, zd, TY>((int)rows, (int)r, (int)r, tmp, rows, rows * r, Rinv, r, r * r, Y, rows,
                                       rows * r, (int)F, s)));
@@ -217,7 +289,10 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
   }
   RT_ALLOC(sumsq, double, ceil_div(l * m, 2) + 1, sc);
   int64_t nblk = 0;
-  RT_TRY((launch_rfft<Tin, Tw>(A, l * m, (int)n, Ah, l * m, Ah16, sumsq, &nblk, s)));
+  {
+    RT_TIMED(RTSVD_T_FFT_A);
+    RT_TRY((launch_rfft<Tin, Tw>(A, l * m, (int)n, Ah, l * m, Ah16, sumsq, &nblk, s)));
+  }
 
   // outputs owned by the handle
   RT_ALLOC(Qo, zw, F * l * r, sc);
@@ -242,45 +317,73 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     RT_ALLOC(tmp, zw, F * std::max(l, m) * r, sc);
     RT_ALLOC(Ch, zd, F * m * r, sc);  // C^H = A-hat^H Q, m x r per face (C = Q^H A-hat)
     RT_ALLOC(rown, double, F * r, sc);
-    RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+    {
+      RT_TIMED(RTSVD_T_FFT_OMEGA);
+      RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+    }
     // sketch Y = A-hat Omega-hat, then Q = orth(Y) (q power iterations in between)
-    if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
-    else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
+    {
+      RT_TIMED(RTSVD_T_SKETCH);
+      {
+        RT_TIMED(RTSVD_T_POWER);
+        if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
+        else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
+      }
+    }
     RT_TRY(orthonormalize<zw>(Y, l, r, F, q == 0 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
     for (int it = 0; it < q; ++it) {
-      if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(true, Ah16, l, m, Y, r, Omh, F, s)));
-      else RT_TRY((big_gemm<zw, zw, zw, Tw>(true, Ah, l, m, Y, r, Omh, F, s)));
+      {
+        RT_TIMED(RTSVD_T_POWER);
+        if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(true, Ah16, l, m, Y, r, Omh, F, s)));
+        else RT_TRY((big_gemm<zw, zw, zw, Tw>(true, Ah, l, m, Y, r, Omh, F, s)));
+      }
       RT_TRY(orthonormalize<zw>(Omh, m, r, F, 1, G, Rinv, tmp, flags, sc, s));
-      if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
-      else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
+      {
+        RT_TIMED(RTSVD_T_POWER);
+        if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
+        else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
+      }
       RT_TRY(orthonormalize<zw>(Y, l, r, F, it == q - 1 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
     }
     RT_CHECK_HIP(hipMemcpyAsync(Qo, Y, sizeof(zw) * F * l * r, hipMemcpyDeviceToDevice, s));
     // projection C^H = A-hat^H Q
-    if (bf16) RT_TRY((big_gemm<zb, zw, zd, float>(true, Ah16, l, m, Qo, r, Ch, F, s)));
-    else RT_TRY((big_gemm<zw, zw, zd, Tw>(true, Ah, l, m, Qo, r, Ch, F, s)));
-    // error indicator eta^[j] (Thm 4.2)
-    hipLaunchKernelGGL((k_colnorms<zd>), dim3((unsigned)r, (unsigned)F), dim3(256), 0, s, Ch, (int)m, (int)r, rown);
-    RT_LAUNCH_OK();
-    hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, rown, (int)F, (int)r, (int)n, eta);
-    RT_LAUNCH_OK();
-    // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
     {
+      RT_TIMED(RTSVD_T_PROJECT);
+      if (bf16) RT_TRY((big_gemm<zb, zw, zd, float>(true, Ah16, l, m, Qo, r, Ch, F, s)));
+      else RT_TRY((big_gemm<zw, zw, zd, Tw>(true, Ah, l, m, Qo, r, Ch, F, s)));
+    }
+    {
+      RT_TIMED(RTSVD_T_SVDAUX);
+      // error indicator eta^[j] (Thm 4.2)
+      hipLaunchKernelGGL((k_colnorms<zd>), dim3((unsigned)r, (unsigned)F), dim3(256), 0, s, Ch, (int)m, (int)r, rown);
+      RT_LAUNCH_OK();
+      hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, rown, (int)F, (int)r, (int)n, eta);
+      RT_LAUNCH_OK();
+      // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
       const int ks = gram_splits(m, r, F);
       zd* part = sc.get<zd>(F * ks * r * r);
       if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
       RT_TRY(gram_fp64<zd>(Ch, m, (int)r, m * r, (int)F, part, ks, G, s));
     }
-    RT_TRY(launch_heev(G, (int)r, F, Ub, lam, sc, s));
-    hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
-    RT_LAUNCH_OK();
-    // V = C^H U-breve diag(1/sigma)
-    RT_TRY((small_k_cgemm<zd, zd, zd>((int)m, (int)r, (int)r, Ch, m, m * r, Ub, r, r * r, V, m, m * r, (int)F, s)));
-    hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * m * r)), dim3(256), 0, s, V, V, sigma, (int)m,
-                       (int)r, (int)F);
-    RT_LAUNCH_OK();
+    {
+      RT_TIMED(RTSVD_T_HEEV);
+      RT_TRY(launch_heev(G, (int)r, F, Ub, lam, sc, s));
+    }
+    {
+      RT_TIMED(RTSVD_T_SVDAUX);
+      hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
+      RT_LAUNCH_OK();
+      // V = C^H U-breve diag(1/sigma)
+      RT_TRY((small_k_cgemm<zd, zd, zd>((int)m, (int)r, (int)r, Ch, m, m * r, Ub, r, r * r, V, m, m * r, (int)F, s)));
+      hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * m * r)), dim3(256), 0, s, V, V, sigma, (int)m,
+                         (int)r, (int)F);
+      RT_LAUNCH_OK();
+    }
     // W = A-hat V: exact residuals of the discrepancy principle
-    RT_TRY((big_gemm<zw, zd, zw, Tw>(false, Ah, l, m, V, r, Wo, F, s)));
+    {
+      RT_TIMED(RTSVD_T_W);
+      RT_TRY((big_gemm<zw, zd, zw, Tw>(false, Ah, l, m, V, r, Wo, F, s)));
+    }
   } else {
     // full facewise SVD through G = A-hat^H A-hat = V diag(sigma^2) V^H; W = A-hat V; U = W diag(1/sigma)
     {
@@ -411,6 +514,7 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   const int64_t l = h->l, m = h->m, n = h->n, F = h->F, r = h->r;
   const int groups = (int)bounds.size();
   Scratch sc(s);
+  RT_TIMED(RTSVD_T_SOLVE);
   RT_ALLOC(Bh, zw, F * l * p, sc);
   RT_TRY((launch_rfft<Tio, Tw>(B, l * p, (int)n, Bh, l * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
   RT_ALLOC(D, zd, F * r * p, sc);

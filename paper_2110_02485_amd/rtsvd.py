@@ -24,7 +24,8 @@ E_ARG, E_HIP, E_NOMEM, E_UNSUPPORTED = -1, -3, -4, -5
 PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
-           "tprod", "tprod_adjoint", "tgkb_solve", "rtsvd_status_string", "rtsvd_last_error"]
+           "tprod", "tprod_adjoint", "tgkb_solve", "rtsvd_status_string", "rtsvd_last_error",
+           "rtsvd_timer_enable", "rtsvd_timer_read"]
 
 
 class RtsvdError(RuntimeError):
@@ -65,6 +66,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rtsvd_status_string.restype = ctypes.c_char_p
     lib.rtsvd_status_string.argtypes = [ctypes.c_int]
     lib.rtsvd_last_error.restype = ctypes.c_char_p
+    lib.rtsvd_timer_enable.argtypes = [ctypes.c_int]
+    lib.rtsvd_timer_read.argtypes = [ctypes.c_int, pdbl, pi32]
     _lib = lib
     return lib
 
