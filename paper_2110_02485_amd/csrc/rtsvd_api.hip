@@ -15,6 +15,7 @@
 #include "mfma_gemm.hpp"
 #include "heev.hpp"
 #include "solve.hpp"
+#include "tgkb.hpp"
 
 using namespace rt;
 
@@ -628,6 +629,145 @@ extern "C" int tprod_adjoint(const void* A, const void* C, void* B, int64_t l, i
   if (dtype == RTSVD_F64) return tprod_impl<double>((const double*)A, (const double*)C, (double*)B, l, m, p, n, true, s);
   if (dtype == RTSVD_F32) return tprod_impl<float>((const float*)A, (const float*)C, (float*)B, l, m, p, n, true, s);
   return fail(RTSVD_E_ARG, "tprod_adjoint: bad dtype");
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// tGKB_p (Alg. 7 + projected least squares + discrepancy principle), the comparison baseline
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+static int gkb_product(bool conj, const cplx<T>* Ah, int64_t l, int64_t m, int64_t p, const cplx<T>* X, int64_t ldx,
+                       int64_t sX, cplx<T>* Y, int64_t sY, int64_t F, hipStream_t s) {
+  const int64_t out_len = conj ? m : l, in_len = conj ? l : m;
+  if (p <= 4 && in_len * p * (int64_t)sizeof(cplx<T>) <= 65536) {
+    const size_t lds = (size_t)in_len * p * sizeof(cplx<T>);
+    if (!conj)
+      hipLaunchKernelGGL((k_gemv_n<T, 4>), dim3((unsigned)ceil_div(l, 256), (unsigned)F), dim3(256), lds, s, Ah, (int)l,
+                         (int)m, (int)p, X, ldx, sX, Y, out_len, sY);
+    else
+      hipLaunchKernelGGL((k_gemv_c<T, 4>), dim3((unsigned)ceil_div(m, 4), (unsigned)F), dim3(256), lds, s, Ah, (int)l,
+                         (int)m, (int)p, X, ldx, sX, Y, out_len, sY);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  if (!conj)
+    return cgemm<cplx<T>, cplx<T>, cplx<T>, double>(false, false, (int)l, (int)p, (int)m, Ah, l, l * m, X, ldx, sX, Y,
+                                                    out_len, sY, (int)F, 1.0, false, s);
+  return cgemm<cplx<T>, cplx<T>, cplx<T>, double>(true, false, (int)m, (int)p, (int)l, Ah, l, l * m, X, ldx, sX, Y,
+                                                  out_len, sY, (int)F, 1.0, false, s);
+}
+
+static int* pinned_counter() {
+  static int* h = nullptr;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!h && hipHostMalloc((void**)&h, sizeof(int) * 64, hipHostMallocDefault) != hipSuccess) h = nullptr;
+  return h;
+}
+
+template <typename T>
+static int tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, int64_t p,
+                     const std::vector<double>& bounds, int kmax, T* X, int* k_out, double* resid_out, int* status_out,
+                     hipStream_t s) {
+  typedef cplx<T> zt;
+  const int64_t F = n / 2 + 1;
+  const double tol = 64.0 * (sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.960464477539063e-08);
+  Scratch sc(s);
+  RT_TIMED(RTSVD_T_TGKB);
+  RT_ALLOC(Ah, zt, F * l * m, sc);
+  RT_ALLOC(Bh, zt, F * l * p, sc);
+  RT_TRY((launch_rfft<T, T>(A, l * m, (int)n, Ah, l * m, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  RT_TRY((launch_rfft<T, T>(B, l * p, (int)n, Bh, l * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  const int64_t ldq = l * (kmax + 1), ldw = m * kmax;
+  RT_ALLOC(Qb, zt, F * p * ldq, sc);
+  RT_ALLOC(Wb, zt, F * p * ldw, sc);
+  RT_ALLOC(raw, zt, F * p * std::max(l, m), sc);
+  const int64_t cnt = F * p;
+  RT_ALLOC(zc, double, cnt, sc);
+  RT_ALLOC(cc, double, cnt, sc);
+  RT_ALLOC(cprev, double, cnt, sc);
+  RT_ALLOC(phibar, double, cnt, sc);
+  RT_ALLOC(rho_h, double, cnt * kmax, sc);
+  RT_ALLOC(s_h, double, cnt * kmax, sc);
+  RT_ALLOC(phi_h, double, cnt * kmax, sc);
+  RT_ALLOC(alpha_h, double, cnt * kmax, sc);
+  RT_ALLOC(bnd, double, p, sc);
+  RT_ALLOC(remaining, int, 1, sc);
+  RT_ALLOC(kin, int, p, sc);
+  RT_CHECK_HIP(hipMemcpyAsync(bnd, bounds.data(), sizeof(double) * p, hipMemcpyHostToDevice, s));
+  RT_CHECK_HIP(hipMemsetAsync(kin, 0, sizeof(int) * p, s));
+  const int pp = (int)p;
+  RT_CHECK_HIP(hipMemcpyAsync(remaining, &pp, sizeof(int), hipMemcpyHostToDevice, s));
+  if (resid_out) RT_CHECK_HIP(hipMemsetAsync(resid_out, 0, sizeof(double) * p * kmax, s));
+  hipLaunchKernelGGL((k_gkb_init<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, Bh, (int)l, (int)p, Qb, ldq, zc,
+                     phibar, cprev, 0.0);
+  RT_LAUNCH_OK();
+  int* host_rem = pinned_counter();
+  if (!host_rem) return fail(RTSVD_E_NOMEM, "tgkb_solve: pinned host memory");
+  const int check_every = 2;
+  for (int i = 1; i <= kmax; ++i) {
+    // w = A-hat^H q_i - z_i w_{i-1}, re-orthogonalized, c_i = ||w||
+    RT_TRY(gkb_product<T>(true, Ah, l, m, p, Qb + (int64_t)(i - 1) * l, ldq, p * ldq, raw, p * m, F, s));
+    {
+      const size_t lds = 32 * sizeof(double) + (size_t)(kmax + 1) * sizeof(zd) + (size_t)m * sizeof(zd);
+      hipLaunchKernelGGL((k_gkb_orth<T>), dim3((unsigned)p, (unsigned)F), dim3(GKB_THREADS), lds, s, raw, p * m, Wb, ldw,
+                         (int)m, i - 1, (const zt*)(i >= 2 ? Wb : nullptr), ldw, i - 2, (const double*)zc, cc, (int)p, tol);
+      RT_LAUNCH_OK();
+    }
+    // q = A-hat w_i - c_i q_i, re-orthogonalized, z_{i+1} = ||q||
+    RT_TRY(gkb_product<T>(false, Ah, l, m, p, Wb + (int64_t)(i - 1) * m, ldw, p * ldw, raw, p * l, F, s));
+    {
+      const size_t lds = 32 * sizeof(double) + (size_t)(kmax + 1) * sizeof(zd) + (size_t)l * sizeof(zd);
+      hipLaunchKernelGGL((k_gkb_orth<T>), dim3((unsigned)p, (unsigned)F), dim3(GKB_THREADS), lds, s, raw, p * l, Qb, ldq,
+                         (int)l, i, (const zt*)Qb, ldq, i - 1, (const double*)cc, zc, (int)p, tol);
+      RT_LAUNCH_OK();
+    }
+    hipLaunchKernelGGL(k_gkb_givens, dim3(nblocks(cnt)), dim3(256), 0, s, cc, zc, cprev, phibar, rho_h, s_h, phi_h,
+                       alpha_h, kmax, i, (int)cnt);
+    RT_LAUNCH_OK();
+    hipLaunchKernelGGL(k_gkb_dp, dim3(nblocks(p, 64)), dim3(64), 0, s, phibar, (int)F, (int)p, (int)n, bnd, i, kmax, kin,
+                       resid_out, remaining);
+    RT_LAUNCH_OK();
+    if (i % check_every == 0 || i == kmax) {
+      RT_CHECK_HIP(hipMemcpyAsync(host_rem, remaining, sizeof(int), hipMemcpyDeviceToHost, s));
+      RT_CHECK_HIP(hipStreamSynchronize(s));
+      if (*host_rem <= 0) break;
+    }
+  }
+  // solution at each slice's k (k_max where the principle was not met)
+  RT_ALLOC(Xh, zt, F * m * p, sc);
+  hipLaunchKernelGGL((k_gkb_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), (size_t)kmax * sizeof(double), s,
+                     Wb, ldw, (int)m, kin, kmax, (int)p, rho_h, s_h, phi_h, alpha_h, Xh);
+  RT_LAUNCH_OK();
+  RT_TRY((launch_irfft<T, T>(Xh, m * p, m * p, (int)n, X, s)));
+  hipLaunchKernelGGL(k_gkb_finish, dim3(1), dim3(64), 0, s, kin, (int)p, kmax, k_out, status_out);
+  RT_LAUNCH_OK();
+  return 0;
+}
+
+extern "C" int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p, int dtype,
+                          const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, void* X, int32_t* k_out,
+                          double* resid_out, int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !X || !delta || !k_out) return fail(RTSVD_E_ARG, "tgkb_solve: null argument");
+  if (l < 1 || m < 1 || n < 1 || p < 1 || l < m) return fail(RTSVD_E_ARG, "tgkb_solve: need l >= m >= 1, n >= 1, p >= 1");
+  if (k_max < 1 || k_max > m) return fail(RTSVD_E_ARG, "tgkb_solve: need 1 <= k_max <= m");
+  if (n_delta != 1 && n_delta != p) return fail(RTSVD_E_ARG, "tgkb_solve: n_delta must be 1 or p");
+  if (!(eta_dp > 1.0)) return fail(RTSVD_E_ARG, "tgkb_solve: eta_dp must be > 1");
+  if (l > 8192) return fail(RTSVD_E_UNSUPPORTED, "tgkb_solve: l must be <= 8192");
+  std::vector<double> bounds(p);
+  for (int64_t c = 0; c < p; ++c) {
+    const double d = delta[n_delta == 1 ? 0 : c];
+    if (!(d >= 0.0)) return fail(RTSVD_E_ARG, "tgkb_solve: delta must be >= 0");
+    bounds[c] = eta_dp * d;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RTSVD_F64)
+    return tgkb_impl<double>((const double*)A, (const double*)B, l, m, n, p, bounds, k_max, (double*)X, k_out, resid_out,
+                             status_out, s);
+  if (dtype == RTSVD_F32)
+    return tgkb_impl<float>((const float*)A, (const float*)B, l, m, n, p, bounds, k_max, (float*)X, k_out, resid_out,
+                            status_out, s);
+  return fail(RTSVD_E_ARG, "tgkb_solve: bad dtype");
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -185,3 +185,49 @@ def test_ttsvd_fp32_256():
     torch.cuda.synchronize()
     assert int(res.k[0]) == orc["k"]
     assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-5
+
+
+# ---------------------------------------------------------------------------------------------
+# tGKB baseline
+# ---------------------------------------------------------------------------------------------
+def _gpu_tgkb(A, B, delta, eta, k_max, dtype):
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    X, k, resid, status = rt.tgkb_solve(_t(A, dtype), _t(B, dtype), delta, eta, k_max)
+    torch.cuda.synchronize()
+    return X, k, resid, status
+
+
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-10), ("float32", 1e-4)])
+def test_tgkb_blur_single_rhs(dtype, tol):
+    from oracle import tgkb as tg
+    A, X, B, Om, delta = blur_problem(64, 16, 2.0, 6, 1, 1e-2, 20, 0, seed=8)
+    orc = tg.tgkb_restore(wl.to_math(A), wl.to_math(B), delta, 1.01, 30)
+    Xg, k, resid, status = _gpu_tgkb(A, B, delta, 1.01, 30, dtype)
+    assert [int(v) for v in k.cpu()] == orc["k"]
+    assert _rel(_np(Xg), wl.to_storage(orc["X"])) <= tol
+    kk = orc["k"][0]
+    np.testing.assert_allclose(_np(resid)[0, :kk], orc["res"][:kk, 0], rtol=max(tol, 1e-9))
+
+
+def test_tgkb_multi_rhs_per_slice_ragged():
+    from oracle import tgkb as tg
+    A, X, B, Om, delta = blur_problem(40, 6, 2.0, 6, 5, 1e-2, 20, 0, seed=9, video=True)
+    Bm = wl.to_math(B)
+    deltas = [0.02 * np.linalg.norm(Bm[:, j]) for j in range(5)]
+    orc = tg.tgkb_restore(wl.to_math(A), wl.to_math(B), deltas, 1.05, 25)
+    Xg, k, resid, status = _gpu_tgkb(A, B, deltas, 1.05, 25, "float64")
+    assert [int(v) for v in k.cpu()] == orc["k"]
+    assert _rel(_np(Xg), wl.to_storage(orc["X"])) <= 1e-10
+
+
+def test_tgkb_dp_not_met_and_random():
+    from oracle import tgkb as tg
+    l, m, n, p = 33, 21, 5, 2
+    rng = np.random.default_rng(10)
+    A = rng.standard_normal((n, m, l))
+    B = rng.standard_normal((n, p, l))
+    orc = tg.tgkb_restore(wl.to_math(A), wl.to_math(B), 1e-12, 1.01, 6)
+    Xg, k, resid, status = _gpu_tgkb(A, B, 1e-12, 1.01, 6, "float64")
+    assert [int(v) for v in k.cpu()] == [6, 6] and int(status[0]) == 1
+    assert _rel(_np(Xg), wl.to_storage(orc["X"])) <= 1e-10
