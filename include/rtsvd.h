@@ -140,14 +140,28 @@ int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, in
                int dtype, const double* delta, int32_t n_delta, double eta_dp, int32_t k_max,
                void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
 
+/* Gradients of a loss L(X) through the truncated R-tSVD restoration at a fixed truncation index
+ * k (no discrepancy search), fixed Gaussian tensor omega and q = 0 power iterations; the factor is
+ * recomputed from A, not stored.  X = V_k * S_k^{-1} * U_k^T * B (Section 4.2).
+ *   gX   : DEVICE m x p x n, dL/dX.
+ *   gB   : DEVICE l x p x n out, dL/dB = P_k^T * gX (the adjoint t-product of Section 2).
+ *   dA   : DEVICE l x m x n or NULL, a direction dA/ds of the operator (e.g. d/dsigma of the blur);
+ *   gdot : DEVICE double[1] or NULL (together with dA): <gX, dX/ds>, the derivative of L along dA,
+ *          from the forward-mode derivative of the QR, projection and truncated pseudo-inverse
+ *          (Daleckii-Krein divided differences of lambda -> 1/lambda on the kept eigenvalues).
+ * Computed in the dtype (FP64 small matrices).  Errors: RTSVD_E_ARG, RTSVD_E_UNSUPPORTED (r > 256). */
+int rtsvd_solve_vjp(const void* A, const void* dA, const void* B, const void* omega, const void* gX,
+                    int64_t l, int64_t m, int64_t n, int64_t p, int32_t k, int32_t oversample, int dtype,
+                    void* gB, double* gdot, void* stream);
+
 /* Stage timers (for benchmarks and profiling).  While enabled, every tagged stage of every call
  * is bracketed by a pair of HIP events recorded on the call's stream; rtsvd_timer_read
  * synchronizes on the recorded events of one tag and returns the summed elapsed time and the
  * number of bracketed launches.  rtsvd_timer_enable(0 or 1) also clears the record.         */
 #define RTSVD_T_FFT_A 1      /* tube DFT of A (and ||A||_F partial sums)                     */
 #define RTSVD_T_FFT_OMEGA 2  /* tube DFT of the Gaussian tensor                              */
-#define RTSVD_T_SKETCH 3     /* Y = A-hat Omega-hat                                          */
-#define RTSVD_T_POWER 4      /* power iteration products A-hat^H Q and A-hat Q_z             */
+#define RTSVD_T_SKETCH 3     /* Y = A-hat Omega-hat and the power iteration's Y = A-hat Q_z   */
+#define RTSVD_T_POWER 4      /* the power iteration's Z = A-hat^H Q                           */
 #define RTSVD_T_PROJECT 5    /* C^H = A-hat^H Q                                              */
 #define RTSVD_T_W 6          /* W = A-hat V                                                  */
 #define RTSVD_T_GRAM 7       /* FP64 Gram matrices of CholeskyQR                             */

@@ -326,7 +326,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     {
       RT_TIMED(RTSVD_T_SKETCH);
       {
-        RT_TIMED(RTSVD_T_POWER);
+        RT_TIMED(RTSVD_T_SKETCH);
         if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
         else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
       }
@@ -340,7 +340,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
       }
       RT_TRY(orthonormalize<zw>(Omh, m, r, F, 1, G, Rinv, tmp, flags, sc, s));
       {
-        RT_TIMED(RTSVD_T_POWER);
+        RT_TIMED(RTSVD_T_SKETCH);
         if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
         else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
       }
@@ -768,6 +768,165 @@ extern "C" int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, in
     return tgkb_impl<float>((const float*)A, (const float*)B, l, m, n, p, bounds, k_max, (float*)X, k_out, resid_out,
                             status_out, s);
   return fail(RTSVD_E_ARG, "tgkb_solve: bad dtype");
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// gradients of the fixed-k truncated R-tSVD restoration (q = 0), factor recomputed
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+static int vjp_impl(const T* A, const T* dA, const T* B, const T* omega, const T* gX, int64_t l, int64_t m, int64_t n,
+                    int64_t p, int k, int64_t r, T* gB, double* gdot, hipStream_t s) {
+  typedef cplx<T> zt;
+  const int64_t F = n / 2 + 1;
+  Scratch sc(s);
+  RT_ALLOC(Ah, zt, F * l * m, sc);
+  RT_ALLOC(Omh, zt, F * m * r, sc);
+  RT_ALLOC(Bh, zt, F * l * p, sc);
+  RT_ALLOC(Gh, zt, F * m * p, sc);
+  RT_TRY((launch_rfft<T, T>(A, l * m, (int)n, Ah, l * m, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  RT_TRY((launch_rfft<T, T>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  RT_TRY((launch_rfft<T, T>(B, l * p, (int)n, Bh, l * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  RT_TRY((launch_rfft<T, T>(gX, m * p, (int)n, Gh, m * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  // recomputed factor: Y = A-hat Omega-hat, R^{-1} of Y, Q = CholeskyQR2(Y), C^H = A-hat^H Q, eig(C C^H)
+  RT_ALLOC(Y, zt, F * l * r, sc);
+  RT_ALLOC(Q, zt, F * l * r, sc);
+  RT_ALLOC(tmp, zt, F * l * r, sc);
+  RT_ALLOC(G, zd, F * r * r, sc);
+  RT_ALLOC(Ry, zd, F * r * r, sc);
+  RT_ALLOC(Rq, zd, F * r * r, sc);
+  RT_ALLOC(flags, int, 1, sc);
+  RT_TRY((big_gemm<zt, zt, zt, T>(false, Ah, l, m, Omh, r, Y, F, s)));
+  {
+    const int ks = gram_splits(l, r, F);
+    zd* part = sc.get<zd>(F * ks * r * r);
+    if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
+    RT_TRY(gram_fp64<zt>(Y, l, (int)r, l * r, (int)F, part, ks, G, s));
+    RT_TRY(launch_cholinv(G, (int)r, F, Ry, flags, sc, s));
+  }
+  RT_CHECK_HIP(hipMemcpyAsync(Q, Y, sizeof(zt) * F * l * r, hipMemcpyDeviceToDevice, s));
+  RT_TRY(orthonormalize<zt>(Q, l, r, F, 2, G, Rq, tmp, flags, sc, s));
+  RT_ALLOC(Ch, zd, F * m * r, sc);
+  RT_TRY((big_gemm<zt, zt, zd, T>(true, Ah, l, m, Q, r, Ch, F, s)));
+  RT_ALLOC(U, zd, F * r * r, sc);
+  RT_ALLOC(lam, double, F * r, sc);
+  {
+    const int ks = gram_splits(m, r, F);
+    zd* part = sc.get<zd>(F * ks * r * r);
+    if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
+    RT_TRY(gram_fp64<zd>(Ch, m, (int)r, m * r, (int)F, part, ks, G, s));
+  }
+  RT_TRY(launch_heev(G, (int)r, F, U, lam, sc, s));
+  // G_k^+ = U diag(phi) U^H
+  RT_ALLOC(Uphi, zd, F * r * r, sc);
+  RT_ALLOC(Gk, zd, F * r * r, sc);
+  hipLaunchKernelGGL(k_scale_inv_eigs, dim3(nblocks(F * r * r)), dim3(256), 0, s, U, Uphi, lam, (int)r, k, (int)F);
+  RT_LAUNCH_OK();
+  RT_TRY((cgemm<zd, zd, zd, double>(false, true, (int)r, (int)r, (int)r, Uphi, r, r * r, U, r, r * r, Gk, r, r * r,
+                                   (int)F, 1.0, false, s)));
+  // dL/dB = Q G_k^+ C G  (face by face), then the inverse DFT
+  RT_ALLOC(t1, zd, F * r * p, sc);
+  RT_ALLOC(t2, zd, F * r * p, sc);
+  RT_ALLOC(gBh, zt, F * l * p, sc);
+  RT_TRY((cgemm<zd, zt, zd, double>(true, false, (int)r, (int)p, (int)m, Ch, m, m * r, Gh, m, m * p, t1, r, r * p,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, t1, r, r * p, t2, r, r * p,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zt, zd, zt, double>(false, false, (int)l, (int)p, (int)r, Q, l, l * r, t2, r, r * p, gBh, l, l * p,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((launch_irfft<T, T>(gBh, l * p, l * p, (int)n, gB, s)));
+  if (!dA || !gdot) return 0;
+  // forward-mode derivative along dA
+  RT_ALLOC(dAh, zt, F * l * m, sc);
+  RT_TRY((launch_rfft<T, T>(dA, l * m, (int)n, dAh, l * m, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  RT_ALLOC(dY, zd, F * l * r, sc);
+  RT_TRY((cgemm<zt, zt, zd, double>(false, false, (int)l, (int)r, (int)m, dAh, l, l * m, Omh, m, m * r, dY, l, l * r,
+                                   (int)F, 1.0, false, s)));
+  RT_ALLOC(T1, zd, F * r * r, sc);   // Q^H dY
+  RT_ALLOC(Mq, zd, F * r * r, sc);
+  RT_ALLOC(Xq, zd, F * r * r, sc);
+  RT_TRY((cgemm<zt, zd, zd, double>(true, false, (int)r, (int)r, (int)l, Q, l, l * r, dY, l, l * r, T1, r, r * r,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)r, (int)r, T1, r, r * r, Ry, r, r * r, Mq, r, r * r,
+                                   (int)F, 1.0, false, s)));
+  hipLaunchKernelGGL(k_skew_lower, dim3(nblocks(F * r * r)), dim3(256), 0, s, Mq, Xq, (int)r, (int)F);
+  RT_LAUNCH_OK();
+  // P = dY - Q T1 (in place in dY), dQ = Q Xq + P R^{-1}
+  RT_TRY((cgemm<zt, zd, zd, double>(false, false, (int)l, (int)r, (int)r, Q, l, l * r, T1, r, r * r, dY, l, l * r,
+                                   (int)F, -1.0, true, s)));
+  RT_ALLOC(dQ, zd, F * l * r, sc);
+  RT_TRY((cgemm<zt, zd, zd, double>(false, false, (int)l, (int)r, (int)r, Q, l, l * r, Xq, r, r * r, dQ, l, l * r,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)l, (int)r, (int)r, dY, l, l * r, Ry, r, r * r, dQ, l, l * r,
+                                   (int)F, 1.0, true, s)));
+  // dC^H = A-hat^H dQ + dA-hat^H Q
+  RT_ALLOC(dCh, zd, F * m * r, sc);
+  RT_TRY((cgemm<zt, zd, zd, double>(true, false, (int)m, (int)r, (int)l, Ah, l, l * m, dQ, l, l * r, dCh, m, m * r,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zt, zt, zd, double>(true, false, (int)m, (int)r, (int)l, dAh, l, l * m, Q, l, l * r, dCh, m, m * r,
+                                   (int)F, 1.0, true, s)));
+  // dG = dC C^H + C dC^H  = (dC^H)^H C^H + (C^H)^H dC^H
+  RT_ALLOC(dG, zd, F * r * r, sc);
+  RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)m, dCh, m, m * r, Ch, m, m * r, dG, r, r * r,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)m, Ch, m, m * r, dCh, m, m * r, dG, r, r * r,
+                                   (int)F, 1.0, true, s)));
+  // d(G_k^+) = U (Phi o (U^H dG U)) U^H
+  RT_ALLOC(E1, zd, F * r * r, sc);
+  RT_ALLOC(E2, zd, F * r * r, sc);
+  RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)r, U, r, r * r, dG, r, r * r, E1, r, r * r,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)r, (int)r, E1, r, r * r, U, r, r * r, E2, r, r * r,
+                                   (int)F, 1.0, false, s)));
+  hipLaunchKernelGGL(k_phi_hadamard, dim3(nblocks(F * r * r)), dim3(256), 0, s, E2, lam, (int)r, k, (int)F);
+  RT_LAUNCH_OK();
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)r, (int)r, U, r, r * r, E2, r, r * r, E1, r, r * r,
+                                   (int)F, 1.0, false, s)));
+  RT_ALLOC(dGk, zd, F * r * r, sc);
+  RT_TRY((cgemm<zd, zd, zd, double>(false, true, (int)r, (int)r, (int)r, E1, r, r * r, U, r, r * r, dGk, r, r * r,
+                                   (int)F, 1.0, false, s)));
+  // d = Q^H B-hat, dd = dQ^H B-hat, dX-hat = dC^H G_k^+ d + C^H dG_k^+ d + C^H G_k^+ dd
+  RT_ALLOC(d, zd, F * r * p, sc);
+  RT_ALLOC(dd, zd, F * r * p, sc);
+  RT_ALLOC(e, zd, F * r * p, sc);
+  RT_TRY((cgemm<zt, zt, zd, double>(true, false, (int)r, (int)p, (int)l, Q, l, l * r, Bh, l, l * p, d, r, r * p,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zt, zd, double>(true, false, (int)r, (int)p, (int)l, dQ, l, l * r, Bh, l, l * p, dd, r, r * p,
+                                   (int)F, 1.0, false, s)));
+  RT_ALLOC(dXh, zd, F * m * p, sc);
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, d, r, r * p, e, r, r * p,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)p, (int)r, dCh, m, m * r, e, r, r * p, dXh, m, m * p,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)p, (int)r, dGk, r, r * r, d, r, r * p, e, r, r * p,
+                                   (int)F, 1.0, false, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, dd, r, r * p, e, r, r * p,
+                                   (int)F, 1.0, true, s)));
+  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)p, (int)r, Ch, m, m * r, e, r, r * p, dXh, m, m * p,
+                                   (int)F, 1.0, true, s)));
+  hipLaunchKernelGGL((k_weighted_inner<zt>), dim3(1), dim3(256), 0, s, Gh, dXh, m * p, (int)F, (int)n, gdot);
+  RT_LAUNCH_OK();
+  return 0;
+}
+
+extern "C" int rtsvd_solve_vjp(const void* A, const void* dA, const void* B, const void* omega, const void* gX,
+                               int64_t l, int64_t m, int64_t n, int64_t p, int32_t k, int32_t oversample, int dtype,
+                               void* gB, double* gdot, void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !omega || !gX || !gB) return fail(RTSVD_E_ARG, "rtsvd_solve_vjp: null argument");
+  if (l < 1 || m < 1 || n < 1 || p < 1 || l < m) return fail(RTSVD_E_ARG, "rtsvd_solve_vjp: need l >= m >= 1, n, p >= 1");
+  if (k < 1 || k > m || oversample < 0) return fail(RTSVD_E_ARG, "rtsvd_solve_vjp: need 1 <= k <= m, oversample >= 0");
+  const int64_t r = std::min<int64_t>((int64_t)k + oversample, m);
+  if (r > 256) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_solve_vjp: r must be <= 256");
+  if ((dA == nullptr) != (gdot == nullptr)) return fail(RTSVD_E_ARG, "rtsvd_solve_vjp: dA and gdot go together");
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RTSVD_F64)
+    return vjp_impl<double>((const double*)A, (const double*)dA, (const double*)B, (const double*)omega,
+                            (const double*)gX, l, m, n, p, k, r, (double*)gB, gdot, s);
+  if (dtype == RTSVD_F32)
+    return vjp_impl<float>((const float*)A, (const float*)dA, (const float*)B, (const float*)omega, (const float*)gX, l,
+                           m, n, p, k, r, (float*)gB, gdot, s);
+  return fail(RTSVD_E_ARG, "rtsvd_solve_vjp: bad dtype");
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -170,4 +170,68 @@ __global__ void k_sqrt_eigs(const double* __restrict__ lam, double* __restrict__
   sigma[idx] = (l > tol_rel * lmax && l > 0.0) ? sqrt(l) : 0.0;
 }
 
+// Xq = tril(M, -1) - tril(M, -1)^H + i Im diag(M)   (r x r per face)
+__global__ void k_skew_lower(const zd* __restrict__ M, zd* __restrict__ Xq, int r, int F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)F * r * r) return;
+  const int i = (int)(idx % r), j = (int)((idx / r) % r);
+  const int64_t base = idx - i - (int64_t)j * r;
+  zd v;
+  if (i > j) v = M[idx];
+  else if (i < j) v = cscale(cconj(M[base + j + (int64_t)i * r]), -1.0);
+  else v = mk(0.0, M[idx].im);
+  Xq[idx] = v;
+}
+
+// E <- Phi o E with Phi_jl = -1/(l_j l_l) (j,l < k), 1/(l_j (l_j - l_l)) (j < k <= l),
+// 1/(l_l (l_l - l_j)) (l < k <= j), 0 otherwise; lam descending per face
+__global__ void k_phi_hadamard(zd* __restrict__ E, const double* __restrict__ lam, int r, int k, int F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)F * r * r) return;
+  const int j = (int)(idx % r), l = (int)((idx / r) % r);
+  const int64_t f = idx / ((int64_t)r * r);
+  const double lj = lam[f * r + j], ll = lam[f * r + l];
+  double ph = 0.0;
+  if (j < k && l < k) ph = -1.0 / (lj * ll);
+  else if (j < k && l >= k) ph = 1.0 / (lj * (lj - ll));
+  else if (l < k && j >= k) ph = 1.0 / (ll * (ll - lj));
+  E[idx] = cscale(E[idx], ph);
+}
+
+// Uphi = U diag(phi), phi_j = 1/lam_j for j < k, else 0
+__global__ void k_scale_inv_eigs(const zd* __restrict__ U, zd* __restrict__ Uphi, const double* __restrict__ lam, int r,
+                                 int k, int F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)F * r * r) return;
+  const int j = (int)((idx / r) % r);
+  const int64_t f = idx / ((int64_t)r * r);
+  const double lj = lam[f * r + j];
+  Uphi[idx] = (j < k && lj > 0.0) ? cscale(U[idx], 1.0 / lj) : mk(0.0, 0.0);
+}
+
+// out[0] = (1/n) sum_f w_f sum Re(conj(G) dX)  (one block, fixed summation order per thread)
+template <typename TG>
+__global__ void k_weighted_inner(const TG* __restrict__ G, const zd* __restrict__ D, int64_t per_face, int F, int n,
+                                 double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int f = 0; f < F; ++f) {
+    const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
+    double t = 0.0;
+    for (int64_t i = threadIdx.x; i < per_face; i += blockDim.x) {
+      const zd g = ld<double>(G[(int64_t)f * per_face + i]);
+      const zd d = D[(int64_t)f * per_face + i];
+      t += g.re * d.re + g.im * d.im;
+    }
+    s += w * t;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] / (double)n;
+}
+
 }  // namespace rt

@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
            "tprod", "tprod_adjoint", "tgkb_solve", "rtsvd_status_string", "rtsvd_last_error",
-           "rtsvd_timer_enable", "rtsvd_timer_read"]
+           "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp"]
 
 
 class RtsvdError(RuntimeError):
@@ -66,6 +66,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rtsvd_status_string.restype = ctypes.c_char_p
     lib.rtsvd_status_string.argtypes = [ctypes.c_int]
     lib.rtsvd_last_error.restype = ctypes.c_char_p
+    lib.rtsvd_solve_vjp.argtypes = [vp, vp, vp, vp, vp, i64, i64, i64, i64, i32, i32, ctypes.c_int, vp, vp, vp]
     lib.rtsvd_timer_enable.argtypes = [ctypes.c_int]
     lib.rtsvd_timer_read.argtypes = [ctypes.c_int, pdbl, pi32]
     _lib = lib
@@ -244,3 +245,22 @@ def tgkb_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int):
     _check(lib.tgkb_solve(A.data_ptr(), B.data_ptr(), l, m, n, p, _dtype_code(A), arr, len(deltas), eta, k_max,
                           X.data_ptr(), k.data_ptr(), resid.data_ptr(), status.data_ptr(), _stream()), "tgkb_solve")
     return X, k, resid, status
+
+
+def solve_vjp(A: torch.Tensor, dA, B: torch.Tensor, omega: torch.Tensor, gX: torch.Tensor, k: int, oversample: int):
+    """(dL/dB, <dL/dX, dX/ds> or None) of the fixed-k truncated R-tSVD restoration (factor recomputed)."""
+    lib = load()
+    A, B, omega, gX = _dev(A, "A"), _dev(B, "B"), _dev(omega, "omega"), _dev(gX, "gX")
+    n, m, l = A.shape
+    _, p, _ = B.shape
+    gB = torch.empty_like(B)
+    gdot = None
+    dptr = None
+    if dA is not None:
+        dA = _dev(dA, "dA")
+        gdot = torch.zeros(1, dtype=torch.float64, device=A.device)
+        dptr = dA.data_ptr()
+    _check(lib.rtsvd_solve_vjp(A.data_ptr(), dptr, B.data_ptr(), omega.data_ptr(), gX.data_ptr(), l, m, n, p, k,
+                               oversample, _dtype_code(A), gB.data_ptr(), gdot.data_ptr() if gdot is not None else None,
+                               _stream()), "rtsvd_solve_vjp")
+    return gB, gdot

@@ -231,3 +231,54 @@ def test_tgkb_dp_not_met_and_random():
     Xg, k, resid, status = _gpu_tgkb(A, B, 1e-12, 1.01, 6, "float64")
     assert [int(v) for v in k.cpu()] == [6, 6] and int(status[0]) == 1
     assert _rel(_np(Xg), wl.to_storage(orc["X"])) <= 1e-10
+
+
+# ---------------------------------------------------------------------------------------------
+# differentiable restoration: hand-written adjoint vs the FP64 oracle gradient and finite differences
+# ---------------------------------------------------------------------------------------------
+def _grad_problem(size, n, sigma, band, p, k, rho, seed):
+    A = wl.blur_operator(size, n, sigma, band)
+    dA = wl.blur_operator_dsigma(size, n, sigma, band)
+    rng = np.random.default_rng(seed)
+    Xt = wl.lateral_slices(wl.moving_blob_video(size, n, p, rng))
+    B = wl.to_storage(tp.tprod(wl.to_math(A), wl.to_math(Xt)) + 1e-2 * rng.standard_normal((size, p, n)))
+    Om = rng.standard_normal((n, k + rho, size))
+    return A, dA, B, Om, Xt
+
+
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-8), ("float32", 2e-3)])
+def test_vjp_matches_oracle_gradient(dtype, tol):
+    import torch
+    from oracle import adjoint as ad
+    from paper_2110_02485_amd import autograd as ag
+    size, n, sigma, band, p, k, rho = 48, 8, 3.0, 10, 3, 12, 6
+    A, dA, B, Om, Xt = _grad_problem(size, n, sigma, band, p, k, rho, 21)
+    loss, gb, gs = ad.grads(wl.to_math(A), wl.to_math(dA), wl.to_math(B), wl.to_math(Om), k, wl.to_math(Xt))
+    Bt = _t(B, dtype).requires_grad_(True)
+    s = torch.tensor(sigma, dtype=getattr(torch, dtype), device="cuda", requires_grad=True)
+    X = ag.restore(Bt, s, _t(A, dtype), _t(dA, dtype), _t(Om, dtype), k, rho)
+    L = 0.5 * ((X - _t(Xt, dtype)) ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    assert abs(float(L) - loss) <= tol * loss
+    assert _rel(_np(Bt.grad), wl.to_storage(gb)) <= tol
+    assert abs(float(s.grad) - gs) <= tol * abs(gs) + 1e-12
+
+
+def test_vjp_sigma_vs_central_difference_gpu():
+    # h = 1e-3 central difference of the GPU forward itself (FP64)
+    import torch
+    from paper_2110_02485_amd import autograd as ag
+    size, n, sigma, band, p, k, rho = 64, 8, 3.0, 10, 2, 16, 8
+    A, dA, B, Om, Xt = _grad_problem(size, n, sigma, band, p, k, rho, 22)
+    s = torch.tensor(sigma, dtype=torch.float64, device="cuda", requires_grad=True)
+    X = ag.restore(_t(B), s, _t(A), _t(dA), _t(Om), k, rho)
+    L = 0.5 * ((X - _t(Xt)) ** 2).sum()
+    L.backward()
+    def Lval(sg):
+        As = wl.blur_operator(size, n, sg, band)
+        Xs = ag.restore(_t(B), torch.tensor(sg, device="cuda"), _t(As), None, _t(Om), k, rho)
+        return float(0.5 * ((Xs - _t(Xt)) ** 2).sum())
+    h = 1e-3
+    fd = (Lval(sigma + h) - Lval(sigma - h)) / (2 * h)
+    assert abs(fd - float(s.grad)) <= 1e-4 * abs(fd) + 1e-10
