@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM counters against known bytes)")
     return ap.parse_args()
 
 
@@ -204,6 +206,15 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": src.numel() * 4,
+                          "bytes_written_per_copy": src.numel() * 4, "copies": 3}))
+        return
     from paper_2110_02485_amd import rtsvd as rt
     from paper_2110_02485_amd import workloads as wl
     rt.load()

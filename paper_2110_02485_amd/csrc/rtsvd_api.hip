@@ -325,11 +325,8 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     // sketch Y = A-hat Omega-hat, then Q = orth(Y) (q power iterations in between)
     {
       RT_TIMED(RTSVD_T_SKETCH);
-      {
-        RT_TIMED(RTSVD_T_SKETCH);
-        if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
-        else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
-      }
+      if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
+      else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
     }
     RT_TRY(orthonormalize<zw>(Y, l, r, F, q == 0 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
     for (int it = 0; it < q; ++it) {
