@@ -96,7 +96,19 @@ int ttsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype, int3
 int rtsvd_factor_info(rtsvd_handle f, int32_t* r, int32_t* faces, double* eta, int32_t* r_eps,
                       double* sigma, int32_t* flags);
 
+/* Returns the handle's device buffers to the library's workspace cache, where they are reused by
+ * later calls on the handle's stream.  Call it once the last rtsvd_solve that reads the handle
+ * has been issued on that stream (or has completed, if it ran on another stream).  NULL is a
+ * no-op.                                                                                       */
 void rtsvd_factor_destroy(rtsvd_handle f);
+
+/* Device workspace.  Every call takes its scratch buffers (and a factor its outputs) from a cache
+ * of device allocations kept per (device, stream): a buffer released on a stream is handed out
+ * again only to work on that stream, so reuse is ordered by the stream itself.  The cache grows
+ * to the largest working set seen and is kept until rtsvd_trim, which synchronizes every device
+ * holding cached buffers and frees them (buffers of live handles are untouched).
+ * Errors: RTSVD_E_HIP.                                                                          */
+int rtsvd_trim(void);
 
 /* Truncated R-tSVD / T-tSVD solution with the discrepancy principle (eq. (disp), eq. (kinit)):
  *   X_k = V_k * S_k^{-1} * U_k^T * B,  U_k = Q * U-tilde(:, 1:k, :)   (Section 4.2)

@@ -5,7 +5,7 @@
 // B and C are any of zd / zf / zb (double, float, bf16 complex); products accumulate in Acc.
 // Every face f uses A + f*strideA etc.  Generic LDS-tiled kernel for the small and medium
 // products of the path (Gram matrices, triangular factors, solve-side products); the big
-// passes over A-hat use the MFMA kernels in mfma_gemm.hpp.
+// passes over A-hat use the MFMA kernels in skinny.hpp.
 #pragma once
 #include "common.hpp"
 

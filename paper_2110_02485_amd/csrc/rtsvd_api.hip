@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -12,7 +13,7 @@
 #include "common.hpp"
 #include "fft.hpp"
 #include "gemm.hpp"
-#include "mfma_gemm.hpp"
+#include "skinny.hpp"
 #include "heev.hpp"
 #include "solve.hpp"
 #include "tgkb.hpp"
@@ -47,34 +48,80 @@ static int fail(int code, const char* msg) {
 #define RT_LAUNCH_OK() RT_CHECK_HIP(hipGetLastError())
 
 // ---------------------------------------------------------------------------------------------
-// stream-ordered scratch from the device's default memory pool (kept allocated between calls)
+// Device workspace cache.  Buffers are allocated once (stream-ordered) and then kept: a released
+// buffer goes back to a free list of the stream it was used on and is handed out again only to
+// work on that same stream, so stream order alone makes the reuse safe.  Freeing large buffers
+// every call would otherwise cost milliseconds of host time per call and stall the pipeline.
+// rtsvd_trim() returns all cached memory to the device.
 // ---------------------------------------------------------------------------------------------
-static void ensure_pool_keeps_memory() {
-  static std::once_flag once[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-  std::call_once(once[dev], [dev]() {
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t thr = UINT64_MAX;
-      hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-  });
-}
+struct WorkspaceCache {
+  struct Live { int dev; hipStream_t s; size_t bytes; };
+  std::mutex mu;
+  std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void*>> free_;
+  std::map<void*, Live> live_;
 
+  void* acquire(size_t bytes, hipStream_t s) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto& fl = free_[{dev, s}];
+      auto it = fl.lower_bound(bytes);
+      // best fit, without handing a much larger block to a small request
+      if (it != fl.end() && it->first <= bytes + bytes / 4 + 4096) {
+        void* p = it->second;
+        live_[p] = Live{dev, s, it->first};
+        fl.erase(it);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    live_[p] = Live{dev, s, bytes};
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    free_[{it->second.dev, it->second.s}].emplace(it->second.bytes, p);
+    live_.erase(it);
+  }
+  int trim() {
+    std::lock_guard<std::mutex> lk(mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return -1;
+    for (auto& kv : free_) {
+      if (kv.second.empty()) continue;
+      if (hipSetDevice(kv.first.first) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return -1;
+      for (auto& b : kv.second) (void)hipFree(b.second);
+      kv.second.clear();
+    }
+    return hipSetDevice(cur) == hipSuccess ? 0 : -1;
+  }
+};
+static WorkspaceCache g_cache;
+
+// per-call scratch: every buffer goes back to the cache when the call's launches are queued
 struct Scratch {
   hipStream_t s;
   std::vector<void*> ptrs;
-  explicit Scratch(hipStream_t st) : s(st) { ensure_pool_keeps_memory(); }
-  ~Scratch() { for (void* p : ptrs) (void)hipFreeAsync(p, s); }
+  explicit Scratch(hipStream_t st) : s(st) {}
+  ~Scratch() { for (void* p : ptrs) g_cache.release(p); }
   template <typename T> T* get(int64_t count) {
     if (count <= 0) count = 1;
-    void* p = nullptr;
-    if (hipMallocAsync(&p, (size_t)count * sizeof(T), s) != hipSuccess || !p) return nullptr;
+    void* p = g_cache.acquire((size_t)count * sizeof(T), s);
+    if (!p) return nullptr;
     ptrs.push_back(p);
     return static_cast<T*>(p);
   }
-  template <typename T> T* release(T* p) {  // ownership passes to the caller
+  template <typename T> T* release(T* p) {  // ownership passes to the caller (returned with g_cache.release)
     ptrs.erase(std::remove(ptrs.begin(), ptrs.end(), (void*)p), ptrs.end());
     return p;
   }
@@ -85,6 +132,26 @@ struct Scratch {
   if (!var) return fail(RTSVD_E_NOMEM, "device allocation failed: " #var)
 
 static inline unsigned nblocks(int64_t total, int threads = 256) { return (unsigned)ceil_div(total, threads); }
+
+// Small host arrays reach the device as kernel arguments (16 values per launch): stream-ordered,
+// no staging copy from pageable memory (which would block the host until the stream drains).
+struct Vals16 { double v[16]; };
+__global__ void k_set_doubles(double* __restrict__ dst, Vals16 vals, int count) {
+  if ((int)threadIdx.x < count) dst[threadIdx.x] = vals.v[threadIdx.x];
+}
+__global__ void k_set_int(int* __restrict__ dst, int value) {
+  if (threadIdx.x == 0) dst[0] = value;
+}
+static int upload_doubles(double* dst, const double* src, int64_t count, hipStream_t s) {
+  for (int64_t off = 0; off < count; off += 16) {
+    Vals16 v = {};
+    const int c = (int)std::min<int64_t>(16, count - off);
+    for (int i = 0; i < c; ++i) v.v[i] = src[off + i];
+    hipLaunchKernelGGL(k_set_doubles, dim3(1), dim3(64), 0, s, dst + off, v, c);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  return 0;
+}
 
 template <typename TI, typename TO>
 __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t count) {
@@ -225,50 +292,62 @@ static int launch_cholinv(const zd* G, int r, int64_t F, zd* Rinv, int* flags, S
   return 0;
 }
 
-// number of K splits of a Gram product so that the grid has about 1000 blocks
+// number of K splits of an FP64 Gram product so that the grid has about 1000 blocks
 static int gram_splits(int64_t rows, int64_t r, int64_t F) {
-  const int64_t t = ceil_div(r, 64);
-  const int64_t tiles = F * t * (t + 1) / 2;
+  const int64_t tiles = F * ceil_div(r, 64) * ceil_div(r, 128);
   int64_t ks = ceil_div(1024, std::max<int64_t>(tiles, 1));
   ks = std::min<int64_t>(ks, std::max<int64_t>(1, rows / 64));
   return (int)std::max<int64_t>(1, std::min<int64_t>(ks, 16));
 }
 
+// FP64 Gram of Y (F x rows x r) into G (F x r x r), partials from the stream pool
+template <typename TY>
+static int gram(const TY* Y, int64_t rows, int64_t r, int64_t F, zd* G, Scratch& sc, hipStream_t s) {
+  const int ks = gram_splits(rows, r, F);
+  zd* part = sc.get<zd>(F * ks * r * r);
+  if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
+  return sk::gram_fp64<TY>(Y, rows, (int)r, rows * r, (int)F, part, ks, G, s);
+}
+
+// C_f = op(A_f) X_f on MFMA, X packed into pool scratch first
+template <typename TA, typename TX, typename TC>
+static int skinny(bool conjA, int64_t M, int64_t N, int64_t K, const TA* A, int64_t lda, int64_t sA, const TX* X,
+                  int64_t ldx, int64_t sX, TC* C, int64_t ldc, int64_t sC, int64_t F, Scratch& sc, hipStream_t s) {
+  unsigned char* ws = sc.get<unsigned char>(sk::skinny_ws_bytes<TA>((int)K, (int)N, (int)F));
+  if (!ws) return fail(RTSVD_E_NOMEM, "device allocation failed: packed operand");
+  return sk::skinny_cgemm<TA, TX, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, X, ldx, sX, C, ldc, sC, (int)F, ws, s);
+}
+
 // ---------------------------------------------------------------------------------------------
 // CholeskyQR: Y (F x rows x r) <- Y R^{-1} with R^H R = Y^H Y (FP64 Gram + Cholesky), `passes`
-// times (2 = CholeskyQR2, orthonormal to working precision).
+// times (2 = CholeskyQR2, orthonormal to working precision).  The product is written to `tmp` and
+// the two buffers are exchanged, so Y names the result on return.
 // ---------------------------------------------------------------------------------------------
 template <typename TY>
-static int orthonormalize(TY* Y, int64_t rows, int64_t r, int64_t F, int passes, zd* G, zd* Rinv, TY* tmp,
+static int orthonormalize(TY*& Y, int64_t rows, int64_t r, int64_t F, int passes, zd* G, zd* Rinv, TY*& tmp,
                           int* flags, Scratch& sc, hipStream_t s) {
-  const int ksplit = gram_splits(rows, r, F);
-  zd* part = sc.get<zd>(F * ksplit * r * r);
-  if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
   for (int pass = 0; pass < passes; ++pass) {
     {
       RT_TIMED(RTSVD_T_GRAM);
-      RT_TRY(gram_fp64<TY>(Y, rows, (int)r, rows * r, (int)F, part, ksplit, G, s));
+      RT_TRY(gram<TY>(Y, rows, r, F, G, sc, s));
     }
     {
       RT_TIMED(RTSVD_T_CHOL);
       RT_TRY(launch_cholinv(G, (int)r, F, Rinv, flags, sc, s));
     }
     RT_TIMED(RTSVD_T_QMUL);
-    RT_CHECK_HIP(hipMemcpyAsync(tmp, Y, sizeof(TY) * F * rows * r, hipMemcpyDeviceToDevice, s));
-    RT_TRY((small_k_cgemm<TY, zd, TY>((int)rows, (int)r, (int)r, tmp, rows, rows * r, Rinv, r, r * r, Y, rows,
-                                      rows * r, (int)F, s)));
+    RT_TRY((skinny<TY, zd, TY>(false, rows, r, r, Y, rows, rows * r, Rinv, r, r * r, tmp, rows, rows * r, F, sc, s)));
+    std::swap(Y, tmp);
   }
   return 0;
 }
 
 // products over A-hat: Y = A-hat X (conjA = false, Y is l x r) or Y = A-hat^H X (Y is m x r)
-template <typename TA, typename TX, typename TY, typename Acc>
+template <typename TA, typename TX, typename TY>
 static int big_gemm(bool conjA, const TA* Ah, int64_t l, int64_t m, const TX* X, int64_t r, TY* Y, int64_t F,
-                    hipStream_t s) {
-  if (!conjA)
-    return big_cgemm<TA, TX, TY, Acc>(false, (int)l, (int)r, (int)m, Ah, l, l * m, X, m, m * r, Y, l, l * r,
-                                      (int)F, s);
-  return big_cgemm<TA, TX, TY, Acc>(true, (int)m, (int)r, (int)l, Ah, l, l * m, X, l, l * r, Y, m, m * r, (int)F, s);
+                    Scratch& sc, hipStream_t s) {
+  if (!conjA) return skinny<TA, TX, TY>(false, l, r, m, Ah, l, l * m, X, m, m * r, Y, l, l * r, F, sc, s);
+  return skinny<TA, TX, TY>(true, m, r, l, Ah, l, l * m, X, l, l * r, Y, m, m * r, F, sc, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -296,7 +375,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
   }
 
   // outputs owned by the handle
-  RT_ALLOC(Qo, zw, F * l * r, sc);
+  zw* Qo = nullptr;  // Q (R-tSVD) or U (T-tSVD), l x r per face
   RT_ALLOC(sigma, double, F * r, sc);
   RT_ALLOC(V, zd, F * m * r, sc);
   RT_ALLOC(Wo, zw, F * l * r, sc);
@@ -325,30 +404,30 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     // sketch Y = A-hat Omega-hat, then Q = orth(Y) (q power iterations in between)
     {
       RT_TIMED(RTSVD_T_SKETCH);
-      if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
-      else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
+      if (bf16) RT_TRY((big_gemm<zb, zw, zw>(false, Ah16, l, m, Omh, r, Y, F, sc, s)));
+      else RT_TRY((big_gemm<zw, zw, zw>(false, Ah, l, m, Omh, r, Y, F, sc, s)));
     }
     RT_TRY(orthonormalize<zw>(Y, l, r, F, q == 0 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
     for (int it = 0; it < q; ++it) {
       {
         RT_TIMED(RTSVD_T_POWER);
-        if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(true, Ah16, l, m, Y, r, Omh, F, s)));
-        else RT_TRY((big_gemm<zw, zw, zw, Tw>(true, Ah, l, m, Y, r, Omh, F, s)));
+        if (bf16) RT_TRY((big_gemm<zb, zw, zw>(true, Ah16, l, m, Y, r, Omh, F, sc, s)));
+        else RT_TRY((big_gemm<zw, zw, zw>(true, Ah, l, m, Y, r, Omh, F, sc, s)));
       }
       RT_TRY(orthonormalize<zw>(Omh, m, r, F, 1, G, Rinv, tmp, flags, sc, s));
       {
         RT_TIMED(RTSVD_T_SKETCH);
-        if (bf16) RT_TRY((big_gemm<zb, zw, zw, float>(false, Ah16, l, m, Omh, r, Y, F, s)));
-        else RT_TRY((big_gemm<zw, zw, zw, Tw>(false, Ah, l, m, Omh, r, Y, F, s)));
+        if (bf16) RT_TRY((big_gemm<zb, zw, zw>(false, Ah16, l, m, Omh, r, Y, F, sc, s)));
+        else RT_TRY((big_gemm<zw, zw, zw>(false, Ah, l, m, Omh, r, Y, F, sc, s)));
       }
       RT_TRY(orthonormalize<zw>(Y, l, r, F, it == q - 1 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
     }
-    RT_CHECK_HIP(hipMemcpyAsync(Qo, Y, sizeof(zw) * F * l * r, hipMemcpyDeviceToDevice, s));
+    Qo = Y;
     // projection C^H = A-hat^H Q
     {
       RT_TIMED(RTSVD_T_PROJECT);
-      if (bf16) RT_TRY((big_gemm<zb, zw, zd, float>(true, Ah16, l, m, Qo, r, Ch, F, s)));
-      else RT_TRY((big_gemm<zw, zw, zd, Tw>(true, Ah, l, m, Qo, r, Ch, F, s)));
+      if (bf16) RT_TRY((big_gemm<zb, zw, zd>(true, Ah16, l, m, Qo, r, Ch, F, sc, s)));
+      else RT_TRY((big_gemm<zw, zw, zd>(true, Ah, l, m, Qo, r, Ch, F, sc, s)));
     }
     {
       RT_TIMED(RTSVD_T_SVDAUX);
@@ -358,10 +437,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
       hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, rown, (int)F, (int)r, (int)n, eta);
       RT_LAUNCH_OK();
       // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
-      const int ks = gram_splits(m, r, F);
-      zd* part = sc.get<zd>(F * ks * r * r);
-      if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
-      RT_TRY(gram_fp64<zd>(Ch, m, (int)r, m * r, (int)F, part, ks, G, s));
+      RT_TRY(gram<zd>(Ch, m, r, F, G, sc, s));
     }
     {
       RT_TIMED(RTSVD_T_HEEV);
@@ -372,7 +448,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
       hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
       RT_LAUNCH_OK();
       // V = C^H U-breve diag(1/sigma)
-      RT_TRY((small_k_cgemm<zd, zd, zd>((int)m, (int)r, (int)r, Ch, m, m * r, Ub, r, r * r, V, m, m * r, (int)F, s)));
+      RT_TRY((skinny<zd, zd, zd>(false, m, r, r, Ch, m, m * r, Ub, r, r * r, V, m, m * r, F, sc, s)));
       hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * m * r)), dim3(256), 0, s, V, V, sigma, (int)m,
                          (int)r, (int)F);
       RT_LAUNCH_OK();
@@ -380,22 +456,19 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     // W = A-hat V: exact residuals of the discrepancy principle
     {
       RT_TIMED(RTSVD_T_W);
-      RT_TRY((big_gemm<zw, zd, zw, Tw>(false, Ah, l, m, V, r, Wo, F, s)));
+      RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, r, Wo, F, sc, s)));
     }
   } else {
     // full facewise SVD through G = A-hat^H A-hat = V diag(sigma^2) V^H; W = A-hat V; U = W diag(1/sigma)
-    {
-      const int ks = gram_splits(l, m, F);
-      zd* part = sc.get<zd>(F * ks * m * m);
-      if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
-      RT_TRY(gram_fp64<zw>(Ah, l, (int)m, l * m, (int)F, part, ks, G, s));
-    }
+    RT_TRY(gram<zw>(Ah, l, m, F, G, sc, s));
     RT_TRY(launch_heev(G, (int)m, F, V, lam, sc, s));
     hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
     RT_LAUNCH_OK();
     hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, lam, (int)F, (int)r, (int)n, eta);
     RT_LAUNCH_OK();
-    RT_TRY((big_gemm<zw, zd, zw, Tw>(false, Ah, l, m, V, r, Wo, F, s)));
+    RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, r, Wo, F, sc, s)));
+    RT_ALLOC(Uo, zw, F * l * r, sc);
+    Qo = Uo;
     hipLaunchKernelGGL((k_scale_cols<zw, zw>), dim3(nblocks(F * l * r)), dim3(256), 0, s, Wo, Qo, sigma, (int)l,
                        (int)r, (int)F);
     RT_LAUNCH_OK();
@@ -414,7 +487,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
 
 static void free_handle(rtsvd_factor_s* h) {
   if (!h) return;
-  for (void* p : h->owned) (void)hipFreeAsync(p, h->stream);
+  for (void* p : h->owned) g_cache.release(p);
   delete h;
 }
 
@@ -478,6 +551,12 @@ extern "C" int ttsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int 
 
 extern "C" void rtsvd_factor_destroy(rtsvd_handle f) { free_handle(f); }
 
+extern "C" int rtsvd_trim(void) {
+  g_last_error.clear();
+  if (g_cache.trim() != 0) return fail(RTSVD_E_HIP, "rtsvd_trim: releasing cached device memory failed");
+  return RTSVD_OK;
+}
+
 extern "C" int rtsvd_factor_info(rtsvd_handle f, int32_t* r, int32_t* faces, double* eta, int32_t* r_eps,
                                  double* sigma, int32_t* flags) {
   g_last_error.clear();
@@ -533,7 +612,7 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   RT_LAUNCH_OK();
   RT_ALLOC(bnd, double, groups, sc);
   RT_ALLOC(rho_tmp, double, (int64_t)groups * kcap, sc);
-  RT_CHECK_HIP(hipMemcpyAsync(bnd, bounds.data(), sizeof(double) * groups, hipMemcpyHostToDevice, s));
+  RT_TRY(upload_doubles(bnd, bounds.data(), groups, s));
   hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(256), 0, s, partial, (int)F, tiles, (int)p, kcap, (int)n, groups, bnd,
                      k_start, k_out, resid_out, status_out, rho_tmp);
   RT_LAUNCH_OK();
@@ -690,10 +769,10 @@ static int tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, in
   RT_ALLOC(bnd, double, p, sc);
   RT_ALLOC(remaining, int, 1, sc);
   RT_ALLOC(kin, int, p, sc);
-  RT_CHECK_HIP(hipMemcpyAsync(bnd, bounds.data(), sizeof(double) * p, hipMemcpyHostToDevice, s));
+  RT_TRY(upload_doubles(bnd, bounds.data(), p, s));
   RT_CHECK_HIP(hipMemsetAsync(kin, 0, sizeof(int) * p, s));
-  const int pp = (int)p;
-  RT_CHECK_HIP(hipMemcpyAsync(remaining, &pp, sizeof(int), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, remaining, (int)p);
+  RT_LAUNCH_OK();
   if (resid_out) RT_CHECK_HIP(hipMemsetAsync(resid_out, 0, sizeof(double) * p * kmax, s));
   hipLaunchKernelGGL((k_gkb_init<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, Bh, (int)l, (int)p, Qb, ldq, zc,
                      phibar, cprev, 0.0);
@@ -793,26 +872,16 @@ static int vjp_impl(const T* A, const T* dA, const T* B, const T* omega, const T
   RT_ALLOC(Ry, zd, F * r * r, sc);
   RT_ALLOC(Rq, zd, F * r * r, sc);
   RT_ALLOC(flags, int, 1, sc);
-  RT_TRY((big_gemm<zt, zt, zt, T>(false, Ah, l, m, Omh, r, Y, F, s)));
-  {
-    const int ks = gram_splits(l, r, F);
-    zd* part = sc.get<zd>(F * ks * r * r);
-    if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
-    RT_TRY(gram_fp64<zt>(Y, l, (int)r, l * r, (int)F, part, ks, G, s));
-    RT_TRY(launch_cholinv(G, (int)r, F, Ry, flags, sc, s));
-  }
+  RT_TRY((big_gemm<zt, zt, zt>(false, Ah, l, m, Omh, r, Y, F, sc, s)));
+  RT_TRY(gram<zt>(Y, l, r, F, G, sc, s));
+  RT_TRY(launch_cholinv(G, (int)r, F, Ry, flags, sc, s));
   RT_CHECK_HIP(hipMemcpyAsync(Q, Y, sizeof(zt) * F * l * r, hipMemcpyDeviceToDevice, s));
   RT_TRY(orthonormalize<zt>(Q, l, r, F, 2, G, Rq, tmp, flags, sc, s));
   RT_ALLOC(Ch, zd, F * m * r, sc);
-  RT_TRY((big_gemm<zt, zt, zd, T>(true, Ah, l, m, Q, r, Ch, F, s)));
+  RT_TRY((big_gemm<zt, zt, zd>(true, Ah, l, m, Q, r, Ch, F, sc, s)));
   RT_ALLOC(U, zd, F * r * r, sc);
   RT_ALLOC(lam, double, F * r, sc);
-  {
-    const int ks = gram_splits(m, r, F);
-    zd* part = sc.get<zd>(F * ks * r * r);
-    if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
-    RT_TRY(gram_fp64<zd>(Ch, m, (int)r, m * r, (int)F, part, ks, G, s));
-  }
+  RT_TRY(gram<zd>(Ch, m, r, F, G, sc, s));
   RT_TRY(launch_heev(G, (int)r, F, U, lam, sc, s));
   // G_k^+ = U diag(phi) U^H
   RT_ALLOC(Uphi, zd, F * r * r, sc);

@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
            "tprod", "tprod_adjoint", "tgkb_solve", "rtsvd_status_string", "rtsvd_last_error",
-           "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp"]
+           "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim"]
 
 
 class RtsvdError(RuntimeError):
@@ -69,6 +69,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rtsvd_solve_vjp.argtypes = [vp, vp, vp, vp, vp, i64, i64, i64, i64, i32, i32, ctypes.c_int, vp, vp, vp]
     lib.rtsvd_timer_enable.argtypes = [ctypes.c_int]
     lib.rtsvd_timer_read.argtypes = [ctypes.c_int, pdbl, pi32]
+    lib.rtsvd_trim.argtypes = []
     _lib = lib
     return lib
 
@@ -218,6 +219,11 @@ class Factor:
             self.close()
         except Exception:
             pass
+
+
+def trim() -> None:
+    """Free the library's cached device workspace (synchronizes the devices that hold it)."""
+    _check(load().rtsvd_trim(), "rtsvd_trim")
 
 
 def factor(A, k_max, oversample, power_iters=0, precision="fp64", omega=None, eps=0.0) -> Factor:
