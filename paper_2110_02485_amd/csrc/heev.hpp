@@ -14,6 +14,7 @@
 //          pivot at or below tol_rel * max diag marks a dependent column: its row and column of
 //          Rinv are zero and the face is flagged (Alg. 3's breakdown).
 #pragma once
+#include <type_traits>
 #include "common.hpp"
 
 namespace rt {
@@ -39,6 +40,28 @@ __device__ __forceinline__ zd pk_get(const zd* S, const int* cb, int i, int j) {
 }
 
 // reduce `v` over the 8 aligned lanes of a group
+// lower triangle of the column-major r x r matrix G into packed storage S; every thread keeps 8
+// independent loads in flight
+__device__ __forceinline__ void load_lower_packed(const zd* __restrict__ G, int r, zd* S, int tid, int nt) {
+  const int total = r * r;
+  for (int base = 0; base < total; base += 8 * nt) {
+    zd v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * nt + tid;
+      v[u] = idx < total ? G[idx] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * nt + tid;
+      if (idx < total) {
+        const int i = idx % r, j = idx / r;
+        if (i >= j) S[pk_off(j, r) + (i - j)] = v[u];
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ double grp8_sum(double v) {
   v += __shfl_xor(v, 1, 64);
   v += __shfl_xor(v, 2, 64);
@@ -117,13 +140,18 @@ constexpr int HEEV_UREG = 16;   // rows per lane of the register-resident back-t
 // lam: F x r out (descending).  gpk: F x packed_size(r) global scratch (the reflectors; also the
 // working matrix when !in_lds); zs: F x r x (r+1) doubles (eigenvectors of T when !in_lds);
 // lu: F x r x 5r doubles (LU factors of T - lambda I).
+// IN_LDS: the packed working matrix (and later Z) live in LDS; a template parameter so that LDS
+// accesses compile to LDS instructions rather than generic (flat) ones.
+template <bool IN_LDS>
 __global__ void __launch_bounds__(HEEV_THREADS)
 k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restrict__ lamout,
-       zd* __restrict__ gpk, double* __restrict__ zs, double* __restrict__ lu, int in_lds) {
+       zd* __restrict__ gpk, double* __restrict__ zs, double* __restrict__ lu) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   HeevLds& L = *reinterpret_cast<HeevLds*>(smem_raw);
   const int f = blockIdx.x;
-  zd* S = in_lds ? reinterpret_cast<zd*>(smem_raw + sizeof(HeevLds)) : gpk + (int64_t)f * packed_size(r);
+  zd* S;
+  if constexpr (IN_LDS) S = reinterpret_cast<zd*>(smem_raw + sizeof(HeevLds));
+  else S = gpk + (int64_t)f * packed_size(r);
   zd* Sg = gpk + (int64_t)f * packed_size(r);
   const zd* G = Gin + (int64_t)f * r * r;
   zd* U = Uout + (int64_t)f * r * r;
@@ -135,8 +163,7 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   for (int j = tid; j <= r; j += blockDim.x) L.cb[j] = (int)pk_off(j, r);
   if (tid < 2) { L.acc[tid] = 0.0; L.accre[tid] = 0.0; L.accim[tid] = 0.0; }
   // ---- load the lower triangle -----------------------------------------------------------
-  for (int j = 0; j < r; ++j)
-    for (int i = j + tid; i < r; i += blockDim.x) S[pk_off(j, r) + (i - j)] = G[i + (int64_t)j * r];
+  load_lower_packed(G, r, S, tid, blockDim.x);
   __syncthreads();
 
   RT_PHASE(1);
@@ -263,12 +290,14 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   RT_PHASE(3);
   // ---- the reflectors move to global memory; LDS (or the global slice) then holds Z ------------
   // Z column j (stride zst = r + 1 doubles) = eigenvector of T for lam[j]
-  if (in_lds) {
+  if constexpr (IN_LDS) {
     for (int64_t i = tid; i < packed_size(r); i += blockDim.x) Sg[i] = S[i];
     __syncthreads();
   }
   const int zst = r + 1;
-  double* Zp = in_lds ? reinterpret_cast<double*>(smem_raw + sizeof(HeevLds)) : Z;
+  double* Zp;
+  if constexpr (IN_LDS) Zp = reinterpret_cast<double*>(smem_raw + sizeof(HeevLds));
+  else Zp = Z;
 
   // ---- eigenvectors of T: inverse iteration, one thread per eigenvalue ---------------------------
   for (int j = tid; j < r; j += blockDim.x) {
@@ -364,7 +393,7 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
 
   RT_PHASE(5);
   // ---- back-transformation U = Q_H Z, 8 lanes per column ---------------------------------------
-  if (in_lds && r <= 8 * HEEV_UREG) {
+  if (IN_LDS && r <= 8 * HEEV_UREG) {
     // column in registers (lane sub owns rows sub + 8 t), reflectors back in LDS
     const int c = grp;                       // one column per 8-lane group (r <= 128 = ngrp)
     const bool on = c < r;
@@ -436,95 +465,278 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
 // -------------------------------------------------------------------------------------------
 // Cholesky and triangular inverse: Rinv = L^{-H}
 // -------------------------------------------------------------------------------------------
-struct CholLds {
-  zd x[HEEV_RMAX], t[HEEV_RMAX];
-  int cb[HEEV_RMAX + 1];
-  double piv, tol;
+// ---------------------------------------------------------------------------------------------
+// Cholesky factor and triangular inverse of the r x r Gram matrices (one workgroup per face), FP64:
+//   G = L L^H (L lower, real positive diagonal),  Rinv = L^{-H}  (upper), so Q = Y Rinv.
+// Blocked by 16 columns.  Per diagonal block K, one wave factors the 16 x 16 block and inverts it
+// in registers (lane (i, j) layout, column data exchanged by cross-lane shuffles); the panel below
+// is G_panel D^H (D = L_KK^{-1}) and the trailing update is S -= P P^H, both on FP64 MFMA 16x16x4
+// tiles spread over the waves.  The inverse runs over the diagonal blocks backwards:
+//   Linv(J1:, J) = -Linv(J1:, J1:) X D_J,  X = L(J1:, J)  (MFMA tiles, three barriers per block).
+// A pivot at or below tol_rel * max diag marks a dependent column: its row and column of L^{-1}
+// are zero and flags gets bit 0.  The packed lower triangle lives in LDS when it fits (else in
+// `gpk`, global scratch of packed_size(r) per face); `gdi` (F x ceil(r/16) x 256) keeps the block
+// inverses between the two sweeps.
+// ---------------------------------------------------------------------------------------------
+constexpr int CH_NB = 16, CH_PS = CH_NB + 1;  // block width, padded row stride of the panel buffers
+constexpr int CH_THREADS = 512;
+
+struct CholHdr {
+  double tol;
   int bad;
+  int pad_;
+  double ipiv[HEEV_RMAX];   // 1 / L(j, j), 0 for a dependent column
 };
 
 inline size_t chol_lds_bytes(int r, bool packed_in_lds) {
-  return sizeof(CholLds) + (packed_in_lds ? (size_t)packed_size(r) * sizeof(zd) : 0);
+  size_t b = (sizeof(CholHdr) + 15) / 16 * 16;
+  b += (size_t)r * CH_PS * sizeof(zd);       // panel buffer P
+  b += (size_t)CH_NB * CH_PS * sizeof(zd);   // diagonal block inverse DI
+  if (packed_in_lds) b += (size_t)packed_size(r) * sizeof(zd);
+  return b;
+}
+RT_HOST_DEVICE int64_t chol_gdi_elems(int r) { return (int64_t)((r + CH_NB - 1) / CH_NB) * CH_NB * CH_NB; }
+
+typedef double ch_f64x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ ch_f64x4 ch_mma(double a, double b, ch_f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// C += a b for one k-group of a complex 16 x 16 x 4 product (lane's A and B operand elements)
+__device__ __forceinline__ void ch_cmma(zd a, zd b, ch_f64x4& cr, ch_f64x4& ci) {
+  cr = ch_mma(a.re, b.re, cr);
+  cr = ch_mma(-a.im, b.im, cr);
+  ci = ch_mma(a.re, b.im, ci);
+  ci = ch_mma(a.im, b.re, ci);
+}
+__device__ __forceinline__ zd ch_shfl(zd v, int src) { return mk(__shfl(v.re, src), __shfl(v.im, src)); }
+// component-wise select (a conditional on whole structs can force them into private memory)
+__device__ __forceinline__ zd zsel(bool c, zd x, zd y) { return mk(c ? x.re : y.re, c ? x.im : y.im); }
+// f(integral_constant<int, I>) for I = B .. E-1, unrolled at compile time (register arrays stay
+// statically indexed)
+template <int B, int E, typename Fn> __device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
 }
 
-__global__ void __launch_bounds__(HEEV_THREADS)
+template <bool IN_LDS>
+__global__ void __launch_bounds__(CH_THREADS)
 k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_rel, int* __restrict__ flags,
-          zd* __restrict__ gpk, int in_lds) {
+          zd* __restrict__ gpk, zd* __restrict__ gdi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  CholLds& L = *reinterpret_cast<CholLds*>(smem_raw);
+  CholHdr& H = *reinterpret_cast<CholHdr*>(smem_raw);
+  zd* P = reinterpret_cast<zd*>(smem_raw + (sizeof(CholHdr) + 15) / 16 * 16);
+  zd* DI = P + (size_t)r * CH_PS;
   const int f = blockIdx.x;
-  zd* S = in_lds ? reinterpret_cast<zd*>(smem_raw + sizeof(CholLds)) : gpk + (int64_t)f * packed_size(r);
+  zd* S;
+  if constexpr (IN_LDS) S = DI + CH_NB * CH_PS;
+  else S = gpk + (int64_t)f * packed_size(r);
   const zd* G = Gin + (int64_t)f * r * r;
   zd* R = Rinv + (int64_t)f * r * r;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-  for (int j = tid; j <= r; j += blockDim.x) L.cb[j] = (int)pk_off(j, r);
-  for (int j = 0; j < r; ++j)
-    for (int i = j + tid; i < r; i += blockDim.x) S[pk_off(j, r) + (i - j)] = G[i + (int64_t)j * r];
-  if (tid == 0) { L.bad = 0; }
+  zd* GD = gdi + (int64_t)f * chol_gdi_elems(r);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nw = (int)blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, rho = lane & 15;   // MFMA lane coordinates
+  // packed lower storage, column j at j r - j (j - 1) / 2
+  auto at = [&](int i, int j) -> zd& { return S[j * r - (j * (j - 1)) / 2 + (i - j)]; };  // i >= j
+  const zd zero = mk(0.0, 0.0);
+
+  RT_PHASE(7);
+  load_lower_packed(G, r, S, tid, blockDim.x);
+  if (tid == 0) H.bad = 0;
   __syncthreads();
-  if (tid == 0) {
+  if (wave == 0) {
     double mx = 0.0;
-    for (int j = 0; j < r; ++j) mx = fmax(mx, S[L.cb[j]].re);
-    L.tol = tol_rel * mx;
+    for (int j = lane; j < r; j += 64) mx = fmax(mx, at(j, j).re);
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if (lane == 0) H.tol = tol_rel * mx;
   }
   __syncthreads();
+  const double tol = H.tol;
+
   RT_PHASE(8);
-  // right-looking Cholesky
-  for (int j = 0; j < r; ++j) {
-    if (tid == 0) {
-      const double d = S[L.cb[j]].re;
-      double pv = 0.0;
-      if (d > L.tol && d > 0.0) pv = sqrt(d); else L.bad = 1;
-      L.piv = pv;
-      S[L.cb[j]] = mk(pv, 0.0);
-    }
-    __syncthreads();
-    const double pv = L.piv;
-    const double ipv = pv > 0.0 ? 1.0 / pv : 0.0;
-    for (int i = j + 1 + tid; i < r; i += blockDim.x) {
-      zd& a = S[L.cb[j] + (i - j)];
-      a = cscale(a, ipv);
-      L.x[i] = a;
-    }
-    __syncthreads();
-    for (int c = j + 1 + wave; c < r; c += nw) {
-      const zd lc = cconj(L.x[c]);
-      for (int i = c + lane; i < r; i += 64) {
-        zd& a = S[L.cb[c] + (i - c)];
-        a = csub(a, cmul(L.x[i], lc));
+  // ---- blocked right-looking Cholesky ----
+  for (int K = 0; K < r; K += CH_NB) {
+    const int kb = min(CH_NB, r - K), K1 = K + kb, m = r - K1;
+    // (a) wave 0: factor the diagonal block and invert it; lane holds (i, j_s), i = rho, j_s = g + 4 s.
+    // A block narrower than 16 is padded with the identity (its extra pivots are 1), so the
+    // unrolled column loop has no bound tests; only rows and columns < kb are written back.
+    if (wave == 0) {
+      zd a[4], d[4];
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int j = g + 4 * s2;
+        const bool in = rho < kb && j < kb && rho >= j;
+        const zd diag = mk(rho == j ? 1.0 : 0.0, 0.0);
+        a[s2] = in ? at(K + rho, K + j) : diag;
+        d[s2] = diag;
+      }
+      double myipv = 1.0;   // 1 / L(rho, rho) once column rho is factored
+#pragma unroll
+      for (int c = 0; c < CH_NB; ++c) {
+        const int cs = c & 3, sl = c >> 2;
+        const zd ac = a[sl];
+        const double dd = __shfl(ac.re, c + 16 * cs);
+        const double pv = (c >= kb) ? 1.0 : ((dd > tol && dd > 0.0) ? sqrt(dd) : 0.0);
+        const double ipv = pv > 0.0 ? 1.0 / pv : 0.0;
+        myipv = (rho == c) ? ipv : myipv;
+        const zd acn = zsel(g != cs || rho < c, ac, zsel(rho == c, mk(pv, 0.0), cscale(ac, ipv)));
+        a[sl] = acn;
+        const zd lic = ch_shfl(acn, rho + 16 * cs);   // L(rho, c)
+        zd ljc[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) ljc[s2] = ch_shfl(acn, g + 4 * s2 + 16 * cs);   // L(j_s, c)
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int j = g + 4 * s2;
+          const zd upd = csub(a[s2], cmul(lic, cconj(ljc[s2])));
+          a[s2] = zsel(j > c && rho >= j, upd, a[s2]);
+        }
+      }
+      if (g == 0 && rho < kb) {
+        H.ipiv[K + rho] = myipv;
+        if (myipv == 0.0) H.bad = 1;
+      }
+      // D = L_KK^{-1}: forward substitution, row t final then eliminated from the rows below
+#pragma unroll
+      for (int t = 0; t < CH_NB; ++t) {
+        const double sc = (rho == t) ? myipv : 1.0;   // branch-free: the arrays stay in registers
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) d[s2] = cscale(d[s2], sc);
+        const zd lit = ch_shfl(a[t >> 2], rho + 16 * (t & 3));   // L(rho, t)
+        const zd lm = zsel(rho > t, lit, zero);
+        zd dtj[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) dtj[s2] = ch_shfl(d[s2], t + 16 * g);   // D(t, j_s)
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) d[s2] = csub(d[s2], cmul(lm, dtj[s2]));
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int j = g + 4 * s2;
+        if (rho < kb && j < kb && rho >= j) at(K + rho, K + j) = a[s2];
+        const zd dv = zsel(rho < kb && j < kb, d[s2], zero);
+        DI[rho * CH_PS + j] = dv;
+        GD[(K / CH_NB) * CH_NB * CH_NB + rho * CH_NB + j] = dv;
       }
     }
     __syncthreads();
-  }
-  RT_PHASE(9);
-  // in-place inverse of the lower triangular L (columns from the last to the first)
-  for (int j = r - 1; j >= 0; --j) {
-    const double ljj = S[L.cb[j]].re;
-    const double ajj = ljj > 0.0 ? 1.0 / ljj : 0.0;
-    for (int i = j + 1 + tid; i < r; i += blockDim.x) L.x[i] = S[L.cb[j] + (i - j)];
-    __syncthreads();
-    // t_i = sum_{k=j+1..i} Linv(i,k) x_k, 8 lanes per row
-    for (int base = j + 1; base < r; base += (int)blockDim.x / 8) {
-      const int i = base + tid / 8, sub = tid % 8;
-      zd s = mk(0.0, 0.0);
-      if (i < r)
-        for (int k = j + 1 + sub; k <= i; k += 8) s = cadd(s, cmul(S[L.cb[k] + (i - k)], L.x[k]));
-      s.re = grp8_sum(s.re);
-      s.im = grp8_sum(s.im);
-      if (i < r && sub == 0) L.t[i] = s;
+    if (K == 0) RT_PHASE(12);
+    // (b) panel P(i, c) = sum_t G(i, K + t) conj(D(c, t)), rows i >= K1, 16-row MFMA tiles
+    for (int ti = wave; ti * 16 < m; ti += nw) {
+      const int i0 = K1 + 16 * ti;
+      ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+      for (int kg = 0; kg < 4; ++kg) {
+        const int k = 4 * kg + g;
+        const zd av = (i0 + rho < r && k < kb) ? at(i0 + rho, K + k) : zero;
+        const zd bv = (k < kb && rho < kb) ? cconj(DI[rho * CH_PS + k]) : zero;
+        ch_cmma(av, bv, cr, ci);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + g + 4 * v;
+        if (i < r && rho < kb) {
+          const zd x = mk(cr[v], ci[v]);
+          at(i, K + rho) = x;
+          P[(size_t)i * CH_PS + rho] = x;
+        }
+      }
     }
     __syncthreads();
-    for (int i = j + 1 + tid; i < r; i += blockDim.x) S[L.cb[j] + (i - j)] = cscale(L.t[i], -ajj);
-    if (tid == 0) S[L.cb[j]] = mk(ajj, 0.0);
+    if (K == 0) RT_PHASE(13);
+    // (c) trailing update S(i, j) -= sum_c P(i, c) conj(P(j, c)), lower 16 x 16 tiles
+    const int T = (m + 15) / 16;
+    for (int q = wave; q < T * (T + 1) / 2; q += nw) {
+      int ti = (int)((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
+      while (ti * (ti + 1) / 2 > q) --ti;
+      while ((ti + 1) * (ti + 2) / 2 <= q) ++ti;
+      const int tj = q - ti * (ti + 1) / 2;
+      const int i0 = K1 + 16 * ti, j0 = K1 + 16 * tj;
+      ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+      for (int kg = 0; kg < 4; ++kg) {
+        const int k = 4 * kg + g;
+        const zd av = (i0 + rho < r && k < kb) ? P[(size_t)(i0 + rho) * CH_PS + k] : zero;
+        const zd bv = (j0 + rho < r && k < kb) ? cconj(P[(size_t)(j0 + rho) * CH_PS + k]) : zero;
+        ch_cmma(av, bv, cr, ci);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + g + 4 * v, j = j0 + rho;
+        if (i < r && j < r && i >= j) at(i, j) = csub(at(i, j), mk(cr[v], ci[v]));
+      }
+    }
+    __syncthreads();
+    if (K == 0) RT_PHASE(14);
+  }
+  RT_PHASE(9);
+  // ---- in-place inverse of L, diagonal blocks from the last to the first ----
+  const int nblk = (r + CH_NB - 1) / CH_NB;
+  for (int Jb = nblk - 1; Jb >= 0; --Jb) {
+    const int J = Jb * CH_NB, kb = min(CH_NB, r - J), J1 = J + kb, m = r - J1;
+    // (d) block inverse D_J back from global; panel X = L(J1:, J) copied into P
+    for (int q = tid; q < CH_NB * CH_NB; q += blockDim.x) DI[(q / CH_NB) * CH_PS + q % CH_NB] = GD[Jb * CH_NB * CH_NB + q];
+    for (int q = tid; q < m * kb; q += blockDim.x) {
+      const int k = J1 + q / kb, c = q % kb;
+      P[(size_t)k * CH_PS + c] = at(k, J + c);
+    }
+    __syncthreads();
+    // (e) T = Linv(J1:, J1:) X, written over the panel slots (X is safe in P)
+    for (int ti = wave; ti * 16 < m; ti += nw) {
+      const int i0 = J1 + 16 * ti;
+      ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      for (int tk = 0; tk <= ti; ++tk) {
+#pragma unroll
+        for (int kg = 0; kg < 4; ++kg) {
+          const int kk = J1 + 16 * tk + 4 * kg + g;
+          const int i = i0 + rho;
+          const zd av = (i < r && kk <= i) ? at(i, kk) : zero;
+          const zd bv = (kk < r && rho < kb) ? P[(size_t)kk * CH_PS + rho] : zero;
+          ch_cmma(av, bv, cr, ci);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + g + 4 * v;
+        if (i < r && rho < kb) at(i, J + rho) = mk(cr[v], ci[v]);
+      }
+    }
+    __syncthreads();
+    // (f) Linv(i, J + c) = -sum_t T(i, t) D(t, c) (each wave reads back only its own row tiles);
+    // the diagonal block becomes D
+    for (int ti = wave; ti * 16 < m; ti += nw) {
+      const int i0 = J1 + 16 * ti;
+      ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+      for (int kg = 0; kg < 4; ++kg) {
+        const int t = 4 * kg + g;
+        const zd av = (i0 + rho < r && t < kb) ? at(i0 + rho, J + t) : zero;
+        const zd bv = (t < kb && rho < kb) ? DI[t * CH_PS + rho] : zero;
+        ch_cmma(av, bv, cr, ci);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + g + 4 * v;
+        if (i < r && rho < kb) at(i, J + rho) = mk(-cr[v], -ci[v]);
+      }
+    }
+    for (int q = tid; q < kb * kb; q += blockDim.x) {
+      const int i = q / kb, c = q % kb;
+      if (i >= c) at(J + i, J + c) = DI[i * CH_PS + c];
+    }
     __syncthreads();
   }
   RT_PHASE(10);
   // Rinv(i, j) = conj(Linv(j, i)) for i <= j, zero below the diagonal
   for (int idx = tid; idx < r * r; idx += blockDim.x) {
     const int i = idx % r, j = idx / r;
-    R[idx] = (i <= j) ? cconj(S[L.cb[i] + (j - i)]) : mk(0.0, 0.0);
+    R[idx] = (i <= j) ? cconj(at(j, i)) : zero;
   }
-  if (tid == 0 && flags && L.bad) atomicOr(flags, 1);
+  RT_PHASE(11);
+  if (tid == 0 && flags && H.bad) atomicOr(flags, 1);
 }
 
 }  // namespace rt

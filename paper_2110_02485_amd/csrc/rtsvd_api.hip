@@ -271,8 +271,9 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
   double* zs = sc.get<double>(in_lds ? 1 : F * r * (int64_t)(r + 1));
   double* lu = sc.get<double>(F * r * 5 * (int64_t)r);
   if (!zs || !lu) return fail(RTSVD_E_NOMEM, "device allocation failed: heev scratch");
-  if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)k_heev, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  hipLaunchKernelGGL(k_heev, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu, (int)in_lds);
+  auto kern = in_lds ? k_heev<true> : k_heev<false>;
+  if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu);
   RT_LAUNCH_OK();
   return 0;
 }
@@ -286,8 +287,11 @@ static int launch_cholinv(const zd* G, int r, int64_t F, zd* Rinv, int* flags, S
     gpk = sc.get<zd>(F * packed_size(r));
     if (!gpk) return fail(RTSVD_E_NOMEM, "device allocation failed: cholinv packed scratch");
   }
-  if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)k_cholinv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  hipLaunchKernelGGL(k_cholinv, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, Rinv, 1e-13, flags, gpk, (int)in_lds);
+  zd* gdi = sc.get<zd>(F * chol_gdi_elems(r));
+  if (!gdi) return fail(RTSVD_E_NOMEM, "device allocation failed: cholinv block inverses");
+  auto kern = in_lds ? k_cholinv<true> : k_cholinv<false>;
+  if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(CH_THREADS), bytes, s, G, r, Rinv, 1e-13, flags, gpk, gdi);
   RT_LAUNCH_OK();
   return 0;
 }
