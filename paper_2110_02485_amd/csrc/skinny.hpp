@@ -3,17 +3,15 @@
 // the passes over A-hat of the randomized factorization (sketch, power iteration, projection,
 // W = A-hat V), the FP64 Gram matrices of CholeskyQR and the right-multiplications Y R^{-1}.
 //
-// Design (block = 8 waves = WR row groups x WC column groups; a wave owns 16*RT rows and 16*NTW
-// columns of C; the waves of a row group read the same A fragments, all but one from L1/L2):
-//  * op(A) is streamed from global memory straight into MFMA operand registers, without LDS, so
-//    each element of A is read from HBM once per block column.  NN (A column-major, rows contiguous): a
-//    lane loads RT neighbouring rows for each of its k (16 lanes cover 128-256 contiguous bytes);
-//    CN: a lane loads KL consecutive k of one column.  The MFMA k slot is a relabelling of k
-//    (lane group g = lane/16 holds k = k0 + KL*g + e), applied identically to X.
-//  * X is staged through LDS one macro step (KS = 4*KL values of k) at a time in a ring of three
-//    buffers, one barrier per step, rows padded to 80 or 144 bytes so 16-byte fragment reads are free of
-//    bank conflicts.  X arrives either pre-packed (split planes of the MFMA type, k contiguous,
-//    zero padded: k_pack_planes) or raw complex (converted while staging).
+// Design (block = 8 waves = WR row groups x WC column groups over a BM x NP tile of C):
+//  * Both operands move through LDS one k-group (4 KL values of k) at a time.  All 512 threads
+//    load the next k-groups cooperatively with 16-byte loads (A rows or columns contiguous, X in
+//    slab-major packed order), keeping SK_DEPTH k-groups in flight in a ring of register sets,
+//    so the memory latency is covered without per-wave duplicate loads; the oldest set goes to
+//    one of two LDS buffers each step (one barrier per k-group).
+//  * A keeps its global layout in LDS; a lane reads the RT rows (NN) or the KL consecutive k (CN)
+//    of its MFMA operand directly, so no transposition is needed.  The MFMA k slot is a
+//    relabelling of k (lane group g = lane/16 holds k = KL*g + e), applied identically to X.
 //  * With RT = 2 the two row tiles of a wave interleave (row 2*rho + t), so a lane's outputs are
 //    8 consecutive rows of one column and are written with 16-byte stores.
 //  * Complex arithmetic is four real MFMA products on split planes:
@@ -93,8 +91,11 @@ __device__ __forceinline__ f32x4 mma(float a, float b, f32x4 c) { return __built
 __device__ __forceinline__ f64x4 mma(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
 constexpr int SK_THREADS = 512;  // 8 waves: 2 per SIMD
+constexpr int SK_DEPTH = 3;      // k-groups in flight in registers beyond the one being stored
+constexpr int SK_RING = SK_DEPTH + 1;
 
 // Block shape for NB column tiles of 16: WC column groups of NTW tiles, WR = 8 / WC row groups.
+// Four column groups (two row groups of waves) measured fastest for the 64- and 128-column products.
 template <int NB> struct Shape {
 #ifdef SKINNY_WC
   static constexpr int WC = NB >= SKINNY_WC ? SKINNY_WC : NB;
@@ -104,37 +105,61 @@ template <int NB> struct Shape {
   static constexpr int NTW = NB / WC, WR = 8 / WC;
 };
 
-// X staging ring: three LDS buffers of (2 planes x 16 NB rows x padded macro step)
-template <class P> constexpr int lds_bytes(int NB) {
-  return 3 * 2 * 16 * NB * (4 * P::KL + P::PADE) * (int)sizeof(typename P::E);
+// k per MFMA k-group (4 lane groups x KL); packed X is padded to whole rings of k-groups
+template <class P> constexpr int kgroup() { return 4 * P::KL; }
+template <class P> constexpr int kslab() { return kgroup<P>(); }
+
+// LDS: two buffers, each an A tile (rows or columns padded by 16 bytes) and an X tile (2 planes)
+template <class P, bool CN, typename TA> constexpr int a_stride_bytes(int BM) {
+  return CN ? kgroup<P>() * (int)sizeof(TA) + 16 : BM * (int)sizeof(TA) + 16;
+}
+template <class P, bool CN, typename TA> constexpr int a_tile_bytes(int BM) {
+  return (CN ? BM : kgroup<P>()) * a_stride_bytes<P, CN, TA>(BM);
+}
+template <class P> constexpr int x_tile_bytes(int NB) {
+  return 2 * 16 * NB * (kgroup<P>() + P::PADE) * (int)sizeof(typename P::E);
+}
+template <class P, bool CN, typename TA> constexpr int lds_bytes(int NB, int BM) {
+  return 2 * (a_tile_bytes<P, CN, TA>(BM) + x_tile_bytes<P>(NB));
 }
 
-// Xp_f = split planes of X_f: Xp[f][plane][n][k] (plane 0 real, 1 imaginary), n < NPt, k < KP,
-// zero outside K x N.  X_f is column-major K x N with leading dimension ldx.
-template <typename TX, typename E>
-__global__ void k_pack_planes(const TX* __restrict__ X, int64_t ldx, int64_t sX, int K, int N, E* __restrict__ Xp,
-                              int KP, int NPt, int batch) {
+// Packed X in slab-major order, so that one slab of one block column is a single contiguous run:
+//   Xp[f][block column nt][slab s][plane][n < NP][kl < KSL],  k = s KSL + kl,  n = nt NP + n,
+// plane 0 real, 1 imaginary, zero outside K x N.  X_f is column-major K x N (leading dimension ldx).
+template <typename TX, typename E, int KSL>
+__global__ void k_pack_slabs(const TX* __restrict__ X, int64_t ldx, int64_t sX, int K, int N, E* __restrict__ Xp,
+                             int KP, int NP, int ntiles, int batch) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per = (int64_t)NPt * KP;
-  if (idx >= per * batch) return;
-  const int64_t f = idx / per;
-  const int n = (int)((idx % per) / KP), k = (int)(idx % KP);
+  const int nsl = KP / KSL;
+  const int64_t total = (int64_t)batch * ntiles * nsl * NP * KSL;
+  if (idx >= total) return;
+  const int kl = (int)(idx % KSL);
+  int64_t t1 = idx / KSL;
+  const int nl = (int)(t1 % NP);
+  t1 /= NP;
+  const int sl = (int)(t1 % nsl);
+  t1 /= nsl;
+  const int nt = (int)(t1 % ntiles);
+  const int64_t f = t1 / ntiles;
+  const int k = sl * KSL + kl, n = nt * NP + nl;
   double re = 0.0, im = 0.0;
   if (n < N && k < K) {
     const cplx<double> v = ld<double>(X[f * sX + k + (int64_t)n * ldx]);
     re = v.re; im = v.im;
   }
-  E* base = Xp + f * 2 * per + (int64_t)n * KP + k;
-  base[0] = cvt_e<E>(re);
-  base[per] = cvt_e<E>(im);
+  E* out = Xp + (((f * ntiles + nt) * nsl + sl) * 2 * NP + nl) * KSL + kl;
+  out[0] = cvt_e<E>(re);
+  out[(int64_t)NP * KSL] = cvt_e<E>(im);
 }
 
 // C_f (+ split * sCsplit) = op(A_f) X_f, M x N, contraction length K.
-// PACKED: X is E* planes [f][2][NPt][ldx] with face stride sX; otherwise X is TX* column-major.
-// SAFE = false: the host guarantees M % (64 RT) == 0, K % (4 KL) == 0 and the alignment of the
-// vector loads of A (and of raw X); SAFE = true clamps every A and X index instead (element
-// loads).  Both paths are branch-free inside the k loop.  LOWER: skip column tiles strictly above
-// the diagonal (Hermitian Gram).  vec_c: the host has checked the alignment of 16-byte stores.
+// PACKED: X is E* packed k-group-major ([f][nt][k-group][plane][NP][KG]) with face stride sX and
+// ldx = its padded K; otherwise X is TX* column-major (raw, converted while staging).
+// SAFE = false: the host guarantees M % BM == 0, K % KG == 0 and the alignment of the 16-byte
+// loads of A (and of raw X); SAFE = true clamps every A and X index instead (element loads).
+// Both paths are branch-free inside the k loop.  LOWER: skip column tiles strictly above the
+// diagonal (Hermitian Gram).  vec_c: the host has checked the alignment of 16-byte stores.
+// k-groups past kend see X = 0 (packed X is zero-padded, raw X is zeroed while staging).
 template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, typename TA, typename TX, typename TC, int NB>
 __global__ void __launch_bounds__(SK_THREADS, 2)
 k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA, const void* __restrict__ Xv,
@@ -143,16 +168,24 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
   typedef typename P::E E;
   typedef typename P::V V;
   typedef typename P::Acc Acc;
-  constexpr int KL = P::KL, RT = P::RT, KS = 4 * KL, ROWE = KS + P::PADE, NP = 16 * NB;  // NP: block columns
+  constexpr int KL = P::KL, RT = P::RT, KG = kgroup<P>(), ROWE = KG + P::PADE;
+  constexpr int NP = 16 * NB;  // block columns
   constexpr int NT = Shape<NB>::NTW, WR = Shape<NB>::WR;
   constexpr int BM = WR * 16 * RT;
-  constexpr int PLANE = NP * ROWE, BUF = 2 * PLANE;
-  constexpr int CK = 16 / (int)sizeof(E);  // E per 16-byte chunk
-  constexpr int CPR = KS / CK;             // chunks per LDS row
+  constexpr int ASTR = a_stride_bytes<P, CN, TA>(BM);       // bytes between A rows (NN: k rows)
+  constexpr int ATILE = a_tile_bytes<P, CN, TA>(BM);
+  constexpr int XPLANE = NP * ROWE;                         // E per X plane
+  constexpr int BUFB = ATILE + x_tile_bytes<P>(NB);         // bytes per LDS buffer
+  constexpr int CK = 16 / (int)sizeof(E);                   // E per 16-byte X chunk
+  constexpr int XCPR = KG / CK;                             // X chunks per LDS row
+  constexpr int TAC = 16 / (int)sizeof(TA) > 0 ? 16 / (int)sizeof(TA) : 1;  // TA per 16-byte A chunk
+  constexpr int ACH_PER_LINE = CN ? KG / TAC : BM / TAC;     // A chunks per column (CN) / k row (NN)
+  constexpr int ACH = (CN ? BM : KG) * ACH_PER_LINE;         // A chunks per k-group
+  constexpr int NAC = (ACH + SK_THREADS - 1) / SK_THREADS;   // A chunks per thread
   static_assert(KL == CK, "one 16-byte X fragment per lane, plane and column tile");
   static_assert((RT == 2) == std::is_same<Acc, float>::value, "output layout assumes f32 accumulators iff RT = 2");
+  static_assert(sizeof(TA) <= 16 && 16 % sizeof(TA) == 0, "A element size");
   extern __shared__ __align__(16) unsigned char sk_lds[];
-  E* const Bs = reinterpret_cast<E*>(sk_lds);
 
   // XCD-aware decode: the hardware dispatches block b to XCD b % 8; the tiles of a face share it
   const int tiles = mtiles * ntiles;
@@ -175,13 +208,10 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
   const int split = blockIdx.y;
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
-  const int nsteps = kbeg < kend ? (kend - kbeg + KS - 1) / KS : 0;
-  const int klast = kbeg + (nsteps - 1) * KS;   // start of the last macro step with data
-  // The k loop runs a multiple of three steps (one basic block per three, so the compiler keeps the
-  // prefetches where they are issued).  Steps past kend see X = 0: packed X is zero-padded up to
-  // a multiple of 3 KS (host side), raw X is zeroed while staging.
-  const int nsteps3 = (nsteps + 2) / 3 * 3;
-  const int kxlast = PACKED ? kbeg + (nsteps3 - 1) * KS : klast;
+  const int nkg = kbeg < kend ? (kend - kbeg + KG - 1) / KG : 0;   // k-groups with data
+  const int nkgr = (nkg + SK_RING - 1) / SK_RING * SK_RING;       // run in whole rings
+  const int kglast = kbeg + (nkg - 1) * KG;                       // last k-group with data
+  const int kxlast = PACKED ? kbeg + (nkgr - 1) * KG : kglast;    // packed X is padded to whole rings
 
   A += (int64_t)f * sA;
   C += (int64_t)f * sC + (int64_t)split * sCsplit;
@@ -189,118 +219,119 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, rho = lane & 15;
-  const int mw = m0 + (wave % WR) * 16 * RT;  // first row of op(A) owned by this wave
-  const int cw = (wave / WR) * 16 * NT;       // first block column owned by this wave
+  const int rw = (wave % WR) * 16 * RT;       // first tile row of this wave (within the block)
+  const int mw = m0 + rw;
+  const int cw = (wave / WR) * 16 * NT;       // first block column of this wave
   const int wmax = mw + 16 * RT - 1;
-  const int r0 = (RT == 2) ? mw + 2 * rho : mw + rho;  // row of tile 0 held by this lane
 
-  // ---- A: straight into registers (k0 clamped to the last step: prefetches past the end are
-  // harmless re-reads) ----
-  // Fast-path lane offsets (32-bit, loop invariant) from uniform per-step bases, so every load is
-  // an SGPR base + one VGPR offset.
-  uint32_t aoff[RT];
+  // ---- cooperative staging: per k-group, A chunks then X chunks of 16 bytes ----
+  typedef typename std::conditional<PACKED, u32x4, TX>::type XR;
+  constexpr int XRN = PACKED ? 1 : CK;
+  constexpr int NXC = PACKED ? (2 * NP * XCPR + SK_THREADS - 1) / SK_THREADS : (NP * XCPR + SK_THREADS - 1) / SK_THREADS;
+  struct Stage { u32x4 a[NAC]; TA ae[NAC][TAC]; XR x[NXC][XRN]; };
+  // chunk coordinates (loop invariant)
+  int a_line[NAC], a_seg[NAC];
+  uint32_t a_goff[NAC];
+  int a_loff[NAC];
 #pragma unroll
-  for (int tt = 0; tt < RT; ++tt)
-    aoff[tt] = CN ? (uint32_t)((r0 + tt) * lda + KL * g) : (uint32_t)(r0 + KL * g * lda);
-  auto load_a = [&](TA (&ra)[RT][KL], int k0) {
-    k0 = min(k0, klast);
-    if constexpr (!CN) {
-      if constexpr (!SAFE) {
+  for (int q = 0; q < NAC; ++q) {
+    const int c = min(tid + SK_THREADS * q, ACH - 1);
+    a_line[q] = c / ACH_PER_LINE;   // NN: k within the group; CN: column within the tile
+    a_seg[q] = c % ACH_PER_LINE;
+    a_goff[q] = CN ? (uint32_t)((int64_t)(m0 + a_line[q]) * lda + a_seg[q] * TAC)
+                   : (uint32_t)((int64_t)a_line[q] * lda + m0 + a_seg[q] * TAC);
+    a_loff[q] = a_line[q] * ASTR + a_seg[q] * 16;
+  }
+  int x_loff[NXC], x_col[NXC], x_k[NXC];
+  uint32_t x_goff[NXC];
 #pragma unroll
-        for (int e = 0; e < KL; ++e) {
-          const TA* base = A + (int64_t)(k0 + e) * lda;
-          TA tmp[RT];
-          vload<TA, RT>(base + aoff[0], tmp);
-#pragma unroll
-          for (int tt = 0; tt < RT; ++tt) ra[tt][e] = tmp[tt];
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < KL; ++e) {
-          const int kk = min(k0 + KL * g + e, K - 1);
-#pragma unroll
-          for (int tt = 0; tt < RT; ++tt) ra[tt][e] = A[min(r0 + tt, M - 1) + (int64_t)kk * lda];
-        }
-      }
-    } else {
-      if constexpr (!SAFE) {
-        const TA* base = A + k0;
-#pragma unroll
-        for (int tt = 0; tt < RT; ++tt) vload<TA, KL>(base + aoff[tt], ra[tt]);
-      } else {
-#pragma unroll
-        for (int tt = 0; tt < RT; ++tt) {
-          const int64_t col = (int64_t)min(r0 + tt, M - 1) * lda;
-#pragma unroll
-          for (int e = 0; e < KL; ++e) ra[tt][e] = A[min(k0 + KL * g + e, K - 1) + col];
-        }
-      }
-    }
-  };
-
-  // ---- X: global -> registers (two steps ahead) -> LDS (one step ahead) ----
-  constexpr int NCH = PACKED ? (2 * NP * CPR + SK_THREADS - 1) / SK_THREADS : (NP * CPR + SK_THREADS - 1) / SK_THREADS;
-  typedef typename std::conditional<PACKED, u32x4, TX>::type RB;
-  constexpr int RBN = PACKED ? 1 : CK;
-  uint32_t boff[NCH];   // global offset of this thread's chunk (k0 excluded)
-  int bldsoff[NCH];     // LDS offset of this thread's chunk
-  int bcol[NCH];        // raw X: block column of the chunk
-#pragma unroll
-  for (int q = 0; q < NCH; ++q) {
+  for (int q = 0; q < NXC; ++q) {
     if constexpr (PACKED) {
-      const int c = min(tid + SK_THREADS * q, 2 * NP * CPR - 1);
-      const int pl = c / (NP * CPR), rem = c % (NP * CPR);
-      const int n = rem / CPR, ch = rem % CPR;
-      boff[q] = (uint32_t)(pl * (sX / 2) + (int64_t)(n0 + n) * ldx + ch * CK);
-      bldsoff[q] = pl * PLANE + n * ROWE + ch * CK;
-      bcol[q] = n;
+      const int c = min(tid + SK_THREADS * q, 2 * NP * XCPR - 1);
+      const int pl = c / (NP * XCPR), rem = c % (NP * XCPR);
+      const int n = rem / XCPR, ch = rem % XCPR;
+      x_goff[q] = (uint32_t)(c * CK);
+      x_loff[q] = pl * XPLANE + n * ROWE + ch * CK;
+      x_col[q] = n;
+      x_k[q] = ch * CK;
     } else {
-      const int c = min(tid + SK_THREADS * q, NP * CPR - 1);
-      const int n = c / CPR, ch = c % CPR;
-      boff[q] = (uint32_t)((int64_t)min(n0 + n, N - 1) * ldx + ch * CK);
-      bldsoff[q] = n * ROWE + ch * CK;
-      bcol[q] = n;
+      const int c = min(tid + SK_THREADS * q, NP * XCPR - 1);
+      const int n = c / XCPR, ch = c % XCPR;
+      x_goff[q] = (uint32_t)((int64_t)min(n0 + n, N - 1) * ldx);
+      x_loff[q] = n * ROWE + ch * CK;
+      x_col[q] = n;
+      x_k[q] = ch * CK;
     }
   }
-  auto load_b = [&](RB (&rb)[NCH][RBN], int k0) {
-    k0 = min(k0, kxlast);
-    if constexpr (PACKED) {
-      const E* base = reinterpret_cast<const E*>(Xv) + (int64_t)f * sX + k0;
+  auto load_stage = [&](Stage& st, int k0) {
+    // A (k-group start clamped to the last one with data: prefetches past the end are re-reads)
+    const int ka = min(k0, kglast);
 #pragma unroll
-      for (int q = 0; q < NCH; ++q) rb[q][0] = *reinterpret_cast<const u32x4*>(base + boff[q]);
+    for (int q = 0; q < NAC; ++q) {
+      if constexpr (!SAFE) {
+        st.a[q] = *reinterpret_cast<const u32x4*>(A + (CN ? (int64_t)ka : (int64_t)ka * lda) + a_goff[q]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < TAC; ++e) {
+          int row, kk;
+          if constexpr (CN) { row = m0 + a_line[q]; kk = ka + a_seg[q] * TAC + e; }
+          else { row = m0 + a_seg[q] * TAC + e; kk = ka + a_line[q]; }
+          st.ae[q][e] = A[min(row, M - 1) * (CN ? lda : (int64_t)1) + (int64_t)min(kk, K - 1) * (CN ? (int64_t)1 : lda)];
+        }
+      }
+    }
+    // X
+    if constexpr (PACKED) {
+      const int kx = min(k0, kxlast);
+      const int64_t ngr = ldx / KG;
+      const E* base = reinterpret_cast<const E*>(Xv) + (int64_t)f * sX + ((int64_t)nt * ngr + kx / KG) * (2 * NP * KG);
+#pragma unroll
+      for (int q = 0; q < NXC; ++q) st.x[q][0] = *reinterpret_cast<const u32x4*>(base + x_goff[q]);
     } else {
       const TX* X = reinterpret_cast<const TX*>(Xv) + (int64_t)f * sX;
 #pragma unroll
-      for (int q = 0; q < NCH; ++q) {
+      for (int q = 0; q < NXC; ++q) {
         if constexpr (!SAFE) {
-          vload<TX, CK>(X + k0 + boff[q], rb[q]);
+          const int kk = min(k0 + x_k[q], K - CK);   // in bounds; k >= kend is zeroed at the store
+          vload<TX, CK>(X + kk + x_goff[q], st.x[q]);
         } else {
-          const int ch = (int)(bldsoff[q] % ROWE) / CK;
-          const int64_t col = (int64_t)min(n0 + bcol[q], N - 1) * ldx;
 #pragma unroll
-          for (int e = 0; e < CK; ++e) rb[q][e] = X[min(k0 + ch * CK + e, K - 1) + col];
+          for (int e = 0; e < CK; ++e) st.x[q][e] = X[min(k0 + x_k[q] + e, K - 1) + (int64_t)x_goff[q]];
         }
       }
     }
   };
-  auto store_b = [&](const RB (&rb)[NCH][RBN], E* Bd, int k0) {
+  auto store_stage = [&](const Stage& st, unsigned char* buf, int k0) {
+    unsigned char* abuf = buf;
+    E* xbuf = reinterpret_cast<E*>(buf + ATILE);
 #pragma unroll
-    for (int q = 0; q < NCH; ++q) {
+    for (int q = 0; q < NAC; ++q) {
+      if (ACH % SK_THREADS == 0 || tid + SK_THREADS * q < ACH) {
+        if constexpr (!SAFE) {
+          *reinterpret_cast<u32x4*>(abuf + a_loff[q]) = st.a[q];
+        } else {
+          u32x4 v;
+          __builtin_memcpy(&v, &st.ae[q][0], 16);
+          *reinterpret_cast<u32x4*>(abuf + a_loff[q]) = v;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NXC; ++q) {
       if constexpr (PACKED) {
-        *reinterpret_cast<u32x4*>(Bd + bldsoff[q]) = rb[q][0];
+        *reinterpret_cast<u32x4*>(xbuf + x_loff[q]) = st.x[q][0];
       } else {
-        const int ch = (bldsoff[q] % ROWE) / CK;
-        const bool colok = n0 + bcol[q] < N;
+        const bool colok = n0 + x_col[q] < N;
         E re[CK], im[CK];
 #pragma unroll
         for (int e = 0; e < CK; ++e) {
-          const bool ok = colok && (k0 + ch * CK + e < kend);
-          const cplx<double> v = ld<double>(rb[q][e]);
+          const bool ok = colok && (k0 + x_k[q] + e < kend);
+          const cplx<double> v = ld<double>(st.x[q][e]);
           re[e] = cvt_e<E>(ok ? v.re : 0.0);
           im[e] = cvt_e<E>(ok ? v.im : 0.0);
         }
-        vstore<E, CK>(Bd + bldsoff[q], re);
-        vstore<E, CK>(Bd + PLANE + bldsoff[q], im);
+        vstore<E, CK>(xbuf + x_loff[q], re);
+        vstore<E, CK>(xbuf + XPLANE + x_loff[q], im);
       }
     }
   };
@@ -313,7 +344,25 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
 #pragma unroll
       for (int v = 0; v < 4; ++v) { accr[tt][c][v] = 0; acci[tt][c][v] = 0; }
 
-  auto compute = [&](const TA (&ra)[RT][KL], const E* Bc) {
+  // one k-group from an LDS buffer
+  auto compute = [&](const unsigned char* buf) {
+    const unsigned char* abuf = buf;
+    const E* Bc = reinterpret_cast<const E*>(buf + ATILE);
+    // A fragments of this lane: ra[tt][e] = op(A) row (rw + 2 rho + tt or rw + rho), k = KL g + e
+    TA ra[RT][KL];
+    if constexpr (!CN) {
+#pragma unroll
+      for (int e = 0; e < KL; ++e) {
+        TA tmp[RT];
+        vload<TA, RT>(reinterpret_cast<const TA*>(abuf + (KL * g + e) * ASTR) + (RT == 2 ? rw + 2 * rho : rw + rho), tmp);
+#pragma unroll
+        for (int tt = 0; tt < RT; ++tt) ra[tt][e] = tmp[tt];
+      }
+    } else {
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt)
+        vload<TA, KL>(reinterpret_cast<const TA*>(abuf + (RT == 2 ? rw + 2 * rho + tt : rw + rho) * ASTR) + KL * g, ra[tt]);
+    }
     if constexpr (std::is_same<P, B16>::value) {
       static_assert(std::is_same<TA, zb>::value, "bf16 products stream bf16 A-hat");
       bf16x8 far[RT], fai[RT], fan[RT];
@@ -331,21 +380,29 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
         fai[tt] = __builtin_bit_cast(bf16x8, CN ? imn : im);
         fan[tt] = __builtin_bit_cast(bf16x8, CN ? im : imn);
       }
+      bf16x8 br[NT], bi[NT];
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        const E* bp = Bc + (cw + 16 * c + rho) * ROWE + KL * g;
+        br[c] = *reinterpret_cast<const bf16x8*>(bp);
+        bi[c] = *reinterpret_cast<const bf16x8*>(bp + XPLANE);
+      }
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
         if (LOWER && n0 + cw + 16 * c > wmax) continue;
-        const E* bp = Bc + (cw + 16 * c + rho) * ROWE + KL * g;
-        const bf16x8 br = *reinterpret_cast<const bf16x8*>(bp);
-        const bf16x8 bi = *reinterpret_cast<const bf16x8*>(bp + PLANE);
 #pragma unroll
         for (int tt = 0; tt < RT; ++tt) {
-          accr[tt][c] = mma(far[tt], br, accr[tt][c]);
-          acci[tt][c] = mma(far[tt], bi, acci[tt][c]);
+          accr[tt][c] = mma(far[tt], br[c], accr[tt][c]);
+          acci[tt][c] = mma(far[tt], bi[c], acci[tt][c]);
         }
+      }
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        if (LOWER && n0 + cw + 16 * c > wmax) continue;
 #pragma unroll
         for (int tt = 0; tt < RT; ++tt) {
-          accr[tt][c] = mma(fan[tt], bi, accr[tt][c]);
-          acci[tt][c] = mma(fai[tt], br, acci[tt][c]);
+          accr[tt][c] = mma(fan[tt], bi[c], accr[tt][c]);
+          acci[tt][c] = mma(fai[tt], br[c], acci[tt][c]);
         }
       }
     } else {
@@ -359,63 +416,69 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
           xi[tt][e] = CN ? -v.im : v.im;
           xn[tt][e] = -xi[tt][e];
         }
+      E br[NT][KL], bi[NT][KL];
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
-        if (LOWER && n0 + cw + 16 * c > wmax) continue;
         const E* bp = Bc + (cw + 16 * c + rho) * ROWE + KL * g;
-        E br[KL], bi[KL];
-        vload<E, KL>(bp, br);
-        vload<E, KL>(bp + PLANE, bi);
+        vload<E, KL>(bp, br[c]);
+        vload<E, KL>(bp + XPLANE, bi[c]);
+      }
 #pragma unroll
-        for (int e = 0; e < KL; ++e) {
+      for (int e = 0; e < KL; ++e) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+          if (LOWER && n0 + cw + 16 * c > wmax) continue;
 #pragma unroll
           for (int tt = 0; tt < RT; ++tt) {
-            accr[tt][c] = mma(xr[tt][e], br[e], accr[tt][c]);
-            acci[tt][c] = mma(xr[tt][e], bi[e], acci[tt][c]);
+            accr[tt][c] = mma(xr[tt][e], br[c][e], accr[tt][c]);
+            acci[tt][c] = mma(xr[tt][e], bi[c][e], acci[tt][c]);
           }
+        }
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+          if (LOWER && n0 + cw + 16 * c > wmax) continue;
 #pragma unroll
           for (int tt = 0; tt < RT; ++tt) {
-            accr[tt][c] = mma(xn[tt][e], bi[e], accr[tt][c]);
-            acci[tt][c] = mma(xi[tt][e], br[e], acci[tt][c]);
+            accr[tt][c] = mma(xn[tt][e], bi[c][e], accr[tt][c]);
+            acci[tt][c] = mma(xi[tt][e], br[c][e], acci[tt][c]);
           }
         }
       }
     }
   };
 
-  // Pipeline (step j): issue the X loads of step j+3 and the A loads of step j+2, run the MFMAs of
-  // step j, write the X registers of step j+1 (loaded two steps earlier) to its LDS buffer,
-  // barrier.  Rings of three register sets and three LDS buffers; the loop body holds three steps
-  // so the rings need no register copies.
-  if (nsteps > 0) {
-    E* const B0 = Bs;
-    E* const B1 = Bs + BUF;
-    E* const B2 = Bs + 2 * BUF;
-    TA ra0[RT][KL], ra1[RT][KL], ra2[RT][KL];
-    RB rb0[NCH][RBN], rb1[NCH][RBN], rb2[NCH][RBN];
-    load_b(rb0, kbeg);
-    load_a(ra0, kbeg);
-    load_b(rb1, kbeg + KS);
-    load_a(ra1, kbeg + KS);
-    load_b(rb2, kbeg + 2 * KS);
-    store_b(rb0, B0, kbeg);
+  // Pipeline (step j): issue the loads of k-group j + SK_DEPTH into ring set (j + DEPTH) % RING,
+  // compute k-group j from LDS buffer j % 2, store set (j + 1) % RING into buffer (j + 1) % 2,
+  // barrier.  The loop body holds SK_RING = 4 steps (ring and buffer parities repeat), with no
+  // branches, so the prefetches stay where they are issued.
+  static_assert(SK_RING == 4, "the unrolled loop below assumes a ring of four stages");
+  if (nkg > 0) {
+    unsigned char* const buf0 = sk_lds;
+    unsigned char* const buf1 = sk_lds + BUFB;
+    Stage s0, s1, s2, s3;
+    load_stage(s0, kbeg);
+    load_stage(s1, kbeg + KG);
+    load_stage(s2, kbeg + 2 * KG);
+    store_stage(s0, buf0, kbeg);
     __syncthreads();
-    int k0 = kbeg;
-    auto step = [&](const TA (&cur)[RT][KL], TA (&pre)[RT][KL], RB (&rbload)[NCH][RBN], const RB (&rbstore)[NCH][RBN],
-                    const E* Bcur, E* Bnext) {
-      load_b(rbload, k0 + 3 * KS);
-      load_a(pre, k0 + 2 * KS);
-      compute(cur, Bcur);
-      store_b(rbstore, Bnext, k0 + KS);
-      __syncthreads();
-      __builtin_amdgcn_sched_barrier(0);  // keep each step's MFMAs between its own barriers
-      k0 += KS;
-    };
-    for (int j = 0; j < nsteps3; j += 3) {
-      step(ra0, ra2, rb0, rb1, B0, B1);
-      step(ra1, ra0, rb1, rb2, B1, B2);
-      step(ra2, ra1, rb2, rb0, B2, B0);
+    // sched_barrier: keep the loads issued before the MFMAs of the step (the scheduler would
+    // otherwise sink them past the LDS stores, whose waits then cover every load in flight)
+#define RT_SK_STEP(LOADSET, KLOAD, BUFC, STORESET, BUFN, KSTORE) \
+    load_stage(LOADSET, KLOAD);                                  \
+    __builtin_amdgcn_sched_barrier(0);                           \
+    compute(BUFC);                                               \
+    __builtin_amdgcn_sched_barrier(0);                           \
+    store_stage(STORESET, BUFN, KSTORE);                         \
+    __syncthreads();                                             \
+    __builtin_amdgcn_sched_barrier(0);
+    for (int j = 0; j < nkgr; j += SK_RING) {
+      const int k0 = kbeg + j * KG;
+      RT_SK_STEP(s3, k0 + 3 * KG, buf0, s1, buf1, k0 + KG)
+      RT_SK_STEP(s0, k0 + 4 * KG, buf1, s2, buf0, k0 + 2 * KG)
+      RT_SK_STEP(s1, k0 + 5 * KG, buf0, s3, buf1, k0 + 3 * KG)
+      RT_SK_STEP(s2, k0 + 6 * KG, buf1, s0, buf0, k0 + 4 * KG)
     }
+#undef RT_SK_STEP
   }
 
   // ---- store ----
@@ -479,13 +542,14 @@ template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, typename TA, typ
 static int sk_launch_nt(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const void* X, int64_t ldx,
                         int64_t sX, TC* C, int64_t ldc, int64_t sC, int batch, int ksplit, int64_t sCsplit,
                         hipStream_t s) {
-  constexpr int BM = Shape<NT>::WR * 16 * P::RT, NP = 16 * NT, KS = 4 * P::KL;
+  constexpr int BM = Shape<NT>::WR * 16 * P::RT, NP = 16 * NT, KS = kgroup<P>();
+  static_assert(NP > 0 && BM > 0, "shape");
   const int mtiles = (int)ceil_div(M, BM), ntiles = (int)ceil_div(N, NP);
   const int tiles = mtiles * ntiles;
   int64_t nblk = (int64_t)batch * tiles;
   if (batch >= 8) nblk = ceil_div(batch, 8) * 8 * (int64_t)tiles;
   const int kchunk = (int)(ceil_div(ceil_div(K, ksplit), KS) * KS);
-  const int bytes = lds_bytes<P>(NT);
+  const int bytes = lds_bytes<P, CN, TA>(NT, BM);
   static int attr_done[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
@@ -535,8 +599,10 @@ template <> struct PrecOf<zf> { typedef F32 P; };
 template <> struct PrecOf<zd> { typedef F64 P; };
 
 // bytes of packed X planes for a product with contraction length K and N columns
-// packed X rows are zero-padded to a multiple of three macro steps (the k loop runs in threes)
-template <class P> static inline int packed_kp(int K) { return (int)(ceil_div(K, 12 * P::KL) * 12 * P::KL); }
+// packed X rows are zero-padded to whole rings of k-groups (the k loop runs in rings)
+template <class P> static inline int packed_kp(int K) {
+  return (int)(ceil_div(K, SK_RING * kgroup<P>()) * SK_RING * kgroup<P>());
+}
 template <class P> static inline int64_t packed_elems(int K, int N, int batch) {
   const int NP = 16 * nt_for<P>(N);
   const int64_t KP = packed_kp<P>(K);
@@ -560,9 +626,11 @@ static int skinny_cgemm(bool conjA, int M, int N, int K, const TA* A, int64_t ld
   const int KP = packed_kp<P>(K);
   const int NPt = (int)(ceil_div(N, NP) * NP);
   E* Xp = static_cast<E*>(ws);
+  constexpr int KSL = kslab<P>();
+  const int ntl = NPt / NP;
   const int64_t total = (int64_t)NPt * KP * batch;
-  hipLaunchKernelGGL((k_pack_planes<TX, E>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, X, ldx, sX, K, N,
-                     Xp, KP, NPt, batch);
+  hipLaunchKernelGGL((k_pack_slabs<TX, E, KSL>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, X, ldx, sX, K, N,
+                     Xp, KP, NP, ntl, batch);
   if (hipGetLastError() != hipSuccess) return -1;
   const int64_t sXp = 2 * (int64_t)NPt * KP;
   // packed X: the raw type parameter is unused, fixed to zd to share instantiations
