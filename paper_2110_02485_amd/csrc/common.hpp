@@ -36,6 +36,10 @@ template <typename T> RT_HOST_DEVICE T cabs2(cplx<T> a) { return a.re * a.re + a
 // bf16 (round to nearest even) <-> float
 // ---------------------------------------------------------------------------------------------
 RT_HOST_DEVICE uint32_t f2bf(float f) {
+#ifdef __HIP_DEVICE_COMPILE__
+  // gfx950 converts with round to nearest even in one instruction (no branch for inf / nan)
+  return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)f);
+#endif
   union { float f; uint32_t u; } v; v.f = f;
   uint32_t u = v.u;
   if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // inf / nan

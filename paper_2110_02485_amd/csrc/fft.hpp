@@ -115,6 +115,110 @@ k_rfft_pow2(const Tin* __restrict__ in, int64_t ntubes, int n, int log2n, int TB
   }
 }
 
+// Register-resident forward transform for short power-of-two tubes (N <= 128 in FP32, <= 64 in
+// FP64): one thread per tube, so one tube element of 64 consecutive tubes is one contiguous
+// 64-lane load and one face of 64 tubes one contiguous store.  The N real samples are packed
+// into M = N/2 complex values z_j = x_{2j} + i x_{2j+1}, Z = DFT_M(z) by radix-2 decimation in
+// frequency (output in bit-reversed order, all indices compile-time so the data stays in VGPRs),
+// then X_f = E_f + w^f O_f with E_f = (Z_f + conj Z_{M-f})/2, O_f = (Z_f - conj Z_{M-f})/(2i),
+// w = exp(-2 pi i / N).  gtw[k] = w^k for k < N/2 (uniform reads, served from the scalar cache).
+constexpr int RFFT_REG_THREADS = 256;
+
+template <int B> constexpr int bitrev(int k) {
+  int r = 0;
+  for (int i = 0; i < B; ++i) r |= ((k >> i) & 1) << (B - 1 - i);
+  return r;
+}
+constexpr int ilog2_ce(int n) { return n <= 1 ? 0 : 1 + ilog2_ce(n / 2); }
+
+template <int N, bool HALF, typename Tin, typename T>
+__global__ void __launch_bounds__(RFFT_REG_THREADS)
+k_rfft_reg(const Tin* __restrict__ in, int64_t ntubes, cplx<T>* __restrict__ out, int64_t face_stride,
+           zb* __restrict__ out16, double* __restrict__ sumsq, const cplx<T>* __restrict__ gtw) {
+  constexpr int M = N / 2, LM = ilog2_ce(M);
+  // One uniform base and 32-bit byte offsets (the host launches this kernel only for tensors
+  // below 4 GiB): per-element 64-bit row pointers would overflow the scalar register file.
+  const int64_t g0 = (int64_t)blockIdx.x * RFFT_REG_THREADS;
+  const bool live = g0 + (int)threadIdx.x < ntubes;
+  const unsigned lt = live ? threadIdx.x : 0u;  // lane 0 of every block holds a valid tube
+  const char* __restrict__ ib = reinterpret_cast<const char*>(in + g0);
+  const unsigned rstride = (unsigned)(ntubes * (int64_t)sizeof(Tin));
+  T re[M], im[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    re[j] = (T)*reinterpret_cast<const Tin*>(ib + (lt * (unsigned)sizeof(Tin) + (unsigned)(2 * j) * rstride));
+    im[j] = (T)*reinterpret_cast<const Tin*>(ib + (lt * (unsigned)sizeof(Tin) + (unsigned)(2 * j + 1) * rstride));
+  }
+  // sum of squares reduced over the wave before the transform overwrites the samples (left for
+  // later, the compiler would keep a second copy of all N samples live through the butterflies)
+  __shared__ double red[RFFT_REG_THREADS / 64];
+  if (sumsq) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc += (double)re[j] * (double)re[j] + (double)im[j] * (double)im[j];
+    if (!live) acc = 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // decimation in frequency: span M/2, M/4, ..., 1; twiddle w_M^{j * M/(2 span)} = w_N^{2 j M/(2 span)}
+#pragma unroll
+  for (int st_ = 0; st_ < LM; ++st_) {
+    const int span = M >> (st_ + 1);
+#pragma unroll
+    for (int b = 0; b < M; b += 2 * span)
+#pragma unroll
+      for (int j = 0; j < span; ++j) {
+        const int u = b + j, v = b + j + span;
+        const T ar = re[u] - re[v], ai = im[u] - im[v];
+        re[u] += re[v];
+        im[u] += im[v];
+        if (j == 0) {
+          re[v] = ar; im[v] = ai;
+        } else {
+          const cplx<T> w = gtw[j * (N / (2 * span))];
+          re[v] = ar * w.re - ai * w.im;
+          im[v] = ar * w.im + ai * w.re;
+        }
+      }
+  }
+  char* __restrict__ ob = reinterpret_cast<char*>(out + g0);
+  char* __restrict__ hb = reinterpret_cast<char*>(out16 + g0);
+  const unsigned ostride = (unsigned)(face_stride * (int64_t)sizeof(cplx<T>));
+  const unsigned hstride = (unsigned)(face_stride * 4);
+  if (live) {
+#pragma unroll
+    for (int f = 0; f <= M; ++f) {
+      const int i1 = bitrev<LM>(f % M), i2 = bitrev<LM>((M - f) % M);
+      cplx<T> x;
+      if (f == 0) {
+        x = mk(re[0] + im[0], (T)0);
+      } else if (f == M) {
+        x = mk(re[0] - im[0], (T)0);
+      } else {
+        const T zr = re[i1], zi = im[i1], cr = re[i2], ci = -im[i2];
+        const T er = (T)0.5 * (zr + cr), ei = (T)0.5 * (zi + ci);
+        const T dr = zr - cr, di = zi - ci;
+        const T orr = (T)0.5 * di, oi = (T)-0.5 * dr;
+        const cplx<T> w = gtw[f];
+        x = mk(er + (w.re * orr - w.im * oi), ei + (w.re * oi + w.im * orr));
+      }
+      *reinterpret_cast<cplx<T>*>(ob + (lt * (unsigned)sizeof(cplx<T>) + (unsigned)f * ostride)) = x;
+      if constexpr (HALF) st(*reinterpret_cast<zb*>(hb + (lt * 4u + (unsigned)f * hstride)), x);
+    }
+  }
+  if (sumsq) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < RFFT_REG_THREADS / 64; ++w) t += red[w];
+      sumsq[blockIdx.x] = t;
+    }
+  }
+}
+
 // inverse: half spectrum (type T) -> real tubes (output type Tout), scaled by 1/n.
 template <typename T, typename Tout>
 __global__ void __launch_bounds__(FFT_THREADS)
@@ -267,7 +371,32 @@ template <typename Tin, typename T>
 int launch_rfft(const Tin* in, int64_t ntubes, int n, cplx<T>* out, int64_t face_stride, zb* out16,
                 double* sumsq, int64_t* nblocks_out, hipStream_t s) {
   const int lg = ilog2_exact(n);
-  if (lg >= 0 && n >= 2 && (int64_t)(2 * (n + 2) + n / 2) * (int64_t)sizeof(cplx<T>) <= 48 * 1024) {
+  const int reg_max = sizeof(T) == 4 ? 128 : 64;
+  const bool small = ntubes * n * (int64_t)sizeof(Tin) < (1LL << 32) &&
+                     (face_stride * (n / 2 + 1) + ntubes) * (int64_t)sizeof(cplx<T>) < (1LL << 32);
+  if (lg >= 2 && n <= reg_max && small) {
+    const cplx<T>* tw = twiddles<T>(n, s);
+    if (!tw) return -1;
+    const int64_t blocks = ceil_div(ntubes, RFFT_REG_THREADS);
+    switch (n) {
+#define RT_RFFT_REG(NN)                                                                                  \
+  case NN:                                                                                               \
+    if constexpr (NN * sizeof(T) <= 512)                                                                 \
+    {                                                                                                  \
+      if (out16)                                                                                         \
+        hipLaunchKernelGGL((k_rfft_reg<NN, true, Tin, T>), dim3((unsigned)blocks), dim3(RFFT_REG_THREADS), \
+                           0, s, in, ntubes, out, face_stride, out16, sumsq, tw);                        \
+      else                                                                                               \
+        hipLaunchKernelGGL((k_rfft_reg<NN, false, Tin, T>), dim3((unsigned)blocks), dim3(RFFT_REG_THREADS), \
+                           0, s, in, ntubes, out, face_stride, out16, sumsq, tw);                        \
+    }                                                                                                    \
+    break;
+      RT_RFFT_REG(4) RT_RFFT_REG(8) RT_RFFT_REG(16) RT_RFFT_REG(32) RT_RFFT_REG(64) RT_RFFT_REG(128)
+#undef RT_RFFT_REG
+      default: return -1;
+    }
+    if (nblocks_out) *nblocks_out = blocks;
+  } else if (lg >= 0 && n >= 2 && (int64_t)(2 * (n + 2) + n / 2) * (int64_t)sizeof(cplx<T>) <= 48 * 1024) {
     const int TB = fft_tile<T>(n);
     const int64_t blocks = ceil_div(ntubes, TB);
     const size_t lds = (size_t)(2 * (n + 2) * (TB / 2) + n / 2) * sizeof(cplx<T>);
