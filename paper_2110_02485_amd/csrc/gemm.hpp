@@ -85,11 +85,101 @@ k_cgemm(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
     }
 }
 
+// Few right-hand sides (N <= GEMV_NP, op(B) = B): matrix-vector products, bound by the one pass
+// over A.  A^H X: one wave per output row (a stored column of A, read contiguously by the lanes),
+// reduced across the wave.  A X: one lane per output row, the K range split over the 4 waves of
+// the block and reduced in LDS.
+constexpr int GEMV_NP = 4;
+
+template <typename TA, typename TB, typename TC, typename Acc, int NP>
+__global__ void __launch_bounds__(256)
+k_gemv_cn(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
+          const TB* __restrict__ B, int64_t ldb, int64_t sB, TC* __restrict__ C, int64_t ldc, int64_t sC,
+          Acc alpha, int accumulate) {
+  const int f = blockIdx.y;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= M) return;
+  const TA* __restrict__ a = A + f * sA + (int64_t)i * lda;
+  const TB* __restrict__ b = B + f * sB;
+  cplx<Acc> acc[NP];
+#pragma unroll
+  for (int c = 0; c < NP; ++c) acc[c] = mk((Acc)0, (Acc)0);
+#pragma unroll 4
+  for (int k = lane; k < K; k += 64) {
+    const cplx<Acc> av = ld<Acc>(a[k]);
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+      if (c < N) acc[c] = cadd(acc[c], cmulc(av, ld<Acc>(b[k + c * ldb])));  // conj(a) b
+  }
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    cplx<Acc> v = acc[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { v.re += __shfl_xor(v.re, o, 64); v.im += __shfl_xor(v.im, o, 64); }
+    if (lane == 0 && c < N) {
+      v = cscale(v, alpha);
+      TC& dst = C[f * sC + i + (int64_t)c * ldc];
+      if (accumulate) v = cadd(v, ld<Acc>(dst));
+      st(dst, v);
+    }
+  }
+}
+
+template <typename TA, typename TB, typename TC, typename Acc, int NP>
+__global__ void __launch_bounds__(256)
+k_gemv_nn(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
+          const TB* __restrict__ B, int64_t ldb, int64_t sB, TC* __restrict__ C, int64_t ldc, int64_t sC,
+          Acc alpha, int accumulate) {
+  __shared__ cplx<Acc> part[3][NP][64];
+  const int f = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const bool on = i < M;
+  const TA* __restrict__ a = A + f * sA + (on ? i : 0);
+  const TB* __restrict__ b = B + f * sB;
+  const int kq = (K + 3) / 4, k0 = w * kq, k1 = min(K, k0 + kq);
+  cplx<Acc> acc[NP];
+#pragma unroll
+  for (int c = 0; c < NP; ++c) acc[c] = mk((Acc)0, (Acc)0);
+#pragma unroll 8
+  for (int k = k0; k < k1; ++k) {
+    const cplx<Acc> av = ld<Acc>(a[(int64_t)k * lda]);
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+      if (c < N) acc[c] = cadd(acc[c], cmul(av, ld<Acc>(b[k + c * ldb])));
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) part[w - 1][c][lane] = acc[c];
+  }
+  __syncthreads();
+  if (w == 0 && on) {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      if (c >= N) break;
+      cplx<Acc> v = cadd(cadd(acc[c], part[0][c][lane]), cadd(part[1][c][lane], part[2][c][lane]));
+      v = cscale(v, alpha);
+      TC& dst = C[f * sC + i + (int64_t)c * ldc];
+      if (accumulate) v = cadd(v, ld<Acc>(dst));
+      st(dst, v);
+    }
+  }
+}
+
 template <typename TA, typename TB, typename TC, typename Acc>
 int cgemm(bool conjA, bool conjB, int M, int N, int K, const TA* A, int64_t lda, int64_t sA,
           const TB* B, int64_t ldb, int64_t sB, TC* C, int64_t ldc, int64_t sC, int batch,
           Acc alpha, bool accumulate, hipStream_t s) {
   if (M <= 0 || N <= 0 || batch <= 0) return 0;
+  if (N <= GEMV_NP && !conjB && K > 0) {
+    if (conjA)
+      hipLaunchKernelGGL((k_gemv_cn<TA, TB, TC, Acc, GEMV_NP>), dim3((unsigned)ceil_div(M, 4), (unsigned)batch),
+                         dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate);
+    else
+      hipLaunchKernelGGL((k_gemv_nn<TA, TB, TC, Acc, GEMV_NP>), dim3((unsigned)ceil_div(M, 64), (unsigned)batch),
+                         dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   constexpr int BM = 64, BN = 64, BK = 8;
   dim3 grid((unsigned)ceil_div(M, BM), (unsigned)ceil_div(N, BN), (unsigned)batch);
   if (!conjA && !conjB)
