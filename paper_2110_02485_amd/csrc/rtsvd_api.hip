@@ -438,7 +438,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
       // error indicator eta^[j] (Thm 4.2)
       hipLaunchKernelGGL((k_colnorms<zd>), dim3((unsigned)r, (unsigned)F), dim3(256), 0, s, Ch, (int)m, (int)r, rown);
       RT_LAUNCH_OK();
-      hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, rown, (int)F, (int)r, (int)n, eta);
+      hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, rown, (int)F, (int)r, (int)n, eta);
       RT_LAUNCH_OK();
       // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
       RT_TRY(gram<zd>(Ch, m, r, F, G, sc, s));
@@ -468,7 +468,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     RT_TRY(launch_heev(G, (int)m, F, V, lam, sc, s));
     hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
     RT_LAUNCH_OK();
-    hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(256), 0, s, sumsq, nblk, lam, (int)F, (int)r, (int)n, eta);
+    hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, lam, (int)F, (int)r, (int)n, eta);
     RT_LAUNCH_OK();
     RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, r, Wo, F, sc, s)));
     RT_ALLOC(Uo, zw, F * l * r, sc);
@@ -617,7 +617,7 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   RT_ALLOC(bnd, double, groups, sc);
   RT_ALLOC(rho_tmp, double, (int64_t)groups * kcap, sc);
   RT_TRY(upload_doubles(bnd, bounds.data(), groups, s));
-  hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(256), 0, s, partial, (int)F, tiles, (int)p, kcap, (int)n, groups, bnd,
+  hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(DP_SEL_THREADS), 0, s, partial, (int)F, tiles, (int)p, kcap, (int)n, groups, bnd,
                      k_start, k_out, resid_out, status_out, rho_tmp);
   RT_LAUNCH_OK();
   // X-hat = V T', T' = T with rows >= k zeroed; X = inverse DFT

@@ -13,7 +13,10 @@
 
 namespace rt {
 
-constexpr int DP_ROWS = 256;
+constexpr int DP_ROWS = 64;        // rows per block (one wave) of the residual pass
+constexpr int DP_KCH = 64;         // residual orders per transposition chunk
+constexpr int DP_SEL_THREADS = 1024;
+constexpr int HEEV_RMAX_SOLVE = 256;  // largest r (the eigensolver's limit)
 
 // T = diag(1/sigma) E, zero where sigma <= 0 (dependent columns excluded from the pseudo-inverse)
 __global__ void k_scale_rows(zd* __restrict__ T, const double* __restrict__ sigma, int r, int p, int F) {
@@ -27,56 +30,74 @@ __global__ void k_scale_rows(zd* __restrict__ T, const double* __restrict__ sigm
 }
 
 // partial[((f * tiles + tile) * p + c) * kcap + (k-1)] = sum over the tile's rows of
-// |B-hat - W[:, :k] T[:k, c]|^2, FP64.  Block = DP_ROWS threads = one row tile of one column.
+// |B-hat - W[:, :k] T[:k, c]|^2, FP64.  Block = one wave = one 64-row tile of one column.  The
+// residual is updated one rank-1 term at a time; the 64 row values of each order k are summed
+// through an LDS transposition (lane kk sums row kk of a 64 x 64 chunk), so there is no
+// per-order cross-lane reduction chain.
 template <typename TBh, typename TW>
 __global__ void __launch_bounds__(DP_ROWS)
 k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __restrict__ T,
              int l, int p, int r, int kcap, double* __restrict__ partial) {
   const int tile = blockIdx.x, c = blockIdx.y, f = blockIdx.z;
   const int tiles = gridDim.x;
-  const int row = tile * DP_ROWS + threadIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ double wsum[DP_ROWS / 64][256];
-  zd R = mk(0.0, 0.0);
+  const int lane = threadIdx.x;
+  const int row = tile * DP_ROWS + lane;
+  __shared__ double sq[DP_KCH][DP_ROWS + 1];
   const bool on = row < l;
+  zd R = mk(0.0, 0.0);
   if (on) R = ld<double>(Bh[(int64_t)f * l * p + (int64_t)c * l + row]);
-  const TW* wf = W + (int64_t)f * l * r;
-  const zd* tf = T + (int64_t)f * r * p + (int64_t)c * r;
-  for (int k = 1; k <= kcap; ++k) {
-    if (on) R = csub(R, cmul(ld<double>(wf[(int64_t)(k - 1) * l + row]), tf[k - 1]));
-    double v = on ? cabs2(R) : 0.0;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) wsum[wave][k - 1] = v;
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < kcap; k += blockDim.x) {
-    double s = 0.0;
-    for (int w = 0; w < DP_ROWS / 64; ++w) s += wsum[w][k];
-    partial[(((int64_t)f * tiles + tile) * p + c) * kcap + k] = s;
+  const TW* __restrict__ wf = W + (int64_t)f * l * r + (on ? row : 0);
+  const zd* __restrict__ tf = T + (int64_t)f * r * p + (int64_t)c * r;
+  double* __restrict__ out = partial + (((int64_t)f * tiles + tile) * p + c) * kcap;
+  for (int k0 = 0; k0 < kcap; k0 += DP_KCH) {
+    const int kn = min(DP_KCH, kcap - k0);
+#pragma unroll 8
+    for (int kk = 0; kk < kn; ++kk) {
+      const int k = k0 + kk;                       // order k+1 uses column k
+      R = csub(R, cmul(ld<double>(wf[(int64_t)k * l]), tf[k]));
+      sq[kk][lane] = on ? cabs2(R) : 0.0;
+    }
+    __syncthreads();
+    if (lane < kn) {
+      double s = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < DP_ROWS; ++i) s += sq[lane][i];
+      out[k0 + lane] = s;
+    }
+    __syncthreads();
   }
 }
 
-// One block.  groups = 1 (joint) or p (per slice).  k_start >= 1.
-__global__ void k_dp_select(const double* __restrict__ partial, int F, int tiles, int p, int kcap, int n,
-                            int groups, const double* __restrict__ bound /* eta*delta per group */,
-                            int k_start, int* __restrict__ k_out, double* __restrict__ resid_out,
-                            int* __restrict__ status_out, double* __restrict__ rho_tmp) {
+// One block of DP_SEL_THREADS.  groups = 1 (joint) or p (per slice).  k_start >= 1.
+// rho_k^2 = (1/n) sum_f w_f sum_{tiles, columns of the group} partial: one wave per (group, k),
+// summed in a fixed order (deterministic).
+__global__ void __launch_bounds__(DP_SEL_THREADS)
+k_dp_select(const double* __restrict__ partial, int F, int tiles, int p, int kcap, int n,
+            int groups, const double* __restrict__ bound /* eta*delta per group */,
+            int k_start, int* __restrict__ k_out, double* __restrict__ resid_out,
+            int* __restrict__ status_out, double* __restrict__ rho_tmp) {
   // rho_tmp: groups * kcap doubles of scratch
-  for (int idx = threadIdx.x; idx < groups * kcap; idx += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int idx = wave; idx < groups * kcap; idx += nw) {
     const int g = idx / kcap, k = idx % kcap;
-    const int c0 = groups == 1 ? 0 : g, c1 = groups == 1 ? p : g + 1;
-    double tot = 0.0;
-    for (int f = 0; f < F; ++f) {
-      const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
-      double s = 0.0;
-      for (int t = 0; t < tiles; ++t)
-        for (int c = c0; c < c1; ++c) s += partial[(((int64_t)f * tiles + t) * p + c) * kcap + k];
-      tot += w * s;
+    const int c0 = groups == 1 ? 0 : g, nc = groups == 1 ? p : 1;
+    const int per = tiles * nc, cnt = F * per;
+    double s = 0.0;
+    for (int e = lane; e < cnt; e += 64) {
+      const int fi = e / per, rem = e % per;
+      const int t = rem / nc, c = c0 + rem % nc;
+      const double w = (fi == 0 || 2 * fi == n) ? 1.0 : 2.0;
+      s += w * partial[(((int64_t)fi * tiles + t) * p + c) * kcap + k];
     }
-    const double rho = sqrt(fmax(tot / (double)n, 0.0));
-    rho_tmp[idx] = rho;
-    if (resid_out) resid_out[idx] = rho;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) {
+      const double rho = sqrt(fmax(s / (double)n, 0.0));
+      rho_tmp[idx] = rho;
+      if (resid_out) resid_out[idx] = rho;
+    }
   }
+  __threadfence_block();
   __syncthreads();
   __shared__ int any_fail;
   if (threadIdx.x == 0) any_fail = 0;
@@ -121,27 +142,30 @@ __global__ void k_colnorms(const TC* __restrict__ Ch, int m, int r, double* __re
   if (threadIdx.x == 0) rown[(int64_t)f * r + j] = red[0];
 }
 
-// eta[j] = ||A||^2 - (1/n) sum_f w_f sum_{j' < j} rown[f][j'],  j = 0..r  (one block)
-__global__ void k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __restrict__ rown,
-                             int F, int r, int n, double* __restrict__ eta) {
-  __shared__ double red[256];
-  __shared__ double rows[257];
+// eta[j] = ||A||^2 - (1/n) sum_f w_f sum_{j' < j} rown[f][j'],  j = 0..r  (one block of
+// DP_SEL_THREADS; fixed summation order)
+__global__ void __launch_bounds__(DP_SEL_THREADS)
+k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __restrict__ rown,
+             int F, int r, int n, double* __restrict__ eta) {
+  __shared__ double red[DP_SEL_THREADS / 64];
+  __shared__ double rows[HEEV_RMAX_SOLVE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < nsumsq; i += blockDim.x) s += sumsq[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) red[wave] = s;
+  for (int j = wave; j < r; j += nw) {
     double t = 0.0;
-    for (int f = 0; f < F; ++f) t += ((f == 0 || 2 * f == n) ? 1.0 : 2.0) * rown[(int64_t)f * r + j];
-    rows[j] = t / (double)n;
+    for (int f = lane; f < F; f += 64) t += ((f == 0 || 2 * f == n) ? 1.0 : 2.0) * rown[(int64_t)f * r + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) rows[j] = t / (double)n;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double e = red[0];
+    double e = 0.0;
+    for (int w = 0; w < nw; ++w) e += red[w];
     eta[0] = e;
     for (int j = 0; j < r; ++j) { e -= rows[j]; eta[j + 1] = e; }
   }
