@@ -32,6 +32,9 @@ template <typename T> RT_HOST_DEVICE cplx<T> cconj(cplx<T> a) { return mk(a.re, 
 template <typename T> RT_HOST_DEVICE cplx<T> cscale(cplx<T> a, T s) { return mk(a.re * s, a.im * s); }
 template <typename T> RT_HOST_DEVICE T cabs2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
 
+RT_HOST_DEVICE double cadd_any(double a, double b) { return a + b; }
+template <typename T> RT_HOST_DEVICE cplx<T> cadd_any(cplx<T> a, cplx<T> b) { return cadd(a, b); }
+
 // ---------------------------------------------------------------------------------------------
 // bf16 (round to nearest even) <-> float
 // ---------------------------------------------------------------------------------------------
@@ -59,6 +62,38 @@ template <typename Acc> RT_HOST_DEVICE void st(zf& d, cplx<Acc> v) { d.re = (flo
 template <typename Acc> RT_HOST_DEVICE void st(zb& d, cplx<Acc> v) {
   d.bits = f2bf((float)v.re) | (f2bf((float)v.im) << 16);
 }
+
+// ---------------------------------------------------------------------------------------------
+// cross-lane moves by DPP (data-parallel primitives: VALU operand swizzles within 16-lane rows,
+// no LDS round trip).  All lanes of the wave must be active.
+// ---------------------------------------------------------------------------------------------
+constexpr int DPP_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_MIRROR8 = 0x141;  // row_half_mirror: lane i <- 7 - i within 8 lanes
+constexpr int DPP_MIRROR16 = 0x140; // row_mirror: lane i <- 15 - i within 16 lanes
+constexpr int DPP_ROR8 = 0x128;     // row_ror:8: lane i <- i ^ 8 within 16 lanes
+
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL> __device__ __forceinline__ cplx<double> dpp(cplx<double> v) { return mk(dpp<CTRL>(v.re), dpp<CTRL>(v.im)); }
+// sum over the 16 lanes of a row, every lane gets it
+template <typename T> __device__ __forceinline__ T row_sum16(T v) {
+  v = cadd_any(v, dpp<DPP_XOR1>(v));
+  v = cadd_any(v, dpp<DPP_XOR2>(v));
+  v = cadd_any(v, dpp<DPP_MIRROR8>(v));
+  v = cadd_any(v, dpp<DPP_MIRROR16>(v));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_sum16(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+__device__ __forceinline__ cplx<double> wave_sum(cplx<double> v) { return mk(wave_sum(v.re), wave_sum(v.im)); }
 
 // ---------------------------------------------------------------------------------------------
 // error handling on the host

@@ -134,6 +134,256 @@ __device__ __forceinline__ int sturm_count_fast(const double* d, const double* e
   return cnt;
 }
 
+// Gershgorin interval, norm, pivot floor and absolute tolerance of the tridiagonal (d, e)
+struct TriBounds { double gl, gu, tnorm, pivmin, atol; };
+__device__ __forceinline__ TriBounds tri_bounds(const double* d, const double* e, const double* e2, int r) {
+  double gl = 1e308, gu = -1e308, emax2 = 0.0;
+  for (int i = 0; i < r; ++i) {
+    const double off = fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0);
+    gl = fmin(gl, d[i] - off);
+    gu = fmax(gu, d[i] + off);
+    emax2 = fmax(emax2, e2[i]);
+  }
+  TriBounds tb;
+  const double eps = 2.220446049250313e-16;
+  tb.tnorm = fmax(fabs(gl), fabs(gu));
+  tb.pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  tb.atol = 2.0 * eps * tb.tnorm + 4.0 * tb.pivmin;
+  tb.gl = gl - (2.0 * eps * tb.tnorm + tb.pivmin);
+  tb.gu = gu + (2.0 * eps * tb.tnorm + tb.pivmin);
+  return tb;
+}
+
+// j-th largest eigenvalue of the tridiagonal by multisection: the 8 aligned lanes of a group
+// (sub = lane & 7) evaluate Sturm counts at 8 interior points per round.  All lanes of the group
+// return the same value.
+__device__ __forceinline__ double tri_eigval(const double* d, const double* e2, int r, int j, bool on, int sub,
+                                             const TriBounds& tb) {
+  const double eps = 2.220446049250313e-16;
+  const int a = r - 1 - (on ? j : 0);           // ascending index
+  double lo = tb.gl, hi = tb.gu;
+  for (int it = 0; it < 200; ++it) {
+    if (hi - lo <= tb.atol + 2.0 * eps * fmax(fabs(lo), fabs(hi))) break;
+    const double x = lo + (hi - lo) * (double)(sub + 1) / 9.0;
+    const int cnt = on ? sturm_count_fast(d, e2, r, x, tb.pivmin) : 0;
+    double nlo = (cnt <= a) ? x : -1e308;
+    double nhi = (cnt > a) ? x : 1e308;
+    nlo = fmax(nlo, dpp<DPP_XOR1>(nlo));
+    nhi = fmin(nhi, dpp<DPP_XOR1>(nhi));
+    nlo = fmax(nlo, dpp<DPP_XOR2>(nlo));
+    nhi = fmin(nhi, dpp<DPP_XOR2>(nhi));
+    nlo = fmax(nlo, dpp<DPP_MIRROR8>(nlo));
+    nhi = fmin(nhi, dpp<DPP_MIRROR8>(nhi));
+    if (nlo > lo) lo = nlo;
+    if (nhi < hi) hi = nhi;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Number of eigenvalues below x of the tridiagonal (ds, e2s), by sign changes of the leading
+// principal minors p_i = det(T_i - x I):  p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2},  p_0 = 1.
+// One fused multiply-add per row on the dependency chain (the ratio form needs a division).
+// Expects the matrix prescaled by a power of two so that |d|, |e| <= 1; the pair (p_{i-1}, p_i)
+// is rescaled by an exact power of two every 4 rows, and an exact zero takes the sign opposite
+// to its predecessor (a relative perturbation of 2^-60).  Each computed p_i is the exact minor of
+// a tridiagonal with d_i and e_{i-1}^2 perturbed by a few ulps, so the count is backward stable.
+__device__ __forceinline__ int sturm_count_minors_safe(const double* __restrict__ ds, const double* __restrict__ e2s,
+                                                       int r, double x) {
+  double pm = 1.0, pmm = 0.0;
+  int cnt = 0;
+  for (int i = 0; i < r; ++i) {
+    double p = fma(ds[i] - x, pm, -(i > 0 ? e2s[i - 1] : 0.0) * pmm);
+    p = p == 0.0 ? -pm * 0x1p-60 : p;
+    cnt += ((p < 0.0) != (pm < 0.0)) ? 1 : 0;
+    pmm = pm;
+    pm = p;
+    if ((i & 3) == 3) {
+      const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pm), fabs(pmm)));
+      pm = ldexp(pm, -ex);
+      pmm = ldexp(pmm, -ex);
+    }
+  }
+  return cnt;
+}
+
+// Fast path: only the fused multiply-add is on the dependency chain; signs are counted from the
+// high words, and a lane that meets an exact zero minor recounts with the guarded recurrence
+// (sturm_count_minors_safe: the zero takes the sign opposite to its predecessor).
+__device__ __forceinline__ int sturm_count_minors(const double* __restrict__ ds, const double* __restrict__ e2s, int r,
+                                                  double x) {
+  double pm = 1.0, pmm = 0.0;
+  int cnt = 0;
+  unsigned zero = 0u;
+  int i = 0;
+  for (; i + 4 <= r; i += 4) {
+    double dv[4], ev[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { dv[u] = ds[i + u] - x; ev[u] = (i + u > 0) ? e2s[i + u - 1] : 0.0; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double p = fma(dv[u], pm, -ev[u] * pmm);
+      const unsigned hp = (unsigned)(__double_as_longlong(p) >> 32), hm = (unsigned)(__double_as_longlong(pm) >> 32);
+      cnt += (int)((hp ^ hm) >> 31);
+      zero |= (unsigned)(p == 0.0);
+      pmm = pm;
+      pm = p;
+    }
+    const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pm), fabs(pmm)));
+    pm = ldexp(pm, -ex);
+    pmm = ldexp(pmm, -ex);
+  }
+  for (; i < r; ++i) {
+    const double p = fma(ds[i] - x, pm, -(i > 0 ? e2s[i - 1] : 0.0) * pmm);
+    const unsigned hp = (unsigned)(__double_as_longlong(p) >> 32), hm = (unsigned)(__double_as_longlong(pm) >> 32);
+    cnt += (int)((hp ^ hm) >> 31);
+    zero |= (unsigned)(p == 0.0);
+    pmm = pm;
+    pm = p;
+  }
+  if (zero) cnt = sturm_count_minors_safe(ds, e2s, r, x);
+  return cnt;
+}
+
+// tri_eigval on the prescaled tridiagonal (ds, e2s) = (s d, s^2 e^2), s a power of two; tb holds
+// the bounds of the unscaled matrix; returns the unscaled eigenvalue.
+__device__ __forceinline__ double tri_eigval_minors(const double* ds, const double* e2s, double s, int r, int j,
+                                                    bool on, int sub, const TriBounds& tb) {
+  const double eps = 2.220446049250313e-16;
+  const int a = r - 1 - (on ? j : 0);           // ascending index
+  double lo = tb.gl, hi = tb.gu;
+  for (int it = 0; it < 200; ++it) {
+    if (hi - lo <= tb.atol + 2.0 * eps * fmax(fabs(lo), fabs(hi))) break;
+    const double x = lo + (hi - lo) * (double)(sub + 1) / 9.0;
+    const int cnt = on ? sturm_count_minors(ds, e2s, r, x * s) : 0;
+    double nlo = (cnt <= a) ? x : -1e308;
+    double nhi = (cnt > a) ? x : 1e308;
+    nlo = fmax(nlo, dpp<DPP_XOR1>(nlo));
+    nhi = fmin(nhi, dpp<DPP_XOR1>(nhi));
+    nlo = fmax(nlo, dpp<DPP_XOR2>(nlo));
+    nhi = fmin(nhi, dpp<DPP_XOR2>(nhi));
+    nlo = fmax(nlo, dpp<DPP_MIRROR8>(nlo));
+    nhi = fmin(nhi, dpp<DPP_MIRROR8>(nhi));
+    if (nlo > lo) lo = nlo;
+    if (nhi < hi) hi = nhi;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Eigenvector of the tridiagonal for eigenvalue lam by two steps of inverse iteration (LU of
+// T - lam I with partial pivoting, tiny pivots replaced by eps ||T||), from a deterministic start
+// vector; z (stride 1) gets the unit-norm result.  lu: 5 r doubles of workspace.
+__device__ __forceinline__ void tri_invit(const double* d, const double* e, int r, double lam, double tnorm, int j,
+                                          double* lu, double* z) {
+  const double eps = 2.220446049250313e-16;
+  double* ui = lu;            // 1 / pivot
+  double* us1 = ui + r;
+  double* us2 = us1 + r;
+  double* ml = us2 + r;
+  double* sw = ml + r;
+  const double pert = eps * tnorm > 0.0 ? eps * tnorm : 1e-300;
+  double a = d[0] - lam, b = r > 1 ? e[0] : 0.0;
+  for (int k = 0; k < r - 1; ++k) {
+    const double c = e[k];              // sub-diagonal entry of row k+1
+    const double anext = d[k + 1] - lam;
+    const double bnext = (k + 1 < r - 1) ? e[k + 1] : 0.0;
+    if (fabs(a) >= fabs(c)) {
+      const double ap = fabs(a) < pert ? (a < 0.0 ? -pert : pert) : a;
+      const double ia = inv_d(ap);
+      const double mlt = c * ia;
+      ui[k] = ia; us1[k] = b; us2[k] = 0.0; ml[k] = mlt; sw[k] = 0.0;
+      a = anext - mlt * b;
+      b = bnext;
+    } else {
+      const double mlt = a * inv_d(c);
+      ui[k] = inv_d(c); us1[k] = anext; us2[k] = bnext; ml[k] = mlt; sw[k] = 1.0;
+      a = b - mlt * anext;
+      b = -mlt * bnext;
+    }
+  }
+  ui[r - 1] = inv_d(fabs(a) < pert ? (a < 0.0 ? -pert : pert) : a);
+  uint32_t st = 0x9E3779B9u ^ (uint32_t)(j * 2654435761u);
+  for (int i = 0; i < r; ++i) {
+    st = st * 1664525u + 1013904223u;
+    z[i] = ((double)(st >> 8) / 16777216.0) - 0.5;
+  }
+  for (int iter = 0; iter < 2; ++iter) {
+    for (int k = 0; k < r - 1; ++k) {
+      if (sw[k] != 0.0) { const double t = z[k]; z[k] = z[k + 1]; z[k + 1] = t - ml[k] * z[k + 1]; }
+      else z[k + 1] -= ml[k] * z[k];
+    }
+    double z1 = 0.0, z2 = 0.0, nn = 0.0;     // z[k+1], z[k+2] of the back substitution
+    for (int k = r - 1; k >= 0; --k) {
+      const double zk = (z[k] - us1[k] * z1 - us2[k] * z2) * ui[k];
+      z[k] = zk;
+      z2 = z1; z1 = zk;
+      nn += zk * zk;
+    }
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    for (int i = 0; i < r; ++i) z[i] *= inv;
+  }
+}
+
+// tri_invit with the LU factors in LDS, branch-free (one reciprocal per elimination step), the
+// pivot swaps as an int array and U's second superdiagonal recovered from e (it is e_{k+1} where
+// rows k and k+1 were swapped, else 0): 3 r doubles + r ints per eigenvalue.  Same arithmetic
+// as tri_invit.
+__device__ __forceinline__ void tri_invit_lds(const double* __restrict__ d, const double* __restrict__ e, int r,
+                                              double lam, double tnorm, int j, double* __restrict__ ui,
+                                              double* __restrict__ us1, double* __restrict__ ml, int* __restrict__ sw,
+                                              double* __restrict__ z) {
+  const double eps = 2.220446049250313e-16;
+  const double pert = eps * tnorm > 0.0 ? eps * tnorm : 1e-300;
+  double a = d[0] - lam, b = r > 1 ? e[0] : 0.0;
+#pragma unroll 4
+  for (int k = 0; k < r - 1; ++k) {
+    const double c = e[k];
+    const double anext = d[k + 1] - lam;
+    const double bnext = (k + 1 < r - 1) ? e[k + 1] : 0.0;
+    const bool piv = fabs(a) >= fabs(c);
+    const double ap = fabs(a) < pert ? (a < 0.0 ? -pert : pert) : a;
+    const double ix = inv_d(piv ? ap : c);
+    const double mlt = (piv ? c : a) * ix;
+    ui[k] = ix;
+    us1[k] = piv ? b : anext;
+    ml[k] = mlt;
+    sw[k] = piv ? 0 : 1;
+    const double an = piv ? fma(-mlt, b, anext) : fma(-mlt, anext, b);
+    b = piv ? bnext : -mlt * bnext;
+    a = an;
+  }
+  ui[r - 1] = inv_d(fabs(a) < pert ? (a < 0.0 ? -pert : pert) : a);
+  uint32_t st = 0x9E3779B9u ^ (uint32_t)(j * 2654435761u);
+  for (int i = 0; i < r; ++i) {
+    st = st * 1664525u + 1013904223u;
+    z[i] = ((double)(st >> 8) / 16777216.0) - 0.5;
+  }
+  for (int iter = 0; iter < 2; ++iter) {
+    // forward: apply the row operations (and swaps) of the elimination to z
+    double cz = z[0];
+#pragma unroll 4
+    for (int k = 0; k < r - 1; ++k) {
+      const double zo = z[k + 1];
+      const double m = ml[k];
+      const bool swp = sw[k] != 0;
+      z[k] = swp ? zo : cz;
+      cz = swp ? fma(-m, zo, cz) : fma(-m, cz, zo);
+    }
+    z[r - 1] = cz;
+    // back substitution with U (diagonal 1/ui, superdiagonals us1 and us2)
+    double z1 = 0.0, z2 = 0.0, nn = 0.0;
+#pragma unroll 4
+    for (int k = r - 1; k >= 0; --k) {
+      const double u2 = (k < r - 1 && sw[k] != 0 && k + 1 < r - 1) ? e[k + 1] : 0.0;
+      const double zk = (z[k] - us1[k] * z1 - u2 * z2) * ui[k];
+      z[k] = zk;
+      z2 = z1; z1 = zk;
+      nn += zk * zk;
+    }
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    for (int i = 0; i < r; ++i) z[i] *= inv;
+  }
+}
+
 constexpr int HEEV_UREG = 16;   // rows per lane of the register-resident back-transformation (r <= 128)
 
 // G: F x r x r (full, column-major, only the lower triangle is read); U: F x r x r out;
@@ -142,10 +392,16 @@ constexpr int HEEV_UREG = 16;   // rows per lane of the register-resident back-t
 // lu: F x r x 5r doubles (LU factors of T - lambda I).
 // IN_LDS: the packed working matrix (and later Z) live in LDS; a template parameter so that LDS
 // accesses compile to LDS instructions rather than generic (flat) ones.
-template <bool IN_LDS>
+// MODE 0: the whole solver.  MODE 1: the tridiagonal form was computed beforehand (k_hetrd_reg):
+// tri holds d (r) then e (r) per face, taus the reflector scalars, gpk the reflectors; the kernel
+// starts at the eigenvalues.  MODE 2: in addition the eigenvalues (lamout) and the eigenvectors of
+// the tridiagonal (zs, stride r + 1) were computed by k_tri_stein; the kernel starts at the
+// re-orthogonalization of clusters.
+template <bool IN_LDS, int MODE = 0>
 __global__ void __launch_bounds__(HEEV_THREADS)
 k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restrict__ lamout,
-       zd* __restrict__ gpk, double* __restrict__ zs, double* __restrict__ lu) {
+       zd* __restrict__ gpk, double* __restrict__ zs, double* __restrict__ lu,
+       const double* __restrict__ tri, const zd* __restrict__ taus) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   HeevLds& L = *reinterpret_cast<HeevLds*>(smem_raw);
   const int f = blockIdx.x;
@@ -162,6 +418,15 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   RT_PHASE(0);
   for (int j = tid; j <= r; j += blockDim.x) L.cb[j] = (int)pk_off(j, r);
   if (tid < 2) { L.acc[tid] = 0.0; L.accre[tid] = 0.0; L.accim[tid] = 0.0; }
+  constexpr bool FROM_TRI = MODE >= 1;
+  if constexpr (FROM_TRI) {
+    for (int j = tid; j < r; j += blockDim.x) {
+      L.d[j] = tri[(int64_t)f * 2 * r + j];
+      L.e[j] = tri[(int64_t)f * 2 * r + r + j];
+      L.tau[j] = taus[(int64_t)f * r + j];
+    }
+    __syncthreads();
+  } else {
   // ---- load the lower triangle -----------------------------------------------------------
   load_lower_packed(G, r, S, tid, blockDim.x);
   __syncthreads();
@@ -247,50 +512,30 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
     L.e[r - 1] = 0.0;
   }
   __syncthreads();
+  }  // !FROM_TRI
   for (int i = tid; i < r; i += blockDim.x) L.e2[i] = L.e[i] * L.e[i];
   __syncthreads();
 
   RT_PHASE(2);
   // ---- eigenvalues of T: multisection, 8 lanes per eigenvalue ------------------------------
-  double gl = 1e308, gu = -1e308, emax2 = 0.0;
-  for (int i = 0; i < r; ++i) {
-    const double off = fabs(L.e[i]) + (i > 0 ? fabs(L.e[i - 1]) : 0.0);
-    gl = fmin(gl, L.d[i] - off);
-    gu = fmax(gu, L.d[i] + off);
-    emax2 = fmax(emax2, L.e2[i]);
-  }
-  const double tnorm = fmax(fabs(gl), fabs(gu));
-  const double eps = 2.220446049250313e-16;
-  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-  const double atol = 2.0 * eps * tnorm + 4.0 * pivmin;
-  gl -= 2.0 * eps * tnorm + pivmin;
-  gu += 2.0 * eps * tnorm + pivmin;
-  for (int base = 0; base < r; base += ngrp) {
-    const int j = base + grp;                      // j-th largest eigenvalue
-    const bool on = j < r;
-    const int a = r - 1 - (on ? j : 0);           // ascending index
-    double lo = gl, hi = gu;
-    for (int it = 0; it < 200; ++it) {
-      if (hi - lo <= atol + 2.0 * eps * fmax(fabs(lo), fabs(hi))) break;
-      const double x = lo + (hi - lo) * (double)(sub + 1) / 9.0;
-      const int cnt = on ? sturm_count_fast(L.d, L.e2, r, x, pivmin) : 0;
-      double nlo = (cnt <= a) ? x : -1e308;
-      double nhi = (cnt > a) ? x : 1e308;
-      for (int o = 1; o < 8; o <<= 1) {
-        nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
-        nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
-      }
-      if (nlo > lo) lo = nlo;
-      if (nhi < hi) hi = nhi;
+  const TriBounds tb = tri_bounds(L.d, L.e, L.e2, r);
+  const double tnorm = tb.tnorm;
+  if constexpr (MODE < 2) {
+    for (int base = 0; base < r; base += ngrp) {
+      const int j = base + grp;                      // j-th largest eigenvalue
+      const bool on = j < r;
+      const double lam = tri_eigval(L.d, L.e2, r, j, on, sub, tb);
+      if (on && sub == 0) L.lam[j] = lam;
     }
-    if (on && sub == 0) L.lam[j] = 0.5 * (lo + hi);
+  } else {
+    for (int j = tid; j < r; j += blockDim.x) L.lam[j] = lamout[(int64_t)f * r + j];
   }
   __syncthreads();
 
   RT_PHASE(3);
   // ---- the reflectors move to global memory; LDS (or the global slice) then holds Z ------------
   // Z column j (stride zst = r + 1 doubles) = eigenvector of T for lam[j]
-  if constexpr (IN_LDS) {
+  if constexpr (IN_LDS && !FROM_TRI) {
     for (int64_t i = tid; i < packed_size(r); i += blockDim.x) Sg[i] = S[i];
     __syncthreads();
   }
@@ -300,58 +545,13 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   else Zp = Z;
 
   // ---- eigenvectors of T: inverse iteration, one thread per eigenvalue ---------------------------
-  for (int j = tid; j < r; j += blockDim.x) {
-    const double lam = L.lam[j];
-    double* ui = lu + ((int64_t)f * r + j) * 5 * r;   // 1 / pivot
-    double* us1 = ui + r;
-    double* us2 = us1 + r;
-    double* ml = us2 + r;
-    double* sw = ml + r;
-    const double pert = eps * tnorm > 0.0 ? eps * tnorm : 1e-300;
-    // LU with partial pivoting of T - lam I
-    double a = L.d[0] - lam, b = r > 1 ? L.e[0] : 0.0;
-    for (int k = 0; k < r - 1; ++k) {
-      const double c = L.e[k];              // sub-diagonal entry of row k+1
-      const double anext = L.d[k + 1] - lam;
-      const double bnext = (k + 1 < r - 1) ? L.e[k + 1] : 0.0;
-      if (fabs(a) >= fabs(c)) {
-        const double ap = fabs(a) < pert ? (a < 0.0 ? -pert : pert) : a;
-        const double ia = inv_d(ap);
-        const double mlt = c * ia;
-        ui[k] = ia; us1[k] = b; us2[k] = 0.0; ml[k] = mlt; sw[k] = 0.0;
-        a = anext - mlt * b;
-        b = bnext;
-      } else {
-        const double mlt = a * inv_d(c);
-        ui[k] = inv_d(c); us1[k] = anext; us2[k] = bnext; ml[k] = mlt; sw[k] = 1.0;
-        a = b - mlt * anext;
-        b = -mlt * bnext;
-      }
-    }
-    ui[r - 1] = inv_d(fabs(a) < pert ? (a < 0.0 ? -pert : pert) : a);
-    // start vector: deterministic, not aligned with any structure
-    double* z = Zp + (int64_t)j * zst;
-    uint32_t st = 0x9E3779B9u ^ (uint32_t)(j * 2654435761u);
-    for (int i = 0; i < r; ++i) {
-      st = st * 1664525u + 1013904223u;
-      z[i] = ((double)(st >> 8) / 16777216.0) - 0.5;
-    }
-    for (int iter = 0; iter < 2; ++iter) {
-      for (int k = 0; k < r - 1; ++k) {
-        if (sw[k] != 0.0) { const double t = z[k]; z[k] = z[k + 1]; z[k + 1] = t - ml[k] * z[k + 1]; }
-        else z[k + 1] -= ml[k] * z[k];
-      }
-      double z1 = 0.0, z2 = 0.0, nn = 0.0;     // z[k+1], z[k+2] of the back substitution
-      for (int k = r - 1; k >= 0; --k) {
-        const double zk = (z[k] - us1[k] * z1 - us2[k] * z2) * ui[k];
-        z[k] = zk;
-        z2 = z1; z1 = zk;
-        nn += zk * zk;
-      }
-      const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-      for (int i = 0; i < r; ++i) z[i] *= inv;
-    }
+  if constexpr (MODE < 2) {
+    for (int j = tid; j < r; j += blockDim.x)
+      tri_invit(L.d, L.e, r, L.lam[j], tnorm, j, lu + ((int64_t)f * r + j) * 5 * r, Zp + (int64_t)j * zst);
+  } else if constexpr (IN_LDS) {
+    for (int64_t i = tid; i < (int64_t)r * zst; i += blockDim.x) Zp[i] = Z[i];
   }
+  __syncthreads();
   RT_PHASE(4);
   // clusters: maximal runs of eigenvalues with consecutive gaps <= ortol
   const double ortol = 1e-3 * tnorm;
@@ -460,6 +660,71 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
     }
   }
   RT_PHASE(6);
+}
+
+// -------------------------------------------------------------------------------------------
+// Eigenvalues and tridiagonal eigenvectors, STEIN_EPB eigenvalues per block (grid ceil(r/EPB) x F)
+// -------------------------------------------------------------------------------------------
+// Spreads the eigenvalue multisection (8 lanes per eigenvalue) and the inverse iterations (one
+// lane per eigenvalue, LU factors in LDS) of every face over many workgroups; k_heev<., 2> then
+// re-orthogonalizes clusters and back-transforms.  tri: d (r) then e (r) per face; lamout: F x r
+// (descending); zs: F x r x (r + 1) doubles (column j = eigenvector of the tridiagonal for lam_j).
+constexpr int STEIN_EPB = 8;
+constexpr int STEIN_THREADS = 8 * STEIN_EPB;
+// d, e, e^2; per eigenvalue: z, 1/pivots, U's first superdiagonal, multipliers (doubles), swaps (ints)
+inline size_t stein_lds_bytes(int r) {
+  return (size_t)(3 * r + STEIN_EPB * 4 * r) * sizeof(double) + (size_t)STEIN_EPB * r * sizeof(int);
+}
+
+__global__ void __launch_bounds__(STEIN_THREADS)
+k_tri_stein(const double* __restrict__ tri, int r, double* __restrict__ lamout, double* __restrict__ zs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* d = reinterpret_cast<double*>(smem_raw);
+  double* e = d + r;
+  double* e2 = e + r;
+  double* lu = e2 + r;                    // STEIN_EPB x 3 r
+  double* zl = lu + STEIN_EPB * 3 * r;    // STEIN_EPB x r
+  int* swl = reinterpret_cast<int*>(zl + STEIN_EPB * r);   // STEIN_EPB x r
+  double* ds = zl;                        // prescaled copies for the Sturm counts, overwritten
+  double* e2s = zl + r;                   // by the eigenvectors afterwards (2 r <= STEIN_EPB r)
+  __shared__ double lams[STEIN_EPB];
+  const int f = blockIdx.y, j0 = blockIdx.x * STEIN_EPB;
+  const int tid = threadIdx.x, sub = tid & 7, grp = tid >> 3;
+  for (int i = tid; i < r; i += blockDim.x) {
+    d[i] = tri[(int64_t)f * 2 * r + i];
+    const double ei = tri[(int64_t)f * 2 * r + r + i];
+    e[i] = ei;
+    e2[i] = ei * ei;
+  }
+  __syncthreads();
+  const TriBounds tb = tri_bounds(d, e, e2, r);
+  // power-of-two scale with s ||T|| <= 1
+  const double sc = tb.tnorm > 0.0 ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(tb.tnorm)) : 1.0;
+  for (int i = tid; i < r; i += blockDim.x) {
+    ds[i] = d[i] * sc;
+    e2s[i] = e2[i] * (sc * sc);
+  }
+  __syncthreads();
+  const int j = j0 + grp;
+  const bool on = j < r;
+  const double lam = tri_eigval_minors(ds, e2s, sc, r, j, on, sub, tb);
+  if (sub == 0) {
+    lams[grp] = lam;
+    if (on) lamout[(int64_t)f * r + j] = lam;
+  }
+  __syncthreads();
+  if (tid < STEIN_EPB && j0 + tid < r) {
+    double* z = zl + tid * r;
+    double* l3 = lu + tid * 3 * r;
+    tri_invit_lds(d, e, r, lams[tid], tb.tnorm, j0 + tid, l3, l3 + r, l3 + 2 * r, swl + tid * r, z);
+  }
+  __syncthreads();
+  // eigenvectors out (column j0 + q, stride r + 1)
+  const int nq = min(STEIN_EPB, r - j0);
+  for (int idx = tid; idx < nq * r; idx += blockDim.x) {
+    const int q = idx / r, i = idx % r;
+    zs[((int64_t)f * r + j0 + q) * (r + 1) + i] = zl[q * r + i];
+  }
 }
 
 // -------------------------------------------------------------------------------------------
@@ -737,6 +1002,184 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
   }
   RT_PHASE(11);
   if (tid == 0 && flags && H.bad) atomicOr(flags, 1);
+}
+
+// -------------------------------------------------------------------------------------------
+// Register-resident Householder tridiagonalization for r <= TRD_R (one 512-thread block per face)
+// -------------------------------------------------------------------------------------------
+// The (zero-padded) 128 x 128 Hermitian matrix lives in registers, full storage: thread
+// (wave w, lane l) owns the 4 x 8 block at rows 4a.., columns 8b.. with a = 4w + l/16, b = l%16
+// (two waves per SIMD, 32 complex entries per lane).  Per reflector k (x = A(k+1:, k)):
+//   (1) the owners of column k put it in LDS; barrier;
+//   (2) every wave forms H = I - tau v v^H with H^H x = beta e_1 from it (the same arithmetic in
+//       every wave) and keeps v in a wave-private LDS row;
+//   (3) p = tau A v: 4 x 8 block products, summed over the 16 lanes of a row group by a
+//       reduce-scatter, p^H v summed per wave; barrier;
+//   (4) w = p - (tau p^H v / 2) v, A -= v w^H + w v^H on the owned block.
+// Waves whose 16 rows are all eliminated skip (3) and (4).  FP64 throughput of the vector ALUs
+// bounds the kernel (12 FMAs per stored entry and reflector).  Output: d, e (real tridiagonal,
+// e_k = beta_k), tau, and v_k (rows k+1..r-1, v_k(k+1) = 1) in the packed layout of k_heev.
+constexpr int TRD_R = 128;
+constexpr int TRD_THREADS = 512;
+constexpr int TRD_WAVES = TRD_THREADS / 64;
+
+__device__ __forceinline__ zd shfl_xor_z(zd v, int o) { return mk(__shfl_xor(v.re, o, 64), __shfl_xor(v.im, o, 64)); }
+// acc + a b and acc - a b as four fused multiply-adds each
+__device__ __forceinline__ zd zfma(zd a, zd b, zd acc) {
+  return mk(fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im)));
+}
+__device__ __forceinline__ zd zfms(zd a, zd b, zd acc) {
+  return mk(fma(-a.re, b.re, fma(a.im, b.im, acc.re)), fma(-a.re, b.im, fma(-a.im, b.re, acc.im)));
+}
+
+__global__ void __launch_bounds__(TRD_THREADS)
+k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __restrict__ taus,
+            zd* __restrict__ gpk) {
+  __shared__ zd xcol[2][TRD_R];
+  __shared__ zd xsh[2][TRD_R];
+  __shared__ zd xv[2][TRD_WAVES];
+  __shared__ zd vpriv[TRD_WAVES][TRD_R];
+  const int f = blockIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int a = 4 * w + (l >> 4), b = l & 15;
+  const int r0 = 4 * a, c0 = 8 * b;
+  const zd* __restrict__ G = Gin + (int64_t)f * r * r;
+  zd* __restrict__ S = gpk + (int64_t)f * packed_size(r);
+  double* __restrict__ dout = tri + (int64_t)f * 2 * r;
+  double* __restrict__ eout = dout + r;
+  zd* __restrict__ vp = vpriv[w];
+  zd A[4][8];
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int i = r0 + ii, j = c0 + jj;
+      zd v = mk(0.0, 0.0);
+      if (i < r && j < r) v = i >= j ? G[i + (int64_t)j * r] : cconj(G[j + (int64_t)i * r]);
+      A[ii][jj] = v;
+    }
+  const bool b3 = (l & 8) != 0, b2 = (l & 4) != 0;
+  const int myrow = r0 + 2 * (int)b3 + (int)b2;   // row held after the reduce-scatter
+  for (int k = 0; k < r - 1; ++k) {
+    const int par = k & 1;
+    // (1) column k into LDS (entries 0..127; the diagonal entry gives d_k).  k is uniform, so the
+    // column is picked by a uniform branch, not by per-lane selects.
+    if (b == (k >> 3)) {
+      const int jk = k & 7;
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj)
+        if (jk == jj) {
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) xcol[par][r0 + ii] = A[ii][jj];
+        }
+    }
+    __syncthreads();
+    // (2) the reflector (identical in every wave)
+    double xn = 0.0;
+#pragma unroll
+    for (int t0 = 0; t0 < TRD_R; t0 += 64) {
+      const int t = t0 + l;
+      const zd xt = xcol[par][t];
+      xn += (t >= k + 2 && t < r) ? cabs2(xt) : 0.0;
+    }
+    xn = wave_sum(xn);
+    const zd alpha = xcol[par][k + 1];
+    const bool active = (xn > 0.0 || alpha.im != 0.0);   // uniform
+    double beta = alpha.re;
+    zd tau = mk(0.0, 0.0), sc = mk(0.0, 0.0);
+    if (active) {
+      const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn);
+      beta = alpha.re >= 0.0 ? -nrm : nrm;
+      const double ib = 1.0 / beta;
+      tau = mk((beta - alpha.re) * ib, -alpha.im * ib);
+      const zd den = mk(alpha.re - beta, alpha.im);
+      const double idd = 1.0 / cabs2(den);
+      sc = mk(den.re * idd, -den.im * idd);
+    }
+#pragma unroll
+    for (int t0 = 0; t0 < TRD_R; t0 += 64) {
+      const int t = t0 + l;
+      const zd sv = cmul(xcol[par][t], sc);
+      const zd vt = zsel(t == k + 1, mk(1.0, 0.0), zsel(t > k + 1 && t < r && active, sv, mk(0.0, 0.0)));
+      vp[t] = vt;
+      if (w == 0 && t > k && t < r) S[pk_off(k, r) + (t - k)] = vt;
+    }
+    if (w == 0 && l == 0) {
+      dout[k] = xcol[par][k].re;
+      eout[k] = beta;
+      taus[(int64_t)f * r + k] = tau;
+    }
+    if (!active) continue;           // uniform: H = I, nothing to update
+    const bool wave_on = 16 * w + 15 > k;
+    if (wave_on) {
+      // (3) p = tau A v over the owned block, reduce-scatter over the 16-lane row group
+      zd sp[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) sp[ii] = mk(0.0, 0.0);
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const zd vj = vp[c0 + jj];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) sp[ii] = zfma(A[ii][jj], vj, sp[ii]);
+      }
+      // partners: lane ^ 8 (row rotate by 8), then lane 7 - lane within 8 (half mirror, opposite
+      // bit 2), then full sums over quads
+      zd k0 = zsel(b3, sp[2], sp[0]), k1 = zsel(b3, sp[3], sp[1]);
+      const zd o0 = zsel(b3, sp[0], sp[2]), o1 = zsel(b3, sp[1], sp[3]);
+      k0 = cadd(k0, dpp<DPP_ROR8>(o0));
+      k1 = cadd(k1, dpp<DPP_ROR8>(o1));
+      zd qv = zsel(b2, k1, k0);
+      qv = cadd(qv, dpp<DPP_MIRROR8>(zsel(b2, k0, k1)));
+      qv = cadd(qv, dpp<DPP_XOR2>(qv));
+      qv = cadd(qv, dpp<DPP_XOR1>(qv));
+      zd x = cmul(tau, qv);
+      if (myrow <= k || myrow >= r) x = mk(0.0, 0.0);
+      const bool writer = (l & 3) == 0;
+      zd c = writer ? cmulc(x, vp[myrow]) : mk(0.0, 0.0);   // conj(x) v
+      if (writer) xsh[par][myrow] = x;
+      c = wave_sum(c);
+      if (l == 0) xv[par][w] = c;
+    } else {
+      if ((l & 3) == 0) xsh[par][myrow] = mk(0.0, 0.0);
+      if (l == 0) xv[par][w] = mk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (wave_on) {
+      // (4) rank-2 update of the owned block
+      zd xhv = mk(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < TRD_WAVES; ++q) xhv = cadd(xhv, xv[par][q]);
+      const zd a2 = cscale(cmul(tau, xhv), -0.5);
+      zd wcc[8], vcc[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const zd vj = vp[c0 + jj];
+        vcc[jj] = cconj(vj);
+        wcc[jj] = cconj(cadd(xsh[par][c0 + jj], cmul(a2, vj)));
+      }
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const zd vi = vp[r0 + ii];
+        const zd wi = cadd(xsh[par][r0 + ii], cmul(a2, vi));
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) A[ii][jj] = zfms(wi, vcc[jj], zfms(vi, wcc[jj], A[ii][jj]));
+      }
+    }
+  }
+  // last diagonal entry
+  {
+    const int t = r - 1;
+    if (a == (t >> 2) && b == (t >> 3)) {
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+          if ((t & 3) == ii && (t & 7) == jj) {
+            dout[t] = A[ii][jj].re;
+            eout[t] = 0.0;
+          }
+    }
+  }
 }
 
 }  // namespace rt

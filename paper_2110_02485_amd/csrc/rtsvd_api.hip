@@ -268,12 +268,31 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
   const size_t bytes = in_lds ? full : heev_lds_bytes(r, false);
   zd* gpk = sc.get<zd>(F * packed_size(r));
   if (!gpk) return fail(RTSVD_E_NOMEM, "device allocation failed: heev packed scratch");
-  double* zs = sc.get<double>(in_lds ? 1 : F * r * (int64_t)(r + 1));
+  double* zs = sc.get<double>(F * r * (int64_t)(r + 1));
   double* lu = sc.get<double>(F * r * 5 * (int64_t)r);
   if (!zs || !lu) return fail(RTSVD_E_NOMEM, "device allocation failed: heev scratch");
+  if (r <= TRD_R) {
+    // tridiagonal form from the register-resident kernel, then eigenvalues / vectors
+    double* tri = sc.get<double>(F * 2 * (int64_t)r);
+    zd* taus = sc.get<zd>(F * (int64_t)r);
+    if (!tri || !taus) return fail(RTSVD_E_NOMEM, "device allocation failed: heev tridiagonal");
+    hipLaunchKernelGGL(k_hetrd_reg, dim3((unsigned)F), dim3(TRD_THREADS), 0, s, G, r, tri, taus, gpk);
+    RT_LAUNCH_OK();
+    const size_t sb = stein_lds_bytes(r);   // <= 52 KB for r <= TRD_R
+    hipLaunchKernelGGL(k_tri_stein, dim3((unsigned)ceil_div(r, STEIN_EPB), (unsigned)F), dim3(STEIN_THREADS), sb, s,
+                       (const double*)tri, r, lam, zs);
+    RT_LAUNCH_OK();
+    auto kern = in_lds ? k_heev<true, 2> : k_heev<false, 2>;
+    if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
+                       (const double*)tri, (const zd*)taus);
+    RT_LAUNCH_OK();
+    return 0;
+  }
   auto kern = in_lds ? k_heev<true> : k_heev<false>;
   if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu);
+  hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
+                     (const double*)nullptr, (const zd*)nullptr);
   RT_LAUNCH_OK();
   return 0;
 }
