@@ -87,11 +87,22 @@ template <typename T> __device__ __forceinline__ T row_sum16(T v) {
   v = cadd_any(v, dpp<DPP_MIRROR16>(v));
   return v;
 }
+constexpr int DPP_ROW_BCAST15 = 0x142;  // lane 15 of each row to the next row
+constexpr int DPP_ROW_BCAST31 = 0x143;  // lane 31 to rows 2 and 3
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_rows(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// sum over the wave, every lane gets it: row sums, then rows combined towards lane 63 by row
+// broadcasts (rows not written receive 0), then lane 63 read back as a scalar
 __device__ __forceinline__ double wave_sum(double v) {
   v = row_sum16(v);
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
+  v += dpp_rows<DPP_ROW_BCAST15, 0xa>(v);
+  v += dpp_rows<DPP_ROW_BCAST31, 0xc>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ cplx<double> wave_sum(cplx<double> v) { return mk(wave_sum(v.re), wave_sum(v.im)); }
 

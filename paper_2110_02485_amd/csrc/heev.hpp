@@ -384,6 +384,17 @@ __device__ __forceinline__ void tri_invit_lds(const double* __restrict__ d, cons
   }
 }
 
+// acc + a b, acc - a b and acc + conj(a) b as four fused multiply-adds each
+__device__ __forceinline__ zd zfma(zd a, zd b, zd acc) {
+  return mk(fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im)));
+}
+__device__ __forceinline__ zd zfms(zd a, zd b, zd acc) {
+  return mk(fma(-a.re, b.re, fma(a.im, b.im, acc.re)), fma(-a.re, b.im, fma(-a.im, b.re, acc.im)));
+}
+__device__ __forceinline__ zd zcfma(zd a, zd b, zd acc) {
+  return mk(fma(a.re, b.re, fma(a.im, b.im, acc.re)), fma(a.re, b.im, fma(-a.im, b.re, acc.im)));
+}
+
 constexpr int HEEV_UREG = 16;   // rows per lane of the register-resident back-transformation (r <= 128)
 
 // G: F x r x r (full, column-major, only the lower triangle is read); U: F x r x r out;
@@ -563,33 +574,64 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
     L.ncl = nc;
   }
   __syncthreads();
-  // modified Gram-Schmidt inside every cluster (two passes): the pivot vector is normalized by one
-  // wave, then every later vector of the cluster loses its component along it, one wave per vector
+  // modified Gram-Schmidt inside every cluster (two passes).  Step i: every wave forms the pivot's
+  // squared norm nn (the same arithmetic in each), and every later vector q of the cluster, one
+  // wave per vector, loses (z_i . z_q / nn) z_i; the pivot itself is scaled to unit norm during
+  // the next step (nobody reads it then), so one barrier per pivot suffices.
   for (int c = 0; c < L.ncl; ++c) {
     const int j0 = L.cstart[c], j1 = L.cstart[c + 1];
     if (j1 - j0 < 2) continue;
-    for (int pass = 0; pass < 2; ++pass)
-      for (int i = j0; i < j1; ++i) {
-        double* zi = Zp + (int64_t)i * zst;
-        if (wave == 0) {
-          double nn = 0.0;
-          for (int x = lane; x < r; x += 64) nn += zi[x] * zi[x];
-          for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
-          const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-          for (int x = lane; x < r; x += 64) zi[x] *= inv;
+    for (int pass = 0; pass < 2; ++pass) {
+      double pinv = 0.0;                     // 1/||z_{i-1}||, applied by wave (i-1) % nw
+      for (int i = j0; i <= j1; ++i) {
+        if (i > j0 && wave == (i - 1) % nw) {
+          double* zp = Zp + (int64_t)(i - 1) * zst;
+          for (int x = lane; x < r; x += 64) zp[x] *= pinv;
         }
-        __syncthreads();
-        for (int q = i + 1 + wave; q < j1; q += nw) {
+        if (i == j1) break;
+        const double* zi = Zp + (int64_t)i * zst;
+        // the pivot's norm and up to 3 of this wave's dot products as independent reductions
+        int q = i + 1 + wave;
+        double nn = 0.0, dt[3] = {0.0, 0.0, 0.0};
+        for (int x = lane; x < r; x += 64) {
+          const double zx = zi[x];
+          nn += zx * zx;
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+            if (q + u * nw < j1) dt[u] += zx * Zp[(int64_t)(q + u * nw) * zst + x];
+        }
+        nn = wave_sum(nn);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) dt[u] = wave_sum(dt[u]);
+        const double inn = nn > 0.0 ? 1.0 / nn : 0.0;
+        pinv = nn > 0.0 ? sqrt(inn) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (q + u * nw < j1) {
+            double* zq = Zp + (int64_t)(q + u * nw) * zst;
+            const double c = dt[u] * inn;
+            for (int x = lane; x < r; x += 64) zq[x] -= c * zi[x];
+          }
+        for (q += 3 * nw; q < j1; q += nw) {   // clusters longer than 3 nw + 1
           double* zq = Zp + (int64_t)q * zst;
-          double dt = 0.0;
-          for (int x = lane; x < r; x += 64) dt += zi[x] * zq[x];
-          for (int o = 32; o > 0; o >>= 1) dt += __shfl_xor(dt, o, 64);
-          for (int x = lane; x < r; x += 64) zq[x] -= dt * zi[x];
+          double d1 = 0.0;
+          for (int x = lane; x < r; x += 64) d1 += zi[x] * zq[x];
+          d1 = wave_sum(d1) * inn;
+          for (int x = lane; x < r; x += 64) zq[x] -= d1 * zi[x];
         }
         __syncthreads();
       }
+      __syncthreads();
+    }
   }
   __syncthreads();
+  if constexpr (MODE == 2) {
+    // the back-transformation runs in k_heev_backtr
+    if constexpr (IN_LDS) {
+      for (int64_t i = tid; i < (int64_t)r * zst; i += blockDim.x) Z[i] = Zp[i];
+    }
+    return;
+  }
 
   RT_PHASE(5);
   // ---- back-transformation U = Q_H Z, 8 lanes per column ---------------------------------------
@@ -724,6 +766,73 @@ k_tri_stein(const double* __restrict__ tri, int r, double* __restrict__ lamout, 
   for (int idx = tid; idx < nq * r; idx += blockDim.x) {
     const int q = idx / r, i = idx % r;
     zs[((int64_t)f * r + j0 + q) * (r + 1) + i] = zl[q * r + i];
+  }
+}
+
+// -------------------------------------------------------------------------------------------
+// Back-transformation U = Q_H Z for r <= 8 HEEV_UREG, BT_COLS columns per block (grid ceil(r/BT_COLS) x F)
+// -------------------------------------------------------------------------------------------
+// Column c of U is Z(:, c) with H_{r-2}, ..., H_0 applied (H_k = I - tau_k v_k v_k^H): 8 lanes per
+// column, lane s holds rows s + 8 t in registers; the reflectors pass through LDS in chunks of
+// BT_CH (dense rows, zero above the sub-diagonal), last chunk first.  gpk: packed reflectors,
+// taus: F x r, zs: F x r x (r + 1) (real Z), U: F x r x r out.
+constexpr int BT_COLS = 32;
+constexpr int BT_THREADS = 8 * BT_COLS;
+constexpr int BT_CH = 32;
+constexpr int BT_RP = 8 * HEEV_UREG;   // padded rows (128)
+
+__global__ void __launch_bounds__(BT_THREADS)
+k_heev_backtr(const zd* __restrict__ gpk, const zd* __restrict__ taus, const double* __restrict__ zs, int r,
+              zd* __restrict__ Uout) {
+  __shared__ zd vbuf[BT_CH][BT_RP];
+  __shared__ zd tbuf[BT_CH];
+  const int f = blockIdx.y;
+  const int tid = threadIdx.x, sub = tid & 7, grp = tid >> 3;
+  const int c = blockIdx.x * BT_COLS + grp;
+  const bool on = c < r;
+  const zd* __restrict__ S = gpk + (int64_t)f * packed_size(r);
+  const zd* __restrict__ tf = taus + (int64_t)f * r;
+  const double* __restrict__ Z = zs + (int64_t)f * r * (r + 1) + (int64_t)(on ? c : 0) * (r + 1);
+  zd u[HEEV_UREG];
+#pragma unroll
+  for (int t = 0; t < HEEV_UREG; ++t) {
+    const int i = sub + 8 * t;
+    u[t] = mk((on && i < r) ? Z[i] : 0.0, 0.0);
+  }
+  const int nref = r - 1;
+  for (int kc0 = ((nref - 1) / BT_CH) * BT_CH; kc0 >= 0; kc0 -= BT_CH) {
+    const int kc1 = min(kc0 + BT_CH, nref);
+    __syncthreads();
+    for (int idx = tid; idx < BT_CH * BT_RP; idx += BT_THREADS) {
+      const int kk = idx / BT_RP, i = idx % BT_RP, k = kc0 + kk;
+      zd v = mk(0.0, 0.0);
+      if (k < kc1 && i > k && i < r) v = S[pk_off(k, r) + (i - k)];
+      vbuf[kk][i] = v;
+    }
+    if (tid < BT_CH) tbuf[tid] = kc0 + tid < kc1 ? tf[kc0 + tid] : mk(0.0, 0.0);
+    __syncthreads();
+    for (int k = kc1 - 1; k >= kc0; --k) {
+      const zd tau = tbuf[k - kc0];
+      const zd* vk = vbuf[k - kc0];
+      zd part[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+#pragma unroll
+      for (int t = 0; t < HEEV_UREG; ++t) part[t & 3] = zcfma(vk[sub + 8 * t], u[t], part[t & 3]);  // zeros above
+      zd sacc = cadd(cadd(part[0], part[1]), cadd(part[2], part[3]));
+      sacc = cadd(sacc, dpp<DPP_XOR1>(sacc));
+      sacc = cadd(sacc, dpp<DPP_XOR2>(sacc));
+      sacc = cadd(sacc, dpp<DPP_MIRROR8>(sacc));
+      sacc = cmul(tau, sacc);
+#pragma unroll
+      for (int t = 0; t < HEEV_UREG; ++t) u[t] = zfms(vk[sub + 8 * t], sacc, u[t]);
+    }
+  }
+  if (on) {
+    zd* U = Uout + (int64_t)f * r * r + (int64_t)c * r;
+#pragma unroll
+    for (int t = 0; t < HEEV_UREG; ++t) {
+      const int i = sub + 8 * t;
+      if (i < r) U[i] = u[t];
+    }
   }
 }
 
@@ -1024,13 +1133,7 @@ constexpr int TRD_THREADS = 512;
 constexpr int TRD_WAVES = TRD_THREADS / 64;
 
 __device__ __forceinline__ zd shfl_xor_z(zd v, int o) { return mk(__shfl_xor(v.re, o, 64), __shfl_xor(v.im, o, 64)); }
-// acc + a b and acc - a b as four fused multiply-adds each
-__device__ __forceinline__ zd zfma(zd a, zd b, zd acc) {
-  return mk(fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im)));
-}
-__device__ __forceinline__ zd zfms(zd a, zd b, zd acc) {
-  return mk(fma(-a.re, b.re, fma(a.im, b.im, acc.re)), fma(-a.re, b.im, fma(-a.im, b.re, acc.im)));
-}
+
 
 __global__ void __launch_bounds__(TRD_THREADS)
 k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __restrict__ taus,

@@ -287,6 +287,9 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
     hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
                        (const double*)tri, (const zd*)taus);
     RT_LAUNCH_OK();
+    hipLaunchKernelGGL(k_heev_backtr, dim3((unsigned)ceil_div(r, BT_COLS), (unsigned)F), dim3(BT_THREADS), 0, s,
+                       (const zd*)gpk, (const zd*)taus, (const double*)zs, r, U);
+    RT_LAUNCH_OK();
     return 0;
   }
   auto kern = in_lds ? k_heev<true> : k_heev<false>;
