@@ -12,6 +12,7 @@
 
 #include "common.hpp"
 #include "fft.hpp"
+#include "gram.hpp"
 #include "gemm.hpp"
 #include "skinny.hpp"
 #include "heev.hpp"
@@ -318,21 +319,12 @@ static int launch_cholinv(const zd* G, int r, int64_t F, zd* Rinv, int* flags, S
   return 0;
 }
 
-// number of K splits of an FP64 Gram product so that the grid has about 1000 blocks
-static int gram_splits(int64_t rows, int64_t r, int64_t F) {
-  const int64_t tiles = F * ceil_div(r, 64) * ceil_div(r, 128);
-  int64_t ks = ceil_div(1024, std::max<int64_t>(tiles, 1));
-  ks = std::min<int64_t>(ks, std::max<int64_t>(1, rows / 64));
-  return (int)std::max<int64_t>(1, std::min<int64_t>(ks, 16));
-}
-
-// FP64 Gram of Y (F x rows x r) into G (F x r x r), partials from the stream pool
+// G_f = Y_f^H Y_f (lower triangle), FP64
 template <typename TY>
 static int gram(const TY* Y, int64_t rows, int64_t r, int64_t F, zd* G, Scratch& sc, hipStream_t s) {
-  const int ks = gram_splits(rows, r, F);
-  zd* part = sc.get<zd>(F * ks * r * r);
-  if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
-  return sk::gram_fp64<TY>(Y, rows, (int)r, rows * r, (int)F, part, ks, G, s);
+  (void)sc;
+  if (rows > INT32_MAX || r > INT32_MAX) return fail(RTSVD_E_UNSUPPORTED, "gram: dimensions exceed 2^31");
+  return gram_lower<TY>(Y, (int)rows, (int)r, rows, rows * r, (int)F, G, s);
 }
 
 // C_f = op(A_f) X_f on MFMA, X packed into pool scratch first
