@@ -322,8 +322,14 @@ static int launch_cholinv(const zd* G, int r, int64_t F, zd* Rinv, int* flags, S
 // G_f = Y_f^H Y_f (lower triangle), FP64
 template <typename TY>
 static int gram(const TY* Y, int64_t rows, int64_t r, int64_t F, zd* G, Scratch& sc, hipStream_t s) {
-  (void)sc;
   if (rows > INT32_MAX || r > INT32_MAX) return fail(RTSVD_E_UNSUPPORTED, "gram: dimensions exceed 2^31");
+  // measured on 1024 x 120 panels: the slab kernel wins for FP64 panels (its LDS staging halves
+  // the memory traffic per tile), the per-tile kernel for FP32 panels
+  if (sizeof(TY) == sizeof(zd) && r <= GS_RMAX && rows >= 16 * GS_KS * 4) {
+    zd* part = sc.get<zd>(gram_part_elems((int)r, (int)F));
+    if (!part) return fail(RTSVD_E_NOMEM, "device allocation failed: gram partials");
+    return gram_slab<TY>(Y, (int)rows, (int)r, rows, rows * r, (int)F, part, G, s);
+  }
   return gram_lower<TY>(Y, (int)rows, (int)r, rows, rows * r, (int)F, G, s);
 }
 
@@ -414,7 +420,6 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     RT_ALLOC(Y, zw, F * std::max(l, m) * r, sc);
     RT_ALLOC(tmp, zw, F * std::max(l, m) * r, sc);
     RT_ALLOC(Ch, zd, F * m * r, sc);  // C^H = A-hat^H Q, m x r per face (C = Q^H A-hat)
-    RT_ALLOC(rown, double, F * r, sc);
     {
       RT_TIMED(RTSVD_T_FFT_OMEGA);
       RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
@@ -449,13 +454,12 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     }
     {
       RT_TIMED(RTSVD_T_SVDAUX);
-      // error indicator eta^[j] (Thm 4.2)
-      hipLaunchKernelGGL((k_colnorms<zd>), dim3((unsigned)r, (unsigned)F), dim3(256), 0, s, Ch, (int)m, (int)r, rown);
-      RT_LAUNCH_OK();
-      hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, rown, (int)F, (int)r, (int)n, eta);
-      RT_LAUNCH_OK();
       // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
       RT_TRY(gram<zd>(Ch, m, r, F, G, sc, s));
+      // error indicator eta^[j] (Thm 4.2); ||C(j, :)||^2 is the real diagonal of G
+      hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, (const double*)G,
+                         (int64_t)2 * r * r, (int64_t)2 * (r + 1), (int)F, (int)r, (int)n, eta);
+      RT_LAUNCH_OK();
     }
     {
       RT_TIMED(RTSVD_T_HEEV);
@@ -465,11 +469,12 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
       RT_TIMED(RTSVD_T_SVDAUX);
       hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
       RT_LAUNCH_OK();
-      // V = C^H U-breve diag(1/sigma)
-      RT_TRY((skinny<zd, zd, zd>(false, m, r, r, Ch, m, m * r, Ub, r, r * r, V, m, m * r, F, sc, s)));
-      hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * m * r)), dim3(256), 0, s, V, V, sigma, (int)m,
+      // V = C^H (U-breve diag(1/sigma)): the scaling goes on the r x r factor
+      RT_ALLOC(Ubs, zd, F * r * r, sc);
+      hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * r * r)), dim3(256), 0, s, Ub, Ubs, sigma, (int)r,
                          (int)r, (int)F);
       RT_LAUNCH_OK();
+      RT_TRY((skinny<zd, zd, zd>(false, m, r, r, Ch, m, m * r, Ubs, r, r * r, V, m, m * r, F, sc, s)));
     }
     // W = A-hat V: exact residuals of the discrepancy principle
     {
@@ -482,7 +487,8 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     RT_TRY(launch_heev(G, (int)m, F, V, lam, sc, s));
     hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
     RT_LAUNCH_OK();
-    hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, lam, (int)F, (int)r, (int)n, eta);
+    hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, (const double*)lam, (int64_t)r,
+                       (int64_t)1, (int)F, (int)r, (int)n, eta);
     RT_LAUNCH_OK();
     RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, r, Wo, F, sc, s)));
     RT_ALLOC(Uo, zw, F * l * r, sc);

@@ -81,13 +81,20 @@ k_dp_select(const double* __restrict__ partial, int F, int tiles, int p, int kca
   for (int idx = wave; idx < groups * kcap; idx += nw) {
     const int g = idx / kcap, k = idx % kcap;
     const int c0 = groups == 1 ? 0 : g, nc = groups == 1 ? p : 1;
-    const int per = tiles * nc, cnt = F * per;
+    // lanes over (face, tile) pairs, columns of the group summed in a short inner loop
+    const int cnt = F * tiles;
     double s = 0.0;
+    int fi = lane / tiles, t = lane % tiles;
+    const int step_f = 64 / tiles, step_t = 64 % tiles;
     for (int e = lane; e < cnt; e += 64) {
-      const int fi = e / per, rem = e % per;
-      const int t = rem / nc, c = c0 + rem % nc;
       const double w = (fi == 0 || 2 * fi == n) ? 1.0 : 2.0;
-      s += w * partial[(((int64_t)fi * tiles + t) * p + c) * kcap + k];
+      const double* pp = partial + (((int64_t)fi * tiles + t) * p + c0) * kcap + k;
+      double v = 0.0;
+      for (int c = 0; c < nc; ++c) v += pp[(int64_t)c * kcap];
+      s += w * v;
+      fi += step_f;
+      t += step_t;
+      if (t >= tiles) { t -= tiles; ++fi; }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
@@ -125,27 +132,11 @@ __global__ void k_mask_coeffs(const zd* __restrict__ T, zd* __restrict__ Tm, con
   Tm[idx] = j < k ? T[idx] : mk(0.0, 0.0);
 }
 
-// Column sums of |C^H|^2 per face: rown[f*r + j] = ||C_f(j, :)||^2 (C^H stored m x r).
-template <typename TC>
-__global__ void k_colnorms(const TC* __restrict__ Ch, int m, int r, double* __restrict__ rown) {
-  const int j = blockIdx.x, f = blockIdx.y;
-  const TC* col = Ch + (int64_t)f * m * r + (int64_t)j * m;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) s += cabs2(ld<double>(col[i]));
-  __shared__ double red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) rown[(int64_t)f * r + j] = red[0];
-}
-
 // eta[j] = ||A||^2 - (1/n) sum_f w_f sum_{j' < j} rown[f][j'],  j = 0..r  (one block of
-// DP_SEL_THREADS; fixed summation order)
+// DP_SEL_THREADS; fixed summation order).  rown[f][j] = rn[f * sf + j * sj] (the squared row norms
+// of C_f: the real diagonal of its Gram matrix, or the eigenvalues of A-hat_f^H A-hat_f).
 __global__ void __launch_bounds__(DP_SEL_THREADS)
-k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __restrict__ rown,
+k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __restrict__ rn, int64_t sf, int64_t sj,
              int F, int r, int n, double* __restrict__ eta) {
   __shared__ double red[DP_SEL_THREADS / 64];
   __shared__ double rows[HEEV_RMAX_SOLVE];
@@ -157,7 +148,7 @@ k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __r
   if (lane == 0) red[wave] = s;
   for (int j = wave; j < r; j += nw) {
     double t = 0.0;
-    for (int f = lane; f < F; f += 64) t += ((f == 0 || 2 * f == n) ? 1.0 : 2.0) * rown[(int64_t)f * r + j];
+    for (int f = lane; f < F; f += 64) t += ((f == 0 || 2 * f == n) ? 1.0 : 2.0) * rn[(int64_t)f * sf + (int64_t)j * sj];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
     if (lane == 0) rows[j] = t / (double)n;
