@@ -31,7 +31,11 @@ HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 
 TAGS = {1: "fft_A", 2: "fft_omega", 3: "sketch", 4: "power", 5: "project", 6: "W", 7: "gram", 8: "chol",
-        9: "qmul", 10: "heev", 11: "svd_aux", 12: "solve"}
+        9: "qmul", 10: "heev", 11: "svd_aux", 12: "solve", 14: "W_mma"}
+# stages whose launches are one kernel each (the roofline object reports the dominant one);
+# the others bracket several kernels (packing passes, the four eigensolver kernels, the solve)
+SINGLE_KERNEL = {"fft_A": "k_rfft_reg", "fft_omega": "k_rfft_reg", "gram": "k_gram_lower", "chol": "k_cholinv",
+                 "W_mma": "k_skinny (FP32 MFMA, W = A-hat V)"}
 
 
 def stage_model(w, precision):
@@ -50,6 +54,8 @@ def stage_model(w, precision):
         "power": (big, F * l * m * ca + F * (m + l) * r * cw, None, gp),
         "project": (big, F * l * m * ca + F * l * r * cw + F * m * r * 16, None, gp),
         "W": (big, F * l * m * cw + F * m * r * 16 + F * l * r * cw, None, "fp64" if precision == "fp64" else "fp32"),
+        "W_mma": (big, F * l * m * cw + F * m * r * 16 + F * l * r * cw, None,
+                  "fp64" if precision == "fp64" else "fp32"),
         "gram": (4.0 * l * r * r * F, F * l * r * cw + F * r * r * 16, None, "fp64"),
         "chol": (F * (8.0 / 3.0) * r ** 3, F * 2 * r * r * 16, "alu", "fp64"),
         "qmul": (4.0 * l * r * r * F, 2 * F * l * r * cw + F * r * r * 16, None, "fp64" if precision == "fp64" else "fp32"),
@@ -59,6 +65,32 @@ def stage_model(w, precision):
                   l * p * n * s_in + F * l * p * cw + F * (2 * l * r + m * r) * cw + m * p * n * s_in, "hbm", None),
     }
     return mdl
+
+
+# HBM traffic of a kernel from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE per dispatch, each
+# scaled by the ratio of known bytes to the counter's reading for a plain device copy); valid only
+# while the kernel's source is the one that was measured (sha256 of the source file)
+# Measured on the blur1024 workload (profiles/w_mma_cholinv_blur1024_hbm_counters.md): copy
+# calibration 1 GiB -> FETCH_SIZE 524302 KiB (factor 2.0), WRITE_SIZE 1048576 KiB (factor 1.0).
+TRAFFIC = {
+    ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
+                         "sha256": "2823752e9ee44f6b632160318e8678683082db4e1a6d45518033d5aec1c31b4b",
+                         "bytes_per_launch": 677424834},
+    ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
+                        "sha256": "3886cfd9bb8192d695dbeb0ff3495f1526d0ba2e52f1d5a0666c22d5a067446c",
+                        "bytes_per_launch": 35854079},
+}
+
+
+def traffic_of(stage, precision):
+    import hashlib
+    t = TRAFFIC.get((stage, precision))
+    if not t:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != t["sha256"]:
+            return None
+    return t["bytes_per_launch"]
 
 
 def roofline_of(name, ms, launches, w, precision):
@@ -223,7 +255,11 @@ def main():
     dev = torch.device("cuda:0")
     prob = make_problem(w, dev, torch, rt, wl)
     print(f"[bench] inputs ready: {w.name} l=m={w.size} n={w.n} r={w.r}", file=sys.stderr, flush=True)
-    ms, wall, out = time_steps(torch, rt, prob, w, precision, args.steps, args.warmup, timers=True)
+    ms, wall, out = time_steps(torch, rt, prob, w, precision, args.steps, args.warmup)
+    # stage timers (HIP events inside the library) in a separate pass, so that the headline time
+    # carries no event records
+    _, _, out_st = time_steps(torch, rt, prob, w, precision, args.steps, 1, timers=True)
+    out["stages"] = out_st.get("stages", {})
     x_true = prob["X64"]
     err = float(torch.linalg.norm(out["X"].double() - x_true) / torch.linalg.norm(x_true))
     result = {
@@ -239,11 +275,13 @@ def main():
     }
     stages = out.get("stages", {})
     if stages:
-        dom = max(stages, key=lambda k: stages[k]["ms_per_step"])
+        single = [k for k in stages if k in SINGLE_KERNEL]
+        dom = max(single, key=lambda k: stages[k]["ms_per_step"])
         st = stages[dom]
-        result["roofline"] = {"kernel": dom, "bound": st["bound"], "achieved": st["achieved"], "peak": st["peak"],
-                              "unit": st["unit"], "frac": st["frac"], "traffic": None,
-                              "avg_launch_us": st["avg_launch_us"]}
+        result["roofline"] = {"kernel": SINGLE_KERNEL[dom], "stage": dom, "bound": st["bound"],
+                              "achieved": st["achieved"], "peak": st["peak"], "unit": st["unit"], "frac": st["frac"],
+                              "traffic": traffic_of(dom, precision), "avg_launch_us": st["avg_launch_us"],
+                              "launches_per_step": st["launches_per_step"]}
         result["stages"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                             for k, v in stages.items()}
     if not args.no_fp64 and precision != "fp64":

@@ -183,6 +183,7 @@ int rtsvd_solve_vjp(const void* A, const void* dA, const void* B, const void* om
 #define RTSVD_T_SVDAUX 11    /* Gram C C^H, V = C^H U-breve diag(1/sigma), error indicator    */
 #define RTSVD_T_SOLVE 12     /* whole rtsvd_solve                                            */
 #define RTSVD_T_TGKB 13      /* whole tgkb_solve                                             */
+#define RTSVD_T_W_MMA 14     /* the MFMA kernel of W = A-hat V alone (inside RTSVD_T_W)        */
 int rtsvd_timer_enable(int on);
 int rtsvd_timer_read(int tag, double* total_ms, int32_t* launches);
 

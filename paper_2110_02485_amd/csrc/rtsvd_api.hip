@@ -334,12 +334,21 @@ static int gram(const TY* Y, int64_t rows, int64_t r, int64_t F, zd* G, Scratch&
 }
 
 // C_f = op(A_f) X_f on MFMA, X packed into pool scratch first
+// ktag: optional timer tag for the product kernel alone (without the packing pass)
 template <typename TA, typename TX, typename TC>
 static int skinny(bool conjA, int64_t M, int64_t N, int64_t K, const TA* A, int64_t lda, int64_t sA, const TX* X,
-                  int64_t ldx, int64_t sX, TC* C, int64_t ldc, int64_t sC, int64_t F, Scratch& sc, hipStream_t s) {
+                  int64_t ldx, int64_t sX, TC* C, int64_t ldc, int64_t sC, int64_t F, Scratch& sc, hipStream_t s,
+                  int ktag = 0) {
+  if (M <= 0 || N <= 0 || F <= 0) return 0;
+  if (K <= 0) return fail(RTSVD_E_ARG, "skinny product: K must be positive");
   unsigned char* ws = sc.get<unsigned char>(sk::skinny_ws_bytes<TA>((int)K, (int)N, (int)F));
   if (!ws) return fail(RTSVD_E_NOMEM, "device allocation failed: packed operand");
-  return sk::skinny_cgemm<TA, TX, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, X, ldx, sX, C, ldc, sC, (int)F, ws, s);
+  if (sk::skinny_pack<TA, TX>((int)N, (int)K, X, ldx, sX, (int)F, ws, s)) return fail(RTSVD_E_HIP, "skinny pack launch");
+  if (ktag) {
+    RT_TIMED(ktag);
+    return sk::skinny_run<TA, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s);
+  }
+  return sk::skinny_run<TA, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -369,9 +378,9 @@ static int orthonormalize(TY*& Y, int64_t rows, int64_t r, int64_t F, int passes
 // products over A-hat: Y = A-hat X (conjA = false, Y is l x r) or Y = A-hat^H X (Y is m x r)
 template <typename TA, typename TX, typename TY>
 static int big_gemm(bool conjA, const TA* Ah, int64_t l, int64_t m, const TX* X, int64_t r, TY* Y, int64_t F,
-                    Scratch& sc, hipStream_t s) {
-  if (!conjA) return skinny<TA, TX, TY>(false, l, r, m, Ah, l, l * m, X, m, m * r, Y, l, l * r, F, sc, s);
-  return skinny<TA, TX, TY>(true, m, r, l, Ah, l, l * m, X, l, l * r, Y, m, m * r, F, sc, s);
+                    Scratch& sc, hipStream_t s, int ktag = 0) {
+  if (!conjA) return skinny<TA, TX, TY>(false, l, r, m, Ah, l, l * m, X, m, m * r, Y, l, l * r, F, sc, s, ktag);
+  return skinny<TA, TX, TY>(true, m, r, l, Ah, l, l * m, X, l, l * r, Y, m, m * r, F, sc, s, ktag);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -479,7 +488,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     // W = A-hat V: exact residuals of the discrepancy principle
     {
       RT_TIMED(RTSVD_T_W);
-      RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, r, Wo, F, sc, s)));
+      RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, r, Wo, F, sc, s, RTSVD_T_W_MMA)));
     }
   } else {
     // full facewise SVD through G = A-hat^H A-hat = V diag(sigma^2) V^H; W = A-hat V; U = W diag(1/sigma)

@@ -512,20 +512,6 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
   }
 }
 
-// G_f = sum over splits of the partials, lower triangle; upper triangle mirrored (Hermitian).
-__global__ void k_gram_reduce(const zd* __restrict__ part, int r, int ksplit, int64_t sPart, zd* __restrict__ G) {
-  const int f = blockIdx.y;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)r * r) return;
-  const int i = (int)(idx % r), j = (int)(idx / r);
-  const int ii = i >= j ? i : j, jj = i >= j ? j : i;  // lower element (ii >= jj)
-  const zd* p = part + (int64_t)f * ksplit * sPart;
-  zd s = mk(0.0, 0.0);
-  for (int q = 0; q < ksplit; ++q) s = cadd(s, p[(int64_t)q * sPart + ii + (int64_t)jj * r]);
-  if (i == j) s.im = 0.0;
-  G[(int64_t)f * r * r + idx] = (i >= j) ? s : cconj(s);
-}
-
 // ---------------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------------
@@ -614,42 +600,35 @@ template <typename TA> static inline int64_t skinny_ws_bytes(int K, int N, int b
   return packed_elems<P>(K, N, batch) * (int64_t)sizeof(typename P::E);
 }
 
-// C_f = op(A_f) X_f with X packed into `ws` (skinny_ws_bytes<TA>(K, N, batch) bytes) first.
-template <typename TA, typename TX, typename TC>
-static int skinny_cgemm(bool conjA, int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const TX* X,
-                        int64_t ldx, int64_t sX, TC* C, int64_t ldc, int64_t sC, int batch, void* ws, hipStream_t s) {
+// C_f = op(A_f) X_f with X packed into `ws` (skinny_ws_bytes<TA>(K, N, batch) bytes) first:
+// skinny_pack, then skinny_run (split so that the caller can time the product kernel alone).
+template <typename TA, typename TX>
+static int skinny_pack(int N, int K, const TX* X, int64_t ldx, int64_t sX, int batch, void* ws, hipStream_t s) {
   typedef typename PrecOf<TA>::P P;
   typedef typename P::E E;
-  if (M <= 0 || N <= 0 || batch <= 0) return 0;
-  if (K <= 0) return -1;
   const int NP = 16 * nt_for<P>(N);
   const int KP = packed_kp<P>(K);
   const int NPt = (int)(ceil_div(N, NP) * NP);
-  E* Xp = static_cast<E*>(ws);
   constexpr int KSL = kslab<P>();
-  const int ntl = NPt / NP;
   const int64_t total = (int64_t)NPt * KP * batch;
   hipLaunchKernelGGL((k_pack_slabs<TX, E, KSL>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, X, ldx, sX, K, N,
-                     Xp, KP, NP, ntl, batch);
-  if (hipGetLastError() != hipSuccess) return -1;
+                     static_cast<E*>(ws), KP, NP, NPt / NP, batch);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename TA, typename TC>
+static int skinny_run(bool conjA, int M, int N, int K, const TA* A, int64_t lda, int64_t sA, TC* C, int64_t ldc,
+                      int64_t sC, int batch, const void* ws, hipStream_t s) {
+  typedef typename PrecOf<TA>::P P;
+  typedef typename P::E E;
+  const int NP = 16 * nt_for<P>(N);
+  const int KP = packed_kp<P>(K);
+  const int NPt = (int)(ceil_div(N, NP) * NP);
+  const E* Xp = static_cast<const E*>(ws);
   const int64_t sXp = 2 * (int64_t)NPt * KP;
   // packed X: the raw type parameter is unused, fixed to zd to share instantiations
   if (!conjA) return sk_launch<P, false, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
   return sk_launch<P, true, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
-}
-
-// FP64 Gram G_f = Y_f^H Y_f (r x r) of Y_f (rows x r, any complex storage type): split-K partials
-// (batch x ksplit x r x r) in `part`, lower tiles only, then a deterministic reduction.
-template <typename TY>
-static int gram_fp64(const TY* Y, int64_t rows, int r, int64_t sY, int batch, zd* part, int ksplit, zd* G,
-                     hipStream_t s) {
-  const int64_t sPart = (int64_t)r * r;
-  int rc = sk_launch<F64, true, false, true, TY, TY, zd>(r, r, (int)rows, Y, rows, sY, Y, rows, sY, part, r,
-                                                         (int64_t)ksplit * sPart, batch, ksplit, sPart, s);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div((int64_t)r * r, 256), (unsigned)batch), dim3(256), 0, s,
-                     part, r, ksplit, sPart, G);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace sk
