@@ -913,6 +913,8 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
   const int nw = (int)blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, rho = lane & 15;   // MFMA lane coordinates
+  __shared__ zd chx[2][CH_NB];                // wave 0's column / row exchange (double-buffered)
+  __shared__ zd chl[CH_NB][CH_NB + 1];        // the factored diagonal block
   // packed lower storage, column j at j r - j (j - 1) / 2
   auto at = [&](int i, int j) -> zd& { return S[j * r - (j * (j - 1)) / 2 + (i - j)]; };  // i >= j
   const zd zero = mk(0.0, 0.0);
@@ -948,20 +950,25 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
         d[s2] = diag;
       }
       double myipv = 1.0;   // 1 / L(rho, rho) once column rho is factored
+      // column exchange through LDS (one write, broadcast reads; the wave's LDS operations run in
+      // order) and pivots read from a fixed lane as scalars: no chains of cross-lane permutes
 #pragma unroll
       for (int c = 0; c < CH_NB; ++c) {
         const int cs = c & 3, sl = c >> 2;
         const zd ac = a[sl];
-        const double dd = __shfl(ac.re, c + 16 * cs);
+        const double dd = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ac.re), c + 16 * cs),
+                                           __builtin_amdgcn_readlane(__double2loint(ac.re), c + 16 * cs));
         const double pv = (c >= kb) ? 1.0 : ((dd > tol && dd > 0.0) ? sqrt(dd) : 0.0);
         const double ipv = pv > 0.0 ? 1.0 / pv : 0.0;
         myipv = (rho == c) ? ipv : myipv;
         const zd acn = zsel(g != cs || rho < c, ac, zsel(rho == c, mk(pv, 0.0), cscale(ac, ipv)));
         a[sl] = acn;
-        const zd lic = ch_shfl(acn, rho + 16 * cs);   // L(rho, c)
+        if (g == cs) chx[c & 1][rho] = acn;   // column c of L (rows < c hold the upper part, unused)
+        __builtin_amdgcn_wave_barrier();
+        const zd lic = chx[c & 1][rho];        // L(rho, c)
         zd ljc[4];
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) ljc[s2] = ch_shfl(acn, g + 4 * s2 + 16 * cs);   // L(j_s, c)
+        for (int s2 = 0; s2 < 4; ++s2) ljc[s2] = chx[c & 1][g + 4 * s2];   // L(j_s, c)
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
           const int j = g + 4 * s2;
@@ -969,6 +976,10 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
           a[s2] = zsel(j > c && rho >= j, upd, a[s2]);
         }
       }
+      // the factored block to LDS for the substitution below
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) chl[rho][g + 4 * s2] = a[s2];
+      __builtin_amdgcn_wave_barrier();
       if (g == 0 && rho < kb) {
         H.ipiv[K + rho] = myipv;
         if (myipv == 0.0) H.bad = 1;
@@ -979,11 +990,17 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
         const double sc = (rho == t) ? myipv : 1.0;   // branch-free: the arrays stay in registers
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) d[s2] = cscale(d[s2], sc);
-        const zd lit = ch_shfl(a[t >> 2], rho + 16 * (t & 3));   // L(rho, t)
+        // row t of D is final: publish it, then eliminate it from the rows below
+        if (rho == t) {
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) chx[t & 1][g + 4 * s2] = d[s2];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const zd lit = chl[rho][t];                 // L(rho, t)
         const zd lm = zsel(rho > t, lit, zero);
         zd dtj[4];
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) dtj[s2] = ch_shfl(d[s2], t + 16 * g);   // D(t, j_s)
+        for (int s2 = 0; s2 < 4; ++s2) dtj[s2] = chx[t & 1][g + 4 * s2];   // D(t, j_s)
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) d[s2] = csub(d[s2], cmul(lm, dtj[s2]));
       }
