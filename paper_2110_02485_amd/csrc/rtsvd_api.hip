@@ -334,11 +334,12 @@ static int gram(const TY* Y, int64_t rows, int64_t r, int64_t F, zd* G, Scratch&
 }
 
 // C_f = op(A_f) X_f on MFMA, X packed into pool scratch first
-// ktag: optional timer tag for the product kernel alone (without the packing pass)
+// ktag: optional timer tag for the product kernel alone (without the packing pass);
+// utri: X is upper triangular (its zero blocks are skipped)
 template <typename TA, typename TX, typename TC>
 static int skinny(bool conjA, int64_t M, int64_t N, int64_t K, const TA* A, int64_t lda, int64_t sA, const TX* X,
                   int64_t ldx, int64_t sX, TC* C, int64_t ldc, int64_t sC, int64_t F, Scratch& sc, hipStream_t s,
-                  int ktag = 0) {
+                  int ktag = 0, int utri = 0) {
   if (M <= 0 || N <= 0 || F <= 0) return 0;
   if (K <= 0) return fail(RTSVD_E_ARG, "skinny product: K must be positive");
   unsigned char* ws = sc.get<unsigned char>(sk::skinny_ws_bytes<TA>((int)K, (int)N, (int)F));
@@ -346,9 +347,9 @@ static int skinny(bool conjA, int64_t M, int64_t N, int64_t K, const TA* A, int6
   if (sk::skinny_pack<TA, TX>((int)N, (int)K, X, ldx, sX, (int)F, ws, s)) return fail(RTSVD_E_HIP, "skinny pack launch");
   if (ktag) {
     RT_TIMED(ktag);
-    return sk::skinny_run<TA, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s);
+    return sk::skinny_run<TA, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri);
   }
-  return sk::skinny_run<TA, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s);
+  return sk::skinny_run<TA, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -369,7 +370,8 @@ static int orthonormalize(TY*& Y, int64_t rows, int64_t r, int64_t F, int passes
       RT_TRY(launch_cholinv(G, (int)r, F, Rinv, flags, sc, s));
     }
     RT_TIMED(RTSVD_T_QMUL);
-    RT_TRY((skinny<TY, zd, TY>(false, rows, r, r, Y, rows, rows * r, Rinv, r, r * r, tmp, rows, rows * r, F, sc, s)));
+    // R^{-1} is upper triangular
+    RT_TRY((skinny<TY, zd, TY>(false, rows, r, r, Y, rows, rows * r, Rinv, r, r * r, tmp, rows, rows * r, F, sc, s, 0, 1)));
     std::swap(Y, tmp);
   }
   return 0;

@@ -160,7 +160,7 @@ __global__ void k_pack_slabs(const TX* __restrict__ X, int64_t ldx, int64_t sX, 
 // Both paths are branch-free inside the k loop.  LOWER: skip column tiles strictly above the
 // diagonal (Hermitian Gram).  vec_c: the host has checked the alignment of 16-byte stores.
 // k-groups past kend see X = 0 (packed X is zero-padded, raw X is zeroed while staging).
-template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, typename TA, typename TX, typename TC, int NB>
+template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, bool UTRI, typename TA, typename TX, typename TC, int NB>
 __global__ void __launch_bounds__(SK_THREADS, 2)
 k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA, const void* __restrict__ Xv,
          int64_t ldx, int64_t sX, TC* __restrict__ C, int64_t ldc, int64_t sC, int batch, int mtiles, int ntiles,
@@ -238,8 +238,9 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
     const int c = min(tid + SK_THREADS * q, ACH - 1);
     a_line[q] = c / ACH_PER_LINE;   // NN: k within the group; CN: column within the tile
     a_seg[q] = c % ACH_PER_LINE;
+    // full offset of the chunk; the triangular-X products clamp the k row instead (below)
     a_goff[q] = CN ? (uint32_t)((int64_t)(m0 + a_line[q]) * lda + a_seg[q] * TAC)
-                   : (uint32_t)((int64_t)a_line[q] * lda + m0 + a_seg[q] * TAC);
+                   : (uint32_t)((UTRI ? 0 : (int64_t)a_line[q] * lda) + m0 + a_seg[q] * TAC);
     a_loff[q] = a_line[q] * ASTR + a_seg[q] * 16;
   }
   int x_loff[NXC], x_col[NXC], x_k[NXC];
@@ -269,7 +270,16 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
 #pragma unroll
     for (int q = 0; q < NAC; ++q) {
       if constexpr (!SAFE) {
-        st.a[q] = *reinterpret_cast<const u32x4*>(A + (CN ? (int64_t)ka : (int64_t)ka * lda) + a_goff[q]);
+        if constexpr (CN) {
+          st.a[q] = *reinterpret_cast<const u32x4*>(A + (int64_t)ka + a_goff[q]);
+        } else if constexpr (UTRI) {
+          // K need not be a multiple of the k-group here (K = r): k rows past K re-read row K - 1,
+          // finite values that meet the zero padding of the packed X
+          const uint32_t line = (uint32_t)min(a_line[q], K - 1 - ka);
+          st.a[q] = *reinterpret_cast<const u32x4*>(A + (int64_t)ka * lda + (line * (uint32_t)lda + a_goff[q]));
+        } else {
+          st.a[q] = *reinterpret_cast<const u32x4*>(A + (int64_t)ka * lda + a_goff[q]);
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < TAC; ++e) {
@@ -345,7 +355,10 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
       for (int v = 0; v < 4; ++v) { accr[tt][c][v] = 0; acci[tt][c][v] = 0; }
 
   // one k-group from an LDS buffer
-  auto compute = [&](const unsigned char* buf) {
+  // UTRI: X is upper triangular (X[k][n] = 0 for k > n), so column tile c skips k-groups that
+  // start below its last column (NN only)
+  auto skip = [&](int kc, int c) { return UTRI && kc > n0 + cw + 16 * c + 15; };
+  auto compute = [&](const unsigned char* buf, int kc) {
     const unsigned char* abuf = buf;
     const E* Bc = reinterpret_cast<const E*>(buf + ATILE);
     // A fragments of this lane: ra[tt][e] = op(A) row (rw + 2 rho + tt or rw + rho), k = KL g + e
@@ -389,7 +402,7 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
       }
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
-        if (LOWER && n0 + cw + 16 * c > wmax) continue;
+        if ((LOWER && n0 + cw + 16 * c > wmax) || skip(kc, c)) continue;
 #pragma unroll
         for (int tt = 0; tt < RT; ++tt) {
           accr[tt][c] = mma(far[tt], br[c], accr[tt][c]);
@@ -398,7 +411,7 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
       }
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
-        if (LOWER && n0 + cw + 16 * c > wmax) continue;
+        if ((LOWER && n0 + cw + 16 * c > wmax) || skip(kc, c)) continue;
 #pragma unroll
         for (int tt = 0; tt < RT; ++tt) {
           accr[tt][c] = mma(fan[tt], bi[c], accr[tt][c]);
@@ -427,7 +440,7 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
       for (int e = 0; e < KL; ++e) {
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-          if (LOWER && n0 + cw + 16 * c > wmax) continue;
+          if ((LOWER && n0 + cw + 16 * c > wmax) || skip(kc, c)) continue;
 #pragma unroll
           for (int tt = 0; tt < RT; ++tt) {
             accr[tt][c] = mma(xr[tt][e], br[c][e], accr[tt][c]);
@@ -436,7 +449,7 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
         }
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-          if (LOWER && n0 + cw + 16 * c > wmax) continue;
+          if ((LOWER && n0 + cw + 16 * c > wmax) || skip(kc, c)) continue;
 #pragma unroll
           for (int tt = 0; tt < RT; ++tt) {
             accr[tt][c] = mma(xn[tt][e], bi[c][e], accr[tt][c]);
@@ -466,7 +479,7 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
 #define RT_SK_STEP(LOADSET, KLOAD, BUFC, STORESET, BUFN, KSTORE) \
     load_stage(LOADSET, KLOAD);                                  \
     __builtin_amdgcn_sched_barrier(0);                           \
-    compute(BUFC);                                               \
+    compute(BUFC, (KLOAD) - SK_DEPTH * KG);                      \
     __builtin_amdgcn_sched_barrier(0);                           \
     store_stage(STORESET, BUFN, KSTORE);                         \
     __syncthreads();                                             \
@@ -524,7 +537,7 @@ static inline bool aligned_elems(const void* p, int64_t a, int64_t b, int64_t c,
 // column tiles of 16 per block
 template <class P> static inline int nt_for(int N) { return N <= 16 ? 1 : (N <= 32 ? 2 : (N <= 64 ? 4 : 8)); }
 
-template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, typename TA, typename TX, typename TC, int NT>
+template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, bool UTRI, typename TA, typename TX, typename TC, int NT>
 static int sk_launch_nt(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const void* X, int64_t ldx,
                         int64_t sX, TC* C, int64_t ldc, int64_t sC, int batch, int ksplit, int64_t sCsplit,
                         hipStream_t s) {
@@ -539,7 +552,7 @@ static int sk_launch_nt(int M, int N, int K, const TA* A, int64_t lda, int64_t s
   static int attr_done[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
-  auto kern = k_skinny<P, CN, PACKED, SAFE, LOWER, TA, TX, TC, NT>;
+  auto kern = k_skinny<P, CN, PACKED, SAFE, LOWER, UTRI, TA, TX, TC, NT>;
   if (bytes > 65536 && dev >= 0 && dev < 64 && !attr_done[dev]) {
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) return -1;
     attr_done[dev] = 1;
@@ -551,7 +564,7 @@ static int sk_launch_nt(int M, int N, int K, const TA* A, int64_t lda, int64_t s
 }
 
 // picks the column-tile count by N and the unchecked (vector) path when shapes and alignment allow
-template <class P, bool CN, bool PACKED, bool LOWER, typename TA, typename TX, typename TC>
+template <class P, bool CN, bool PACKED, bool LOWER, typename TA, typename TX, typename TC, bool UTRI = false>
 static int sk_launch(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const void* X, int64_t ldx, int64_t sX,
                      TC* C, int64_t ldc, int64_t sC, int batch, int ksplit, int64_t sCsplit, hipStream_t s) {
   constexpr int KS = 4 * P::KL;
@@ -565,11 +578,13 @@ static int sk_launch(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, 
                          (PACKED || (int64_t)N * ldx < (1LL << 31));
   const int nt = nt_for<P>(N);
   const int BM = (nt == 1 ? Shape<1>::WR : nt == 2 ? Shape<2>::WR : nt == 4 ? Shape<4>::WR : Shape<8>::WR) * 16 * P::RT;
-  const bool fast = vec_a && vec_x && small_off && M % BM == 0 && K % KS == 0;
+  // the triangular-X NN products clamp the k rows of a partial last k-group; the others need
+  // whole k-groups on the unchecked path
+  const bool fast = vec_a && vec_x && small_off && M % BM == 0 && (K % KS == 0 || (UTRI && !CN));
 #define RT_SK_NT(NTV)                                                                                          \
-  (fast ? sk_launch_nt<P, CN, PACKED, false, LOWER, TA, TX, TC, NTV>(M, N, K, A, lda, sA, X, ldx, sX, C, ldc, sC, \
+  (fast ? sk_launch_nt<P, CN, PACKED, false, LOWER, UTRI, TA, TX, TC, NTV>(M, N, K, A, lda, sA, X, ldx, sX, C, ldc, sC, \
                                                                     batch, ksplit, sCsplit, s)                 \
-        : sk_launch_nt<P, CN, PACKED, true, LOWER, TA, TX, TC, NTV>(M, N, K, A, lda, sA, X, ldx, sX, C, ldc, sC,  \
+        : sk_launch_nt<P, CN, PACKED, true, LOWER, UTRI, TA, TX, TC, NTV>(M, N, K, A, lda, sA, X, ldx, sX, C, ldc, sC,  \
                                                                    batch, ksplit, sCsplit, s))
   if (nt == 1) return RT_SK_NT(1);
   if (nt == 2) return RT_SK_NT(2);
@@ -618,7 +633,7 @@ static int skinny_pack(int N, int K, const TX* X, int64_t ldx, int64_t sX, int b
 
 template <typename TA, typename TC>
 static int skinny_run(bool conjA, int M, int N, int K, const TA* A, int64_t lda, int64_t sA, TC* C, int64_t ldc,
-                      int64_t sC, int batch, const void* ws, hipStream_t s) {
+                      int64_t sC, int batch, const void* ws, hipStream_t s, int utri = 0) {
   typedef typename PrecOf<TA>::P P;
   typedef typename P::E E;
   const int NP = 16 * nt_for<P>(N);
@@ -627,8 +642,10 @@ static int skinny_run(bool conjA, int M, int N, int K, const TA* A, int64_t lda,
   const E* Xp = static_cast<const E*>(ws);
   const int64_t sXp = 2 * (int64_t)NPt * KP;
   // packed X: the raw type parameter is unused, fixed to zd to share instantiations
-  if (!conjA) return sk_launch<P, false, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
-  return sk_launch<P, true, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
+  if (conjA) return sk_launch<P, true, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
+  if (utri)
+    return sk_launch<P, false, true, false, TA, zd, TC, true>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
+  return sk_launch<P, false, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
 }
 
 }  // namespace sk
