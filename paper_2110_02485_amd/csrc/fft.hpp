@@ -132,7 +132,9 @@ template <int B> constexpr int bitrev(int k) {
 constexpr int ilog2_ce(int n) { return n <= 1 ? 0 : 1 + ilog2_ce(n / 2); }
 
 template <int N, bool HALF, typename Tin, typename T>
-__global__ void __launch_bounds__(RFFT_REG_THREADS)
+// two waves per SIMD for the variant with the bf16 copy (the A-hat pass: measured faster despite
+// a small spill); one for the other
+__global__ void __launch_bounds__(RFFT_REG_THREADS, HALF ? 2 : 1)
 k_rfft_reg(const Tin* __restrict__ in, int64_t ntubes, cplx<T>* __restrict__ out, int64_t face_stride,
            zb* __restrict__ out16, double* __restrict__ sumsq, const cplx<T>* __restrict__ gtw) {
   constexpr int M = N / 2, LM = ilog2_ce(M);

@@ -648,8 +648,11 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   RT_ALLOC(bnd, double, groups, sc);
   RT_ALLOC(rho_tmp, double, (int64_t)groups * kcap, sc);
   RT_TRY(upload_doubles(bnd, bounds.data(), groups, s));
-  hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(DP_SEL_THREADS), 0, s, partial, (int)F, tiles, (int)p, kcap, (int)n, groups, bnd,
-                     k_start, k_out, resid_out, status_out, rho_tmp);
+  hipLaunchKernelGGL(k_dp_rho, dim3((unsigned)(groups * kcap)), dim3(DP_RHO_THREADS), 0, s, partial, (int)F, tiles,
+                     (int)p, kcap, (int)n, groups, resid_out, rho_tmp);
+  RT_LAUNCH_OK();
+  hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(256), 0, s, kcap, groups, (const double*)bnd, k_start, (const double*)rho_tmp,
+                     k_out, status_out);
   RT_LAUNCH_OK();
   // X-hat = V T', T' = T with rows >= k zeroed; X = inverse DFT
   hipLaunchKernelGGL(k_mask_coeffs, dim3(nblocks(F * r * p)), dim3(256), 0, s, T, D, k_out, groups, (int)r, (int)p,

@@ -68,44 +68,43 @@ k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __r
   }
 }
 
-// One block of DP_SEL_THREADS.  groups = 1 (joint) or p (per slice).  k_start >= 1.
-// rho_k^2 = (1/n) sum_f w_f sum_{tiles, columns of the group} partial: one wave per (group, k),
-// summed in a fixed order (deterministic).
-__global__ void __launch_bounds__(DP_SEL_THREADS)
-k_dp_select(const double* __restrict__ partial, int F, int tiles, int p, int kcap, int n,
-            int groups, const double* __restrict__ bound /* eta*delta per group */,
-            int k_start, int* __restrict__ k_out, double* __restrict__ resid_out,
-            int* __restrict__ status_out, double* __restrict__ rho_tmp) {
-  // rho_tmp: groups * kcap doubles of scratch
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int idx = wave; idx < groups * kcap; idx += nw) {
-    const int g = idx / kcap, k = idx % kcap;
-    const int c0 = groups == 1 ? 0 : g, nc = groups == 1 ? p : 1;
-    // lanes over (face, tile) pairs, columns of the group summed in a short inner loop
-    const int cnt = F * tiles;
-    double s = 0.0;
-    int fi = lane / tiles, t = lane % tiles;
-    const int step_f = 64 / tiles, step_t = 64 % tiles;
-    for (int e = lane; e < cnt; e += 64) {
-      const double w = (fi == 0 || 2 * fi == n) ? 1.0 : 2.0;
-      const double* pp = partial + (((int64_t)fi * tiles + t) * p + c0) * kcap + k;
-      double v = 0.0;
-      for (int c = 0; c < nc; ++c) v += pp[(int64_t)c * kcap];
-      s += w * v;
-      fi += step_f;
-      t += step_t;
-      if (t >= tiles) { t -= tiles; ++fi; }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) {
-      const double rho = sqrt(fmax(s / (double)n, 0.0));
-      rho_tmp[idx] = rho;
-      if (resid_out) resid_out[idx] = rho;
-    }
+// rho_k^2 = (1/n) sum_f w_f sum_{tiles, columns of the group} partial: one 256-thread workgroup
+// per (group, k) (grid groups * kcap), summed in a fixed order (deterministic).
+constexpr int DP_RHO_THREADS = 256;
+__global__ void __launch_bounds__(DP_RHO_THREADS)
+k_dp_rho(const double* __restrict__ partial, int F, int tiles, int p, int kcap, int n, int groups,
+         double* __restrict__ resid_out, double* __restrict__ rho_tmp) {
+  __shared__ double red[DP_RHO_THREADS / 64];
+  const int idx = blockIdx.x;
+  const int g = idx / kcap, k = idx % kcap;
+  const int c0 = groups == 1 ? 0 : g, nc = groups == 1 ? p : 1;
+  const int cnt = F * tiles;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < cnt; e += DP_RHO_THREADS) {
+    const int fi = e / tiles, t = e - fi * tiles;
+    const double w = (fi == 0 || 2 * fi == n) ? 1.0 : 2.0;
+    const double* pp = partial + (((int64_t)fi * tiles + t) * p + c0) * kcap + k;
+    double v = 0.0;
+    for (int c = 0; c < nc; ++c) v += pp[(int64_t)c * kcap];
+    s += w * v;
   }
-  __threadfence_block();
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < DP_RHO_THREADS / 64; ++w) t += red[w];
+    const double rho = sqrt(fmax(t / (double)n, 0.0));
+    rho_tmp[idx] = rho;
+    if (resid_out) resid_out[idx] = rho;
+  }
+}
+
+// The first k >= k_start with rho_k <= eta delta of each group (one block).  k_start >= 1.
+__global__ void k_dp_select(int kcap, int groups, const double* __restrict__ bound /* eta*delta per group */,
+                            int k_start, const double* __restrict__ rho_tmp, int* __restrict__ k_out,
+                            int* __restrict__ status_out) {
   __shared__ int any_fail;
   if (threadIdx.x == 0) any_fail = 0;
   __syncthreads();
