@@ -65,6 +65,12 @@ typedef struct {
                         /* tensor columns play the role of the Gaussian slices G of Alg. 6      */
   double eps;           /* > 0: also report r_eps = min{ j : eta^[j] < eps^2 } (Alg. 6 stopping */
                         /* rule, Thm 4.2); <= 0: not used                                        */
+  int32_t adaptive;     /* nonzero (with eps > 0): the fixed-precision R-tSVD of Alg. 6 -- the  */
+                        /* factor keeps the first r_eps sketch columns (r_max = min(k_max +     */
+                        /* oversample, m) if eta^[j] >= eps^2 for all j), so that rtsvd_solve   */
+                        /* with k_start = 0 searches k from r_eps - oversample (the experiments' */
+                        /* rule, Section 5).  The nested sketch makes this the factor Alg. 6    */
+                        /* builds column by column.  Costs one host synchronization.            */
 } rtsvd_opts;
 
 /* R-tSVD factorization (Section 4.2, Alg. 6 in block form, Thms 4.1-4.2).

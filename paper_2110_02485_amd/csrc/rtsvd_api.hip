@@ -388,9 +388,19 @@ static int big_gemm(bool conjA, const TA* Ah, int64_t l, int64_t m, const TX* X,
 // ---------------------------------------------------------------------------------------------
 // R-tSVD factor (Alg. 6, block form) and the T-tSVD comparator (Alg. 1)
 // ---------------------------------------------------------------------------------------------
+// k x k leading block of every face's r x r matrix (column-major), packed to k x k
+__global__ void k_lead_block(const zd* __restrict__ G, int r, int k, int F, zd* __restrict__ Gk) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)F * k * k) return;
+  const int i = (int)(idx % k), j = (int)((idx / k) % k);
+  const int64_t f = idx / ((int64_t)k * k);
+  Gk[idx] = G[f * r * r + i + (int64_t)j * r];
+}
+
+// adapt_eps > 0: the fixed-precision factor of Alg. 6 (keep the first r_eps sketch columns)
 template <typename Tin, typename Tw>
 static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int64_t n, int64_t r, int precision,
-                       int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd_mode) {
+                       int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd_mode, double adapt_eps = 0.0) {
   typedef cplx<Tw> zw;
   const int64_t F = n / 2 + 1;
   const bool bf16 = (precision == RTSVD_P_BF16);
@@ -472,26 +482,50 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
                          (int64_t)2 * r * r, (int64_t)2 * (r + 1), (int)F, (int)r, (int)n, eta);
       RT_LAUNCH_OK();
     }
+    // fixed precision (Alg. 6): r_eps = first j >= 1 with eta^[j] < eps^2.  QR and the power
+    // updates are nested, so the first r_eps columns of Q (and rows of C) are what the algorithm
+    // builds from the first r_eps Gaussian columns; G's leading block is C_{r_eps} C_{r_eps}^H.
+    int64_t rr = r;
+    zd* Gs = G;
+    if (adapt_eps > 0.0) {
+      std::vector<double> he((size_t)r + 1);
+      RT_CHECK_HIP(hipMemcpyAsync(he.data(), eta, sizeof(double) * (r + 1), hipMemcpyDeviceToHost, s));
+      RT_CHECK_HIP(hipStreamSynchronize(s));
+      for (int64_t j = 1; j <= r; ++j)
+        if (he[j] < adapt_eps * adapt_eps) { rr = j; break; }
+      if (rr < r) {
+        RT_ALLOC(Gk, zd, F * rr * rr, sc);
+        hipLaunchKernelGGL(k_lead_block, dim3(nblocks(F * rr * rr)), dim3(256), 0, s, (const zd*)G, (int)r, (int)rr,
+                           (int)F, Gk);
+        RT_LAUNCH_OK();
+        Gs = Gk;
+        RT_ALLOC(Qk, zw, F * l * rr, sc);
+        RT_CHECK_HIP(hipMemcpy2DAsync(Qk, sizeof(zw) * l * rr, Qo, sizeof(zw) * l * r, sizeof(zw) * l * rr, F,
+                                      hipMemcpyDeviceToDevice, s));
+        Qo = Qk;
+      }
+    }
     {
       RT_TIMED(RTSVD_T_HEEV);
-      RT_TRY(launch_heev(G, (int)r, F, Ub, lam, sc, s));
+      RT_TRY(launch_heev(Gs, (int)rr, F, Ub, lam, sc, s));
     }
     {
       RT_TIMED(RTSVD_T_SVDAUX);
-      hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * r)), dim3(256), 0, s, lam, sigma, (int)r, (int)F, eig_tol);
+      hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * rr)), dim3(256), 0, s, lam, sigma, (int)rr, (int)F, eig_tol);
       RT_LAUNCH_OK();
       // V = C^H (U-breve diag(1/sigma)): the scaling goes on the r x r factor
-      RT_ALLOC(Ubs, zd, F * r * r, sc);
-      hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * r * r)), dim3(256), 0, s, Ub, Ubs, sigma, (int)r,
-                         (int)r, (int)F);
+      RT_ALLOC(Ubs, zd, F * rr * rr, sc);
+      hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * rr * rr)), dim3(256), 0, s, Ub, Ubs, sigma, (int)rr,
+                         (int)rr, (int)F);
       RT_LAUNCH_OK();
-      RT_TRY((skinny<zd, zd, zd>(false, m, r, r, Ch, m, m * r, Ubs, r, r * r, V, m, m * r, F, sc, s)));
+      RT_TRY((skinny<zd, zd, zd>(false, m, rr, rr, Ch, m, m * r, Ubs, rr, rr * rr, V, m, m * rr, F, sc, s)));
     }
     // W = A-hat V: exact residuals of the discrepancy principle
     {
       RT_TIMED(RTSVD_T_W);
-      RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, r, Wo, F, sc, s, RTSVD_T_W_MMA)));
+      RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, rr, Wo, F, sc, s, RTSVD_T_W_MMA)));
     }
+    h->r = rr;
   } else {
     // full facewise SVD through G = A-hat^H A-hat = V diag(sigma^2) V^H; W = A-hat V; U = W diag(1/sigma)
     RT_TRY(gram<zw>(Ah, l, m, F, G, sc, s));
@@ -527,15 +561,17 @@ static void free_handle(rtsvd_factor_s* h) {
 }
 
 static int dispatch_factor(const void* A, const void* omega, int dtype, int64_t l, int64_t m, int64_t n, int64_t r,
-                           int precision, int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd) {
+                           int precision, int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd, double ae = 0.0) {
   if (dtype == RTSVD_F64) {
     if (work_is_double(precision))
-      return factor_impl<double, double>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd);
-    return factor_impl<double, float>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd);
+      return factor_impl<double, double>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd,
+                                         ae);
+    return factor_impl<double, float>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd,
+                                      ae);
   }
   if (work_is_double(precision))
-    return factor_impl<float, double>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd);
-  return factor_impl<float, float>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd);
+    return factor_impl<float, double>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd, ae);
+  return factor_impl<float, float>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd, ae);
 }
 
 extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype, const rtsvd_opts* opts,
@@ -557,7 +593,8 @@ extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int 
   rtsvd_factor_s* h = new rtsvd_factor_s();
   h->l = l; h->m = m; h->n = n; h->F = n / 2 + 1; h->r = r; h->dtype = dtype; h->precision = o.precision;
   h->kind = 0; h->k_max = o.k_max; h->oversample = o.oversample; h->eps = o.eps; h->stream = s;
-  const int rc = dispatch_factor(A, o.omega, dtype, l, m, n, r, o.precision, o.power_iters, h, s, false);
+  const double ae = (o.adaptive && o.eps > 0.0) ? o.eps : 0.0;
+  const int rc = dispatch_factor(A, o.omega, dtype, l, m, n, r, o.precision, o.power_iters, h, s, false, ae);
   if (rc != 0) { delete h; return rc; }
   *out = h;
   return RTSVD_OK;

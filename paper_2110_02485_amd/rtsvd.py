@@ -37,7 +37,7 @@ class RtsvdError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("omega", ctypes.c_void_p),
-                ("eps", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("adaptive", ctypes.c_int32)]
 
 
 _lib = None
@@ -146,7 +146,8 @@ class Factor:
 
     @classmethod
     def rtsvd(cls, A: torch.Tensor, k_max: int, oversample: int, power_iters: int = 0, precision: str = "fp64",
-              omega: torch.Tensor | None = None, eps: float = 0.0, seed: int = 0) -> "Factor":
+              omega: torch.Tensor | None = None, eps: float = 0.0, seed: int = 0,
+              adaptive: bool = False) -> "Factor":
         lib = load()
         A = _dev(A, "A")
         n, m, l = A.shape
@@ -156,12 +157,15 @@ class Factor:
         omega = _dev(omega, "omega")
         if tuple(omega.shape) != (n, r, m) or omega.dtype != A.dtype:
             raise ValueError(f"omega must have shape {(n, r, m)} and dtype {A.dtype}")
-        opts = _Opts(k_max, oversample, power_iters, PRECISIONS[precision], seed, omega.data_ptr(), eps)
+        opts = _Opts(k_max, oversample, power_iters, PRECISIONS[precision], seed, omega.data_ptr(), eps,
+                     1 if adaptive else 0)
         h = ctypes.c_void_p()
         _check(lib.rtsvd_factor(A.data_ptr(), l, m, n, _dtype_code(A), ctypes.byref(opts), _stream(),
                                 ctypes.byref(h)), "rtsvd_factor")
         f = cls(h.value, A.dtype, A.device, m, k_max, r, oversample)
         f._keep = omega  # the factor reads omega asynchronously
+        if adaptive and eps > 0.0:
+            f.r = f.info()[0]   # the fixed-precision factor keeps r_eps columns (the call synchronized)
         return f
 
     @classmethod
@@ -226,9 +230,9 @@ def trim() -> None:
     _check(load().rtsvd_trim(), "rtsvd_trim")
 
 
-def factor(A, k_max, oversample, power_iters=0, precision="fp64", omega=None, eps=0.0) -> Factor:
-    """R-tSVD factor of A (see Factor.rtsvd)."""
-    return Factor.rtsvd(A, k_max, oversample, power_iters, precision, omega, eps)
+def factor(A, k_max, oversample, power_iters=0, precision="fp64", omega=None, eps=0.0, adaptive=False) -> Factor:
+    """R-tSVD factor of A (see Factor.rtsvd); adaptive=True with eps > 0: Alg. 6's fixed-precision rank."""
+    return Factor.rtsvd(A, k_max, oversample, power_iters, precision, omega, eps, adaptive=adaptive)
 
 
 def ttsvd_factor(A, k_max, precision="fp64") -> Factor:

@@ -109,6 +109,41 @@ def test_rtsvd_per_slice_and_paper_mode():
     assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-11
 
 
+@pytest.mark.parametrize("q", [0, 1])
+def test_rtsvd_fixed_precision_adaptive(q):
+    # Alg. 6's fixed-precision rank: the factor keeps r_eps = first j with eta^[j] < eps^2 sketch
+    # columns; the solve then searches k from r_eps - rho (experiments' rule).  eps is placed
+    # midway (geometrically) between eta^[j0] and eta^[j0 - 1] of the oracle, far from a tie.
+    A, X, B, Om, delta = blur_problem(56, 12, 2.0, 6, 1, 1e-2, 16, 8, seed=11)
+    k_max, rho = 16, 8
+    Am = wl.to_math(A)
+    full = fa.rtsvd_block(Am, wl.to_math(Om), q)
+    eta_o = fa.eta_prefix(Am, full["C"])
+    j0 = 14
+    eps = float(np.sqrt(np.sqrt(eta_o[j0] * eta_o[j0 - 1])))
+    if q == 0:
+        lit = fa.rtsvd_literal(Am, wl.to_math(Om), eps=eps)
+        assert lit["Q"].shape[1] == j0
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    f = rt.factor(_t(A), k_max, rho, q, "fp64", _t(Om), eps=eps, adaptive=True)
+    r, faces, eta, r_eps, sig, flags = f.info()
+    assert r == j0 and r_eps == j0 and f.r == j0
+    np.testing.assert_allclose(eta, eta_o[:j0 + 1], rtol=0, atol=1e-12 * eta_o[0])
+    Om_j0 = np.ascontiguousarray(Om[:, :j0, :])
+    orc = _oracle_rtsvd(A, B, Om_j0, delta, 1.01, k_max, q, k_start=0, rho=rho)
+    np.testing.assert_allclose(sig, orc["factor"]["s"][:, :faces].T, rtol=1e-12, atol=1e-14 * sig.max())
+    res = f.solve(_t(B), delta, 1.01, 0)
+    torch.cuda.synchronize()
+    assert int(res.k[0]) == orc["k"] and int(res.k[0]) >= j0 - rho
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-11
+    # eps above eta^[1] everywhere: r_eps = 1; eps below every eta: the full r_max columns
+    f1 = rt.factor(_t(A), k_max, rho, q, "fp64", _t(Om), eps=float(np.sqrt(eta_o[0])), adaptive=True)
+    assert f1.info()[0] == 1
+    f2 = rt.factor(_t(A), k_max, rho, q, "fp64", _t(Om), eps=float(np.sqrt(eta_o[-1]) * 0.5), adaptive=True)
+    assert f2.info()[0] == k_max + rho
+
+
 def test_rtsvd_dp_not_met_status():
     A, X, B, Om, delta = blur_problem(40, 8, 2.0, 6, 1, 1e-2, 8, 4, seed=4)
     f, res = _gpu_rtsvd(A, B, Om, 1e-12, 1.01, 8, 4, 0, "fp64", "float64")

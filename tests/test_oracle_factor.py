@@ -105,6 +105,27 @@ def test_fixed_precision_stopping():
     assert eta[-1] < 0.05 ** 2 and eta[-2] >= 0.05 ** 2
 
 
+@pytest.mark.parametrize("power_iters", [0, 1])
+def test_block_factor_is_nested(power_iters):
+    # The fixed-precision factor keeps the first r' sketch columns of an r-column block factor.
+    # QR is nested (column j of Q depends on columns <= j of its argument) and the power step
+    # maps column j to column j, so those columns are the block factor built from the first r'
+    # Gaussian columns; with q = 0 that is Alg. 6 stopped after r' columns.
+    a = _rand((9, 7, 6), 21)
+    om = _rand((7, 6, 6), 22)
+    full = fa.rtsvd_block(a, om, power_iters)
+    for rp in (1, 3, 5):
+        part = fa.rtsvd_block(a, om[:, :rp, :], power_iters)
+        np.testing.assert_allclose(full["Q"][:, :rp, :], part["Q"], atol=1e-11)
+        np.testing.assert_allclose(full["C"][:rp, :, :], part["C"], atol=1e-11)
+        np.testing.assert_allclose(fa.eta_prefix(a, full["C"])[:rp + 1], fa.eta_prefix(a, part["C"]),
+                                   atol=1e-11 * tp.fro(a) ** 2)
+    if power_iters == 0:
+        eps = np.sqrt(fa.eta_prefix(a, full["C"])[3] * 1.0001)   # eta^[3] < eps^2 <= eta^[2]
+        lit = fa.rtsvd_literal(a, om, eps=eps)
+        assert lit["Q"].shape[1] == 3
+
+
 def test_exact_low_tubal_rank_recovery():
     a = _low_tubal_rank(10, 8, 6, 3, 14)
     om = _rand((8, 5, 6), 16)
