@@ -145,3 +145,54 @@ def tgkb_restore(a: np.ndarray, b: np.ndarray, delta, eta: float, k_max: int):
         ks.append(chosen)
         X[:, j:j + 1, :] = ifft_tubes(tgkb_solution(W, c, z, chosen))
     return {"k": ks, "X": X, "res": res, "status": status}
+
+
+# ----------------------------------------------------------------------------------------------
+# Alg. 8 -- nested_tGKB_p: one t-Krylov space recycled over the lateral slices
+# ----------------------------------------------------------------------------------------------
+def projected_lsq(W: np.ndarray, Q: np.ndarray, c: np.ndarray, z: np.ndarray, bh: np.ndarray, k: int):
+    """For one right-hand side b-hat (l x n): per face f, y = argmin ||P-bar_k y - Q_{k+1}^H b-hat_f||
+    (the projected problem of Alg. 8, steps 3 and 9).  Returns (X_k-hat (m x n), projected residual
+    ||P-bar_k Y - Q_{k+1}^T * B||_F in the spatial domain, i.e. (1/n) sum over faces, square-rooted).
+    """
+    m, _, n = W.shape
+    xh = np.zeros((m, n), dtype=complex)
+    tot = 0.0
+    for f in range(n):
+        P = bidiag(c, z, k, f)
+        g = Q[:, :k + 1, f].conj().T @ bh[:, f]
+        y, *_ = np.linalg.lstsq(P, g, rcond=None)
+        xh[:, f] = W[:, :k, f] @ y
+        tot += float(np.sum(np.abs(P @ y - g) ** 2))
+    return xh, np.sqrt(tot / n)
+
+
+def nested_tgkb_restore(a: np.ndarray, b: np.ndarray, delta, eta: float, k_max: int, k_init: int = 2):
+    """nested_tGKB_p (Alg. 8): the bidiagonalization is started from B_1 only; slice j is solved in
+    the present t-Krylov space, and the space grows (k <- k + 1, never restarted) while the
+    projected residual of slice j is >= eta delta_j.  Slice 1 starts at k = k_init; every later
+    slice at the k reached by its predecessor.  Returns ks, X, projected residuals (k_max x p, for
+    every k), status (DP_NOT_MET when k_max was reached without the principle holding).
+    """
+    l, p, n = b.shape
+    deltas = np.broadcast_to(np.asarray(delta, dtype=np.float64), (p,))
+    ah = fft_tubes(a)
+    bh = fft_tubes(b)
+    W, Q, c, z = tgkb_faces(ah, bh[:, 0, :], k_max)
+    res = np.zeros((k_max, p))
+    for j in range(p):
+        for k in range(1, k_max + 1):
+            res[k - 1, j] = projected_lsq(W, Q, c, z, bh[:, j, :], k)[1]
+    X = np.zeros((a.shape[1], p, n))
+    ks, status = [], OK
+    k = max(1, min(k_init, k_max))
+    for j in range(p):
+        while res[k - 1, j] >= eta * deltas[j]:
+            if k == k_max:
+                status = DP_NOT_MET
+                break
+            k += 1
+        ks.append(k)
+        X[:, j, :] = ifft_tubes(projected_lsq(W, Q, c, z, bh[:, j, :], k)[0][:, None, :])[:, 0, :]
+    return {"k": ks, "X": X, "res": res, "status": status}
+
