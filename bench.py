@@ -121,6 +121,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fixed-precision", action="store_true",
                     help="skip the timing of the fixed-precision (eps-adaptive) R-tSVD restoration")
+    ap.add_argument("--no-krylov", action="store_true",
+                    help="skip the tGKB_p / nested_tGKB_p timing on the colour-image workload")
+    ap.add_argument("--krylov-only", action="store_true",
+                    help="only the tGKB_p / nested_tGKB_p timing on the colour-image workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM counters against known bytes)")
     return ap.parse_args()
@@ -210,6 +214,30 @@ def time_steps(torch, rt, prob, w, precision, steps, warmup, timers=False):
     return ev_ms / steps, wall, out
 
 
+def time_krylov(torch, rt, wl, steps):
+    """tGKB_p and nested_tGKB_p (FP64) on the colour-image workload: solves/s, k per slice, error."""
+    w = wl.WORKLOADS["rgb256"]
+    prob = make_problem(w, torch.device("cuda:0"), torch, rt, wl)
+    A, B, x_true = prob["A64"], prob["B64"], prob["X64"]
+    E = B - rt.tprod(A, x_true)
+    deltas = [float(torch.linalg.norm(E[:, j, :])) for j in range(B.shape[1])]
+    out = {"workload": w.name, "l": w.size, "m": w.size, "n": w.n, "p": B.shape[1], "k_max": w.k_max,
+           "noise": w.noise, "eta": w.eta, "precision": "fp64"}
+    for name, fn in (("tgkb_p", lambda: rt.tgkb_solve(A, B, deltas, w.eta, w.k_max)),
+                     ("nested_tgkb_p", lambda: rt.nested_tgkb_solve(A, B, deltas, w.eta, w.k_max))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            X, k, resid, status = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = float(torch.linalg.norm(X - x_true) / torch.linalg.norm(x_true))
+        out[name] = {"value": 1000.0 / ms, "unit": "solves/s", "ms_per_step": ms,
+                     "k": [int(v) for v in k.cpu()], "dp_status": int(status[0]), "rel_error": err}
+    return out
+
+
 def cpu_baseline(w, wl):
     """Time the FP64 oracle on a bounded sample of the same workload and scale to one solve."""
     import threading
@@ -271,6 +299,9 @@ def main():
     from paper_2110_02485_amd import rtsvd as rt
     from paper_2110_02485_amd import workloads as wl
     rt.load()
+    if args.krylov_only:
+        print(json.dumps({"krylov": time_krylov(torch, rt, wl, args.steps)}), flush=True)
+        return
     w = wl.WORKLOADS[args.workload]
     precision = args.precision or w.precision
     dev = torch.device("cuda:0")
@@ -328,6 +359,9 @@ def main():
                                      "eps_rel": eps / float(np.sqrt(eta0[0])), "r_eps": r_eps,
                                      "k": int(resf.k[0]), "rel_error": errf,
                                      "timing": "host wall clock (one device-to-host read of eta per factor)"}
+    if not args.no_krylov:
+        print("[bench] Krylov comparison (tGKB_p, nested_tGKB_p)", file=sys.stderr, flush=True)
+        result["krylov"] = time_krylov(torch, rt, wl, 3)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, wl)

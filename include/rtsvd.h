@@ -158,6 +158,27 @@ int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, in
                int dtype, const double* delta, int32_t n_delta, double eta_dp, int32_t k_max,
                void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
 
+/* nested_tGKB_p regularization (Alg. 8, Section 4.3): one run of Alg. 7 (full
+ * re-orthogonalization), started from the first lateral slice B_1, serves every slice.  Slice j
+ * is solved in the present t-Krylov space by the projected problem
+ * min ||P-bar_k * Y - Q_{k+1}^T * B_j||_F (per face, complex right-hand side, Alg. 5), and the
+ * space grows (never restarted) while that projected residual is >= eta_dp * delta_j.  Slice 1
+ * starts at k = k_init (the algorithm's k_init = 2), every later slice at the k its predecessor
+ * reached, so k_1 <= k_2 <= ... <= k_p.  A slice still unmet at k = k_max takes k_max, and so do
+ * all later slices (status RTSVD_W_DP_NOT_MET).
+ * A: DEVICE l x m x n; B: DEVICE l x p x n; X: DEVICE m x p x n (dtype; computed in dtype,
+ * sums and the projected problems in FP64).  delta: HOST, n_delta = 1 or p.  k_init >= 1 (taken
+ * as min(k_init, k_max)).  k_out: DEVICE int32[p]; resid_out: DEVICE double[k_max * p] or NULL:
+ * resid_out[j*k_max + k-1] is slice j's projected residual at k for every k the basis reached
+ * (0 beyond it).  status_out: DEVICE int32[1] or NULL.  Synchronizes the stream once per two
+ * steps to test whether every slice has been decided.
+ * Errors: RTSVD_E_ARG (sizes, l < m, k_max outside [1, m], eta_dp <= 1, negative delta),
+ * RTSVD_E_UNSUPPORTED (l > 8192).                                                             */
+int nested_tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p,
+                      int dtype, const double* delta, int32_t n_delta, double eta_dp, int32_t k_max,
+                      int32_t k_init, void* X, int32_t* k_out, double* resid_out, int32_t* status_out,
+                      void* stream);
+
 /* Gradients of a loss L(X) through the truncated R-tSVD restoration at a fixed truncation index
  * k (no discrepancy search), fixed Gaussian tensor omega and q = 0 power iterations; the factor is
  * recomputed from A, not stored.  X = V_k * S_k^{-1} * U_k^T * B (Section 4.2).
@@ -190,6 +211,7 @@ int rtsvd_solve_vjp(const void* A, const void* dA, const void* B, const void* om
 #define RTSVD_T_SOLVE 12     /* whole rtsvd_solve                                            */
 #define RTSVD_T_TGKB 13      /* whole tgkb_solve                                             */
 #define RTSVD_T_W_MMA 14     /* the MFMA kernel of W = A-hat V alone (inside RTSVD_T_W)        */
+#define RTSVD_T_NESTED 15    /* whole nested_tgkb_solve                                      */
 int rtsvd_timer_enable(int on);
 int rtsvd_timer_read(int tag, double* total_ms, int32_t* launches);
 

@@ -786,34 +786,111 @@ extern "C" int tprod_adjoint(const void* A, const void* C, void* B, int64_t l, i
 // ---------------------------------------------------------------------------------------------
 // tGKB_p (Alg. 7 + projected least squares + discrepancy principle), the comparison baseline
 // ---------------------------------------------------------------------------------------------
+// One product of a step, A-hat^H X (conj) or A-hat X over every face, as FP64 partial vectors
+// (face f, slice c of partial t at part + t*tStride + f*p*out_len + c*out_len) that
+// k_gkb_orth sums; nparts / tStride describe them.  live: see k_gkb_orth.
 template <typename T>
 static int gkb_product(bool conj, const cplx<T>* Ah, int64_t l, int64_t m, int64_t p, const cplx<T>* X, int64_t ldx,
-                       int64_t sX, cplx<T>* Y, int64_t sY, int64_t F, hipStream_t s) {
-  const int64_t out_len = conj ? m : l, in_len = conj ? l : m;
-  if (p <= 4 && in_len * p * (int64_t)sizeof(cplx<T>) <= 65536) {
-    const size_t lds = (size_t)in_len * p * sizeof(cplx<T>);
-    if (!conj)
-      hipLaunchKernelGGL((k_gemv_n<T, 4>), dim3((unsigned)ceil_div(l, 256), (unsigned)F), dim3(256), lds, s, Ah, (int)l,
-                         (int)m, (int)p, X, ldx, sX, Y, out_len, sY);
-    else
-      hipLaunchKernelGGL((k_gemv_c<T, 4>), dim3((unsigned)ceil_div(m, 4), (unsigned)F), dim3(256), lds, s, Ah, (int)l,
-                         (int)m, (int)p, X, ldx, sX, Y, out_len, sY);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+                       int64_t sX, zd* part, int64_t F, int* nparts, int64_t* tStride, const int* live,
+                       hipStream_t s) {
+  const int64_t out_len = conj ? m : l, sY = p * out_len;
+  *nparts = 1;
+  *tStride = 0;
+  if (p <= 4) {
+    if (conj && l * p * (int64_t)sizeof(cplx<T>) <= 65536) {
+      hipLaunchKernelGGL((k_gv_c<T, 4>), dim3((unsigned)ceil_div(m, 4 * GVC_COLS), (unsigned)F), dim3(256),
+                         (size_t)l * p * sizeof(cplx<T>), s, Ah, (int)l, (int)m, (int)p, X, ldx, sX, part, sY, live);
+      return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
+    if (!conj) {
+      const int64_t nch0 = std::min<int64_t>(GVN_MAXCHUNK, ceil_div(m, 32));
+      const int64_t kw = ceil_div(ceil_div(m, 4 * nch0), GVN_UNROLL) * GVN_UNROLL;
+      const int64_t nch = ceil_div(m, 4 * kw);
+      const size_t lds = 3 * 64 * 4 * sizeof(zd) + (size_t)(p * 4 * kw) * sizeof(cplx<T>);
+      if (lds <= 65536) {
+        hipLaunchKernelGGL((k_gv_n<T, 4>), dim3((unsigned)ceil_div(l, 64), (unsigned)nch, (unsigned)F), dim3(256), lds,
+                           s, Ah, (int)l, (int)m, (int)p, X, ldx, sX, (int)kw, part, F * sY, sY, live);
+        *nparts = (int)nch;
+        *tStride = F * sY;
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+      }
+    }
   }
   if (!conj)
-    return cgemm<cplx<T>, cplx<T>, cplx<T>, double>(false, false, (int)l, (int)p, (int)m, Ah, l, l * m, X, ldx, sX, Y,
-                                                    out_len, sY, (int)F, 1.0, false, s);
-  return cgemm<cplx<T>, cplx<T>, cplx<T>, double>(true, false, (int)m, (int)p, (int)l, Ah, l, l * m, X, ldx, sX, Y,
-                                                  out_len, sY, (int)F, 1.0, false, s);
+    return cgemm<cplx<T>, cplx<T>, zd, double>(false, false, (int)l, (int)p, (int)m, Ah, l, l * m, X, ldx, sX, part,
+                                               out_len, sY, (int)F, 1.0, false, s);
+  return cgemm<cplx<T>, cplx<T>, zd, double>(true, false, (int)m, (int)p, (int)l, Ah, l, l * m, X, ldx, sX, part,
+                                             out_len, sY, (int)F, 1.0, false, s);
 }
 
-static int* pinned_counter() {
-  static int* h = nullptr;
-  static std::mutex mu;
-  std::lock_guard<std::mutex> lk(mu);
-  if (!h && hipHostMalloc((void**)&h, sizeof(int) * 64, hipHostMallocDefault) != hipSuccess) h = nullptr;
-  return h;
+// FP64 elements of the partial-vector buffer gkb_product may fill
+static int64_t gkb_part_elems(int64_t l, int64_t m, int64_t p, int64_t F) {
+  return (p <= 4 ? GVN_MAXCHUNK : 1) * F * p * std::max(l, m);
 }
+
+// Progress words of the Krylov step loops: a ring of 64 words in coherent pinned host memory (one
+// cache line each), a call tagged with a 16-bit id so that a word left by an earlier call is
+// never read as this call's progress.
+struct Progress {
+  uint64_t* host = nullptr;
+  uint64_t* dev = nullptr;
+  uint32_t id = 0;
+};
+constexpr int PROG_RING = 64, PROG_STRIDE = 8;
+
+static bool progress_open(Progress& pr) {
+  static std::mutex mu;
+  static uint64_t* ring = nullptr;
+  static uint64_t* ring_dev = nullptr;
+  static uint32_t next_id = 1;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ring) {
+    uint64_t* h = nullptr;
+    if (hipHostMalloc((void**)&h, sizeof(uint64_t) * PROG_RING * PROG_STRIDE,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+      return false;
+    uint64_t* d = nullptr;
+    if (hipHostGetDevicePointer((void**)&d, h, 0) != hipSuccess) return false;
+    ring = h;
+    ring_dev = d;
+  }
+  uint32_t id = next_id++ & 0xffffu;
+  if (id == 0) id = next_id++ & 0xffffu;   // a cleared word never carries a valid id
+  const int slot = (int)(id % PROG_RING);
+  pr.host = ring + slot * PROG_STRIDE;
+  pr.dev = ring_dev + slot * PROG_STRIDE;
+  pr.id = id;
+  __atomic_store_n(pr.host, (uint64_t)0, __ATOMIC_RELEASE);
+  return true;
+}
+
+// Throttle of the step loop after enqueueing step i: waits until the device has finished step
+// i - ahead.  Returns 1 once every slice is decided, 0 to go on, -1 on a HIP error.  When the
+// stream has drained without a matching word, the device counter is read directly.
+static int await_progress(const Progress& pr, int i, int ahead, const int* remaining_dev, hipStream_t s) {
+  for (long spin = 1;; ++spin) {
+    const uint64_t w = __atomic_load_n(pr.host, __ATOMIC_ACQUIRE);
+    if ((uint32_t)(w >> 48) == pr.id) {
+      const int done = (int)((w >> 32) & 0xffff), rem = (int)(uint32_t)w;
+      if (done >= 1 && rem <= 0) return 1;
+      if (done >= i - ahead) return 0;
+    } else if (i - ahead <= 0) {
+      return 0;
+    }
+    if ((spin & 1023) == 0) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return -1;
+      int rem = 0;
+      if (hipMemcpy(&rem, remaining_dev, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+      return rem <= 0 ? 1 : 0;
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// steps in flight beyond the last one known to be finished
+constexpr int KRYLOV_AHEAD = 2;
 
 template <typename T>
 static int tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, int64_t p,
@@ -831,7 +908,9 @@ static int tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, in
   const int64_t ldq = l * (kmax + 1), ldw = m * kmax;
   RT_ALLOC(Qb, zt, F * p * ldq, sc);
   RT_ALLOC(Wb, zt, F * p * ldw, sc);
-  RT_ALLOC(raw, zt, F * p * std::max(l, m), sc);
+  RT_ALLOC(raw, zd, gkb_part_elems(l, m, p, F), sc);
+  int nparts = 1;
+  int64_t tstr = 0;
   const int64_t cnt = F * p;
   RT_ALLOC(zc, double, cnt, sc);
   RT_ALLOC(cc, double, cnt, sc);
@@ -849,39 +928,40 @@ static int tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, in
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, remaining, (int)p);
   RT_LAUNCH_OK();
   if (resid_out) RT_CHECK_HIP(hipMemsetAsync(resid_out, 0, sizeof(double) * p * kmax, s));
-  hipLaunchKernelGGL((k_gkb_init<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, Bh, (int)l, (int)p, Qb, ldq, zc,
-                     phibar, cprev, 0.0);
+  hipLaunchKernelGGL((k_gkb_init<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, Bh, l * p, (int)l, (int)p, Qb,
+                     ldq, zc, phibar, cprev, 0.0);
   RT_LAUNCH_OK();
-  int* host_rem = pinned_counter();
-  if (!host_rem) return fail(RTSVD_E_NOMEM, "tgkb_solve: pinned host memory");
-  const int check_every = 2;
+  Progress prog;
+  if (!progress_open(prog)) return fail(RTSVD_E_NOMEM, "tgkb_solve: pinned host memory");
   for (int i = 1; i <= kmax; ++i) {
     // w = A-hat^H q_i - z_i w_{i-1}, re-orthogonalized, c_i = ||w||
-    RT_TRY(gkb_product<T>(true, Ah, l, m, p, Qb + (int64_t)(i - 1) * l, ldq, p * ldq, raw, p * m, F, s));
+    RT_TRY(gkb_product<T>(true, Ah, l, m, p, Qb + (int64_t)(i - 1) * l, ldq, p * ldq, raw, F, &nparts, &tstr, remaining,
+                          s));
     {
       const size_t lds = 32 * sizeof(double) + (size_t)(kmax + 1) * sizeof(zd) + (size_t)m * sizeof(zd);
-      hipLaunchKernelGGL((k_gkb_orth<T>), dim3((unsigned)p, (unsigned)F), dim3(GKB_THREADS), lds, s, raw, p * m, Wb, ldw,
-                         (int)m, i - 1, (const zt*)(i >= 2 ? Wb : nullptr), ldw, i - 2, (const double*)zc, cc, (int)p, tol);
+      hipLaunchKernelGGL((k_gkb_orth<T, 0>), dim3((unsigned)p, (unsigned)F), dim3(GKB_THREADS), lds, s, (const zd*)raw,
+                         nparts, tstr, p * m, Wb, ldw, (int)m, i - 1, (const zt*)(i >= 2 ? Wb : nullptr), ldw, i - 2,
+                         (const double*)zc, cc, (int)p, tol, GkbRot{}, (const int*)remaining);
       RT_LAUNCH_OK();
     }
-    // q = A-hat w_i - c_i q_i, re-orthogonalized, z_{i+1} = ||q||
-    RT_TRY(gkb_product<T>(false, Ah, l, m, p, Wb + (int64_t)(i - 1) * m, ldw, p * ldw, raw, p * l, F, s));
+    // q = A-hat w_i - c_i q_i, re-orthogonalized, z_{i+1} = ||q||; Givens rotation i
+    RT_TRY(gkb_product<T>(false, Ah, l, m, p, Wb + (int64_t)(i - 1) * m, ldw, p * ldw, raw, F, &nparts, &tstr, remaining,
+                          s));
     {
       const size_t lds = 32 * sizeof(double) + (size_t)(kmax + 1) * sizeof(zd) + (size_t)l * sizeof(zd);
-      hipLaunchKernelGGL((k_gkb_orth<T>), dim3((unsigned)p, (unsigned)F), dim3(GKB_THREADS), lds, s, raw, p * l, Qb, ldq,
-                         (int)l, i, (const zt*)Qb, ldq, i - 1, (const double*)cc, zc, (int)p, tol);
+      const GkbRot rot{cc, cprev, rho_h, s_h, alpha_h, phibar, phi_h, nullptr, nullptr, nullptr, 0, kmax, i};
+      hipLaunchKernelGGL((k_gkb_orth<T, 1>), dim3((unsigned)p, (unsigned)F), dim3(GKB_THREADS), lds, s, (const zd*)raw,
+                         nparts, tstr, p * l, Qb, ldq, (int)l, i, (const zt*)Qb, ldq, i - 1, (const double*)cc, zc,
+                         (int)p, tol, rot, (const int*)remaining);
       RT_LAUNCH_OK();
     }
-    hipLaunchKernelGGL(k_gkb_givens, dim3(nblocks(cnt)), dim3(256), 0, s, cc, zc, cprev, phibar, rho_h, s_h, phi_h,
-                       alpha_h, kmax, i, (int)cnt);
+    hipLaunchKernelGGL(k_gkb_dp, dim3(1), dim3(1024), 0, s, phibar, (int)F, (int)p, (int)n, bnd, i, kmax, kin,
+                       resid_out, remaining, prog.dev, prog.id);
     RT_LAUNCH_OK();
-    hipLaunchKernelGGL(k_gkb_dp, dim3(nblocks(p, 64)), dim3(64), 0, s, phibar, (int)F, (int)p, (int)n, bnd, i, kmax, kin,
-                       resid_out, remaining);
-    RT_LAUNCH_OK();
-    if (i % check_every == 0 || i == kmax) {
-      RT_CHECK_HIP(hipMemcpyAsync(host_rem, remaining, sizeof(int), hipMemcpyDeviceToHost, s));
-      RT_CHECK_HIP(hipStreamSynchronize(s));
-      if (*host_rem <= 0) break;
+    if (i < kmax) {
+      const int r = await_progress(prog, i, KRYLOV_AHEAD, remaining, s);
+      if (r < 0) return fail(RTSVD_E_HIP, "tgkb_solve: stream error while waiting for progress");
+      if (r > 0) break;
     }
   }
   // solution at each slice's k (k_max where the principle was not met)
@@ -920,6 +1000,125 @@ extern "C" int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, in
                             status_out, s);
   return fail(RTSVD_E_ARG, "tgkb_solve: bad dtype");
 }
+
+// ---------------------------------------------------------------------------------------------
+// nested_tGKB_p (Alg. 8): the basis of Alg. 7 started from B_1 serves every lateral slice
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+static int nested_tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, int64_t p,
+                            const std::vector<double>& bounds, int kmax, int kinit, T* X, int* k_out, double* resid_out,
+                            int* status_out, hipStream_t s) {
+  typedef cplx<T> zt;
+  const int64_t F = n / 2 + 1;
+  const double tol = 64.0 * (sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.960464477539063e-08);
+  Scratch sc(s);
+  RT_TIMED(RTSVD_T_NESTED);
+  RT_ALLOC(Ah, zt, F * l * m, sc);
+  RT_ALLOC(Bh, zt, F * l * p, sc);
+  RT_TRY((launch_rfft<T, T>(A, l * m, (int)n, Ah, l * m, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  RT_TRY((launch_rfft<T, T>(B, l * p, (int)n, Bh, l * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  const int64_t ldq = l * (kmax + 1), ldw = m * kmax;
+  RT_ALLOC(Qb, zt, F * ldq, sc);
+  RT_ALLOC(Wb, zt, F * ldw, sc);
+  RT_ALLOC(raw, zd, gkb_part_elems(l, m, 1, F), sc);
+  int nparts = 1;
+  int64_t tstr = 0;
+  RT_ALLOC(zc, double, F, sc);
+  RT_ALLOC(cc, double, F, sc);
+  RT_ALLOC(cprev, double, F, sc);
+  RT_ALLOC(phib0, double, F, sc);          // the basis' own right-hand side (unused by the slices)
+  RT_ALLOC(rho_h, double, F * kmax, sc);
+  RT_ALLOC(s_h, double, F * kmax, sc);
+  RT_ALLOC(alpha_h, double, F * kmax, sc);
+  RT_ALLOC(phibar, zd, F * p, sc);
+  RT_ALLOC(phi_h, zd, F * p * kmax, sc);
+  RT_ALLOC(res, double, p * kmax, sc);
+  RT_ALLOC(bnd, double, p, sc);
+  RT_ALLOC(kin, int, p, sc);
+  RT_ALLOC(st, int, 4, sc);
+  RT_ALLOC(remaining, int, 1, sc);
+  RT_TRY(upload_doubles(bnd, bounds.data(), p, s));
+  RT_CHECK_HIP(hipMemsetAsync(res, 0, sizeof(double) * p * kmax, s));
+  hipLaunchKernelGGL(k_nest_reset, dim3(1), dim3(64), 0, s, st, kinit, remaining, (int)p);
+  RT_LAUNCH_OK();
+  // q_1 = b-hat_1 / ||b-hat_1|| per face, then phi-bar_1 = q_1^H b-hat_j for every slice
+  hipLaunchKernelGGL((k_gkb_init<T>), dim3(1, (unsigned)F), dim3(256), 0, s, Bh, l * p, (int)l, 1, Qb, ldq, zc, phib0,
+                     cprev, 0.0);
+  RT_LAUNCH_OK();
+  hipLaunchKernelGGL((k_nest_init<T>), dim3((unsigned)ceil_div(p, NEST_WAVES), (unsigned)F), dim3(64 * NEST_WAVES), 0,
+                     s, Qb, ldq, Bh, (int)l, (int)p, phibar);
+  RT_LAUNCH_OK();
+  Progress prog;
+  if (!progress_open(prog)) return fail(RTSVD_E_NOMEM, "nested_tgkb_solve: pinned host memory");
+  for (int i = 1; i <= kmax; ++i) {
+    RT_TRY(gkb_product<T>(true, Ah, l, m, 1, Qb + (int64_t)(i - 1) * l, ldq, ldq, raw, F, &nparts, &tstr, remaining, s));
+    {
+      const size_t lds = 32 * sizeof(double) + (size_t)(kmax + 1) * sizeof(zd) + (size_t)m * sizeof(zd);
+      hipLaunchKernelGGL((k_gkb_orth<T, 0>), dim3(1, (unsigned)F), dim3(GKB_THREADS), lds, s, (const zd*)raw, nparts,
+                         tstr, m, Wb, ldw, (int)m, i - 1, (const zt*)(i >= 2 ? Wb : nullptr), ldw, i - 2,
+                         (const double*)zc, cc, 1, tol, GkbRot{}, (const int*)remaining);
+      RT_LAUNCH_OK();
+    }
+    RT_TRY(gkb_product<T>(false, Ah, l, m, 1, Wb + (int64_t)(i - 1) * m, ldw, ldw, raw, F, &nparts, &tstr, remaining, s));
+    {
+      const size_t lds = 32 * sizeof(double) + (size_t)(kmax + 1) * sizeof(zd) + (size_t)l * sizeof(zd);
+      // rotation i of every face and every slice's right-hand side update, in the same kernel
+      const GkbRot rot{cc, cprev, rho_h, s_h, alpha_h, nullptr, nullptr, Bh, phibar, phi_h, (int)p, kmax, i};
+      hipLaunchKernelGGL((k_gkb_orth<T, 2>), dim3(1, (unsigned)F), dim3(GKB_THREADS), lds, s, (const zd*)raw, nparts,
+                         tstr, l, Qb, ldq, (int)l, i, (const zt*)Qb, ldq, i - 1, (const double*)cc, zc, 1, tol, rot,
+                         (const int*)remaining);
+      RT_LAUNCH_OK();
+    }
+    hipLaunchKernelGGL(k_nest_dp, dim3(1), dim3(256), 0, s, (const zd*)phibar, (int)F, (int)p, (int)n, bnd, i, kmax,
+                       res, kin, st, remaining, prog.dev, prog.id);
+    RT_LAUNCH_OK();
+    if (i < kmax) {
+      const int r = await_progress(prog, i, KRYLOV_AHEAD, remaining, s);
+      if (r < 0) return fail(RTSVD_E_HIP, "nested_tgkb_solve: stream error while waiting for progress");
+      if (r > 0) break;
+    }
+  }
+  RT_ALLOC(Xh, zt, F * m * p, sc);
+  hipLaunchKernelGGL((k_nest_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), (size_t)kmax * sizeof(zd), s, Wb,
+                     ldw, (int)m, kin, kmax, (int)p, rho_h, s_h, alpha_h, (const zd*)phi_h, Xh);
+  RT_LAUNCH_OK();
+  RT_TRY((launch_irfft<T, T>(Xh, m * p, m * p, (int)n, X, s)));
+  hipLaunchKernelGGL(k_nest_finish, dim3(1), dim3(256), 0, s, kin, st, (int)p, k_out, status_out);
+  RT_LAUNCH_OK();
+  if (resid_out)
+    RT_CHECK_HIP(hipMemcpyAsync(resid_out, res, sizeof(double) * p * kmax, hipMemcpyDeviceToDevice, s));
+  return 0;
+}
+
+extern "C" int nested_tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p, int dtype,
+                                 const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, int32_t k_init,
+                                 void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !X || !delta || !k_out) return fail(RTSVD_E_ARG, "nested_tgkb_solve: null argument");
+  if (l < 1 || m < 1 || n < 1 || p < 1 || l < m)
+    return fail(RTSVD_E_ARG, "nested_tgkb_solve: need l >= m >= 1, n >= 1, p >= 1");
+  if (k_max < 1 || k_max > m) return fail(RTSVD_E_ARG, "nested_tgkb_solve: need 1 <= k_max <= m");
+  if (k_init < 1) return fail(RTSVD_E_ARG, "nested_tgkb_solve: need k_init >= 1");
+  if (n_delta != 1 && n_delta != p) return fail(RTSVD_E_ARG, "nested_tgkb_solve: n_delta must be 1 or p");
+  if (!(eta_dp > 1.0)) return fail(RTSVD_E_ARG, "nested_tgkb_solve: eta_dp must be > 1");
+  if (l > 8192) return fail(RTSVD_E_UNSUPPORTED, "nested_tgkb_solve: l must be <= 8192");
+  std::vector<double> bounds(p);
+  for (int64_t c = 0; c < p; ++c) {
+    const double d = delta[n_delta == 1 ? 0 : c];
+    if (!(d >= 0.0)) return fail(RTSVD_E_ARG, "nested_tgkb_solve: delta must be >= 0");
+    bounds[c] = eta_dp * d;
+  }
+  const int kin = std::min<int>(k_init, k_max);
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RTSVD_F64)
+    return nested_tgkb_impl<double>((const double*)A, (const double*)B, l, m, n, p, bounds, k_max, kin, (double*)X,
+                                    k_out, resid_out, status_out, s);
+  if (dtype == RTSVD_F32)
+    return nested_tgkb_impl<float>((const float*)A, (const float*)B, l, m, n, p, bounds, k_max, kin, (float*)X, k_out,
+                                   resid_out, status_out, s);
+  return fail(RTSVD_E_ARG, "nested_tgkb_solve: bad dtype");
+}
+
 
 
 // ---------------------------------------------------------------------------------------------

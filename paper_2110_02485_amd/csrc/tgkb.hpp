@@ -22,82 +22,129 @@ namespace rt {
 
 constexpr int GKB_THREADS = 1024;
 
-// y(:, c) = A-hat x(:, c) for c < p (p <= 4), batched over faces; one thread per row.
-// X column c of face f at X + f*sX + c*ldx.
+// The two products of every step stream all of A-hat once each (HBM-bound: about 16 l m F bytes
+// in FP64), so they are written for memory-level parallelism: many blocks per face, several
+// independent loads in flight per lane, the right-hand vectors staged in LDS.  Results are FP64
+// partial vectors that the re-orthogonalization kernel sums in a fixed order.
+constexpr int GVN_UNROLL = 8;     // columns loaded back to back per lane
+constexpr int GVN_MAXCHUNK = 16;  // column chunks (partial vectors) per face at most
+constexpr int GVC_COLS = 4;       // columns per wave in the conjugate product
+
+// part[ch] (face f, slice c, row i at ch*tStride + f*sY + c*l + i) = sum over the chunk's columns
+// of A-hat(i, col) x(col, c), p <= PMAX.  Grid (ceil(l/64), chunks, F); block 256 = 4 waves, each
+// wave kw columns (multiple of GVN_UNROLL), lane = row; the 4 waves are summed in LDS.
 template <typename T, int PMAX>
 __global__ void __launch_bounds__(256)
-k_gemv_n(const cplx<T>* __restrict__ A, int l, int m, int p, const cplx<T>* __restrict__ X, int64_t ldx, int64_t sX,
-         cplx<T>* __restrict__ Y, int64_t ldy, int64_t sY) {
+k_gv_n(const cplx<T>* __restrict__ A, int l, int m, int p, const cplx<T>* __restrict__ X, int64_t ldx, int64_t sX,
+       int kw, zd* __restrict__ part, int64_t tStride, int64_t sY, const int* __restrict__ live) {
+  if (live && *live <= 0) return;   // every slice decided: a step enqueued ahead does nothing
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);  // m x p
-  const int f = blockIdx.y;
-  const cplx<T>* Af = A + (int64_t)f * l * m;
-  for (int idx = threadIdx.x; idx < m * p; idx += blockDim.x) {
-    const int k = idx % m, c = idx / m;
-    xs[c * m + k] = X[(int64_t)f * sX + (int64_t)c * ldx + k];
+  const int KC = 4 * kw;
+  zd* red = reinterpret_cast<zd*>(smem_raw);                                   // 3 x 64 x PMAX
+  cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw + 3 * 64 * PMAX * sizeof(zd));  // p x KC
+  const int f = blockIdx.z, ch = blockIdx.y;
+  const int c0 = ch * KC;
+  for (int idx = threadIdx.x; idx < p * KC; idx += blockDim.x) {
+    const int c = idx / KC, u = idx - c * KC, col = c0 + u;
+    xs[idx] = col < m ? X[(int64_t)f * sX + (int64_t)c * ldx + col] : cplx<T>{(T)0, (T)0};
   }
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= l) return;
-  cplx<double> acc[PMAX];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = blockIdx.x * 64 + lane;
+  const int rr = row < l ? row : l - 1;            // clamped row: loads stay inside the face
+  const cplx<T>* a = A + (int64_t)f * l * m + rr;
+  const int cb = w * kw;
+  zd acc[PMAX];
 #pragma unroll
   for (int c = 0; c < PMAX; ++c) acc[c] = mk(0.0, 0.0);
-  for (int k = 0; k < m; ++k) {
-    const cplx<T> a = Af[i + (int64_t)k * l];
+  for (int t = 0; t < kw; t += GVN_UNROLL) {
+    zd av[GVN_UNROLL];
+#pragma unroll
+    for (int u = 0; u < GVN_UNROLL; ++u) {
+      const int col = c0 + cb + t + u;
+      av[u] = col < m ? ld<double>(a[(int64_t)col * l]) : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < GVN_UNROLL; ++u)
+#pragma unroll
+      for (int c = 0; c < PMAX; ++c)
+        if (c < p) {
+          const zd x = ld<double>(xs[c * KC + cb + t + u]);
+          acc[c].re = fma(av[u].re, x.re, fma(-av[u].im, x.im, acc[c].re));
+          acc[c].im = fma(av[u].re, x.im, fma(av[u].im, x.re, acc[c].im));
+        }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int c = 0; c < PMAX; ++c) red[((w - 1) * 64 + lane) * PMAX + c] = acc[c];
+  }
+  __syncthreads();
+  if (w != 0 || row >= l) return;
+#pragma unroll
+  for (int c = 0; c < PMAX; ++c)
+    if (c < p) {
+      zd v = acc[c];
+      for (int q = 0; q < 3; ++q) v = cadd(v, red[(q * 64 + lane) * PMAX + c]);
+      part[(int64_t)ch * tStride + (int64_t)f * sY + (int64_t)c * l + row] = v;
+    }
+}
+
+// part (face f, slice c, entry j at f*sY + c*m + j) = sum_i conj(A-hat(i, j)) x(i, c), p <= PMAX.
+// Grid (ceil(m / (4*GVC_COLS)), F); block 256 = 4 waves, each wave GVC_COLS columns, lanes over
+// the rows; x staged in LDS (l x p).
+template <typename T, int PMAX>
+__global__ void __launch_bounds__(256)
+k_gv_c(const cplx<T>* __restrict__ A, int l, int m, int p, const cplx<T>* __restrict__ X, int64_t ldx, int64_t sX,
+       zd* __restrict__ part, int64_t sY, const int* __restrict__ live) {
+  if (live && *live <= 0) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);  // p x l
+  const int f = blockIdx.y;
+  for (int idx = threadIdx.x; idx < l * p; idx += blockDim.x) {
+    const int c = idx / l, i = idx - c * l;
+    xs[idx] = X[(int64_t)f * sX + (int64_t)c * ldx + i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j0 = (blockIdx.x * 4 + w) * GVC_COLS;
+  if (j0 >= m) return;
+  const cplx<T>* Af = A + (int64_t)f * l * m;
+  zd acc[GVC_COLS][PMAX];
+#pragma unroll
+  for (int u = 0; u < GVC_COLS; ++u)
+#pragma unroll
+    for (int c = 0; c < PMAX; ++c) acc[u][c] = mk(0.0, 0.0);
+  for (int i = lane; i < l; i += 64) {
+    zd av[GVC_COLS];
+#pragma unroll
+    for (int u = 0; u < GVC_COLS; ++u) {
+      const int col = j0 + u < m ? j0 + u : m - 1;  // clamped column (its sum is not stored)
+      av[u] = ld<double>(Af[(int64_t)col * l + i]);
+    }
 #pragma unroll
     for (int c = 0; c < PMAX; ++c)
       if (c < p) {
-        const cplx<T> x = xs[c * m + k];
-        acc[c].re += (double)a.re * x.re - (double)a.im * x.im;
-        acc[c].im += (double)a.re * x.im + (double)a.im * x.re;
+        const zd x = ld<double>(xs[c * l + i]);
+#pragma unroll
+        for (int u = 0; u < GVC_COLS; ++u) {
+          acc[u][c].re = fma(av[u].re, x.re, fma(av[u].im, x.im, acc[u][c].re));
+          acc[u][c].im = fma(av[u].re, x.im, fma(-av[u].im, x.re, acc[u][c].im));
+        }
       }
   }
 #pragma unroll
   for (int c = 0; c < PMAX; ++c)
-    if (c < p) Y[(int64_t)f * sY + (int64_t)c * ldy + i] = mk((T)acc[c].re, (T)acc[c].im);
-}
-
-// y(:, c) = A-hat^H x(:, c), one wave per output row j (a column of A-hat), p <= 4
-template <typename T, int PMAX>
-__global__ void __launch_bounds__(256)
-k_gemv_c(const cplx<T>* __restrict__ A, int l, int m, int p, const cplx<T>* __restrict__ X, int64_t ldx, int64_t sX,
-         cplx<T>* __restrict__ Y, int64_t ldy, int64_t sY) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);  // l x p
-  const int f = blockIdx.y;
-  const cplx<T>* Af = A + (int64_t)f * l * m;
-  for (int idx = threadIdx.x; idx < l * p; idx += blockDim.x) {
-    const int k = idx % l, c = idx / l;
-    xs[c * l + k] = X[(int64_t)f * sX + (int64_t)c * ldx + k];
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (j >= m) return;
-  const cplx<T>* col = Af + (int64_t)j * l;
-  cplx<double> acc[PMAX];
+    if (c < p) {
 #pragma unroll
-  for (int c = 0; c < PMAX; ++c) acc[c] = mk(0.0, 0.0);
-  for (int i = lane; i < l; i += 64) {
-    const cplx<T> a = col[i];
-#pragma unroll
-    for (int c = 0; c < PMAX; ++c)
-      if (c < p) {
-        const cplx<T> x = xs[c * l + i];
-        acc[c].re += (double)a.re * x.re + (double)a.im * x.im;
-        acc[c].im += (double)a.re * x.im - (double)a.im * x.re;
+      for (int u = 0; u < GVC_COLS; ++u) {
+        const zd v = wave_sum(acc[u][c]);
+        if (lane == 0 && j0 + u < m) part[(int64_t)f * sY + (int64_t)c * m + j0 + u] = v;
       }
-  }
-#pragma unroll
-  for (int c = 0; c < PMAX; ++c) {
-    double re = acc[c].re, im = acc[c].im;
-    for (int o = 32; o > 0; o >>= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
-    if (lane == 0 && c < p) Y[(int64_t)f * sY + (int64_t)c * ldy + j] = mk((T)re, (T)im);
-  }
+    }
 }
 
 __device__ __forceinline__ double gkb_block_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
   if (lane == 0) red[w] = v;
@@ -107,19 +154,48 @@ __device__ __forceinline__ double gkb_block_sum(double v, double* red) {
   return s;
 }
 
+// Bookkeeping of step i folded into its q half-step, once z_{i+1} is known.  Givens rotation i of
+// the basis (alpha = c_i, beta = z_{i+1}; cprev = cosine of rotation i-1, -1 before the first):
+//     rho-bar = -cprev alpha, rho = sqrt(rho-bar^2 + beta^2), c = rho-bar / rho, s = beta / rho,
+// recorded for the back substitution (rho, s, alpha) and applied to the right-hand side(s):
+// MODE 1 (tGKB_p): the basis' own e_1 z_1, phi_i = c phi-bar, phi-bar <- s phi-bar (real);
+// MODE 2 (nested): every slice j of B-hat, g = q_{i+1}^H b-hat_j, phi_i = c phi-bar + s g,
+// phi-bar <- s phi-bar - c g (complex).
+struct GkbRot {
+  const double* alpha;
+  double* cprev;
+  double* rho_h;
+  double* s_h;
+  double* alpha_h;
+  double* phibar;     // MODE 1, per basis
+  double* phi_h;      // MODE 1, per basis x kmax
+  const void* bh;     // MODE 2: face f, slice j at bh + (f*p_rhs + j)*len (storage type of the basis)
+  zd* nphibar;        // MODE 2, per (f, j)
+  zd* nphi_h;         // MODE 2, per (f, j) x kmax
+  int p_rhs, kmax, i;
+};
+
 // One half-step of Alg. 7 for every (face, slice): v = raw - prevcoef * prev, CGS2 against the
 // first nb basis vectors, normalize, store as basis vector nb.  Basis of (f, c): Bas + ((f*p + c)
 // * ld_basis) with vectors of length len and stride len.  coef_prev / coef_out: (f, c) arrays of
-// real scalars (z_i / c_i).  raw: result of the big product (face f, slice c at raw + f*sRaw + c*len).
-template <typename T>
+// real scalars (z_i / c_i).  raw = the product, as nparts FP64 partial vectors summed in order
+// (partial t of face f, slice c at part + t*tStride + f*sRaw + c*len).  MODE 0: the w half-step;
+// MODE 1 / 2: the q half-step with the rotation bookkeeping above.  live (or NULL): number of
+// slices still undecided; at 0 the kernel returns at once (a step enqueued ahead of the host's
+// knowledge that the process has ended).
+template <typename T, int MODE>
 __global__ void __launch_bounds__(GKB_THREADS)
-k_gkb_orth(const cplx<T>* __restrict__ raw, int64_t sRaw, cplx<T>* __restrict__ Bas, int64_t ld_basis, int len,
-           int nb, const cplx<T>* __restrict__ prev, int64_t ld_prev, int prev_idx, const double* __restrict__ coef_prev,
-           double* __restrict__ coef_out, int p, double tol) {
+k_gkb_orth(const zd* __restrict__ part, int nparts, int64_t tStride, int64_t sRaw, cplx<T>* __restrict__ Bas,
+           int64_t ld_basis, int len, int nb, const cplx<T>* __restrict__ prev, int64_t ld_prev, int prev_idx,
+           const double* __restrict__ coef_prev, double* __restrict__ coef_out, int p, double tol, GkbRot rot,
+           const int* __restrict__ live) {
+  if (live && *live <= 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double rcs[2];
   const int f = blockIdx.y, c = blockIdx.x;
   double* red = reinterpret_cast<double*>(smem_raw);              // 32 doubles
   zd* h = reinterpret_cast<zd*>(smem_raw + 32 * sizeof(double));  // nb coefficients
+  zd* vs = h + nb;                                                 // len entries
   cplx<T>* bas = Bas + ((int64_t)f * p + c) * ld_basis;
   const int per = (len + blockDim.x - 1) / blockDim.x;             // rows per thread (<= 8)
   zd v[8];
@@ -130,7 +206,9 @@ k_gkb_orth(const cplx<T>* __restrict__ raw, int64_t sRaw, cplx<T>* __restrict__ 
     const int i = threadIdx.x + t * blockDim.x;
     zd x = mk(0.0, 0.0);
     if (t < per && i < len) {
-      x = ld<double>(raw[(int64_t)f * sRaw + (int64_t)c * len + i]);
+      const zd* src = part + (int64_t)f * sRaw + (int64_t)c * len + i;
+      x = src[0];
+      for (int q = 1; q < nparts; ++q) x = cadd(x, src[(int64_t)q * tStride]);
       if (pv) x = csub(x, cscale(ld<double>(pv[i]), cp));
     }
     v[t] = x;
@@ -142,8 +220,7 @@ k_gkb_orth(const cplx<T>* __restrict__ raw, int64_t sRaw, cplx<T>* __restrict__ 
   n0 = sqrt(gkb_block_sum(n0, red));
   for (int pass = 0; pass < 2; ++pass) {
     if (nb == 0) break;
-    // h_j = b_j^H v for all j < nb: stage v in LDS (after the coefficients), one wave per j
-    zd* vs = h + nb;
+    // h_j = b_j^H v for all j < nb: stage v in LDS, one wave per j
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int i = threadIdx.x + t * blockDim.x;
@@ -156,10 +233,11 @@ k_gkb_orth(const cplx<T>* __restrict__ raw, int64_t sRaw, cplx<T>* __restrict__ 
       for (int i = lane; i < len; i += 64) {
         const zd b = ld<double>(bj[i]);
         const zd x = vs[i];
-        re += b.re * x.re + b.im * x.im;
-        im += b.re * x.im - b.im * x.re;
+        re = fma(b.re, x.re, fma(b.im, x.im, re));
+        im = fma(b.re, x.im, fma(-b.im, x.re, im));
       }
-      for (int o = 32; o > 0; o >>= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
+      re = wave_sum(re);
+      im = wave_sum(im);
       if (lane == 0) h[j] = mk(re, im);
     }
     __syncthreads();
@@ -183,49 +261,99 @@ k_gkb_orth(const cplx<T>* __restrict__ raw, int64_t sRaw, cplx<T>* __restrict__ 
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
     const int i = threadIdx.x + t * blockDim.x;
-    if (t < per && i < len) st(out[i], cscale(v[t], inv));
+    if (t < per && i < len) {
+      const zd q = cscale(v[t], inv);
+      st(out[i], q);
+      if (MODE == 2) vs[i] = ld<double>(ld<T>(q));   // the stored (rounded) q_{i+1}
+    }
   }
-  if (threadIdx.x == 0) coef_out[(int64_t)f * p + c] = ok ? nn : 0.0;
+  const int64_t bi = (int64_t)f * p + c;
+  if (threadIdx.x == 0) coef_out[bi] = ok ? nn : 0.0;
+  if (MODE == 0) return;
+  if (threadIdx.x == 0) {
+    const double a = rot.alpha[bi], b = ok ? nn : 0.0;
+    const double rbar = -rot.cprev[bi] * a;
+    const double rho = sqrt(rbar * rbar + b * b);
+    double cs, sn;
+    if (rho > 0.0) { cs = rbar / rho; sn = b / rho; } else { cs = 0.0; sn = 1.0; }
+    const int64_t hi = bi * rot.kmax + rot.i - 1;
+    rot.rho_h[hi] = rho;
+    rot.s_h[hi] = sn;
+    rot.alpha_h[hi] = a;
+    rot.cprev[bi] = cs;
+    if (MODE == 1) {
+      const double pb = rot.phibar[bi];
+      rot.phi_h[hi] = cs * pb;
+      rot.phibar[bi] = sn * pb;
+    }
+    rcs[0] = cs;
+    rcs[1] = sn;
+  }
+  if (MODE != 2) return;
+  __syncthreads();
+  const double cs = rcs[0], sn = rcs[1];
+  for (int j = wave; j < rot.p_rhs; j += nw) {
+    const cplx<T>* bj = reinterpret_cast<const cplx<T>*>(rot.bh) + ((int64_t)f * rot.p_rhs + j) * len;
+    double re = 0.0, im = 0.0;
+    for (int i = lane; i < len; i += 64) {
+      const zd q = vs[i], x = ld<double>(bj[i]);
+      re = fma(q.re, x.re, fma(q.im, x.im, re));
+      im = fma(q.re, x.im, fma(-q.im, x.re, im));
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+      const int64_t idx = (int64_t)f * rot.p_rhs + j;
+      const zd pb = rot.nphibar[idx];
+      rot.nphi_h[idx * rot.kmax + rot.i - 1] = mk(fma(cs, pb.re, sn * re), fma(cs, pb.im, sn * im));
+      rot.nphibar[idx] = mk(fma(sn, pb.re, -cs * re), fma(sn, pb.im, -cs * im));
+    }
+  }
 }
 
-// Givens update of the projected least-squares problem after step i (1-based), per (f, c):
-// alpha = c_i, beta = z_{i+1}.  State: cprev (cosine of the previous rotation, -1 initially),
-// phibar.  Records rho_i, s_i, phi_i (for the final back substitution) and the face residual.
-__global__ void k_gkb_givens(const double* __restrict__ alpha, const double* __restrict__ beta, double* __restrict__ cprev,
-                             double* __restrict__ phibar, double* __restrict__ rho_h, double* __restrict__ s_h,
-                             double* __restrict__ phi_h, double* __restrict__ alpha_h, int kmax, int i, int count) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
-  const double a = alpha[idx], b = beta[idx];
-  const double rbar = -cprev[idx] * a;
-  const double rho = sqrt(rbar * rbar + b * b);
-  double c, s;
-  if (rho > 0.0) { c = rbar / rho; s = b / rho; } else { c = 0.0; s = 1.0; }
-  const double pb = phibar[idx];
-  rho_h[(int64_t)idx * kmax + i - 1] = rho;
-  s_h[(int64_t)idx * kmax + i - 1] = s;
-  phi_h[(int64_t)idx * kmax + i - 1] = c * pb;
-  alpha_h[(int64_t)idx * kmax + i - 1] = a;
-  phibar[idx] = s * pb;
-  cprev[idx] = c;
+// Progress of the step loop for the host: after step i the discrepancy kernel stores one 64-bit
+// word (call id << 48 | i << 32 | slices still undecided) into coherent pinned host memory at
+// system scope, so that the host can keep a bounded number of steps in flight without
+// synchronizing the stream.  i < 2^16 (k_max <= m <= 8192).
+__device__ __forceinline__ void report_progress(uint64_t* prog, uint32_t pid, int i, int undecided) {
+  if (!prog) return;
+  const uint64_t word = ((uint64_t)(pid & 0xffffu) << 48) | ((uint64_t)(i & 0xffff) << 32) | (uint32_t)undecided;
+  __hip_atomic_store(prog, word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// discrepancy check after step i: one thread per slice c, sums over faces in a fixed order
-__global__ void k_gkb_dp(const double* __restrict__ phibar, int F, int p, int n, const double* __restrict__ bound,
-                         int i, int kmax, int* __restrict__ kout, double* __restrict__ resid, int* __restrict__ remaining) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= p) return;
-  double tot = 0.0;
-  for (int f = 0; f < F; ++f) {
-    const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
-    const double v = phibar[(int64_t)f * p + c];
-    tot += w * v * v;
+// discrepancy check after step i (one block): one wave per slice c, lanes over the faces (a fixed
+// order); remaining counts the undecided slices
+__global__ void __launch_bounds__(1024)
+k_gkb_dp(const double* __restrict__ phibar, int F, int p, int n, const double* __restrict__ bound, int i, int kmax,
+         int* __restrict__ kout, double* __restrict__ resid, int* __restrict__ remaining, uint64_t* __restrict__ prog,
+         uint32_t pid) {
+  if (*remaining <= 0) return;
+  __shared__ int decided;
+  if (threadIdx.x == 0) decided = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int c = threadIdx.x >> 6; c < p; c += nw) {
+    double tot = 0.0;
+    for (int f = lane; f < F; f += 64) {
+      const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
+      const double v = phibar[(int64_t)f * p + c];
+      tot = fma(w * v, v, tot);
+    }
+    tot = wave_sum(tot);
+    if (lane == 0) {
+      const double r = sqrt(tot / (double)n);
+      if (resid) resid[(int64_t)c * kmax + i - 1] = r;
+      if (kout[c] == 0 && r <= bound[c]) {
+        kout[c] = i;
+        atomicAdd(&decided, 1);
+      }
+    }
   }
-  const double r = sqrt(tot / (double)n);
-  if (resid) resid[(int64_t)c * kmax + i - 1] = r;
-  if (kout[c] == 0 && r <= bound[c]) {
-    kout[c] = i;
-    atomicSub(remaining, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int rem = *remaining - decided;
+    *remaining = rem;
+    report_progress(prog, pid, i, rem);
   }
 }
 
@@ -265,13 +393,14 @@ k_gkb_solution(const cplx<T>* __restrict__ Wb, int64_t ld_basis, int m, const in
 }
 
 // initial normalization: q_1 = b-hat / ||b-hat||, z_1 = ||b-hat|| per (f, c); phibar = z_1
+// (face stride of B-hat: sB)
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_gkb_init(const cplx<T>* __restrict__ Bh, int l, int p, cplx<T>* __restrict__ Qb, int64_t ld_basis,
+k_gkb_init(const cplx<T>* __restrict__ Bh, int64_t sB, int l, int p, cplx<T>* __restrict__ Qb, int64_t ld_basis,
            double* __restrict__ z1, double* __restrict__ phibar, double* __restrict__ cprev, double tol) {
   __shared__ double red[32];
   const int c = blockIdx.x, f = blockIdx.y;
-  const cplx<T>* b = Bh + (int64_t)f * l * p + (int64_t)c * l;
+  const cplx<T>* b = Bh + (int64_t)f * sB + (int64_t)c * l;
   double nn = 0.0;
   for (int i = threadIdx.x; i < l; i += blockDim.x) nn += cabs2(ld<double>(b[i]));
   for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
@@ -304,6 +433,135 @@ __global__ void k_gkb_finish(const int* __restrict__ kin, int p, int kmax, int* 
   }
   __syncthreads();
   if (threadIdx.x == 0 && status) *status = fail_any ? RTSVD_W_DP_NOT_MET : RTSVD_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// nested_tGKB_p (Alg. 8): one basis, started from B_1, shared by every lateral slice
+// ---------------------------------------------------------------------------------------------
+// The bidiagonal P-bar_k and its Givens rotations belong to the basis alone (one set per face);
+// slice j only brings its own right-hand side g = Q_{k+1}^H b-hat_j.  With the rotation
+// [c s; s -c] of step i acting on rows i, i+1 of [phi-bar_i; g_{i+1}]:
+//     phi_i = c phi-bar_i + s g_{i+1},   phi-bar_{i+1} = s phi-bar_i - c g_{i+1},
+// phi-bar_1 = g_1, and |phi-bar_{k+1}| is the face residual of min ||P-bar_k y - g||, so every
+// slice advances in lockstep with the basis (complex right-hand sides, real rotations).
+
+constexpr int NEST_WAVES = 4;
+
+// phi-bar_1 = q_1^H b-hat_j for every (face f, slice j); one wave each
+template <typename T>
+__global__ void __launch_bounds__(64 * NEST_WAVES)
+k_nest_init(const cplx<T>* __restrict__ Qb, int64_t ld_basis, const cplx<T>* __restrict__ Bh, int l, int p,
+            zd* __restrict__ phibar) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * NEST_WAVES + (threadIdx.x >> 6), f = blockIdx.y;
+  if (j >= p) return;
+  const cplx<T>* q = Qb + (int64_t)f * ld_basis;
+  const cplx<T>* b = Bh + ((int64_t)f * p + j) * l;
+  double re = 0.0, im = 0.0;
+  for (int t = lane; t < l; t += 64) {
+    const zd a = ld<double>(q[t]), x = ld<double>(b[t]);
+    re = fma(a.re, x.re, fma(a.im, x.im, re));
+    im = fma(a.re, x.im, fma(-a.im, x.re, im));
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) phibar[(int64_t)f * p + j] = mk(re, im);
+}
+
+// chain state: st[0] = slice being decided, st[1] = its smallest admissible k, st[2] = 1 once a
+// slice took k_max without meeting the principle
+__global__ void k_nest_reset(int* __restrict__ st, int k_init, int* __restrict__ remaining, int p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st[0] = 0;
+    st[1] = k_init;
+    st[2] = 0;
+    *remaining = p;
+  }
+}
+
+// After step i: residual of every slice (faces summed in a fixed order with the half-spectrum
+// weights, one wave per slice), res[j*kmax + i-1]; then the slices are decided in order: slice j takes the first
+// k >= k_{j-1} (k_init for j = 1), k <= i, whose residual is below eta*delta_j; at i = k_max an
+// undecided slice takes k_max and the failure is recorded.  One block; nothing once every slice
+// is decided.
+__global__ void __launch_bounds__(256)
+k_nest_dp(const zd* __restrict__ phibar, int F, int p, int n, const double* __restrict__ bound, int i, int kmax,
+          double* __restrict__ res, int* __restrict__ kout, int* __restrict__ st, int* __restrict__ remaining,
+          uint64_t* __restrict__ prog, uint32_t pid) {
+  if (*remaining <= 0) return;
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int j = threadIdx.x >> 6; j < p; j += nw) {   // one wave per slice, lanes over the faces
+    double tot = 0.0;
+    for (int f = lane; f < F; f += 64) {
+      const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
+      tot = fma(w, cabs2(phibar[(int64_t)f * p + j]), tot);
+    }
+    tot = wave_sum(tot);
+    if (lane == 0) res[(int64_t)j * kmax + i - 1] = sqrt(tot / (double)n);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int j = st[0], k = st[1], failed = st[2];
+  while (j < p) {
+    while (k <= i && !(res[(int64_t)j * kmax + k - 1] < bound[j])) ++k;
+    if (k <= i) {
+      kout[j++] = k;
+    } else if (i == kmax) {
+      k = kmax;
+      kout[j++] = kmax;
+      failed = 1;
+    } else {
+      break;
+    }
+  }
+  st[0] = j;
+  st[1] = k;
+  st[2] = failed;
+  *remaining = p - j;
+  report_progress(prog, pid, i, p - j);
+}
+
+// X-hat(:, j) on face f = W_k y, y from R y = phi (R upper bidiagonal: diagonal rho_t, super-
+// diagonal s_t alpha_{t+1}; complex phi of slice j), k = k_j.  One block per (j, f).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_nest_solution(const cplx<T>* __restrict__ Wb, int64_t ld_basis, int m, const int* __restrict__ kin, int kmax, int p,
+                const double* __restrict__ rho_h, const double* __restrict__ s_h, const double* __restrict__ alpha_h,
+                const zd* __restrict__ phi_h, cplx<T>* __restrict__ Xh) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  zd* y = reinterpret_cast<zd*>(smem_raw);
+  const int j = blockIdx.x, f = blockIdx.y;
+  const int k = kin[j];
+  if (threadIdx.x == 0) {
+    const double* rh = rho_h + (int64_t)f * kmax;
+    const double* sh = s_h + (int64_t)f * kmax;
+    const double* ah = alpha_h + (int64_t)f * kmax;
+    const zd* ph = phi_h + ((int64_t)f * p + j) * kmax;
+    zd ynext = mk(0.0, 0.0);
+    for (int t = k - 1; t >= 0; --t) {
+      const double theta = (t + 1 < k) ? sh[t] * ah[t + 1] : 0.0;
+      zd yt = mk(0.0, 0.0);
+      if (rh[t] > 0.0) {
+        const double inv = 1.0 / rh[t];
+        yt = mk((ph[t].re - theta * ynext.re) * inv, (ph[t].im - theta * ynext.im) * inv);
+      }
+      y[t] = yt;
+      ynext = yt;
+    }
+  }
+  __syncthreads();
+  const cplx<T>* W = Wb + (int64_t)f * ld_basis;
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    zd acc = mk(0.0, 0.0);
+    for (int t = 0; t < k; ++t) acc = cadd(acc, cmul(ld<double>(W[(int64_t)t * m + r]), y[t]));
+    Xh[(int64_t)f * m * p + (int64_t)j * m + r] = mk((T)acc.re, (T)acc.im);
+  }
+}
+
+__global__ void k_nest_finish(const int* __restrict__ kin, const int* __restrict__ st, int p, int* __restrict__ kout,
+                              int* __restrict__ status) {
+  for (int j = threadIdx.x; j < p; j += blockDim.x) kout[j] = kin[j];
+  if (threadIdx.x == 0 && status) *status = st[2] ? RTSVD_W_DP_NOT_MET : RTSVD_OK;
 }
 
 }  // namespace rt

@@ -24,7 +24,7 @@ E_ARG, E_HIP, E_NOMEM, E_UNSUPPORTED = -1, -3, -4, -5
 PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
-           "tprod", "tprod_adjoint", "tgkb_solve", "rtsvd_status_string", "rtsvd_last_error",
+           "tprod", "tprod_adjoint", "tgkb_solve", "nested_tgkb_solve", "rtsvd_status_string", "rtsvd_last_error",
            "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim"]
 
 
@@ -63,6 +63,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tprod_adjoint.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int, vp]
     if hasattr(lib, "tgkb_solve"):
         lib.tgkb_solve.argtypes = [vp, vp, i64, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, vp, vp, vp, vp, vp]
+    if hasattr(lib, "nested_tgkb_solve"):
+        lib.nested_tgkb_solve.argtypes = [vp, vp, i64, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, i32, vp, vp, vp,
+                                          vp, vp]
     lib.rtsvd_status_string.restype = ctypes.c_char_p
     lib.rtsvd_status_string.argtypes = [ctypes.c_int]
     lib.rtsvd_last_error.restype = ctypes.c_char_p
@@ -254,6 +257,24 @@ def tgkb_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int):
     status = torch.empty(1, dtype=torch.int32, device=A.device)
     _check(lib.tgkb_solve(A.data_ptr(), B.data_ptr(), l, m, n, p, _dtype_code(A), arr, len(deltas), eta, k_max,
                           X.data_ptr(), k.data_ptr(), resid.data_ptr(), status.data_ptr(), _stream()), "tgkb_solve")
+    return X, k, resid, status
+
+
+def nested_tgkb_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int, k_init: int = 2):
+    """nested_tGKB_p restoration; returns (X, k (device int32 [p]), resid (device [p, k_max]), status)."""
+    lib = load()
+    A, B = _dev(A, "A"), _dev(B, "B")
+    n, m, l = A.shape
+    _, p, _ = B.shape
+    deltas = [float(d) for d in (delta if hasattr(delta, "__len__") else [delta])]
+    arr = (ctypes.c_double * len(deltas))(*deltas)
+    X = torch.empty((n, p, m), dtype=A.dtype, device=A.device)
+    k = torch.empty(p, dtype=torch.int32, device=A.device)
+    resid = torch.empty((p, k_max), dtype=torch.float64, device=A.device)
+    status = torch.empty(1, dtype=torch.int32, device=A.device)
+    _check(lib.nested_tgkb_solve(A.data_ptr(), B.data_ptr(), l, m, n, p, _dtype_code(A), arr, len(deltas), eta, k_max,
+                                 k_init, X.data_ptr(), k.data_ptr(), resid.data_ptr(), status.data_ptr(), _stream()),
+           "nested_tgkb_solve")
     return X, k, resid, status
 
 

@@ -165,7 +165,7 @@ def gaussian_omega(m: int, r: int, n: int, rng: np.random.Generator) -> np.ndarr
 
 
 # ----------------------------------------------------------------------------------------------
-# named workloads (the five benchmark configurations)
+# named workloads (the benchmark configurations and the colour-image Krylov comparison)
 # ----------------------------------------------------------------------------------------------
 @dataclass
 class Workload:
@@ -200,6 +200,9 @@ WORKLOADS = {
     "video512": Workload("video512", 512, 64, 3.0, 10, 64, 80, 10, 0, 1e-2, precision="fp32", video=True),
     "blur1024": Workload("blur1024", 1024, 128, 3.0, 10, 1, 100, 20, 1, 1e-3, precision="mixed"),
     "diff512": Workload("diff512", 512, 64, 3.0, 10, 0, 80, 10, 0, 1e-2, precision="fp32", video=True),
+    # colour-image restoration of Section 5 (256 x 256 x 256 blur with band 12, sigma 3; three
+    # channels as lateral slices): the Krylov comparison (tGKB_p, nested_tGKB_p)
+    "rgb256": Workload("rgb256", 256, 256, 3.0, 12, 3, 60, 10, 0, 1e-3, precision="fp64", video=True),
 }
 
 

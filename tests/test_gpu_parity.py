@@ -269,6 +269,78 @@ def test_tgkb_dp_not_met_and_random():
 
 
 # ---------------------------------------------------------------------------------------------
+# nested_tGKB_p: one recycled t-Krylov space for every lateral slice
+# ---------------------------------------------------------------------------------------------
+def _gpu_nested(A, B, delta, eta, k_max, dtype, k_init=2):
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    X, k, resid, status = rt.nested_tgkb_solve(_t(A, dtype), _t(B, dtype), delta, eta, k_max, k_init)
+    torch.cuda.synchronize()
+    return X, k, resid, status
+
+
+def _check_nested(orc, Xg, k, resid, status, tol):
+    ks = [int(v) for v in k.cpu()]
+    assert ks == orc["k"]
+    assert int(status[0]) == orc["status"]
+    assert _rel(_np(Xg), wl.to_storage(orc["X"])) <= tol
+    top = max(ks)          # every slice's projected residual is known up to the largest k reached
+    np.testing.assert_allclose(_np(resid)[:, :top], orc["res"][:top, :].T, rtol=max(tol, 1e-9), atol=0)
+
+
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-10), ("float32", 1e-4)])
+def test_nested_tgkb_video_slices(dtype, tol):
+    # moving-blob video: later frames need a larger space than the one B_1 alone would stop at
+    from oracle import tgkb as tg
+    A, X, B, Om, delta = blur_problem(48, 8, 2.0, 6, 6, 1e-2, 20, 0, seed=31, video=True)
+    Bm = wl.to_math(B)
+    fac = [2.0, 1.5, 1.2, 1.0, 0.8, 0.7]                     # tighter bounds for later frames
+    deltas = [0.01 * fac[j] * np.linalg.norm(Bm[:, j]) for j in range(6)]
+    orc = tg.nested_tgkb_restore(wl.to_math(A), Bm, deltas, 1.05, 30)
+    assert orc["k"][-1] > orc["k"][0]
+    top = max(orc["k"])                                        # no decision within 0.1% of its bound
+    assert np.abs(np.log(orc["res"][:top] / (1.05 * np.array(deltas)))).min() > 1e-3
+    Xg, k, resid, status = _gpu_nested(A, B, deltas, 1.05, 30, dtype)
+    _check_nested(orc, Xg, k, resid, status, tol)
+
+
+def test_nested_tgkb_many_slices_ragged_and_k_init():
+    # p = 9 slices (more than one block of slices), odd n, deltas mixing met at once / late / never
+    from oracle import tgkb as tg
+    l, m, n, p = 37, 29, 7, 9
+    rng = np.random.default_rng(32)
+    A = rng.standard_normal((n, m, l))
+    B = rng.standard_normal((n, p, l))
+    Am, Bm = wl.to_math(A), wl.to_math(B)
+    # bounds relative to each slice's projected residual at k = 1: met at once, after a few
+    # steps, or never (slice 8), with every decision at least 1% away from its bound
+    r1 = tg.nested_tgkb_restore(Am, Bm, 1e-300, 1.01, 1, k_init=1)["res"][0]
+    deltas = list(r1 * np.array([1.3, 0.9, 0.95, 2.0, 0.8, 0.8, 0.75, 1e-13, 2.0]) / 1.01)
+    for k_init in (1, 2, 5):
+        orc = tg.nested_tgkb_restore(Am, Bm, deltas, 1.01, 12, k_init=k_init)
+        assert orc["status"] == tg.DP_NOT_MET and orc["k"][-1] == 12
+        assert np.abs(np.log(orc["res"] / (1.01 * np.array(deltas)))).min() > 1e-2
+        Xg, k, resid, status = _gpu_nested(A, B, deltas, 1.01, 12, "float64", k_init=k_init)
+        _check_nested(orc, Xg, k, resid, status, 1e-10)
+
+
+def test_nested_tgkb_identical_slices_and_single_slice():
+    # identical slices share k and X; one slice reduces to tGKB from k_init = 2
+    from oracle import tgkb as tg
+    A, X, B, Om, delta = blur_problem(40, 6, 2.0, 6, 1, 1e-2, 20, 0, seed=33)
+    B3 = np.concatenate([B] * 3, axis=1)
+    orc = tg.nested_tgkb_restore(wl.to_math(A), wl.to_math(B3), delta, 1.01, 25)
+    Xg, k, resid, status = _gpu_nested(A, B3, delta, 1.01, 25, "float64")
+    _check_nested(orc, Xg, k, resid, status, 1e-10)
+    assert len(set(int(v) for v in k.cpu())) == 1
+    Xs, ks, _, _ = _gpu_nested(A, B, delta, 1.01, 25, "float64")
+    ref = tg.tgkb_restore(wl.to_math(A), wl.to_math(B), delta, 1.01, 25)
+    assert int(ks[0]) == max(2, ref["k"][0])
+    if ref["k"][0] >= 2:
+        assert _rel(_np(Xs), wl.to_storage(ref["X"])) <= 1e-10
+
+
+# ---------------------------------------------------------------------------------------------
 # differentiable restoration: hand-written adjoint vs the FP64 oracle gradient and finite differences
 # ---------------------------------------------------------------------------------------------
 def _grad_problem(size, n, sigma, band, p, k, rho, seed):
