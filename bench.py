@@ -71,14 +71,14 @@ def stage_model(w, precision):
 # scaled by the ratio of known bytes to the counter's reading for a plain device copy); valid only
 # while the kernel's source is the one that was measured (sha256 of the source file)
 # Measured on the blur1024 workload (profiles/w_mma_cholinv_blur1024_hbm_counters.md): copy
-# calibration 1 GiB -> FETCH_SIZE 524302 KiB (factor 2.0), WRITE_SIZE 1048576 KiB (factor 1.0).
+# calibration 1 GiB -> FETCH_SIZE 524302.3 KiB (factor 1.99995), WRITE_SIZE 1048576 KiB (factor 1.0).
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
-                         "sha256": "2823752e9ee44f6b632160318e8678683082db4e1a6d45518033d5aec1c31b4b",
-                         "bytes_per_launch": 677424834},
+                         "sha256": "40c9478d914fb9f45e25e7f3eb93a953b8339e7af2e41935913b0ce9a3a31999",
+                         "bytes_per_launch": 677414042},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
-                        "sha256": "3886cfd9bb8192d695dbeb0ff3495f1526d0ba2e52f1d5a0666c22d5a067446c",
-                        "bytes_per_launch": 35854079},
+                        "sha256": "4f12bda3afa189baf3e1124acd8506f672530ac28b332b7565fec7991a8398c1",
+                        "bytes_per_launch": 35824387},
 }
 
 
