@@ -14,7 +14,10 @@ Modules
   tproduct  -- t-product, transpose, identity, block-circulant form, norms (Section 2)
   factor    -- Normalize (Alg. 3), R-tSVD literal (Alg. 6) and block form, tSVD (Alg. 1)
   solve     -- truncated pseudo-inverse solutions, discrepancy principle, restorations
-  tgkb      -- partial tGKB (Alg. 7), projected least squares (Alg. 5), tGKB method
+  tgkb      -- partial tGKB (Alg. 7), projected least squares (Alg. 5), tGKB method,
+               nested_tGKB_p (Alg. 8)
+  symmetric -- symmetric A: T-tEVD (Alg. 2), t-Lanczos process and method (Alg. 4, eq. (9t)),
+               the Ritz form (eq. (10)), t-Lanczos_p
   adjoint   -- gradients of the truncated R-tSVD restoration (reverse mode in B,
                forward mode in the blur parameter)
 """

@@ -69,18 +69,22 @@ def blur_toeplitz_dsigma(size: int, sigma: float, band: int) -> np.ndarray:
     return np.where(inside, val, 0.0)
 
 
-def tube_weights(n: int, sigma_c: float = 2.0) -> np.ndarray:
-    """Normalized Gaussian tube c_t, t = 1..n."""
+def tube_weights(n: int, sigma_c: float = 2.0, symmetric: bool = False) -> np.ndarray:
+    """Normalized Gaussian tube c_t, t = 1..n.  symmetric: the circularly symmetric tube
+    c_t ~ exp(-min(t-1, n-t+1)^2 / (2 sigma_c^2)), whose DFT is real (a t-symmetric blur)."""
     t = np.arange(n, dtype=np.float64)
+    if symmetric:
+        t = np.minimum(t, n - t)
     c = np.exp(-(t ** 2) / (2.0 * sigma_c * sigma_c))
     return c / c.sum()
 
 
 def blur_operator(size: int, n: int, sigma: float, band: int, sigma_c: float = 2.0,
-                  dtype=np.float64) -> np.ndarray:
-    """Storage-order (n, m, l) blur tensor with A^(t) = c_t T."""
+                  dtype=np.float64, symmetric: bool = False) -> np.ndarray:
+    """Storage-order (n, m, l) blur tensor with A^(t) = c_t T (T symmetric Toeplitz); with a
+    symmetric tube every DFT face c-hat_t T is real symmetric, so A^T = A."""
     T = blur_toeplitz(size, sigma, band)
-    c = tube_weights(n, sigma_c)
+    c = tube_weights(n, sigma_c, symmetric)
     # storage slice t holds A^(t) transposed; T is symmetric
     return np.ascontiguousarray((c[:, None, None] * T.T[None, :, :]).astype(dtype))
 
