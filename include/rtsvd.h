@@ -179,6 +179,32 @@ int nested_tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_
                       int32_t k_init, void* X, int32_t* k_out, double* resid_out, int32_t* status_out,
                       void* stream);
 
+/* T-tEVD factor of a symmetric tensor (Alg. 2, Section 3.1): A in R^{m x m x n} with A^T = A, i.e.
+ * every DFT face A-hat_i Hermitian (the faces' lower triangles are read; symmetry is the caller's
+ * promise, not checked).  Facewise FP64 Hermitian eigendecomposition, eigenpairs ordered by
+ * decreasing |eigenvalue|; the handle stores them as the SVD A-hat_i = (W_i sign(D_i)) |D_i| W_i^H,
+ * so that rtsvd_solve gives the T-tEVD solutions X_k = W_k * D_k^{-1} * W_k^T * B of eqs. (6) and
+ * (61) with the discrepancy principle, and rtsvd_factor_info returns r = m, |eigenvalues| as
+ * sigma and eta^[j] = ||A||_F^2 - (1/n) sum_i sum_{j' <= j} |d_j'^(i)|^2.  Eigenvalues at or below
+ * 4 m u max|d^(i)| count as zero.  A: DEVICE m x m x n; precision FP64 or FP32 (work type of the
+ * stored vectors; the eigensolver is FP64).  Errors: RTSVD_E_ARG, RTSVD_E_UNSUPPORTED (m > 256).  */
+int ttevd_factor(const void* A, int64_t m, int64_t n, int dtype, int32_t precision, int32_t k_max,
+                 void* stream, rtsvd_handle* out);
+
+/* t-Lanczos_p regularization of a symmetric tensor (Alg. 4 with full re-orthogonalization, the
+ * projected least-squares problem of eq. (9t) per face as in Alg. 5, X_k = Q_k * Y_k): every
+ * lateral slice j of B runs its own process from B_j and stops at the first k with
+ * ||B_j - A * X_{j,k}||_F <= eta_dp * delta_j.  A: DEVICE m x m x n with Hermitian DFT faces (the
+ * diagonal entries of the tridiagonal are taken as the real parts of q^H A-hat q); B: DEVICE
+ * m x p x n; X: DEVICE m x p x n (dtype; computed in dtype, sums and the projected problems in
+ * FP64).  delta: HOST, n_delta = 1 or p.  k_out: DEVICE int32[p]; resid_out: DEVICE
+ * double[k_max * p] or NULL (resid_out[j*k_max + k-1], 0 beyond the last step run); status_out:
+ * DEVICE int32[1] or NULL (RTSVD_W_DP_NOT_MET when a slice reached k_max without meeting the
+ * principle; it then takes k_max).  Errors: RTSVD_E_ARG, RTSVD_E_UNSUPPORTED (m > 8192).       */
+int tlanczos_solve(const void* A, const void* B, int64_t m, int64_t n, int64_t p, int dtype,
+                   const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, void* X,
+                   int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
+
 /* Gradients of a loss L(X) through the truncated R-tSVD restoration at a fixed truncation index
  * k (no discrepancy search), fixed Gaussian tensor omega and q = 0 power iterations; the factor is
  * recomputed from A, not stored.  X = V_k * S_k^{-1} * U_k^T * B (Section 4.2).
@@ -212,6 +238,7 @@ int rtsvd_solve_vjp(const void* A, const void* dA, const void* B, const void* om
 #define RTSVD_T_TGKB 13      /* whole tgkb_solve                                             */
 #define RTSVD_T_W_MMA 14     /* the MFMA kernel of W = A-hat V alone (inside RTSVD_T_W)        */
 #define RTSVD_T_NESTED 15    /* whole nested_tgkb_solve                                      */
+#define RTSVD_T_TLANCZOS 16  /* whole tlanczos_solve                                         */
 int rtsvd_timer_enable(int on);
 int rtsvd_timer_read(int tag, double* total_ms, int32_t* launches);
 

@@ -167,7 +167,7 @@ struct rtsvd_factor_s {
   int64_t l = 0, m = 0, n = 0, F = 0, r = 0;
   int dtype = RTSVD_F64;       // caller dtype
   int precision = RTSVD_P_FP64;
-  int kind = 0;                // 0 = R-tSVD, 1 = T-tSVD
+  int kind = 0;                // 0 = R-tSVD, 1 = T-tSVD, 2 = T-tEVD
   int k_max = 0, oversample = 0;
   double eps = 0.0;
   hipStream_t stream = nullptr;
@@ -397,6 +397,45 @@ __global__ void k_lead_block(const zd* __restrict__ G, int r, int k, int F, zd* 
   Gk[idx] = G[f * r * r + i + (int64_t)j * r];
 }
 
+// T-tEVD ordering (Alg. 2, step 3): per face, the eigenpairs (lam descending from the eigensolver,
+// eigenvectors Ve) re-ordered by decreasing |lam| (ties: the eigensolver's order).  Outputs in
+// that order: sigma = |lam| (0 at or below tol_rel |lam|_max), s2 = sigma^2, V = the eigenvectors,
+// U = V diag(sign lam) in the work type, so that V diag(1/sigma) U^H = V diag(1/lam) V^H.
+// One block per face, r <= blockDim.
+template <typename TU>
+__global__ void __launch_bounds__(256)
+k_tevd_sort(const double* __restrict__ lam, const zd* __restrict__ Ve, int r, double tol_rel,
+            double* __restrict__ sigma, double* __restrict__ s2, zd* __restrict__ V, TU* __restrict__ U) {
+  __shared__ int pos[256];
+  __shared__ double sgn[256];
+  const int f = blockIdx.x;
+  const double* lf = lam + (int64_t)f * r;
+  double amax = 0.0;
+  for (int i = 0; i < r; ++i) amax = fmax(amax, fabs(lf[i]));
+  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+    const double a = fabs(lf[j]);
+    int rank = 0;
+    for (int i = 0; i < r; ++i) {
+      const double b = fabs(lf[i]);
+      rank += (b > a || (b == a && i < j)) ? 1 : 0;
+    }
+    pos[j] = rank;
+    sgn[j] = lf[j] < 0.0 ? -1.0 : 1.0;
+    const double sv = a > tol_rel * amax ? a : 0.0;
+    sigma[(int64_t)f * r + rank] = sv;
+    s2[(int64_t)f * r + rank] = sv * sv;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)f * r * r;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)r * r; idx += blockDim.x) {
+    const int i = (int)(idx % r), j = (int)(idx / r);
+    const zd v = Ve[base + idx];
+    const int64_t o = base + (int64_t)pos[j] * r + i;
+    V[o] = v;
+    st(U[o], cscale(v, sgn[j]));
+  }
+}
+
 // adapt_eps > 0: the fixed-precision factor of Alg. 6 (keep the first r_eps sketch columns)
 template <typename Tin, typename Tw>
 static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int64_t n, int64_t r, int precision,
@@ -616,6 +655,88 @@ extern "C" int ttsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int 
   h->l = l; h->m = m; h->n = n; h->F = n / 2 + 1; h->r = m; h->dtype = dtype; h->precision = precision;
   h->kind = 1; h->k_max = k_max; h->oversample = 0; h->stream = s;
   const int rc = dispatch_factor(A, nullptr, dtype, l, m, n, m, precision, 0, h, s, true);
+  if (rc != 0) { delete h; return rc; }
+  *out = h;
+  return RTSVD_OK;
+}
+
+// T-tEVD factor of a symmetric A (Alg. 2): facewise Hermitian eigendecomposition of A-hat_i (its
+// lower triangle, FP64), eigenpairs by decreasing |lambda|, stored as the SVD
+// A-hat_i = (V sign(lambda)) |lambda| V^H so that the solve and the discrepancy principle are the
+// T-tSVD ones; W = A-hat V for the exact residuals.
+template <typename Tin, typename Tw>
+static int tevd_impl(const Tin* A, int64_t m, int64_t n, rtsvd_factor_s* h, hipStream_t s) {
+  typedef cplx<Tw> zw;
+  const int64_t F = n / 2 + 1, r = m;
+  Scratch sc(s);
+  RT_ALLOC(Ah, zw, F * m * m, sc);
+  RT_ALLOC(sumsq, double, ceil_div(m * m, 2) + 1, sc);
+  int64_t nblk = 0;
+  {
+    RT_TIMED(RTSVD_T_FFT_A);
+    RT_TRY((launch_rfft<Tin, Tw>(A, m * m, (int)n, Ah, m * m, (zb*)nullptr, sumsq, &nblk, s)));
+  }
+  RT_ALLOC(sigma, double, F * r, sc);
+  RT_ALLOC(s2, double, F * r, sc);
+  RT_ALLOC(V, zd, F * m * r, sc);
+  RT_ALLOC(Uo, zw, F * m * r, sc);
+  RT_ALLOC(Wo, zw, F * m * r, sc);
+  RT_ALLOC(eta, double, r + 1, sc);
+  RT_ALLOC(flags, int, 1, sc);
+  RT_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
+  RT_ALLOC(G, zd, F * m * m, sc);
+  RT_ALLOC(Ve, zd, F * m * m, sc);
+  RT_ALLOC(lam, double, F * r, sc);
+  {
+    RT_TIMED(RTSVD_T_HEEV);
+    hipLaunchKernelGGL((k_convert<zw, zd>), dim3(nblocks(F * m * m)), dim3(256), 0, s, (const zw*)Ah, G, F * m * m);
+    RT_LAUNCH_OK();
+    RT_TRY(launch_heev(G, (int)m, F, Ve, lam, sc, s));
+  }
+  const double eig_tol = 4.0 * (double)r * 2.220446049250313e-16;
+  hipLaunchKernelGGL((k_tevd_sort<zw>), dim3((unsigned)F), dim3(256), 0, s, (const double*)lam, (const zd*)Ve, (int)r,
+                     eig_tol, sigma, s2, V, Uo);
+  RT_LAUNCH_OK();
+  hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, (const double*)s2, (int64_t)r,
+                     (int64_t)1, (int)F, (int)r, (int)n, eta);
+  RT_LAUNCH_OK();
+  {
+    RT_TIMED(RTSVD_T_W);
+    RT_TRY((big_gemm<zw, zd, zw>(false, Ah, m, m, V, r, Wo, F, sc, s)));
+  }
+  h->Q = sc.release(Uo);
+  h->Ub = nullptr;
+  h->sigma = sc.release(sigma);
+  h->V = sc.release(V);
+  h->W = sc.release(Wo);
+  h->eta = sc.release(eta);
+  h->flags = sc.release(flags);
+  h->owned = {h->Q, h->sigma, h->V, h->W, h->eta, h->flags};
+  return 0;
+}
+
+extern "C" int ttevd_factor(const void* A, int64_t m, int64_t n, int dtype, int32_t precision, int32_t k_max,
+                            void* stream, rtsvd_handle* out) {
+  g_last_error.clear();
+  if (!A || !out) return fail(RTSVD_E_ARG, "ttevd_factor: null argument");
+  *out = nullptr;
+  if (dtype != RTSVD_F64 && dtype != RTSVD_F32) return fail(RTSVD_E_ARG, "ttevd_factor: bad dtype");
+  if (m < 1 || n < 1) return fail(RTSVD_E_ARG, "ttevd_factor: need m >= 1 and n >= 1");
+  if (k_max < 1 || k_max > m) return fail(RTSVD_E_ARG, "ttevd_factor: need 1 <= k_max <= m");
+  if (precision != RTSVD_P_FP64 && precision != RTSVD_P_FP32)
+    return fail(RTSVD_E_ARG, "ttevd_factor: precision must be FP64 or FP32");
+  if (m > 256) return fail(RTSVD_E_UNSUPPORTED, "ttevd_factor: m must be <= 256");
+  hipStream_t s = (hipStream_t)stream;
+  rtsvd_factor_s* h = new rtsvd_factor_s();
+  h->l = m; h->m = m; h->n = n; h->F = n / 2 + 1; h->r = m; h->dtype = dtype; h->precision = precision;
+  h->kind = 2; h->k_max = k_max; h->oversample = 0; h->stream = s;
+  int rc;
+  if (dtype == RTSVD_F64)
+    rc = work_is_double(precision) ? tevd_impl<double, double>((const double*)A, m, n, h, s)
+                                   : tevd_impl<double, float>((const double*)A, m, n, h, s);
+  else
+    rc = work_is_double(precision) ? tevd_impl<float, double>((const float*)A, m, n, h, s)
+                                   : tevd_impl<float, float>((const float*)A, m, n, h, s);
   if (rc != 0) { delete h; return rc; }
   *out = h;
   return RTSVD_OK;
@@ -1117,6 +1238,114 @@ extern "C" int nested_tgkb_solve(const void* A, const void* B, int64_t l, int64_
     return nested_tgkb_impl<float>((const float*)A, (const float*)B, l, m, n, p, bounds, k_max, kin, (float*)X, k_out,
                                    resid_out, status_out, s);
   return fail(RTSVD_E_ARG, "nested_tgkb_solve: bad dtype");
+}
+
+// ---------------------------------------------------------------------------------------------
+// t-Lanczos_p (Alg. 4 with full re-orthogonalization, eq. (9t)) for a symmetric A
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+static int tlanczos_impl(const T* A, const T* B, int64_t m, int64_t n, int64_t p, const std::vector<double>& bounds,
+                         int kmax, T* X, int* k_out, double* resid_out, int* status_out, hipStream_t s) {
+  typedef cplx<T> zt;
+  const int64_t F = n / 2 + 1;
+  const double tol = 64.0 * (sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.960464477539063e-08);
+  Scratch sc(s);
+  RT_TIMED(RTSVD_T_TLANCZOS);
+  RT_ALLOC(Ah, zt, F * m * m, sc);
+  RT_ALLOC(Bh, zt, F * m * p, sc);
+  RT_TRY((launch_rfft<T, T>(A, m * m, (int)n, Ah, m * m, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  RT_TRY((launch_rfft<T, T>(B, m * p, (int)n, Bh, m * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
+  const int64_t ldq = m * (kmax + 1), cnt = F * p;
+  RT_ALLOC(Qb, zt, F * p * ldq, sc);
+  RT_ALLOC(raw, zd, gkb_part_elems(m, m, p, F), sc);
+  int nparts = 1;
+  int64_t tstr = 0;
+  RT_ALLOC(zc, double, cnt, sc);
+  RT_ALLOC(cprev, double, cnt, sc);
+  RT_ALLOC(phibar, double, cnt, sc);
+  RT_ALLOC(rot4, double, 4 * cnt, sc);     // rotations i-1 and i-2: cosines, sines
+  RT_ALLOC(rho_h, double, cnt * kmax, sc);
+  RT_ALLOC(r1_h, double, cnt * kmax, sc);
+  RT_ALLOC(r2_h, double, cnt * kmax, sc);
+  RT_ALLOC(phi_h, double, cnt * kmax, sc);
+  RT_ALLOC(bnd, double, p, sc);
+  RT_ALLOC(remaining, int, 1, sc);
+  RT_ALLOC(kin, int, p, sc);
+  RT_TRY(upload_doubles(bnd, bounds.data(), p, s));
+  RT_CHECK_HIP(hipMemsetAsync(kin, 0, sizeof(int) * p, s));
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, remaining, (int)p);
+  RT_LAUNCH_OK();
+  if (resid_out) RT_CHECK_HIP(hipMemsetAsync(resid_out, 0, sizeof(double) * p * kmax, s));
+  // q_1 = b-hat / ||b-hat||, z_0, phi-bar = z_0; cprev (set to -1) seeds both rotation states
+  hipLaunchKernelGGL((k_gkb_init<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, Bh, m * p, (int)m, (int)p, Qb,
+                     ldq, zc, phibar, cprev, 0.0);
+  RT_LAUNCH_OK();
+  double* l1c = rot4;
+  double* l1s = rot4 + cnt;
+  double* l2c = rot4 + 2 * cnt;
+  double* l2s = rot4 + 3 * cnt;
+  RT_CHECK_HIP(hipMemcpyAsync(l1c, cprev, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+  RT_CHECK_HIP(hipMemcpyAsync(l2c, cprev, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+  RT_CHECK_HIP(hipMemsetAsync(l1s, 0, sizeof(double) * cnt, s));
+  RT_CHECK_HIP(hipMemsetAsync(l2s, 0, sizeof(double) * cnt, s));
+  Progress prog;
+  if (!progress_open(prog)) return fail(RTSVD_E_NOMEM, "tlanczos_solve: pinned host memory");
+  for (int i = 1; i <= kmax; ++i) {
+    // v = A-hat q_i; c_i, v - z_{i-1} q_{i-1} - c_i q_i, re-orthogonalized, z_i; QR update of T-bar_i
+    RT_TRY(gkb_product<T>(false, Ah, m, m, p, Qb + (int64_t)(i - 1) * m, ldq, p * ldq, raw, F, &nparts, &tstr, remaining,
+                          s));
+    {
+      const size_t lds = 32 * sizeof(double) + (size_t)(kmax + 1) * sizeof(zd) + (size_t)m * sizeof(zd);
+      GkbRot rot{nullptr, nullptr, rho_h, nullptr, nullptr, phibar, phi_h, nullptr, nullptr, nullptr, 0, kmax, i,
+                 l1c, l1s, l2c, l2s, r1_h, r2_h};
+      hipLaunchKernelGGL((k_gkb_orth<T, 3>), dim3((unsigned)p, (unsigned)F), dim3(GKB_THREADS), lds, s, (const zd*)raw,
+                         nparts, tstr, p * m, Qb, ldq, (int)m, i, (const zt*)(i >= 2 ? Qb : nullptr), ldq, i - 2,
+                         (const double*)(i >= 2 ? zc : nullptr), zc, (int)p, tol, rot, (const int*)remaining);
+      RT_LAUNCH_OK();
+    }
+    hipLaunchKernelGGL(k_gkb_dp, dim3(1), dim3(1024), 0, s, phibar, (int)F, (int)p, (int)n, bnd, i, kmax, kin,
+                       resid_out, remaining, prog.dev, prog.id);
+    RT_LAUNCH_OK();
+    if (i < kmax) {
+      const int r = await_progress(prog, i, KRYLOV_AHEAD, remaining, s);
+      if (r < 0) return fail(RTSVD_E_HIP, "tlanczos_solve: stream error while waiting for progress");
+      if (r > 0) break;
+    }
+  }
+  RT_ALLOC(Xh, zt, F * m * p, sc);
+  hipLaunchKernelGGL((k_tlan_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), (size_t)kmax * sizeof(double), s,
+                     Qb, ldq, (int)m, kin, kmax, (int)p, rho_h, r1_h, r2_h, phi_h, Xh);
+  RT_LAUNCH_OK();
+  RT_TRY((launch_irfft<T, T>(Xh, m * p, m * p, (int)n, X, s)));
+  hipLaunchKernelGGL(k_gkb_finish, dim3(1), dim3(64), 0, s, kin, (int)p, kmax, k_out, status_out);
+  RT_LAUNCH_OK();
+  return 0;
+}
+
+extern "C" int tlanczos_solve(const void* A, const void* B, int64_t m, int64_t n, int64_t p, int dtype,
+                              const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, void* X,
+                              int32_t* k_out, double* resid_out, int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !X || !delta || !k_out) return fail(RTSVD_E_ARG, "tlanczos_solve: null argument");
+  if (m < 1 || n < 1 || p < 1) return fail(RTSVD_E_ARG, "tlanczos_solve: need m >= 1, n >= 1, p >= 1");
+  if (k_max < 1 || k_max > m) return fail(RTSVD_E_ARG, "tlanczos_solve: need 1 <= k_max <= m");
+  if (n_delta != 1 && n_delta != p) return fail(RTSVD_E_ARG, "tlanczos_solve: n_delta must be 1 or p");
+  if (!(eta_dp > 1.0)) return fail(RTSVD_E_ARG, "tlanczos_solve: eta_dp must be > 1");
+  if (m > 8192) return fail(RTSVD_E_UNSUPPORTED, "tlanczos_solve: m must be <= 8192");
+  std::vector<double> bounds(p);
+  for (int64_t c = 0; c < p; ++c) {
+    const double d = delta[n_delta == 1 ? 0 : c];
+    if (!(d >= 0.0)) return fail(RTSVD_E_ARG, "tlanczos_solve: delta must be >= 0");
+    bounds[c] = eta_dp * d;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == RTSVD_F64)
+    return tlanczos_impl<double>((const double*)A, (const double*)B, m, n, p, bounds, k_max, (double*)X, k_out,
+                                 resid_out, status_out, s);
+  if (dtype == RTSVD_F32)
+    return tlanczos_impl<float>((const float*)A, (const float*)B, m, n, p, bounds, k_max, (float*)X, k_out, resid_out,
+                                status_out, s);
+  return fail(RTSVD_E_ARG, "tlanczos_solve: bad dtype");
 }
 
 

@@ -161,18 +161,32 @@ __device__ __forceinline__ double gkb_block_sum(double v, double* red) {
 // MODE 1 (tGKB_p): the basis' own e_1 z_1, phi_i = c phi-bar, phi-bar <- s phi-bar (real);
 // MODE 2 (nested): every slice j of B-hat, g = q_{i+1}^H b-hat_j, phi_i = c phi-bar + s g,
 // phi-bar <- s phi-bar - c g (complex).
+// MODE 3 (t-Lanczos, Alg. 4): the step's raw vector is A-hat q_i; the kernel forms the diagonal
+// entry c_i = Re(q_i^H A-hat q_i), subtracts z_{i-1} q_{i-1} + c_i q_i, re-orthogonalizes and
+// normalizes (z_i), and updates the QR factorization of the tridiagonal T-bar_i: column i holds
+// z_{i-1}, c_i, z_i in rows i-1, i, i+1; rotations i-2 and i-1 (state l2, l1: cosine, sine;
+// (-1, 0) before the first) give
+//     eps = s2 z_{i-1}, d = -c2 z_{i-1};  delta = c1 d + s1 c_i, g = s1 d - c1 c_i;
+// rotation i then zeroes z_i under g (rho = sqrt(g^2 + z_i^2)), R column i = (eps, delta, rho)
+// on rows i-2, i-1, i, and phi_i = c phi-bar, phi-bar <- s phi-bar as in MODE 1.
 struct GkbRot {
   const double* alpha;
   double* cprev;
   double* rho_h;
   double* s_h;
   double* alpha_h;
-  double* phibar;     // MODE 1, per basis
-  double* phi_h;      // MODE 1, per basis x kmax
+  double* phibar;     // MODE 1 / 3, per basis
+  double* phi_h;      // MODE 1 / 3, per basis x kmax
   const void* bh;     // MODE 2: face f, slice j at bh + (f*p_rhs + j)*len (storage type of the basis)
   zd* nphibar;        // MODE 2, per (f, j)
   zd* nphi_h;         // MODE 2, per (f, j) x kmax
   int p_rhs, kmax, i;
+  double* l1c;        // MODE 3: rotation i-1, per basis
+  double* l1s;
+  double* l2c;        // MODE 3: rotation i-2, per basis
+  double* l2s;
+  double* r1_h;       // MODE 3: R(i-1, i), per basis x kmax
+  double* r2_h;       // MODE 3: R(i-2, i), per basis x kmax
 };
 
 // One half-step of Alg. 7 for every (face, slice): v = raw - prevcoef * prev, CGS2 against the
@@ -209,9 +223,32 @@ k_gkb_orth(const zd* __restrict__ part, int nparts, int64_t tStride, int64_t sRa
       const zd* src = part + (int64_t)f * sRaw + (int64_t)c * len + i;
       x = src[0];
       for (int q = 1; q < nparts; ++q) x = cadd(x, src[(int64_t)q * tStride]);
-      if (pv) x = csub(x, cscale(ld<double>(pv[i]), cp));
     }
     v[t] = x;
+  }
+  double cdiag = 0.0;
+  if (MODE == 3) {   // c_i = Re(q_i^H A-hat q_i), q_i = basis vector nb - 1
+    const cplx<T>* qi = bas + (int64_t)(nb - 1) * len;
+    double d = 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = threadIdx.x + t * blockDim.x;
+      if (t < per && i < len) {
+        const zd q = ld<double>(qi[i]);
+        d = fma(q.re, v[t].re, fma(q.im, v[t].im, d));
+      }
+    }
+    cdiag = gkb_block_sum(d, red);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = threadIdx.x + t * blockDim.x;
+      if (t < per && i < len) v[t] = csub(v[t], cscale(ld<double>(qi[i]), cdiag));
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int i = threadIdx.x + t * blockDim.x;
+    if (pv && t < per && i < len) v[t] = csub(v[t], cscale(ld<double>(pv[i]), cp));
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double n0 = 0.0;
@@ -270,6 +307,29 @@ k_gkb_orth(const zd* __restrict__ part, int nparts, int64_t tStride, int64_t sRa
   const int64_t bi = (int64_t)f * p + c;
   if (threadIdx.x == 0) coef_out[bi] = ok ? nn : 0.0;
   if (MODE == 0) return;
+  if (MODE == 3) {
+    if (threadIdx.x == 0) {
+      const double zp = cp, zn = ok ? nn : 0.0;
+      const double c1 = rot.l1c[bi], s1 = rot.l1s[bi], c2 = rot.l2c[bi], s2 = rot.l2s[bi];
+      const double eps = s2 * zp, d = -c2 * zp;
+      const double delta = fma(c1, d, s1 * cdiag), g = fma(s1, d, -c1 * cdiag);
+      const double rho = sqrt(fma(g, g, zn * zn));
+      double cs, sn;
+      if (rho > 0.0) { cs = g / rho; sn = zn / rho; } else { cs = 0.0; sn = 1.0; }
+      const int64_t hi = bi * rot.kmax + rot.i - 1;
+      rot.rho_h[hi] = rho;
+      rot.r1_h[hi] = delta;
+      rot.r2_h[hi] = eps;
+      const double pb = rot.phibar[bi];
+      rot.phi_h[hi] = cs * pb;
+      rot.phibar[bi] = sn * pb;
+      rot.l2c[bi] = c1;
+      rot.l2s[bi] = s1;
+      rot.l1c[bi] = cs;
+      rot.l1s[bi] = sn;
+    }
+    return;
+  }
   if (threadIdx.x == 0) {
     const double a = rot.alpha[bi], b = ok ? nn : 0.0;
     const double rbar = -rot.cprev[bi] * a;
@@ -388,6 +448,45 @@ k_gkb_solution(const cplx<T>* __restrict__ Wb, int64_t ld_basis, int m, const in
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     zd acc = mk(0.0, 0.0);
     for (int j = 0; j < k; ++j) acc = cadd(acc, cscale(ld<double>(W[(int64_t)j * m + i]), y[j]));
+    Xh[(int64_t)f * m * p + (int64_t)c * m + i] = mk((T)acc.re, (T)acc.im);
+  }
+}
+
+// t-Lanczos solution per (f, c): k = k_c (k_max if unmet), y = R^{-1} phi with R upper triangular
+// of bandwidth 3 (diagonal rho_t, R(t, t+1) = r1_{t+1}, R(t, t+2) = r2_{t+2}), X-hat = Q_k y.
+// One block per (c, f).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_tlan_solution(const cplx<T>* __restrict__ Qb, int64_t ld_basis, int m, const int* __restrict__ kout, int kmax, int p,
+                const double* __restrict__ rho_h, const double* __restrict__ r1_h, const double* __restrict__ r2_h,
+                const double* __restrict__ phi_h, cplx<T>* __restrict__ Xh) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* y = reinterpret_cast<double*>(smem_raw);
+  const int c = blockIdx.x, f = blockIdx.y;
+  const int idx = f * p + c;
+  int k = kout[c];
+  if (k <= 0) k = kmax;
+  if (threadIdx.x == 0) {
+    const double* rh = rho_h + (int64_t)idx * kmax;
+    const double* a1 = r1_h + (int64_t)idx * kmax;
+    const double* a2 = r2_h + (int64_t)idx * kmax;
+    const double* ph = phi_h + (int64_t)idx * kmax;
+    double y1 = 0.0, y2 = 0.0;   // y_{t+1}, y_{t+2}
+    for (int t = k - 1; t >= 0; --t) {
+      double num = ph[t];
+      if (t + 1 < k) num = fma(-a1[t + 1], y1, num);
+      if (t + 2 < k) num = fma(-a2[t + 2], y2, num);
+      const double yt = rh[t] > 0.0 ? num / rh[t] : 0.0;
+      y[t] = yt;
+      y2 = y1;
+      y1 = yt;
+    }
+  }
+  __syncthreads();
+  const cplx<T>* Q = Qb + (int64_t)idx * ld_basis;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    zd acc = mk(0.0, 0.0);
+    for (int j = 0; j < k; ++j) acc = cadd(acc, cscale(ld<double>(Q[(int64_t)j * m + i]), y[j]));
     Xh[(int64_t)f * m * p + (int64_t)c * m + i] = mk((T)acc.re, (T)acc.im);
   }
 }

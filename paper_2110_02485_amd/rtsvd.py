@@ -24,7 +24,7 @@ E_ARG, E_HIP, E_NOMEM, E_UNSUPPORTED = -1, -3, -4, -5
 PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
-           "tprod", "tprod_adjoint", "tgkb_solve", "nested_tgkb_solve", "rtsvd_status_string", "rtsvd_last_error",
+           "tprod", "tprod_adjoint", "tgkb_solve", "nested_tgkb_solve", "ttevd_factor", "tlanczos_solve", "rtsvd_status_string", "rtsvd_last_error",
            "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim"]
 
 
@@ -63,6 +63,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tprod_adjoint.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int, vp]
     if hasattr(lib, "tgkb_solve"):
         lib.tgkb_solve.argtypes = [vp, vp, i64, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, vp, vp, vp, vp, vp]
+    if hasattr(lib, "ttevd_factor"):
+        lib.ttevd_factor.argtypes = [vp, i64, i64, ctypes.c_int, i32, i32, vp, ctypes.POINTER(vp)]
+    if hasattr(lib, "tlanczos_solve"):
+        lib.tlanczos_solve.argtypes = [vp, vp, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, vp, vp, vp, vp, vp]
     if hasattr(lib, "nested_tgkb_solve"):
         lib.nested_tgkb_solve.argtypes = [vp, vp, i64, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, i32, vp, vp, vp,
                                           vp, vp]
@@ -181,6 +185,19 @@ class Factor:
                                 ctypes.byref(h)), "ttsvd_factor")
         return cls(h.value, A.dtype, A.device, m, k_max, m, 0)
 
+    @classmethod
+    def ttevd(cls, A: torch.Tensor, k_max: int, precision: str = "fp64") -> "Factor":
+        """T-tEVD factor of a symmetric A (Hermitian DFT faces)."""
+        lib = load()
+        A = _dev(A, "A")
+        n, m, l = A.shape
+        if l != m:
+            raise ValueError("ttevd needs a square (symmetric) tensor")
+        h = ctypes.c_void_p()
+        _check(lib.ttevd_factor(A.data_ptr(), m, n, _dtype_code(A), PRECISIONS[precision], k_max, _stream(),
+                                ctypes.byref(h)), "ttevd_factor")
+        return cls(h.value, A.dtype, A.device, m, k_max, m, 0)
+
     def info(self):
         """(r, faces, eta (r+1), r_eps, sigma (faces, r), flags); synchronizes."""
         import numpy as np
@@ -241,6 +258,31 @@ def factor(A, k_max, oversample, power_iters=0, precision="fp64", omega=None, ep
 def ttsvd_factor(A, k_max, precision="fp64") -> Factor:
     """Full facewise SVD factor of A (T-tSVD comparator)."""
     return Factor.ttsvd(A, k_max, precision)
+
+
+def ttevd_factor(A, k_max, precision="fp64") -> Factor:
+    """T-tEVD factor of a symmetric A (Hermitian DFT faces); solve it like any factor."""
+    return Factor.ttevd(A, k_max, precision)
+
+
+def tlanczos_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int):
+    """t-Lanczos_p restoration of a symmetric A; returns (X, k (device int32 [p]), resid (device [p, k_max]), status)."""
+    lib = load()
+    A, B = _dev(A, "A"), _dev(B, "B")
+    n, m, l = A.shape
+    if l != m:
+        raise ValueError("t-Lanczos needs a square (symmetric) tensor")
+    _, p, _ = B.shape
+    deltas = [float(d) for d in (delta if hasattr(delta, "__len__") else [delta])]
+    arr = (ctypes.c_double * len(deltas))(*deltas)
+    X = torch.empty((n, p, m), dtype=A.dtype, device=A.device)
+    k = torch.empty(p, dtype=torch.int32, device=A.device)
+    resid = torch.empty((p, k_max), dtype=torch.float64, device=A.device)
+    status = torch.empty(1, dtype=torch.int32, device=A.device)
+    _check(lib.tlanczos_solve(A.data_ptr(), B.data_ptr(), m, n, p, _dtype_code(A), arr, len(deltas), eta, k_max,
+                              X.data_ptr(), k.data_ptr(), resid.data_ptr(), status.data_ptr(), _stream()),
+           "tlanczos_solve")
+    return X, k, resid, status
 
 
 def tgkb_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int):

@@ -8,9 +8,11 @@ from oracle import tproduct as tp
 from paper_2110_02485_amd import workloads as wl
 
 
-def blur_problem(size, n, sigma, band, p, noise, k_max, oversample, seed=0, video=False, squares=0):
-    """Storage-order float64 arrays A (n,m,l), X (n,p,m), B (n,p,l), Omega (n,r,m), delta."""
-    A = wl.blur_operator(size, n, sigma, band)
+def blur_problem(size, n, sigma, band, p, noise, k_max, oversample, seed=0, video=False, squares=0,
+                 symmetric=False):
+    """Storage-order float64 arrays A (n,m,l), X (n,p,m), B (n,p,l), Omega (n,r,m), delta.
+    symmetric: the blur with a circularly symmetric tube (A^T = A)."""
+    A = wl.blur_operator(size, n, sigma, band, symmetric=symmetric)
     rx = wl.rng_for("parity", "xtrue", seed)
     if video or p > 1:
         X = wl.lateral_slices(wl.moving_blob_video(size, n, p, rx))

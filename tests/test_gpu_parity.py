@@ -223,6 +223,110 @@ def test_ttsvd_fp32_256():
 
 
 # ---------------------------------------------------------------------------------------------
+# symmetric A: T-tEVD and t-Lanczos_p
+# ---------------------------------------------------------------------------------------------
+def _sym_storage(m, n, seed, shift=0.0):
+    """Storage-order random t-symmetric tensor S + S^T (+ shift I on the first frontal slice)."""
+    s = np.random.default_rng(seed).standard_normal((m, m, n))
+    a = s + tp.ttranspose(s)
+    a[:, :, 0] += shift * np.eye(m)
+    return wl.to_storage(a)
+
+
+def _check_eigs(f, orc_factor, faces, tol):
+    # stored sigma = |eigenvalues| by decreasing magnitude, face by face
+    sig = f.info()[4]
+    d = np.abs(orc_factor["d"])
+    for i in range(faces):
+        np.testing.assert_allclose(sig[i], d[:, i], rtol=tol, atol=tol * d[0, i])
+
+
+def test_ttevd_symmetric_blur_fp64():
+    from oracle import symmetric as sy
+    A, X, B, Om, delta = blur_problem(40, 12, 2.0, 6, 1, 1e-2, 20, 0, seed=21, symmetric=True)
+    orc = sy.tevd_restore(wl.to_math(A), wl.to_math(B), delta, 1.01, 20)
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    f = rt.ttevd_factor(_t(A), 20, "fp64")
+    res = f.solve(_t(B), delta, 1.01, 1)
+    torch.cuda.synchronize()
+    assert int(res.k[0]) == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-10
+    np.testing.assert_allclose(_np(res.resid)[0, :orc["k"]], orc["res"][:orc["k"], 0], rtol=1e-9)
+    _check_eigs(f, orc["factor"], 7, 1e-10)
+
+
+def test_ttevd_indefinite_per_slice_odd_n():
+    # random t-symmetric A with eigenvalues of both signs, odd n, two slices with their own k
+    from oracle import symmetric as sy
+    A = _sym_storage(24, 7, 22)
+    B = np.random.default_rng(23).standard_normal((7, 2, 24))
+    Bm = wl.to_math(B)
+    deltas = [0.5 * np.linalg.norm(Bm[:, 0]), 0.2 * np.linalg.norm(Bm[:, 1])]
+    orc = sy.tevd_restore(wl.to_math(A), Bm, deltas, 1.01, 24, per_slice=True)
+    assert orc["k"][0] != orc["k"][1]
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    f = rt.ttevd_factor(_t(A), 24, "fp64")
+    res = f.solve(_t(B), deltas, 1.01, 1)
+    torch.cuda.synchronize()
+    assert [int(v) for v in res.k.cpu()] == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-10
+    _check_eigs(f, orc["factor"], 4, 1e-10)
+
+
+def test_ttevd_fp32_256():
+    # m = 256: the eigenproblem takes the eigensolver's global-memory path
+    from oracle import symmetric as sy
+    A, X, B, Om, delta = blur_problem(256, 8, 3.0, 9, 1, 1e-2, 60, 0, seed=24, symmetric=True)
+    orc = sy.tevd_restore(wl.to_math(A), wl.to_math(B), delta, 1.01, 60)
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    f = rt.ttevd_factor(_t(A, "float32"), 60, "fp32")
+    res = f.solve(_t(B, "float32"), delta, 1.01, 1)
+    torch.cuda.synchronize()
+    assert int(res.k[0]) == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-5
+
+
+def _gpu_tlanczos(A, B, delta, eta, k_max, dtype):
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    X, k, resid, status = rt.tlanczos_solve(_t(A, dtype), _t(B, dtype), delta, eta, k_max)
+    torch.cuda.synchronize()
+    return X, k, resid, status
+
+
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-10), ("float32", 1e-4)])
+def test_tlanczos_symmetric_blur(dtype, tol):
+    from oracle import symmetric as sy
+    A, X, B, Om, delta = blur_problem(64, 16, 2.0, 6, 1, 1e-2, 20, 0, seed=25, symmetric=True)
+    orc = sy.tlanczos_restore(wl.to_math(A), wl.to_math(B), delta, 1.01, 30)
+    Xg, k, resid, status = _gpu_tlanczos(A, B, delta, 1.01, 30, dtype)
+    assert [int(v) for v in k.cpu()] == orc["k"] and int(status[0]) == orc["status"]
+    assert _rel(_np(Xg), wl.to_storage(orc["X"])) <= tol
+    kk = orc["k"][0]
+    np.testing.assert_allclose(_np(resid)[0, :kk], orc["res"][:kk, 0], rtol=max(tol, 1e-9))
+
+
+def test_tlanczos_indefinite_slices_ragged():
+    # indefinite t-symmetric A, odd n, 5 slices (more than the 4 per product launch), a never-met
+    # bound: k per slice, X, residuals and status vs the oracle
+    from oracle import symmetric as sy
+    A = _sym_storage(33, 7, 26, shift=2.0)
+    B = np.random.default_rng(27).standard_normal((7, 5, 33))
+    Am, Bm = wl.to_math(A), wl.to_math(B)
+    deltas = [f * np.linalg.norm(Bm[:, j]) for j, f in enumerate([0.9, 0.5, 0.3, 1e-13, 0.7])]
+    orc = sy.tlanczos_restore(Am, Bm, deltas, 1.01, 12)
+    assert orc["status"] == sy.DP_NOT_MET
+    Xg, k, resid, status = _gpu_tlanczos(A, B, deltas, 1.01, 12, "float64")
+    assert [int(v) for v in k.cpu()] == orc["k"] and int(status[0]) == orc["status"]
+    assert _rel(_np(Xg), wl.to_storage(orc["X"])) <= 1e-10
+    for j, kj in enumerate(orc["k"]):
+        np.testing.assert_allclose(_np(resid)[j, :kj], orc["res"][:kj, j], rtol=1e-9)
+
+
+# ---------------------------------------------------------------------------------------------
 # tGKB baseline
 # ---------------------------------------------------------------------------------------------
 def _gpu_tgkb(A, B, delta, eta, k_max, dtype):
