@@ -122,9 +122,10 @@ def parse():
     ap.add_argument("--no-fixed-precision", action="store_true",
                     help="skip the timing of the fixed-precision (eps-adaptive) R-tSVD restoration")
     ap.add_argument("--no-krylov", action="store_true",
-                    help="skip the tGKB_p / nested_tGKB_p timing on the colour-image workload")
+                    help="skip the comparison methods (tGKB_p / nested_tGKB_p on the colour-image workload, "
+                         "the symmetric-A methods on sym256)")
     ap.add_argument("--krylov-only", action="store_true",
-                    help="only the tGKB_p / nested_tGKB_p timing on the colour-image workload")
+                    help="only the comparison methods (colour-image Krylov timing, symmetric-A comparison)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM counters against known bytes)")
     return ap.parse_args()
@@ -238,6 +239,47 @@ def time_krylov(torch, rt, wl, steps):
     return out
 
 
+def time_symmetric(torch, rt, wl, steps):
+    """Symmetric-A comparison (FP64) on sym256: T-tEVD, t-Lanczos, tGKB, T-tSVD and RT-tSVD restorations
+    per second (factor + discrepancy principle + solve for the factor methods), k, relative error."""
+    w = wl.WORKLOADS["sym256"]
+    prob = make_problem(w, torch.device("cuda:0"), torch, rt, wl)
+    A, B, Om, x_true, delta = prob["A64"], prob["B64"], prob["Om64"], prob["X64"], prob["delta"]
+
+    def factor_run(make):
+        def run():
+            f = make()
+            res = f.solve(B, delta, w.eta, 1)
+            X, k, st = res.X, res.k, res.status
+            f.close()
+            return X, k, st
+        return run
+
+    methods = (
+        ("ttevd", factor_run(lambda: rt.ttevd_factor(A, w.k_max, "fp64"))),
+        ("tlanczos", lambda: rt.tlanczos_solve(A, B, delta, w.eta, w.k_max)),
+        ("tgkb", lambda: rt.tgkb_solve(A, B, delta, w.eta, w.k_max)),
+        ("ttsvd", factor_run(lambda: rt.ttsvd_factor(A, w.k_max, "fp64"))),
+        ("rtsvd", factor_run(lambda: rt.factor(A, w.k_max, w.oversample, w.power_iters, "fp64", Om))),
+    )
+    out = {"workload": w.name, "l": w.size, "m": w.size, "n": w.n, "p": 1, "k_max": w.k_max,
+           "oversample": w.oversample, "noise": w.noise, "eta": w.eta, "precision": "fp64",
+           "blur": "circularly symmetric tube (A^T = A)"}
+    for name, fn in methods:
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        X, k, st = r[0], r[1], r[-1]
+        err = float(torch.linalg.norm(X - x_true) / torch.linalg.norm(x_true))
+        out[name] = {"value": 1000.0 / ms, "unit": "solves/s", "ms_per_step": ms, "k": int(k[0]),
+                     "dp_status": int(st[0]), "rel_error": err}
+    return out
+
+
 def cpu_baseline(w, wl):
     """Time the FP64 oracle on a bounded sample of the same workload and scale to one solve."""
     import threading
@@ -300,7 +342,8 @@ def main():
     from paper_2110_02485_amd import workloads as wl
     rt.load()
     if args.krylov_only:
-        print(json.dumps({"krylov": time_krylov(torch, rt, wl, args.steps)}), flush=True)
+        print(json.dumps({"krylov": time_krylov(torch, rt, wl, args.steps),
+                          "symmetric": time_symmetric(torch, rt, wl, args.steps)}), flush=True)
         return
     w = wl.WORKLOADS[args.workload]
     precision = args.precision or w.precision
@@ -362,6 +405,8 @@ def main():
     if not args.no_krylov:
         print("[bench] Krylov comparison (tGKB_p, nested_tGKB_p)", file=sys.stderr, flush=True)
         result["krylov"] = time_krylov(torch, rt, wl, 3)
+        print("[bench] symmetric-A comparison (T-tEVD, t-Lanczos, tGKB, T-tSVD, RT-tSVD)", file=sys.stderr, flush=True)
+        result["symmetric"] = time_symmetric(torch, rt, wl, 3)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, wl)

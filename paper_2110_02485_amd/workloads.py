@@ -192,6 +192,7 @@ class Workload:
     squares: int = 0
     video: bool = False
     problems: list = field(default_factory=list)  # per-problem frame counts (differentiable batch)
+    symmetric: bool = False  # circularly symmetric blur tube (A^T = A)
 
     @property
     def r(self) -> int:
@@ -211,6 +212,10 @@ WORKLOADS = {
     # colour-image restoration of Section 5 (256 x 256 x 256 blur with band 12, sigma 3; three
     # channels as lateral slices): the Krylov comparison (tGKB_p, nested_tGKB_p)
     "rgb256": Workload("rgb256", 256, 256, 3.0, 12, 3, 60, 10, 0, 1e-3, precision="fp64", video=True),
+    # grey-scale image restoration of Section 5 (band 9, sigma 3, eta 1.1) with a symmetric blur:
+    # the comparison of the symmetric-A methods (T-tEVD, t-Lanczos) with tGKB, T-tSVD, RT-tSVD
+    "sym256": Workload("sym256", 256, 256, 3.0, 9, 1, 100, 10, 0, 1e-3, eta=1.1, precision="fp64", squares=3,
+                       symmetric=True),
 }
 
 
@@ -221,7 +226,7 @@ def make_inputs(w: Workload, dtype=np.float64, seed_extra: int = 0):
     B = A * X_true + scale_noise(E0, A * X_true, w.noise) with the product of
     their choice.
     """
-    A = blur_operator(w.size, w.n, w.sigma, w.band, dtype=np.float64)
+    A = blur_operator(w.size, w.n, w.sigma, w.band, dtype=np.float64, symmetric=w.symmetric)
     rx = rng_for(w.name, "xtrue", seed_extra)
     if w.video:
         frames = moving_blob_video(w.size, w.n, max(w.p, 1), rx)
