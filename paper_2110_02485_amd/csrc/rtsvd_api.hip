@@ -4,8 +4,10 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -436,6 +438,195 @@ k_tevd_sort(const double* __restrict__ lam, const zd* __restrict__ Ve, int r, do
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// face groups: the per-face part of the R-tSVD factor split over concurrent streams
+// ---------------------------------------------------------------------------------------------
+// After the tube DFTs every face is independent up to the scalar prefix sums of eta.  The small
+// per-face kernels (Cholesky, eigensolver, Gram) run one workgroup per face and leave most compute
+// units idle, so the faces are split into groups whose sketch / QR / projection / small SVD / W
+// sequences run on separate streams: one group's bandwidth- and MFMA-bound passes overlap another
+// group's latency-bound small-matrix work.
+
+// Arrays of the factor over all faces; a group works on its own face range of each.
+template <typename Tw>
+struct FaceBufs {
+  cplx<Tw>* Ah;
+  zb* Ah16;
+  cplx<Tw>* Omh;   // Omega-hat, m x r per face (read only)
+  cplx<Tw>* Y;     // three work buffers with per-face stride l*r (l >= m)
+  cplx<Tw>* tmp;
+  cplx<Tw>* Z;
+  zd* G;           // r x r per face
+  zd* Rinv;
+  zd* Ch;          // m x r per face
+  zd* Ub;
+  zd* Ubs;
+  double* lam;
+  double* sigma;
+  zd* V;
+  cplx<Tw>* W;
+  int* flags;
+};
+
+// sketch, q power iterations, CholeskyQR, projection C^H = A-hat^H Q and G = C C^H for faces
+// [f0, f0 + Fg), as a sequence of phases (so that several face groups can be issued phase by
+// phase, interleaved).  Phase 0: sketch; 1: QR of Y; then per power iteration Z = A-hat^H Y, QR
+// of Z, Y = A-hat Z, QR of Y; then projection and G.  Q ends in one of the work buffers
+// (per-face stride l*r).  mark (or NULL) is recorded after phase 0.
+template <typename Tw>
+struct QcGroup {
+  typedef cplx<Tw> zw;
+  const FaceBufs<Tw>* fb;
+  int64_t l, m, r, f0, Fg;
+  int q;
+  bool bf16;
+  Scratch* sc;
+  hipStream_t s;
+  hipEvent_t mark;
+  zw *Y, *tmp, *Z;
+  int phases() const { return 2 + 4 * q + 1; }
+  void init() {
+    Y = fb->Y + f0 * l * r;
+    tmp = fb->tmp + f0 * l * r;
+    Z = fb->Z + f0 * l * r;
+  }
+  int product(bool conjA, const zw* X, zw* Out) {
+    const zw* Ah = fb->Ah + f0 * l * m;
+    const zb* Ah16 = fb->Ah16 ? fb->Ah16 + f0 * l * m : nullptr;
+    if (bf16) return big_gemm<zb, zw, zw>(conjA, Ah16, l, m, X, r, Out, Fg, *sc, s);
+    return big_gemm<zw, zw, zw>(conjA, Ah, l, m, X, r, Out, Fg, *sc, s);
+  }
+  int run(int ph) {
+    zd* G = fb->G + f0 * r * r;
+    zd* Rinv = fb->Rinv + f0 * r * r;
+    if (ph == 0) {
+      {
+        RT_TIMED(RTSVD_T_SKETCH);
+        RT_TRY(product(false, fb->Omh + f0 * m * r, Y));
+      }
+      if (mark) RT_CHECK_HIP(hipEventRecord(mark, s));
+      return 0;
+    }
+    if (ph == 1) return orthonormalize<zw>(Y, l, r, Fg, q == 0 ? 2 : 1, G, Rinv, tmp, fb->flags, *sc, s);
+    if (ph < 2 + 4 * q) {
+      const int it = (ph - 2) / 4, k = (ph - 2) % 4;
+      if (k == 0) {
+        RT_TIMED(RTSVD_T_POWER);
+        return product(true, Y, Z);
+      }
+      if (k == 1) return orthonormalize<zw>(Z, m, r, Fg, 1, G, Rinv, tmp, fb->flags, *sc, s);
+      if (k == 2) {
+        RT_TIMED(RTSVD_T_SKETCH);
+        return product(false, Z, Y);
+      }
+      return orthonormalize<zw>(Y, l, r, Fg, it == q - 1 ? 2 : 1, G, Rinv, tmp, fb->flags, *sc, s);
+    }
+    zd* Ch = fb->Ch + f0 * m * r;
+    {
+      RT_TIMED(RTSVD_T_PROJECT);
+      const zw* Ah = fb->Ah + f0 * l * m;
+      const zb* Ah16 = fb->Ah16 ? fb->Ah16 + f0 * l * m : nullptr;
+      if (bf16) RT_TRY((big_gemm<zb, zw, zd>(true, Ah16, l, m, Y, r, Ch, Fg, *sc, s)));
+      else RT_TRY((big_gemm<zw, zw, zd>(true, Ah, l, m, Y, r, Ch, Fg, *sc, s)));
+    }
+    RT_TIMED(RTSVD_T_SVDAUX);
+    // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
+    return gram<zd>(Ch, m, r, Fg, G, *sc, s);
+  }
+};
+
+// small SVD and W for faces [f0, f0 + Fg) keeping rk <= r columns: eigendecomposition of Gsrc
+// (rk x rk per face), sigma, V = C^H U-breve diag(1/sigma), W = A-hat V.  phase: 0 eigensolver,
+// 1 sigma and V, 2 W, -1 all three.
+constexpr int SVD_PHASES = 3;
+template <typename Tw>
+static int rtsvd_faces_svd(const FaceBufs<Tw>& fb, int64_t l, int64_t m, int64_t r, int64_t rk, int64_t f0,
+                           int64_t Fg, const zd* Gsrc, Scratch& sc, hipStream_t s, int phase = -1) {
+  typedef cplx<Tw> zw;
+  const zd* Gg = Gsrc + f0 * rk * rk;
+  zd* Ub = fb.Ub + f0 * rk * rk;
+  zd* Ubs = fb.Ubs + f0 * rk * rk;
+  double* lam = fb.lam + f0 * rk;
+  double* sigma = fb.sigma + f0 * rk;
+  const zd* Ch = fb.Ch + f0 * m * r;
+  zd* V = fb.V + f0 * m * rk;
+  zw* W = fb.W + f0 * l * rk;
+  const zw* Ah = fb.Ah + f0 * l * m;
+  const double eig_tol = 4.0 * (double)r * 2.220446049250313e-16;
+  if (phase < 0 || phase == 0) {
+    RT_TIMED(RTSVD_T_HEEV);
+    RT_TRY(launch_heev(Gg, (int)rk, Fg, Ub, lam, sc, s));
+  }
+  if (phase < 0 || phase == 1) {
+    RT_TIMED(RTSVD_T_SVDAUX);
+    hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(Fg * rk)), dim3(256), 0, s, (const double*)lam, sigma, (int)rk,
+                       (int)Fg, eig_tol);
+    RT_LAUNCH_OK();
+    // V = C^H (U-breve diag(1/sigma)): the scaling goes on the r x r factor
+    hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(Fg * rk * rk)), dim3(256), 0, s, (const zd*)Ub, Ubs,
+                       (const double*)sigma, (int)rk, (int)rk, (int)Fg);
+    RT_LAUNCH_OK();
+    RT_TRY((skinny<zd, zd, zd>(false, m, rk, rk, Ch, m, m * r, Ubs, rk, rk * rk, V, m, m * rk, Fg, sc, s)));
+  }
+  // W = A-hat V: exact residuals of the discrepancy principle
+  if (phase < 0 || phase == 2) {
+    RT_TIMED(RTSVD_T_W);
+    RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, rk, W, Fg, sc, s, RTSVD_T_W_MMA)));
+  }
+  return 0;
+}
+
+// Streams (default priority) and events of the face groups, one set per device; a mutex keeps the
+// fork / join sequence of one call from interleaving with another host thread's.
+// (At most 3 groups: with the caller's stream that is the 4 hardware queues a process gets by
+// default; more streams than queues serialize.)
+constexpr int MAX_FACE_GROUPS = 3;
+struct FaceStreams {
+  std::mutex mu;
+  hipStream_t st[MAX_FACE_GROUPS] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[MAX_FACE_GROUPS] = {};
+  hipEvent_t stagger[MAX_FACE_GROUPS] = {};
+};
+
+static FaceStreams* face_streams(int groups) {
+  static std::mutex mu;
+  static std::map<int, FaceStreams*> per_dev;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || groups > MAX_FACE_GROUPS) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  FaceStreams*& fs = per_dev[dev];
+  if (!fs) {
+    FaceStreams* n = new FaceStreams();
+    bool ok = hipEventCreateWithFlags(&n->fork, hipEventDisableTiming) == hipSuccess;
+    for (int g = 0; ok && g < MAX_FACE_GROUPS; ++g)
+      ok = hipStreamCreateWithFlags(&n->st[g], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&n->join[g], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&n->stagger[g], hipEventDisableTiming) == hipSuccess;
+    if (!ok) return nullptr;   // (the partial set is kept alive: streams are never destroyed)
+    fs = n;
+  }
+  return fs;
+}
+
+// number of face groups: RTSVD_FACE_GROUPS (1..3) if set, else 3 (at least 4 faces per group;
+// measured at 65 faces: 1 group 4.36 ms, 2 groups 4.04 ms, 3 groups 3.95 ms per restoration)
+static int face_groups(int64_t F) {
+  static int env = -1;
+  if (env < 0) {
+    const char* e = std::getenv("RTSVD_FACE_GROUPS");
+    const int v = e ? std::atoi(e) : 0;
+    env = (v >= 1 && v <= MAX_FACE_GROUPS) ? v : 0;
+  }
+  const int g = env > 0 ? env : 3;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, F / 4));
+}
+
+static bool timers_on() {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  return g_timer.on;
+}
+
 // adapt_eps > 0: the fixed-precision factor of Alg. 6 (keep the first r_eps sketch columns)
 template <typename Tin, typename Tw>
 static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int64_t n, int64_t r, int precision,
@@ -476,93 +667,88 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     Ub = sc.get<zd>(F * r * r);
     if (!Ub) return fail(RTSVD_E_NOMEM, "device allocation failed: Ub");
     RT_ALLOC(Rinv, zd, F * r * r, sc);
-    RT_ALLOC(Omh, zw, F * std::max(l, m) * r, sc);
-    RT_ALLOC(Y, zw, F * std::max(l, m) * r, sc);
-    RT_ALLOC(tmp, zw, F * std::max(l, m) * r, sc);
-    RT_ALLOC(Ch, zd, F * m * r, sc);  // C^H = A-hat^H Q, m x r per face (C = Q^H A-hat)
+    RT_ALLOC(Omh, zw, F * m * r, sc);
+    RT_ALLOC(Y, zw, F * l * r, sc);     // per-face stride l*r (l >= m) in the three work buffers,
+    RT_ALLOC(tmp, zw, F * l * r, sc);   // so that face groups own disjoint regions
+    RT_ALLOC(Zb, zw, F * l * r, sc);
+    RT_ALLOC(Ch, zd, F * m * r, sc);    // C^H = A-hat^H Q, m x r per face (C = Q^H A-hat)
+    RT_ALLOC(Ubs, zd, F * r * r, sc);
     {
       RT_TIMED(RTSVD_T_FFT_OMEGA);
       RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
     }
-    // sketch Y = A-hat Omega-hat, then Q = orth(Y) (q power iterations in between)
-    {
-      RT_TIMED(RTSVD_T_SKETCH);
-      if (bf16) RT_TRY((big_gemm<zb, zw, zw>(false, Ah16, l, m, Omh, r, Y, F, sc, s)));
-      else RT_TRY((big_gemm<zw, zw, zw>(false, Ah, l, m, Omh, r, Y, F, sc, s)));
-    }
-    RT_TRY(orthonormalize<zw>(Y, l, r, F, q == 0 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
-    for (int it = 0; it < q; ++it) {
-      {
-        RT_TIMED(RTSVD_T_POWER);
-        if (bf16) RT_TRY((big_gemm<zb, zw, zw>(true, Ah16, l, m, Y, r, Omh, F, sc, s)));
-        else RT_TRY((big_gemm<zw, zw, zw>(true, Ah, l, m, Y, r, Omh, F, sc, s)));
+    FaceBufs<Tw> fb{Ah, Ah16, Omh, Y, tmp, Zb, G, Rinv, Ch, Ub, Ubs, lam, sigma, V, Wo, flags};
+    const int groups = (adapt_eps > 0.0 || timers_on()) ? 1 : face_groups(F);
+    if (groups == 1) {
+      QcGroup<Tw> qg{&fb, l, m, r, 0, F, q, bf16, &sc, s, nullptr};
+      qg.init();
+      for (int ph = 0; ph < qg.phases(); ++ph) RT_TRY(qg.run(ph));
+      Qo = qg.Y;
+    } else {
+      // the face groups run concurrently on the library's streams, joined back into s; group g
+      // starts once group g-1 has finished its first sketch, so that the groups stay out of phase
+      // (one group's sketch / power / projection / W passes over A-hat overlap the other's
+      // latency-bound Gram, Cholesky and eigensolver kernels instead of coinciding with them)
+      FaceStreams* fs = face_streams(groups);
+      if (!fs) return fail(RTSVD_E_HIP, "rtsvd_factor: creating the face-group streams failed");
+      std::lock_guard<std::mutex> lk(fs->mu);
+      RT_CHECK_HIP(hipEventRecord(fs->fork, s));
+      std::vector<std::unique_ptr<Scratch>> scg;
+      std::vector<QcGroup<Tw>> qg;
+      for (int g = 0; g < groups; ++g) {
+        const int64_t f0 = F * g / groups, Fg = F * (g + 1) / groups - f0;
+        hipStream_t sg = fs->st[g];
+        RT_CHECK_HIP(hipStreamWaitEvent(sg, fs->fork, 0));
+        scg.emplace_back(new Scratch(sg));
+        qg.push_back(QcGroup<Tw>{&fb, l, m, r, f0, Fg, q, bf16, scg.back().get(), sg, fs->stagger[g]});
+        qg.back().init();
       }
-      RT_TRY(orthonormalize<zw>(Omh, m, r, F, 1, G, Rinv, tmp, flags, sc, s));
-      {
-        RT_TIMED(RTSVD_T_SKETCH);
-        if (bf16) RT_TRY((big_gemm<zb, zw, zw>(false, Ah16, l, m, Omh, r, Y, F, sc, s)));
-        else RT_TRY((big_gemm<zw, zw, zw>(false, Ah, l, m, Omh, r, Y, F, sc, s)));
+      // issued phase by phase across the groups, so that every stream has work queued early
+      for (int ph = 0; ph < qg[0].phases() + SVD_PHASES; ++ph)
+        for (int g = 0; g < groups; ++g) {
+          if (ph == 0 && g > 0) RT_CHECK_HIP(hipStreamWaitEvent(qg[g].s, fs->stagger[g - 1], 0));
+          if (ph < qg[g].phases()) RT_TRY(qg[g].run(ph));
+          else RT_TRY((rtsvd_faces_svd<Tw>(fb, l, m, r, r, qg[g].f0, qg[g].Fg, fb.G, *scg[g], qg[g].s,
+                                           ph - qg[g].phases())));
+        }
+      for (int g = 0; g < groups; ++g) {
+        RT_CHECK_HIP(hipEventRecord(fs->join[g], qg[g].s));
+        RT_CHECK_HIP(hipStreamWaitEvent(s, fs->join[g], 0));
       }
-      RT_TRY(orthonormalize<zw>(Y, l, r, F, it == q - 1 ? 2 : 1, G, Rinv, tmp, flags, sc, s));
-    }
-    Qo = Y;
-    // projection C^H = A-hat^H Q
-    {
-      RT_TIMED(RTSVD_T_PROJECT);
-      if (bf16) RT_TRY((big_gemm<zb, zw, zd>(true, Ah16, l, m, Qo, r, Ch, F, sc, s)));
-      else RT_TRY((big_gemm<zw, zw, zd>(true, Ah, l, m, Qo, r, Ch, F, sc, s)));
+      Qo = qg[0].Y;
     }
     {
       RT_TIMED(RTSVD_T_SVDAUX);
-      // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
-      RT_TRY(gram<zd>(Ch, m, r, F, G, sc, s));
       // error indicator eta^[j] (Thm 4.2); ||C(j, :)||^2 is the real diagonal of G
       hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, (const double*)G,
                          (int64_t)2 * r * r, (int64_t)2 * (r + 1), (int)F, (int)r, (int)n, eta);
       RT_LAUNCH_OK();
     }
-    // fixed precision (Alg. 6): r_eps = first j >= 1 with eta^[j] < eps^2.  QR and the power
-    // updates are nested, so the first r_eps columns of Q (and rows of C) are what the algorithm
-    // builds from the first r_eps Gaussian columns; G's leading block is C_{r_eps} C_{r_eps}^H.
     int64_t rr = r;
-    zd* Gs = G;
-    if (adapt_eps > 0.0) {
-      std::vector<double> he((size_t)r + 1);
-      RT_CHECK_HIP(hipMemcpyAsync(he.data(), eta, sizeof(double) * (r + 1), hipMemcpyDeviceToHost, s));
-      RT_CHECK_HIP(hipStreamSynchronize(s));
-      for (int64_t j = 1; j <= r; ++j)
-        if (he[j] < adapt_eps * adapt_eps) { rr = j; break; }
-      if (rr < r) {
-        RT_ALLOC(Gk, zd, F * rr * rr, sc);
-        hipLaunchKernelGGL(k_lead_block, dim3(nblocks(F * rr * rr)), dim3(256), 0, s, (const zd*)G, (int)r, (int)rr,
-                           (int)F, Gk);
-        RT_LAUNCH_OK();
-        Gs = Gk;
-        RT_ALLOC(Qk, zw, F * l * rr, sc);
-        RT_CHECK_HIP(hipMemcpy2DAsync(Qk, sizeof(zw) * l * rr, Qo, sizeof(zw) * l * r, sizeof(zw) * l * rr, F,
-                                      hipMemcpyDeviceToDevice, s));
-        Qo = Qk;
+    if (groups == 1) {
+      // fixed precision (Alg. 6): r_eps = first j >= 1 with eta^[j] < eps^2.  QR and the power
+      // updates are nested, so the first r_eps columns of Q (and rows of C) are what the algorithm
+      // builds from the first r_eps Gaussian columns; G's leading block is C_{r_eps} C_{r_eps}^H.
+      zd* Gs = G;
+      if (adapt_eps > 0.0) {
+        std::vector<double> he((size_t)r + 1);
+        RT_CHECK_HIP(hipMemcpyAsync(he.data(), eta, sizeof(double) * (r + 1), hipMemcpyDeviceToHost, s));
+        RT_CHECK_HIP(hipStreamSynchronize(s));
+        for (int64_t j = 1; j <= r; ++j)
+          if (he[j] < adapt_eps * adapt_eps) { rr = j; break; }
+        if (rr < r) {
+          RT_ALLOC(Gk, zd, F * rr * rr, sc);
+          hipLaunchKernelGGL(k_lead_block, dim3(nblocks(F * rr * rr)), dim3(256), 0, s, (const zd*)G, (int)r, (int)rr,
+                             (int)F, Gk);
+          RT_LAUNCH_OK();
+          Gs = Gk;
+          RT_ALLOC(Qk, zw, F * l * rr, sc);
+          RT_CHECK_HIP(hipMemcpy2DAsync(Qk, sizeof(zw) * l * rr, Qo, sizeof(zw) * l * r, sizeof(zw) * l * rr, F,
+                                        hipMemcpyDeviceToDevice, s));
+          Qo = Qk;
+        }
       }
-    }
-    {
-      RT_TIMED(RTSVD_T_HEEV);
-      RT_TRY(launch_heev(Gs, (int)rr, F, Ub, lam, sc, s));
-    }
-    {
-      RT_TIMED(RTSVD_T_SVDAUX);
-      hipLaunchKernelGGL(k_sqrt_eigs, dim3(nblocks(F * rr)), dim3(256), 0, s, lam, sigma, (int)rr, (int)F, eig_tol);
-      RT_LAUNCH_OK();
-      // V = C^H (U-breve diag(1/sigma)): the scaling goes on the r x r factor
-      RT_ALLOC(Ubs, zd, F * rr * rr, sc);
-      hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(F * rr * rr)), dim3(256), 0, s, Ub, Ubs, sigma, (int)rr,
-                         (int)rr, (int)F);
-      RT_LAUNCH_OK();
-      RT_TRY((skinny<zd, zd, zd>(false, m, rr, rr, Ch, m, m * r, Ubs, rr, rr * rr, V, m, m * rr, F, sc, s)));
-    }
-    // W = A-hat V: exact residuals of the discrepancy principle
-    {
-      RT_TIMED(RTSVD_T_W);
-      RT_TRY((big_gemm<zw, zd, zw>(false, Ah, l, m, V, rr, Wo, F, sc, s, RTSVD_T_W_MMA)));
+      RT_TRY((rtsvd_faces_svd<Tw>(fb, l, m, r, rr, 0, F, Gs, sc, s)));
     }
     h->r = rr;
   } else {
