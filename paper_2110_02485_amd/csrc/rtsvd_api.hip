@@ -585,6 +585,8 @@ struct FaceStreams {
   std::mutex mu;
   hipStream_t st[MAX_FACE_GROUPS] = {};
   hipEvent_t fork = nullptr;
+  hipEvent_t start = nullptr;      // the caller's stream at entry (inputs ready)
+  hipEvent_t omega_done = nullptr; // the tube DFT of Omega, run beside that of A
   hipEvent_t join[MAX_FACE_GROUPS] = {};
   hipEvent_t stagger[MAX_FACE_GROUPS] = {};
 };
@@ -598,7 +600,9 @@ static FaceStreams* face_streams(int groups) {
   FaceStreams*& fs = per_dev[dev];
   if (!fs) {
     FaceStreams* n = new FaceStreams();
-    bool ok = hipEventCreateWithFlags(&n->fork, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&n->fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&n->start, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&n->omega_done, hipEventDisableTiming) == hipSuccess;
     for (int g = 0; ok && g < MAX_FACE_GROUPS; ++g)
       ok = hipStreamCreateWithFlags(&n->st[g], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&n->join[g], hipEventDisableTiming) == hipSuccess &&
@@ -635,6 +639,26 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
   const int64_t F = n / 2 + 1;
   const bool bf16 = (precision == RTSVD_P_BF16);
   Scratch sc(s);
+  // face groups (R-tSVD, fixed rank, no stage timers): see rtsvd_faces_qc / QcGroup
+  const int groups = (tsvd_mode || adapt_eps > 0.0 || timers_on()) ? 1 : face_groups(F);
+  FaceStreams* fs = nullptr;
+  std::unique_lock<std::mutex> fs_lock;
+  zw* Omh = nullptr;
+  if (!tsvd_mode) {
+    Omh = sc.get<zw>(F * m * r);
+    if (!Omh) return fail(RTSVD_E_NOMEM, "device allocation failed: Omh");
+  }
+  if (groups > 1) {
+    fs = face_streams(groups);
+    if (!fs) return fail(RTSVD_E_HIP, "rtsvd_factor: creating the face-group streams failed");
+    fs_lock = std::unique_lock<std::mutex>(fs->mu);
+    // the tube DFT of Omega on group 0's stream, beside that of A on the caller's stream
+    RT_CHECK_HIP(hipEventRecord(fs->start, s));
+    RT_CHECK_HIP(hipStreamWaitEvent(fs->st[0], fs->start, 0));
+    RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr,
+                                 fs->st[0])));
+    RT_CHECK_HIP(hipEventRecord(fs->omega_done, fs->st[0]));
+  }
   // tube DFT of A (half spectrum), ||A||_F^2 partial sums on the way
   RT_ALLOC(Ah, zw, F * l * m, sc);
   zb* Ah16 = nullptr;
@@ -667,18 +691,16 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     Ub = sc.get<zd>(F * r * r);
     if (!Ub) return fail(RTSVD_E_NOMEM, "device allocation failed: Ub");
     RT_ALLOC(Rinv, zd, F * r * r, sc);
-    RT_ALLOC(Omh, zw, F * m * r, sc);
     RT_ALLOC(Y, zw, F * l * r, sc);     // per-face stride l*r (l >= m) in the three work buffers,
     RT_ALLOC(tmp, zw, F * l * r, sc);   // so that face groups own disjoint regions
     RT_ALLOC(Zb, zw, F * l * r, sc);
     RT_ALLOC(Ch, zd, F * m * r, sc);    // C^H = A-hat^H Q, m x r per face (C = Q^H A-hat)
     RT_ALLOC(Ubs, zd, F * r * r, sc);
-    {
+    if (groups == 1) {
       RT_TIMED(RTSVD_T_FFT_OMEGA);
       RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
     }
     FaceBufs<Tw> fb{Ah, Ah16, Omh, Y, tmp, Zb, G, Rinv, Ch, Ub, Ubs, lam, sigma, V, Wo, flags};
-    const int groups = (adapt_eps > 0.0 || timers_on()) ? 1 : face_groups(F);
     if (groups == 1) {
       QcGroup<Tw> qg{&fb, l, m, r, 0, F, q, bf16, &sc, s, nullptr};
       qg.init();
@@ -689,9 +711,6 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
       // starts once group g-1 has finished its first sketch, so that the groups stay out of phase
       // (one group's sketch / power / projection / W passes over A-hat overlap the other's
       // latency-bound Gram, Cholesky and eigensolver kernels instead of coinciding with them)
-      FaceStreams* fs = face_streams(groups);
-      if (!fs) return fail(RTSVD_E_HIP, "rtsvd_factor: creating the face-group streams failed");
-      std::lock_guard<std::mutex> lk(fs->mu);
       RT_CHECK_HIP(hipEventRecord(fs->fork, s));
       std::vector<std::unique_ptr<Scratch>> scg;
       std::vector<QcGroup<Tw>> qg;
@@ -699,6 +718,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
         const int64_t f0 = F * g / groups, Fg = F * (g + 1) / groups - f0;
         hipStream_t sg = fs->st[g];
         RT_CHECK_HIP(hipStreamWaitEvent(sg, fs->fork, 0));
+        if (g > 0) RT_CHECK_HIP(hipStreamWaitEvent(sg, fs->omega_done, 0));
         scg.emplace_back(new Scratch(sg));
         qg.push_back(QcGroup<Tw>{&fb, l, m, r, f0, Fg, q, bf16, scg.back().get(), sg, fs->stagger[g]});
         qg.back().init();
