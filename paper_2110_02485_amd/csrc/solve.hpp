@@ -139,23 +139,28 @@ k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __r
              int F, int r, int n, double* __restrict__ eta) {
   __shared__ double red[DP_SEL_THREADS / 64];
   __shared__ double rows[HEEV_RMAX_SOLVE];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < nsumsq; i += blockDim.x) s += sumsq[i];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  s = wave_sum(s);
   if (lane == 0) red[wave] = s;
-  for (int j = wave; j < r; j += nw) {
+  // row sums over the faces: 8 lanes per row j (faces f = sub, sub + 8, ...), all loads of a lane
+  // independent, then a fixed-order 8-lane tree
+  const int sub = threadIdx.x & 7, jl = threadIdx.x >> 3, per = (int)blockDim.x >> 3;
+  for (int j0 = 0; j0 < r; j0 += per) {
+    const int j = j0 + jl;
     double t = 0.0;
-    for (int f = lane; f < F; f += 64) t += ((f == 0 || 2 * f == n) ? 1.0 : 2.0) * rn[(int64_t)f * sf + (int64_t)j * sj];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-    if (lane == 0) rows[j] = t / (double)n;
+    if (j < r)
+      for (int f = sub; f < F; f += 8) t += ((f == 0 || 2 * f == n) ? 1.0 : 2.0) * rn[(int64_t)f * sf + (int64_t)j * sj];
+    t += dpp<DPP_XOR1>(t);
+    t += dpp<DPP_XOR2>(t);
+    t += __shfl_xor(t, 4, 64);
+    if (sub == 0 && j < r) rows[j] = t / (double)n;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double e = 0.0;
-    for (int w = 0; w < nw; ++w) e += red[w];
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) e += red[w];
     eta[0] = e;
     for (int j = 0; j < r; ++j) { e -= rows[j]; eta[j + 1] = e; }
   }
