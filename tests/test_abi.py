@@ -55,3 +55,48 @@ def test_argument_errors_without_gpu():
     assert lib.tprod(None, None, None, 1, 1, 1, 1, 0, None) == rt.E_ARG
     assert lib.tprod(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 1, 1, 1, 7, None) == rt.E_ARG
     assert b"dtype" in lib.rtsvd_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librtsvd.so not built")
+def test_argument_errors_of_the_krylov_and_symmetric_entry_points():
+    # argument checks run before any device call
+    from paper_2110_02485_amd import rtsvd as rt
+    lib = rt.load()
+    p16 = ctypes.c_void_p(16)
+    k = (ctypes.c_int32 * 4)()
+    one = (ctypes.c_double * 1)(0.1)
+    two = (ctypes.c_double * 2)(0.1, 0.1)
+    neg = (ctypes.c_double * 1)(-1.0)
+    # nested_tgkb_solve(A, B, l, m, n, p, dtype, delta, n_delta, eta, k_max, k_init, X, k, resid, status, stream)
+    f = lib.nested_tgkb_solve
+    assert f(None, p16, 8, 4, 4, 1, 0, one, 1, 1.1, 2, 2, p16, k, None, None, None) == rt.E_ARG
+    assert f(p16, p16, 3, 4, 4, 1, 0, one, 1, 1.1, 2, 2, p16, k, None, None, None) == rt.E_ARG      # l < m
+    assert f(p16, p16, 8, 4, 4, 1, 0, one, 1, 1.1, 5, 2, p16, k, None, None, None) == rt.E_ARG      # k_max > m
+    assert f(p16, p16, 8, 4, 4, 1, 0, one, 1, 1.1, 2, 0, p16, k, None, None, None) == rt.E_ARG      # k_init < 1
+    assert f(p16, p16, 8, 4, 4, 1, 0, one, 1, 1.0, 2, 2, p16, k, None, None, None) == rt.E_ARG      # eta <= 1
+    assert f(p16, p16, 8, 4, 4, 3, 0, two, 2, 1.1, 2, 2, p16, k, None, None, None) == rt.E_ARG      # n_delta
+    assert f(p16, p16, 8, 4, 4, 1, 0, neg, 1, 1.1, 2, 2, p16, k, None, None, None) == rt.E_ARG      # delta < 0
+    assert f(p16, p16, 9000, 4, 4, 1, 0, one, 1, 1.1, 2, 2, p16, k, None, None, None) == rt.E_UNSUPPORTED
+    assert b"nested_tgkb_solve" in lib.rtsvd_last_error()
+    # tlanczos_solve(A, B, m, n, p, dtype, delta, n_delta, eta, k_max, X, k, resid, status, stream)
+    g = lib.tlanczos_solve
+    assert g(None, p16, 4, 4, 1, 0, one, 1, 1.1, 2, p16, k, None, None, None) == rt.E_ARG
+    assert g(p16, p16, 4, 4, 1, 0, one, 1, 1.1, 5, p16, k, None, None, None) == rt.E_ARG         # k_max > m
+    assert g(p16, p16, 4, 4, 1, 9, one, 1, 1.1, 2, p16, k, None, None, None) == rt.E_ARG         # dtype
+    assert g(p16, p16, 9000, 4, 1, 0, one, 1, 1.1, 2, p16, k, None, None, None) == rt.E_UNSUPPORTED
+    # ttevd_factor(A, m, n, dtype, precision, k_max, stream, out)
+    h = ctypes.c_void_p()
+    t = lib.ttevd_factor
+    assert t(None, 4, 4, 0, 0, 2, None, ctypes.byref(h)) == rt.E_ARG
+    assert t(p16, 4, 4, 0, 2, 2, None, ctypes.byref(h)) == rt.E_ARG                               # bf16
+    assert t(p16, 4, 4, 0, 0, 5, None, ctypes.byref(h)) == rt.E_ARG                               # k_max > m
+    assert t(p16, 300, 4, 0, 0, 5, None, ctypes.byref(h)) == rt.E_UNSUPPORTED                     # m > 256
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=60)
+    assert out.returncode == 2
+    assert "one GPU" in out.stdout

@@ -326,6 +326,34 @@ def test_tlanczos_indefinite_slices_ragged():
         np.testing.assert_allclose(_np(resid)[j, :kj], orc["res"][:kj, j], rtol=1e-9)
 
 
+@pytest.mark.parametrize("n", [1, 2])
+def test_krylov_and_symmetric_methods_one_and_two_faces(n):
+    # tubes of length 1 and 2 (one and two Fourier faces, both weighted 1): nested_tGKB_p,
+    # t-Lanczos_p and T-tEVD against the oracle, every slice run to k = m (tiny bounds)
+    import torch
+    from oracle import tgkb as tg, symmetric as sy
+    from paper_2110_02485_amd import rtsvd as rt
+    rng = np.random.default_rng(40 + n)
+    A = rng.standard_normal((n, 5, 7))
+    B = rng.standard_normal((n, 2, 7))
+    orc = tg.nested_tgkb_restore(wl.to_math(A), wl.to_math(B), 1e-13, 1.01, 5)
+    Xg, k, resid, status = _gpu_nested(A, B, 1e-13, 1.01, 5, "float64")
+    _check_nested(orc, Xg, k, resid, status, 1e-9)
+    As = _sym_storage(6, n, 50 + n, shift=3.0)
+    Bs = rng.standard_normal((n, 2, 6))
+    orc = sy.tlanczos_restore(wl.to_math(As), wl.to_math(Bs), 1e-13, 1.01, 6)
+    Xg, k, resid, status = _gpu_tlanczos(As, Bs, 1e-13, 1.01, 6, "float64")
+    assert [int(v) for v in k.cpu()] == orc["k"]
+    assert _rel(_np(Xg), wl.to_storage(orc["X"])) <= 1e-9
+    delta = 0.3 * float(np.linalg.norm(Bs))
+    orc = sy.tevd_restore(wl.to_math(As), wl.to_math(Bs), delta, 1.01, 6)
+    f = rt.ttevd_factor(_t(As), 6, "fp64")
+    res = f.solve(_t(Bs), delta, 1.01, 1)
+    torch.cuda.synchronize()
+    assert int(res.k[0]) == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-10
+
+
 # ---------------------------------------------------------------------------------------------
 # tGKB baseline
 # ---------------------------------------------------------------------------------------------
