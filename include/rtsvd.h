@@ -71,6 +71,11 @@ typedef struct {
                         /* with k_start = 0 searches k from r_eps - oversample (the experiments' */
                         /* rule, Section 5).  The nested sketch makes this the factor Alg. 6    */
                         /* builds column by column.  Costs one host synchronization.            */
+  int32_t face_groups;  /* 0: automatic (3 groups, fewer below 12 faces; the environment        */
+                        /* variable RTSVD_FACE_GROUPS = 1..3 overrides); 1..3: split the per-face */
+                        /* work into that many groups on library streams (see rtsvd_factor).     */
+                        /* The result does not depend on it (bit for bit); adaptive factors and  */
+                        /* runs with the stage timers enabled use one group.                     */
 } rtsvd_opts;
 
 /* R-tSVD factorization (Section 4.2, Alg. 6 in block form, Thms 4.1-4.2).

@@ -613,16 +613,17 @@ static FaceStreams* face_streams(int groups) {
   return fs;
 }
 
-// number of face groups: RTSVD_FACE_GROUPS (1..3) if set, else 3 (at least 4 faces per group;
-// measured at 65 faces: 1 group 4.36 ms, 2 groups 4.04 ms, 3 groups 3.95 ms per restoration)
-static int face_groups(int64_t F) {
+// number of face groups: `requested` (1..3) if given, else RTSVD_FACE_GROUPS (1..3) if set, else 3
+// (at least 4 faces per group; measured at 65 faces: 1 group 4.36 ms, 2 groups 4.04 ms, 3 groups
+// 3.95 ms per restoration)
+static int face_groups(int64_t F, int requested) {
   static int env = -1;
   if (env < 0) {
     const char* e = std::getenv("RTSVD_FACE_GROUPS");
     const int v = e ? std::atoi(e) : 0;
     env = (v >= 1 && v <= MAX_FACE_GROUPS) ? v : 0;
   }
-  const int g = env > 0 ? env : 3;
+  const int g = requested > 0 ? requested : (env > 0 ? env : 3);
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, F / 4));
 }
 
@@ -634,13 +635,14 @@ static bool timers_on() {
 // adapt_eps > 0: the fixed-precision factor of Alg. 6 (keep the first r_eps sketch columns)
 template <typename Tin, typename Tw>
 static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int64_t n, int64_t r, int precision,
-                       int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd_mode, double adapt_eps = 0.0) {
+                       int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd_mode, double adapt_eps = 0.0,
+                       int groups_req = 0) {
   typedef cplx<Tw> zw;
   const int64_t F = n / 2 + 1;
   const bool bf16 = (precision == RTSVD_P_BF16);
   Scratch sc(s);
   // face groups (R-tSVD, fixed rank, no stage timers): see rtsvd_faces_qc / QcGroup
-  const int groups = (tsvd_mode || adapt_eps > 0.0 || timers_on()) ? 1 : face_groups(F);
+  const int groups = (tsvd_mode || adapt_eps > 0.0 || timers_on()) ? 1 : face_groups(F, groups_req);
   FaceStreams* fs = nullptr;
   std::unique_lock<std::mutex> fs_lock;
   zw* Omh = nullptr;
@@ -806,17 +808,20 @@ static void free_handle(rtsvd_factor_s* h) {
 }
 
 static int dispatch_factor(const void* A, const void* omega, int dtype, int64_t l, int64_t m, int64_t n, int64_t r,
-                           int precision, int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd, double ae = 0.0) {
+                           int precision, int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd, double ae = 0.0,
+                           int groups = 0) {
   if (dtype == RTSVD_F64) {
     if (work_is_double(precision))
       return factor_impl<double, double>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd,
-                                         ae);
+                                         ae, groups);
     return factor_impl<double, float>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd,
-                                      ae);
+                                      ae, groups);
   }
   if (work_is_double(precision))
-    return factor_impl<float, double>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd, ae);
-  return factor_impl<float, float>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd, ae);
+    return factor_impl<float, double>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd, ae,
+                                      groups);
+  return factor_impl<float, float>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd, ae,
+                                     groups);
 }
 
 extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype, const rtsvd_opts* opts,
@@ -831,6 +836,8 @@ extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int 
     return fail(RTSVD_E_ARG, "rtsvd_factor: need 1 <= k_max <= m, oversample >= 0, power_iters >= 0");
   if (o.precision != RTSVD_P_FP64 && o.precision != RTSVD_P_FP32 && o.precision != RTSVD_P_BF16)
     return fail(RTSVD_E_ARG, "rtsvd_factor: bad precision");
+  if (o.face_groups < 0 || o.face_groups > MAX_FACE_GROUPS)
+    return fail(RTSVD_E_ARG, "rtsvd_factor: face_groups must be 0..3");
   const int64_t r = std::min<int64_t>((int64_t)o.k_max + o.oversample, m);
   if (r > 256) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_factor: r = min(k_max + oversample, m) must be <= 256");
   if (!o.omega) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_factor: omega must be supplied");
@@ -839,7 +846,8 @@ extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int 
   h->l = l; h->m = m; h->n = n; h->F = n / 2 + 1; h->r = r; h->dtype = dtype; h->precision = o.precision;
   h->kind = 0; h->k_max = o.k_max; h->oversample = o.oversample; h->eps = o.eps; h->stream = s;
   const double ae = (o.adaptive && o.eps > 0.0) ? o.eps : 0.0;
-  const int rc = dispatch_factor(A, o.omega, dtype, l, m, n, r, o.precision, o.power_iters, h, s, false, ae);
+  const int rc = dispatch_factor(A, o.omega, dtype, l, m, n, r, o.precision, o.power_iters, h, s, false, ae,
+                                 o.face_groups);
   if (rc != 0) { delete h; return rc; }
   *out = h;
   return RTSVD_OK;

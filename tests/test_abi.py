@@ -52,6 +52,9 @@ def test_argument_errors_without_gpu():
     assert lib.rtsvd_factor(ctypes.c_void_p(16), 8, 4, 4, 0, ctypes.byref(bad), None, ctypes.byref(h)) == rt.E_ARG
     big = rt._Opts(300, 10, 0, 0, 0, ctypes.c_void_p(16), 0.0)
     assert lib.rtsvd_factor(ctypes.c_void_p(16), 400, 400, 4, 0, ctypes.byref(big), None, ctypes.byref(h)) == rt.E_UNSUPPORTED
+    grp = rt._Opts(5, 2, 0, 0, 0, ctypes.c_void_p(16), 0.0, 0, 4)
+    assert lib.rtsvd_factor(ctypes.c_void_p(16), 8, 8, 4, 0, ctypes.byref(grp), None, ctypes.byref(h)) == rt.E_ARG
+    assert b"face_groups" in lib.rtsvd_last_error()
     assert lib.tprod(None, None, None, 1, 1, 1, 1, 0, None) == rt.E_ARG
     assert lib.tprod(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 1, 1, 1, 7, None) == rt.E_ARG
     assert b"dtype" in lib.rtsvd_last_error()

@@ -222,6 +222,29 @@ def test_ttsvd_fp32_256():
     assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-5
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_face_groups_give_identical_factors(precision):
+    # the per-face work split into 1, 2 or 3 concurrently issued face groups: every per-face
+    # computation is the same, so factor and solution agree bit for bit
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    A, X, B, Om, delta = blur_problem(128, 32, 2.0, 8, 1, 1e-2, 20, 10, seed=61)
+    dt = "float64" if precision == "fp64" else "float32"
+    At, Bt, Omt = _t(A, dt), _t(B, dt), _t(Om, dt)
+    outs = []
+    for g in (1, 2, 3):
+        f = rt.factor(At, 20, 10, 1, precision, Omt, face_groups=g)
+        res = f.solve(Bt, delta, 1.01, 1)
+        torch.cuda.synchronize()
+        info = f.info()
+        outs.append((_np(res.X), int(res.k[0]), info[2], info[4]))
+        f.close()
+    for X_, k_, eta_, sig_ in outs[1:]:
+        assert k_ == outs[0][1]
+        assert np.array_equal(X_, outs[0][0])
+        assert np.array_equal(eta_, outs[0][2]) and np.array_equal(sig_, outs[0][3])
+
+
 # ---------------------------------------------------------------------------------------------
 # symmetric A: T-tEVD and t-Lanczos_p
 # ---------------------------------------------------------------------------------------------
