@@ -8,7 +8,10 @@
 // step of 16 rows, lane (i, q) (i = lane % 16, q = lane / 16) holds rows 4q .. 4q+3 of columns
 // 16 I + i and 16 J + i.  The 4 MFMA k-steps use the row permutation k = 4 q + s on both sides,
 // which leaves the sum unchanged and makes every lane's reads 4 consecutive elements.
-// Complex: Re G += Ar Br + Ai Bi, Im G += Ar Bi - Ai Br with A = Y(:, I-tile), B = Y(:, J-tile).
+// Complex, with A = Y(:, I-tile), B = Y(:, J-tile): three real products per step,
+//     P1 = Ar Br, P2 = Ai Bi, P3 = (Ar - Ai)(Br + Bi),  Re G = P1 + P2,  Im G = P3 - P1 + P2
+// (= Ar Bi - Ai Br).  For FP32 panels every product is exact in FP64; the absolute error of the
+// imaginary part stays at the level of the four-product form (a few units of u ||A|| ||B||).
 #pragma once
 #include "common.hpp"
 
@@ -37,9 +40,9 @@ k_gram_lower(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY,
   const TY* __restrict__ yb = Y + (int64_t)f * sY + (int64_t)(okb ? cb : 0) * ldy;
   const int share = (rows + 16 * GRAM_WAVES - 1) / (16 * GRAM_WAVES) * 16;   // rows per wave, a multiple of 16
   const int k0 = w * share, k1 = min(rows, k0 + share);
-  // four independent accumulators (Re: ArBr, AiBi; Im: ArBi, -AiBr) so that consecutive MFMAs
-  // never wait on each other's results
-  gr_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+  // three independent accumulators (P1, P2, P3) so that consecutive MFMAs never wait on each
+  // other's results
+  gr_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0;
   // unconditional loads at clamped rows (in bounds), masked afterwards; the next 16 rows are
   // loaded while the current ones are multiplied
   TY ra[4], rb[4];
@@ -66,11 +69,10 @@ k_gram_lower(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY,
     for (int s = 0; s < 4; ++s) {
       acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].re, bv[s].re, acc0, 0, 0, 0);
       acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].im, bv[s].im, acc1, 0, 0, 0);
-      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].re, bv[s].im, acc2, 0, 0, 0);
-      acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[s].im, bv[s].re, acc3, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].re - a[s].im, bv[s].re + bv[s].im, acc2, 0, 0, 0);
     }
   }
-  gr_f64x4 accr = acc0 + acc1, acci = acc2 + acc3;
+  gr_f64x4 accr = acc0 + acc1, acci = acc2 - acc0 + acc1;
   if (w > 0) {
     red[w - 1][0][lane] = accr;
     red[w - 1][1][lane] = acci;
@@ -144,9 +146,10 @@ k_gram_slab(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY, 
     ti[u] = p < P ? I : -1;
     tj[u] = p - I * (I + 1) / 2;
   }
-  gr_f64x4 accr[GS_TPW], acci[GS_TPW];
+  // per tile the three real products of k_gram_lower: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar - Ai)(Br + Bi)
+  gr_f64x4 ap1[GS_TPW], ap2[GS_TPW], ap3[GS_TPW];
 #pragma unroll
-  for (int u = 0; u < GS_TPW; ++u) { accr[u] = (gr_f64x4){0.0, 0.0, 0.0, 0.0}; acci[u] = accr[u]; }
+  for (int u = 0; u < GS_TPW; ++u) { ap1[u] = (gr_f64x4){0.0, 0.0, 0.0, 0.0}; ap2[u] = ap1[u]; ap3[u] = ap1[u]; }
   int buf = 0;
   if (k0 < k1) { gload(k0); lstore(0, k0); }
   __syncthreads();
@@ -157,18 +160,18 @@ k_gram_slab(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY, 
     for (int u = 0; u < GS_TPW; ++u) {
       if (ti[u] < 0) continue;                  // uniform per wave
       const int ca = 16 * ti[u] + li, cb = 16 * tj[u] + li;
-      gr_f64x4 c0 = accr[u], c1 = acci[u];
+      gr_f64x4 c1 = ap1[u], c2 = ap2[u], c3 = ap3[u];
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
         const zd a = slab[buf][4 * lq + s2][ca];
         const zd b = slab[buf][4 * lq + s2][cb];
-        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, c1, 0, 0, 0);
-        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.im, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.re, c1, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, c1, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.im, c2, 0, 0, 0);
+        c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re - a.im, b.re + b.im, c3, 0, 0, 0);
       }
-      accr[u] = c0;
-      acci[u] = c1;
+      ap1[u] = c1;
+      ap2[u] = c2;
+      ap3[u] = c3;
     }
     if (more) lstore(buf ^ 1, kb + 16);
     __syncthreads();
@@ -182,7 +185,7 @@ k_gram_slab(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY, 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * ti[u] + lq + 4 * v;
-      if (row < r && col < r) pp[row + (int64_t)col * r] = mk(accr[u][v], acci[u][v]);
+      if (row < r && col < r) pp[row + (int64_t)col * r] = mk(ap1[u][v] + ap2[u][v], ap3[u][v] - ap1[u][v] + ap2[u][v]);
     }
   }
 }
