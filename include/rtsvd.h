@@ -85,8 +85,12 @@ typedef struct {
  * W_i = A-hat_i V_i (used for the exact discrepancy residual).  The factor does not depend on B
  * (Section 5), so one handle serves any number of rtsvd_solve calls.  The handle owns its
  * device buffers until rtsvd_factor_destroy; A may be freed after the stream reaches the end of
- * this call.  Errors: RTSVD_E_ARG (l < m, n < 1, k_max < 1, k_max > m, oversample < 0,
- * power_iters < 0, bad precision, null A/opts/out), RTSVD_E_UNSUPPORTED (r > 256).
+ * this call.  The per-face work may be issued on up to three streams of the library's own
+ * (default priority, see rtsvd_opts.face_groups), forked from and joined back into `stream`
+ * with events: all of the call's work is complete when `stream` reaches the end of the call.
+ * Errors: RTSVD_E_ARG (l < m, n < 1, k_max < 1, k_max > m, oversample < 0,
+ * power_iters < 0, bad precision, face_groups outside 0..3, null A/opts/out),
+ * RTSVD_E_UNSUPPORTED (r > 256), RTSVD_E_HIP (the library's streams could not be created).
  * Warning RTSVD_W_RANK_DEFICIENT is reported later by rtsvd_factor_info.                      */
 int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype,
                  const rtsvd_opts* opts, void* stream, rtsvd_handle* out);
@@ -157,8 +161,10 @@ int tprod_adjoint(const void* A, const void* C, void* B, int64_t l, int64_t m, i
  * A: DEVICE l x m x n; B: DEVICE l x p x n; X: DEVICE m x p x n (dtype; computed in dtype,
  * sums in FP64).  delta: HOST, n_delta = 1 (same bound for every slice) or p.
  * k_out: DEVICE int32[p]; resid_out: DEVICE double[k_max * p] or NULL (resid_out[j*k_max+k-1]);
- * status_out: DEVICE int32[1] or NULL.  Synchronizes the stream once per iteration block to
- * test the stopping rule.                                                                    */
+ * status_out: DEVICE int32[1] or NULL.  The stream is never synchronized: after every step the
+ * device posts its progress to pinned host memory, and the calling thread (which waits on that
+ * progress) keeps at most three steps in flight; the call returns once every slice is decided or
+ * k_max steps are enqueued, with the rest of the work queued on the stream.                  */
 int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p,
                int dtype, const double* delta, int32_t n_delta, double eta_dp, int32_t k_max,
                void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
@@ -175,8 +181,8 @@ int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, in
  * sums and the projected problems in FP64).  delta: HOST, n_delta = 1 or p.  k_init >= 1 (taken
  * as min(k_init, k_max)).  k_out: DEVICE int32[p]; resid_out: DEVICE double[k_max * p] or NULL:
  * resid_out[j*k_max + k-1] is slice j's projected residual at k for every k the basis reached
- * (0 beyond it).  status_out: DEVICE int32[1] or NULL.  Synchronizes the stream once per two
- * steps to test whether every slice has been decided.
+ * (0 beyond it).  status_out: DEVICE int32[1] or NULL.  Step loop as in tgkb_solve (no stream
+ * synchronization, at most three steps in flight).
  * Errors: RTSVD_E_ARG (sizes, l < m, k_max outside [1, m], eta_dp <= 1, negative delta),
  * RTSVD_E_UNSUPPORTED (l > 8192).                                                             */
 int nested_tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p,
@@ -205,7 +211,8 @@ int ttevd_factor(const void* A, int64_t m, int64_t n, int dtype, int32_t precisi
  * FP64).  delta: HOST, n_delta = 1 or p.  k_out: DEVICE int32[p]; resid_out: DEVICE
  * double[k_max * p] or NULL (resid_out[j*k_max + k-1], 0 beyond the last step run); status_out:
  * DEVICE int32[1] or NULL (RTSVD_W_DP_NOT_MET when a slice reached k_max without meeting the
- * principle; it then takes k_max).  Errors: RTSVD_E_ARG, RTSVD_E_UNSUPPORTED (m > 8192).       */
+ * principle; it then takes k_max).  Step loop as in tgkb_solve.  Errors: RTSVD_E_ARG,
+ * RTSVD_E_UNSUPPORTED (m > 8192).                                                             */
 int tlanczos_solve(const void* A, const void* B, int64_t m, int64_t n, int64_t p, int dtype,
                    const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, void* X,
                    int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
