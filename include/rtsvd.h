@@ -139,6 +139,10 @@ int rtsvd_trim(void);
  * k_out:     DEVICE int32[n_delta]: chosen k (k_cap when the principle is not met).
  * resid_out: DEVICE double[n_delta * k_cap] or NULL: resid_out[g*k_cap + k-1] = ||B_g - A*X_k||_F.
  * status_out: DEVICE int32[1] or NULL: RTSVD_OK or RTSVD_W_DP_NOT_MET (set on the device).
+ * The call only launches kernels on `stream` (no synchronization, no host copies, outputs stay
+ * on the device), so it can be captured in a HIP graph and replayed for new contents of the same
+ * B buffer: make one call on the capturing stream first (its workspace comes from that stream's
+ * cache, so the captured call allocates nothing), keep the handle alive while the graph is used.
  * Errors: RTSVD_E_ARG (null handle/B/X/delta/k_out, p < 1, n_delta not 1 or p, eta_dp <= 1,
  *         k_start < 0 or > k_max, dtype mismatch with the factor's caller dtype).             */
 int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype,

@@ -245,6 +245,52 @@ def test_face_groups_give_identical_factors(precision):
         assert np.array_equal(eta_, outs[0][2]) and np.array_equal(sig_, outs[0][3])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_captured_in_a_graph_replays_like_eager(precision):
+    # rtsvd_solve keeps k, residuals and status on the device and launches kernels only, so after a
+    # warm-up on the capturing stream (the workspace cache is per stream) it can be captured once and
+    # replayed for new data in the same input buffer; every replay equals an eager solve bit for bit
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    A, X, B, Om, delta = blur_problem(64, 16, 2.0, 6, 2, 1e-2, 20, 10, seed=71, video=True)
+    dt = "float64" if precision == "fp64" else "float32"
+    f = rt.factor(_t(A, dt), 20, 10, 1, precision, _t(Om, dt))
+    rng = np.random.default_rng(72)
+    inputs = [B + 0.01 * np.abs(B).max() * rng.standard_normal(B.shape) for _ in range(3)]
+    deltas = [0.02 * float(np.linalg.norm(B[:, j])) for j in range(2)]
+    eager = []
+    for Bi in inputs:
+        r = f.solve(_t(Bi, dt), deltas, 1.01, 1)
+        torch.cuda.synchronize()
+        eager.append((_np(r.X), r.k.cpu().numpy().copy(), _np(r.resid), int(r.status[0])))
+    s = torch.cuda.Stream()
+    Bbuf = _t(inputs[0], dt).clone()
+    with torch.cuda.stream(s):
+        out = f.solve(Bbuf, deltas, 1.01, 1)
+        f.solve(Bbuf, deltas, 1.01, 1, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        f.solve(Bbuf, deltas, 1.01, 1, out=out)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for i, Bi in enumerate(inputs):
+            Bbuf.copy_(_t(Bi, dt))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            Xe, ke, re, se = eager[i]
+            assert np.array_equal(out.k.cpu().numpy(), ke), (rep, i)
+            assert int(out.status[0]) == se
+            assert np.array_equal(_np(out.X), Xe), (rep, i)
+            assert np.array_equal(_np(out.resid), re), (rep, i)
+            # eager work between replays
+            r = f.solve(_t(inputs[(i + 1) % 3], dt), deltas, 1.01, 1)
+            torch.cuda.synchronize()
+            assert np.array_equal(_np(r.X), eager[(i + 1) % 3][0])
+    f.close()
+
+
 # ---------------------------------------------------------------------------------------------
 # symmetric A: T-tEVD and t-Lanczos_p
 # ---------------------------------------------------------------------------------------------
