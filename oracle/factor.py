@@ -126,6 +126,25 @@ def qr_positive(y: np.ndarray):
     return q, rr
 
 
+def rtsvd_face(A_i: np.ndarray, O_i: np.ndarray, power_iters: int = 0) -> dict:
+    """The block R-tSVD of one Fourier face (the per-face body of rtsvd_block): Q = orth(A_i O_i)
+    refined by q power steps, C = Q^H A_i = U-breve diag(s) V^H.  Returns Q, C, Ub, s, Vh."""
+    q, _ = qr_positive(A_i @ O_i)
+    for _ in range(power_iters):
+        qz, _ = qr_positive(A_i.conj().T @ q)
+        q, _ = qr_positive(A_i @ qz)
+    c = q.conj().T @ A_i
+    u, sv, vh = np.linalg.svd(c, full_matrices=False)
+    return {"Q": q, "C": c, "Ub": u, "s": sv, "Vh": vh}
+
+
+def solution_face(fc: dict, b_i: np.ndarray, k: int) -> np.ndarray:
+    """Face i of the truncated solution X_k = V_k * S_k^{-1} * U_k^T * B (Section 4.2) from one
+    face's factor: V[:, :k] diag(1/s[:k]) U-breve[:, :k]^H Q^H b_i (b_i: l x p)."""
+    t = (fc["Ub"][:, :k].conj().T @ (fc["Q"].conj().T @ b_i)) / fc["s"][:k][:, None]
+    return fc["Vh"][:k, :].conj().T @ t
+
+
 def rtsvd_block(a: np.ndarray, omega: np.ndarray, power_iters: int = 0):
     """Fixed-r R-tSVD, all r Gaussian columns at once, in the Fourier domain.
 
@@ -153,12 +172,8 @@ def rtsvd_block(a: np.ndarray, omega: np.ndarray, power_iters: int = 0):
         A_i, O_i = ah[:, :, i], oh[:, :, i]
         if i == (n - i) % n:  # faces 0 and n/2 of real data are real
             A_i, O_i = A_i.real, O_i.real
-        q, _ = qr_positive(A_i @ O_i)
-        for _ in range(power_iters):
-            qz, _ = qr_positive(A_i.conj().T @ q)
-            q, _ = qr_positive(A_i @ qz)
-        c = q.conj().T @ A_i
-        u, sv, vh = np.linalg.svd(c, full_matrices=False)
+        fc = rtsvd_face(A_i, O_i, power_iters)
+        q, c, u, sv, vh = fc["Q"], fc["C"], fc["Ub"], fc["s"], fc["Vh"]
         for face, conj in ((i, False), ((n - i) % n, True)):
             Q[:, :, face] = np.conj(q) if conj else q
             C[:, :, face] = np.conj(c) if conj else c

@@ -27,6 +27,14 @@ def facewise(ah: np.ndarray, bh: np.ndarray) -> np.ndarray:
     return np.einsum("ijt,jkt->ikt", ah, bh)
 
 
+def dft_face(a: np.ndarray, i: int) -> np.ndarray:
+    """Face i of the tube DFT by its definition, A-hat_i = sum_t A(:, :, t) exp(-2 pi i i t / n)
+    (Section 2), without transforming the other faces."""
+    n = a.shape[2]
+    w = np.exp(-2j * np.pi * i * np.arange(n) / n)
+    return np.tensordot(a, w, axes=([2], [0]))
+
+
 def tprod(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     """t-product A * B via the DFT (Definition 2.1 computed as in Section 2)."""
     assert a.shape[1] == b.shape[0] and a.shape[2] == b.shape[2]

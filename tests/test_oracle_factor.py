@@ -230,3 +230,27 @@ def test_expected_error_bound_statistical():
     # Eckart-Young (Thm 2.1): no sketch of r = k + rho columns beats the best tubal rank-r error
     tail_r = np.sum(ts["s"][k + rho:] ** 2) / n
     assert min(errs) >= tail_r * (1 - 1e-10)
+
+
+@pytest.mark.parametrize("power_iters", [0, 1])
+def test_per_face_factor_and_solution_match_the_block_form(power_iters):
+    # rtsvd_face on a face from dft_face (the DFT by definition) reproduces rtsvd_block's face,
+    # and solution_face reproduces that face of the truncated solution
+    from oracle import solve as so
+    rng = np.random.default_rng(81)
+    a = rng.standard_normal((9, 7, 6))
+    om = rng.standard_normal((7, 5, 6))
+    b = rng.standard_normal((9, 2, 6))
+    f = fa.rtsvd_block(a, om, power_iters)
+    T = so.coefficients_rtsvd(f, b)
+    for i in (0, 1, 3):
+        A_i, O_i = tp.dft_face(a, i), tp.dft_face(om, i)
+        np.testing.assert_allclose(A_i, tp.fft_tubes(a)[:, :, i], atol=1e-12)
+        if i in (0, 3):
+            A_i, O_i = A_i.real, O_i.real
+        fc = fa.rtsvd_face(A_i, O_i, power_iters)
+        np.testing.assert_allclose(fc["s"], f["s"][:, i], rtol=1e-12)
+        np.testing.assert_allclose(np.abs(fc["Q"].conj().T @ f["Q"][:, :, i]), np.eye(5), atol=1e-10)
+        for k in (1, 3, 5):
+            ref = np.einsum("ij,jk->ik", f["V"][:, :k, i], T[:k, :, i])
+            np.testing.assert_allclose(fa.solution_face(fc, tp.dft_face(b, i), k), ref, atol=1e-10)
