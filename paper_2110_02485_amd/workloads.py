@@ -208,7 +208,9 @@ WORKLOADS = {
     "blur256": Workload("blur256", 256, 256, 3.0, 10, 1, 60, 10, 0, 1e-3, precision="fp32", squares=3),
     "video512": Workload("video512", 512, 64, 3.0, 10, 64, 80, 10, 0, 1e-2, precision="fp32", video=True),
     "blur1024": Workload("blur1024", 1024, 128, 3.0, 10, 1, 100, 20, 1, 1e-3, precision="mixed"),
-    "diff512": Workload("diff512", 512, 64, 3.0, 10, 0, 80, 10, 0, 1e-2, precision="fp32", video=True),
+    # differentiable batch: 16 clips of uneven frame counts (4 to 32) restored in one call
+    "diff512": Workload("diff512", 512, 64, 3.0, 10, 260, 80, 10, 0, 1e-2, precision="fp32", video=True,
+                        problems=[4, 32, 9, 17, 6, 25, 12, 30, 5, 20, 14, 28, 8, 11, 23, 16]),
     # colour-image restoration of Section 5 (256 x 256 x 256 blur with band 12, sigma 3; three
     # channels as lateral slices): the Krylov comparison (tGKB_p, nested_tGKB_p)
     "rgb256": Workload("rgb256", 256, 256, 3.0, 12, 3, 60, 10, 0, 1e-3, precision="fp64", video=True),
@@ -236,3 +238,23 @@ def make_inputs(w: Workload, dtype=np.float64, seed_extra: int = 0):
     E0 = noise_direction((w.n, X.shape[1], w.size), rng_for(w.name, "noise", seed_extra))
     Om = gaussian_omega(w.size, w.r, w.n, rng_for(w.name, "omega", seed_extra))
     return A.astype(dtype), X.astype(dtype), E0, Om.astype(dtype)
+
+
+def make_clip_inputs(w: Workload, dtype=np.float64):
+    """Draw the differentiable batch of ``w``: (A, dA/dsigma, X_true, E0 per clip, Omega, offsets).
+
+    Clip j is a moving-blob sequence of ``w.problems[j]`` frames from its own seeded stream; the
+    clips sit side by side as lateral slices of X_true, clip j in slices offsets[j]:offsets[j+1].
+    E0 is a list of per-clip noise directions (each clip is scaled to the relative level by the
+    caller, who forms B with the t-product of their choice).
+    """
+    A = blur_operator(w.size, w.n, w.sigma, w.band, dtype=np.float64)
+    dA = blur_operator_dsigma(w.size, w.n, w.sigma, w.band)
+    clips, E0 = [], []
+    for j, frames in enumerate(w.problems):
+        clips.append(lateral_slices(moving_blob_video(w.size, w.n, frames, rng_for(w.name, "xtrue", j))))
+        E0.append(noise_direction((w.n, frames, w.size), rng_for(w.name, "noise", j)))
+    X = np.concatenate(clips, axis=1)
+    offsets = np.concatenate([[0], np.cumsum(w.problems)]).astype(int)
+    Om = gaussian_omega(w.size, w.r, w.n, rng_for(w.name, "omega"))
+    return A.astype(dtype), dA.astype(dtype), X.astype(dtype), E0, Om.astype(dtype), offsets

@@ -92,3 +92,63 @@ def test_fullsize_video512_fp32():
 def test_fullsize_blur1024_mixed():
     # the benchmark's restoration: 1024 x 1024 x 128 (65 faces), r = 100 + 20, q = 1, BF16 sketch
     _full_case("blur1024", "mixed", 2e-3)
+
+
+def _diff_batch():
+    from oracle import adjoint as ad
+    w = wl.WORKLOADS["diff512"]
+    A, dA, X, E0, Om, off = wl.make_clip_inputs(w)
+    Am, Xm = wl.to_math(A), wl.to_math(X)
+    Bt = tp.tprod(Am, Xm)
+    Bm = Bt.copy()
+    for j in range(len(w.problems)):
+        sl = slice(off[j], off[j + 1])
+        Bm[:, sl, :] += wl.scale_noise(wl.to_math(E0[j]), Bt[:, sl, :], w.noise)
+    loss, gb, gs = ad.grads(Am, wl.to_math(dA), Bm, wl.to_math(Om), w.k_max, Xm)
+    return w, A, dA, X, wl.to_storage(Bm), Om, off, (loss, wl.to_storage(gb), gs)
+
+
+def test_fullsize_diff512_adjoint_fp32():
+    # 512 x 512 x 64 (33 faces), 16 clips of 4 to 32 frames (260 lateral slices) in one batched
+    # FP32 restoration at the fixed k = 80 (rho = 10); the backward pass recomputes the factor.
+    # Against the FP64 oracle gradient over every element: L, dL/dB, dL/dsigma.  Then, from the
+    # GPU path alone: each clip's dL/dB from a call with that clip by itself equals its part of the
+    # batched one (slices are independent), and dL/dsigma matches a central difference with
+    # h = 1e-3 of the GPU forward.
+    import torch
+    from paper_2110_02485_amd import autograd as ag
+    w, A, dA, X, B, Om, off, (loss, gb, gs) = _diff_batch()
+    dev = torch.device("cuda:0")
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
+    At, dAt, Omt, Xt = f32(A), f32(dA), f32(Om), f32(X).double()
+
+    def run(sl, sigma=w.sigma, Aop=At, grad=True):
+        Bg = f32(B[:, sl, :]).requires_grad_(grad)
+        s = torch.tensor(sigma, dtype=torch.float32, device=dev, requires_grad=grad)
+        Xg = ag.restore(Bg, s, Aop, dAt if grad else None, Omt, w.k_max, w.oversample)
+        L = 0.5 * ((Xg.double() - Xt[:, sl, :]) ** 2).sum()
+        if grad:
+            L.backward()
+        torch.cuda.synchronize()
+        return float(L.detach()), (Bg.grad.double().cpu().numpy() if grad else None), (float(s.grad) if grad else None)
+
+    L, gB, gS = run(slice(None))
+    l_err, b_err, s_err = abs(L - loss) / loss, _rel(gB, gb), abs(gS - gs) / abs(gs)
+    print(f"[diff512] {off[-1]} slices: L rel {l_err:.2e}, dL/dB rel {b_err:.2e}, dL/dsigma rel {s_err:.2e} "
+          f"({gS:.6e} vs {gs:.6e})")
+    c_errs = []
+    for j in (0, 1):                                 # the shortest (4 frames) and longest (32) clip
+        sl = slice(off[j], off[j + 1])
+        _, gBj, _ = run(sl)
+        c_err = _rel(gBj, gB[:, sl, :])
+        print(f"[diff512] clip {j} ({off[j + 1] - off[j]} frames) alone vs batched: dL/dB rel {c_err:.2e}")
+        c_errs.append(c_err)
+    h = 1e-3
+    Lp = run(slice(None), w.sigma + h, f32(wl.blur_operator(w.size, w.n, w.sigma + h, w.band)), False)[0]
+    Lm = run(slice(None), w.sigma - h, f32(wl.blur_operator(w.size, w.n, w.sigma - h, w.band)), False)[0]
+    fd = (Lp - Lm) / (2 * h)
+    fd_err = abs(fd - gS) / abs(gS)
+    print(f"[diff512] central difference h = {h}: {fd:.6e}, rel {fd_err:.2e}")
+    assert l_err <= 1e-5 and b_err <= 1e-5 and s_err <= 1e-5
+    assert max(c_errs) <= 1e-6
+    assert fd_err <= 1e-3
