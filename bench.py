@@ -36,10 +36,14 @@ TAGS = {1: "fft_A", 2: "fft_omega", 3: "sketch", 4: "power", 5: "project", 6: "W
 # the others bracket several kernels (packing passes, the four eigensolver kernels, the solve)
 SINGLE_KERNEL = {"fft_A": "k_rfft_reg", "fft_omega": "k_rfft_reg", "gram": "k_gram_lower", "chol": "k_cholinv",
                  "W_mma": "k_skinny (FP32 MFMA, W = A-hat V)"}
+# stages whose brackets in one step are different kernels (svd_aux: the Gram C C^H, V and the error
+# indicator): their model is the work of the whole step, priced against the step's summed time
+PER_STEP = {"svd_aux"}
 
 
 def stage_model(w, precision):
-    """Algorithmic work per launch of each timed stage: (flops, bytes, bound, compute precision)."""
+    """Algorithmic work per launch of each timed stage (per step for PER_STEP stages):
+    (flops, bytes, bound, compute precision)."""
     l = m = w.size
     n, F, r, p = w.n, w.faces, w.r, max(w.p, 1)
     s_in = 8 if precision == "fp64" else 4
@@ -95,7 +99,7 @@ def traffic_of(stage, precision):
 
 def roofline_of(name, ms, launches, w, precision):
     flops, byts, bound, prec = stage_model(w, precision)[name]
-    per = ms / max(launches, 1) / 1e3            # seconds per launch
+    per = ms / (1 if name in PER_STEP else max(launches, 1)) / 1e3   # seconds per modelled unit
     if bound is None:                              # by arithmetic intensity against the ridge point
         ridge = PEAK_TFLOPS[prec] * 1e12 / (HBM_PEAK_GBS * 1e9)
         bound = "mfma" if flops / byts >= ridge else "hbm"

@@ -850,7 +850,9 @@ k_heev_backtr(const zd* __restrict__ gpk, const zd* __restrict__ taus, const dou
 // A pivot at or below tol_rel * max diag marks a dependent column: its row and column of L^{-1}
 // are zero and flags gets bit 0.  The packed lower triangle lives in LDS when it fits (else in
 // `gpk`, global scratch of packed_size(r) per face); `gdi` (F x ceil(r/16) x 256) keeps the block
-// inverses between the two sweeps.
+// inverses between the two sweeps.  Guarded operand loads read a clamped in-range element and
+// select zero by value: a conditional between an LDS element and a zero object would become a
+// generic (flat) load, whose wait also covers the wave's outstanding global stores.
 // ---------------------------------------------------------------------------------------------
 constexpr int CH_NB = 16, CH_PS = CH_NB + 1;  // block width, padded row stride of the panel buffers
 constexpr int CH_THREADS = 512;
@@ -946,7 +948,8 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
         const int j = g + 4 * s2;
         const bool in = rho < kb && j < kb && rho >= j;
         const zd diag = mk(rho == j ? 1.0 : 0.0, 0.0);
-        a[s2] = in ? at(K + rho, K + j) : diag;
+        const int ic = min(K + rho, r - 1), jc = min(K + j, ic);   // in range when !in
+        a[s2] = zsel(in, at(ic, jc), diag);
         d[s2] = diag;
       }
       double myipv = 1.0;   // 1 / L(rho, rho) once column rho is factored
@@ -1022,8 +1025,8 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
 #pragma unroll
       for (int kg = 0; kg < 4; ++kg) {
         const int k = 4 * kg + g;
-        const zd av = (i0 + rho < r && k < kb) ? at(i0 + rho, K + k) : zero;
-        const zd bv = (k < kb && rho < kb) ? cconj(DI[rho * CH_PS + k]) : zero;
+        const zd av = zsel(i0 + rho < r && k < kb, at(min(i0 + rho, r - 1), K + min(k, kb - 1)), zero);
+        const zd bv = zsel(k < kb && rho < kb, cconj(DI[rho * CH_PS + k]), zero);
         ch_cmma(av, bv, cr, ci);
       }
 #pragma unroll
@@ -1050,8 +1053,8 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
 #pragma unroll
       for (int kg = 0; kg < 4; ++kg) {
         const int k = 4 * kg + g;
-        const zd av = (i0 + rho < r && k < kb) ? P[(size_t)(i0 + rho) * CH_PS + k] : zero;
-        const zd bv = (j0 + rho < r && k < kb) ? cconj(P[(size_t)(j0 + rho) * CH_PS + k]) : zero;
+        const zd av = zsel(i0 + rho < r && k < kb, P[(size_t)min(i0 + rho, r - 1) * CH_PS + k], zero);
+        const zd bv = zsel(j0 + rho < r && k < kb, cconj(P[(size_t)min(j0 + rho, r - 1) * CH_PS + k]), zero);
         ch_cmma(av, bv, cr, ci);
       }
 #pragma unroll
@@ -1084,8 +1087,9 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
         for (int kg = 0; kg < 4; ++kg) {
           const int kk = J1 + 16 * tk + 4 * kg + g;
           const int i = i0 + rho;
-          const zd av = (i < r && kk <= i) ? at(i, kk) : zero;
-          const zd bv = (kk < r && rho < kb) ? P[(size_t)kk * CH_PS + rho] : zero;
+          const int ic = min(i, r - 1);
+          const zd av = zsel(i < r && kk <= i, at(ic, min(kk, ic)), zero);
+          const zd bv = zsel(kk < r && rho < kb, P[(size_t)min(kk, r - 1) * CH_PS + rho], zero);
           ch_cmma(av, bv, cr, ci);
         }
       }
@@ -1104,8 +1108,8 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
 #pragma unroll
       for (int kg = 0; kg < 4; ++kg) {
         const int t = 4 * kg + g;
-        const zd av = (i0 + rho < r && t < kb) ? at(i0 + rho, J + t) : zero;
-        const zd bv = (t < kb && rho < kb) ? DI[t * CH_PS + rho] : zero;
+        const zd av = zsel(i0 + rho < r && t < kb, at(min(i0 + rho, r - 1), J + min(t, kb - 1)), zero);
+        const zd bv = zsel(t < kb && rho < kb, DI[t * CH_PS + rho], zero);
         ch_cmma(av, bv, cr, ci);
       }
 #pragma unroll
@@ -1259,30 +1263,34 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
       if (writer) xsh[par][myrow] = x;
       c = wave_sum(c);
       if (l == 0) xv[par][w] = c;
-    } else {
-      if ((l & 3) == 0) xsh[par][myrow] = mk(0.0, 0.0);
-      if (l == 0) xv[par][w] = mk(0.0, 0.0);
     }
+    // Waves whose rows are all eliminated write nothing this step: the readers below take x as
+    // zero at eliminated rows and columns (v is zero there too) and sum xv over the active waves
+    // only.  They also issue no memory access that would make them wait for earlier global
+    // stores before the barrier.
     __syncthreads();
     if (wave_on) {
       // (4) rank-2 update of the owned block
       zd xhv = mk(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < TRD_WAVES; ++q) xhv = cadd(xhv, xv[par][q]);
+      for (int q = 0; q < TRD_WAVES; ++q)
+        if (16 * q + 15 > k) xhv = cadd(xhv, xv[par][q]);
       const zd a2 = cscale(cmul(tau, xhv), -0.5);
-      zd wcc[8], vcc[8];
+      // column by column, so that only the four row values of v and w stay live beside A
+      zd vi[4], wi[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        vi[ii] = vp[r0 + ii];
+        wi[ii] = cadd(xsh[par][r0 + ii], cmul(a2, vi[ii]));
+      }
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
         const zd vj = vp[c0 + jj];
-        vcc[jj] = cconj(vj);
-        wcc[jj] = cconj(cadd(xsh[par][c0 + jj], cmul(a2, vj)));
-      }
+        const zd vcc = cconj(vj);
+        const zd xj = xsh[par][c0 + jj];
+        const zd wcc = cconj(cadd(zsel(c0 + jj > k, xj, mk(0.0, 0.0)), cmul(a2, vj)));
 #pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const zd vi = vp[r0 + ii];
-        const zd wi = cadd(xsh[par][r0 + ii], cmul(a2, vi));
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) A[ii][jj] = zfms(wi, vcc[jj], zfms(vi, wcc[jj], A[ii][jj]));
+        for (int ii = 0; ii < 4; ++ii) A[ii][jj] = zfms(wi[ii], vcc, zfms(vi[ii], wcc, A[ii][jj]));
       }
     }
   }
