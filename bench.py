@@ -123,6 +123,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's automatic work split instead of timing the candidates first")
     ap.add_argument("--no-fixed-precision", action="store_true",
                     help="skip the timing of the fixed-precision (eps-adaptive) R-tSVD restoration")
     ap.add_argument("--no-krylov", action="store_true",
@@ -150,14 +152,34 @@ def make_problem(w, dev, torch, rt, wl):
             "A32": A64.float(), "B32": B64.float(), "Om32": Om64.float(), "X": X}
 
 
-def run_once(rt, prob, w, precision):
+def operands(prob, precision):
     if precision == "fp64":
-        A, B, Om = prob["A64"], prob["B64"], prob["Om64"]
-    else:
-        A, B, Om = prob["A32"], prob["B32"], prob["Om32"]
-    f = rt.factor(A, w.k_max, w.oversample, w.power_iters, precision, Om)
+        return prob["A64"], prob["B64"], prob["Om64"]
+    return prob["A32"], prob["B32"], prob["Om32"]
+
+
+def run_once(rt, prob, w, precision, split=None):
+    A, B, Om = operands(prob, precision)
+    split = split or {}
+    f = rt.factor(A, w.k_max, w.oversample, w.power_iters, precision, Om,
+                  face_groups=split.get("face_groups", 0), sketch_tile=split.get("sketch_tile", 0))
     res = f.solve(B, prob["delta"], w.eta, 1)
     return f, res
+
+
+def tuned_split(torch, prob, w, precision, enabled):
+    """Work split (face groups, sketch tiles) picked by the autotuner for this workload and
+    precision, timed before and outside the measured steps; None: the library's automatic choice."""
+    if not enabled:
+        return None
+    from paper_2110_02485_amd import tune
+    A, B, Om = operands(prob, precision)
+    t = tune.tune(A, B, Om, w.k_max, w.oversample, w.power_iters, precision, prob["delta"], w.eta)
+    print(f"[bench] tuned {precision}: groups {t['face_groups']}, tiles {t['sketch_tile']} "
+          f"({t['ms_per_step']:.3f} ms; {t['table']})", file=sys.stderr, flush=True)
+    if not t["identical"]:
+        raise RuntimeError("autotuner: candidates disagreed; the work split must not change the result")
+    return t
 
 
 def time_fixed_precision(torch, rt, prob, w, precision, steps, eps):
@@ -179,10 +201,10 @@ def time_fixed_precision(torch, rt, prob, w, precision, steps, eps):
     return ms, f.r, res
 
 
-def time_steps(torch, rt, prob, w, precision, steps, warmup, timers=False):
+def time_steps(torch, rt, prob, w, precision, steps, warmup, timers=False, split=None):
     lib = rt.load()
     for _ in range(warmup):
-        f, res = run_once(rt, prob, w, precision)
+        f, res = run_once(rt, prob, w, precision, split)
         f.close()
     torch.cuda.synchronize()
     if timers:
@@ -193,7 +215,7 @@ def time_steps(torch, rt, prob, w, precision, steps, warmup, timers=False):
     start.record()
     last = None
     for i in range(steps):
-        f, res = run_once(rt, prob, w, precision)
+        f, res = run_once(rt, prob, w, precision, split)
         if last is not None:
             last.close()
         last = f
@@ -354,10 +376,11 @@ def main():
     dev = torch.device("cuda:0")
     prob = make_problem(w, dev, torch, rt, wl)
     print(f"[bench] inputs ready: {w.name} l=m={w.size} n={w.n} r={w.r}", file=sys.stderr, flush=True)
-    ms, wall, out = time_steps(torch, rt, prob, w, precision, args.steps, args.warmup)
+    tuned = tuned_split(torch, prob, w, precision, not args.no_tune)
+    ms, wall, out = time_steps(torch, rt, prob, w, precision, args.steps, args.warmup, split=tuned)
     # stage timers (HIP events inside the library) in a separate pass, so that the headline time
-    # carries no event records
-    _, _, out_st = time_steps(torch, rt, prob, w, precision, args.steps, 1, timers=True)
+    # carries no event records (the library runs one face group while its timers are on)
+    _, _, out_st = time_steps(torch, rt, prob, w, precision, args.steps, 1, timers=True, split=tuned)
     out["stages"] = out_st.get("stages", {})
     x_true = prob["X64"]
     err = float(torch.linalg.norm(out["X"].double() - x_true) / torch.linalg.norm(x_true))
@@ -371,6 +394,9 @@ def main():
                    "k_max": w.k_max, "oversample": w.oversample, "r": w.r, "power_iters": w.power_iters,
                    "precision": precision, "noise": w.noise, "eta": w.eta},
         "k": out["k"], "dp_status": out["status"], "rel_error": err,
+        "tuning": ({"face_groups": tuned["face_groups"], "sketch_tile": tuned["sketch_tile"],
+                    "identical_results": tuned["identical"], "candidates_ms": tuned["table"]}
+                   if tuned else "automatic (face_groups 0, sketch_tile 0)"),
     }
     stages = out.get("stages", {})
     if stages:
@@ -384,13 +410,16 @@ def main():
         result["stages"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                             for k, v in stages.items()}
     if not args.no_fp64 and precision != "fp64":
-        ms64, _, out64 = time_steps(torch, rt, prob, w, "fp64", args.fp64_steps, 1)
+        tuned64 = tuned_split(torch, prob, w, "fp64", not args.no_tune)
+        ms64, _, out64 = time_steps(torch, rt, prob, w, "fp64", args.fp64_steps, 1, split=tuned64)
         err64 = float(torch.linalg.norm(out64["X"] - x_true) / torch.linalg.norm(x_true))
         diff = float(torch.linalg.norm(out["X"].double() - out64["X"]) / torch.linalg.norm(out64["X"]))
         result["fp64"] = {"value": 1000.0 / ms64, "ms_per_step": ms64, "k": out64["k"], "rel_error": err64,
                           "mixed_vs_fp64_rel_diff": diff,
                           "matched": abs(err - err64) <= 0.01 * err64,
-                          "speedup_mixed_over_fp64": ms64 / ms}
+                          "speedup_mixed_over_fp64": ms64 / ms,
+                          "tuning": ({"face_groups": tuned64["face_groups"], "sketch_tile": tuned64["sketch_tile"]}
+                                     if tuned64 else "automatic")}
     if not args.no_fixed_precision:
         # eps from the fixed-r factor's error indicator: eps^2 just above eta^[k_max], so Alg. 6
         # would stop after k_max columns and the discrepancy search runs over [k_max - rho, k_max]

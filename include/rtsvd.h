@@ -76,6 +76,11 @@ typedef struct {
                         /* work into that many groups on library streams (see rtsvd_factor).     */
                         /* The result does not depend on it (bit for bit); adaptive factors and  */
                         /* runs with the stage timers enabled use one group.                     */
+  int32_t sketch_tile;  /* 0: automatic (by r: the smallest of 1, 2, 4, 8 sixteen-column MFMA     */
+                        /* tiles per workgroup covering r columns); 1, 2, 4 or 8: that many tiles */
+                        /* in the factor's A-hat products (sketch, power, projection, Q = Y R^-1, */
+                        /* W = A-hat V).  Only the work split changes: the result does not depend */
+                        /* on it (bit for bit).                                                   */
 } rtsvd_opts;
 
 /* R-tSVD factorization (Section 4.2, Alg. 6 in block form, Thms 4.1-4.2).
@@ -89,7 +94,8 @@ typedef struct {
  * (default priority, see rtsvd_opts.face_groups), forked from and joined back into `stream`
  * with events: all of the call's work is complete when `stream` reaches the end of the call.
  * Errors: RTSVD_E_ARG (l < m, n < 1, k_max < 1, k_max > m, oversample < 0,
- * power_iters < 0, bad precision, face_groups outside 0..3, null A/opts/out),
+ * power_iters < 0, bad precision, face_groups outside 0..3, sketch_tile not 0, 1, 2, 4 or 8,
+ * null A/opts/out),
  * RTSVD_E_UNSUPPORTED (r > 256), RTSVD_E_HIP (the library's streams could not be created).
  * Warning RTSVD_W_RANK_DEFICIENT is reported later by rtsvd_factor_info.                      */
 int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype,

@@ -17,6 +17,8 @@ typedef cplx<double> zd;
 typedef cplx<float> zf;
 // bf16 complex: two bf16 in one 32-bit word, low half = real part, high half = imaginary part
 struct zb { uint32_t bits; };
+// up to 16 host doubles passed by value as a kernel argument
+struct Vals16 { double v[16]; };
 
 template <typename T> RT_HOST_DEVICE cplx<T> mk(T a, T b) { cplx<T> z; z.re = a; z.im = b; return z; }
 template <typename T> RT_HOST_DEVICE cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk(a.re + b.re, a.im + b.im); }

@@ -138,7 +138,6 @@ static inline unsigned nblocks(int64_t total, int threads = 256) { return (unsig
 
 // Small host arrays reach the device as kernel arguments (16 values per launch): stream-ordered,
 // no staging copy from pageable memory (which would block the host until the stream drains).
-struct Vals16 { double v[16]; };
 __global__ void k_set_doubles(double* __restrict__ dst, Vals16 vals, int count) {
   if ((int)threadIdx.x < count) dst[threadIdx.x] = vals.v[threadIdx.x];
 }
@@ -589,6 +588,7 @@ struct FaceStreams {
   hipEvent_t omega_done = nullptr; // the tube DFT of Omega, run beside that of A
   hipEvent_t join[MAX_FACE_GROUPS] = {};
   hipEvent_t stagger[MAX_FACE_GROUPS] = {};
+  hipEvent_t gram_done[MAX_FACE_GROUPS] = {};   // the group's G = C C^H is complete
 };
 
 static FaceStreams* face_streams(int groups) {
@@ -606,7 +606,8 @@ static FaceStreams* face_streams(int groups) {
     for (int g = 0; ok && g < MAX_FACE_GROUPS; ++g)
       ok = hipStreamCreateWithFlags(&n->st[g], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&n->join[g], hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&n->stagger[g], hipEventDisableTiming) == hipSuccess;
+           hipEventCreateWithFlags(&n->stagger[g], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&n->gram_done[g], hipEventDisableTiming) == hipSuccess;
     if (!ok) return nullptr;   // (the partial set is kept alive: streams are never destroyed)
     fs = n;
   }
@@ -633,6 +634,17 @@ static bool timers_on() {
 }
 
 // adapt_eps > 0: the fixed-precision factor of Alg. 6 (keep the first r_eps sketch columns)
+
+// error indicator eta^[j] (Thm 4.2) from the Gram matrices G_f = C_f C_f^H: ||C(j, :)||^2 is the
+// real diagonal of G
+static int eta_from_gram(const double* sumsq, int64_t nblk, const zd* G, int64_t F, int64_t r, int64_t n,
+                         double* eta, hipStream_t s) {
+  RT_TIMED(RTSVD_T_SVDAUX);
+  hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, (const double*)G,
+                     (int64_t)2 * r * r, (int64_t)2 * (r + 1), (int)F, (int)r, (int)n, eta);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <typename Tin, typename Tw>
 static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int64_t n, int64_t r, int precision,
                        int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd_mode, double adapt_eps = 0.0,
@@ -729,23 +741,25 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
       for (int ph = 0; ph < qg[0].phases() + SVD_PHASES; ++ph)
         for (int g = 0; g < groups; ++g) {
           if (ph == 0 && g > 0) RT_CHECK_HIP(hipStreamWaitEvent(qg[g].s, fs->stagger[g - 1], 0));
-          if (ph < qg[g].phases()) RT_TRY(qg[g].run(ph));
-          else RT_TRY((rtsvd_faces_svd<Tw>(fb, l, m, r, r, qg[g].f0, qg[g].Fg, fb.G, *scg[g], qg[g].s,
-                                           ph - qg[g].phases())));
+          if (ph < qg[g].phases()) {
+            RT_TRY(qg[g].run(ph));
+            if (ph == qg[g].phases() - 1) RT_CHECK_HIP(hipEventRecord(fs->gram_done[g], qg[g].s));
+          } else {
+            RT_TRY((rtsvd_faces_svd<Tw>(fb, l, m, r, r, qg[g].f0, qg[g].Fg, fb.G, *scg[g], qg[g].s,
+                                        ph - qg[g].phases())));
+          }
         }
+      // the error indicator needs only the Gram matrices: s computes it while the groups still
+      // run their eigensolvers and W passes, then joins them
+      for (int g = 0; g < groups; ++g) RT_CHECK_HIP(hipStreamWaitEvent(s, fs->gram_done[g], 0));
+      RT_TRY(eta_from_gram(sumsq, nblk, G, F, r, n, eta, s));
       for (int g = 0; g < groups; ++g) {
         RT_CHECK_HIP(hipEventRecord(fs->join[g], qg[g].s));
         RT_CHECK_HIP(hipStreamWaitEvent(s, fs->join[g], 0));
       }
       Qo = qg[0].Y;
     }
-    {
-      RT_TIMED(RTSVD_T_SVDAUX);
-      // error indicator eta^[j] (Thm 4.2); ||C(j, :)||^2 is the real diagonal of G
-      hipLaunchKernelGGL(k_eta_prefix, dim3(1), dim3(DP_SEL_THREADS), 0, s, sumsq, nblk, (const double*)G,
-                         (int64_t)2 * r * r, (int64_t)2 * (r + 1), (int)F, (int)r, (int)n, eta);
-      RT_LAUNCH_OK();
-    }
+    if (groups == 1) RT_TRY(eta_from_gram(sumsq, nblk, G, F, r, n, eta, s));
     int64_t rr = r;
     if (groups == 1) {
       // fixed precision (Alg. 6): r_eps = first j >= 1 with eta^[j] < eps^2.  QR and the power
@@ -838,6 +852,9 @@ extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int 
     return fail(RTSVD_E_ARG, "rtsvd_factor: bad precision");
   if (o.face_groups < 0 || o.face_groups > MAX_FACE_GROUPS)
     return fail(RTSVD_E_ARG, "rtsvd_factor: face_groups must be 0..3");
+  if (o.sketch_tile != 0 && o.sketch_tile != 1 && o.sketch_tile != 2 && o.sketch_tile != 4 && o.sketch_tile != 8)
+    return fail(RTSVD_E_ARG, "rtsvd_factor: sketch_tile must be 0, 1, 2, 4 or 8");
+  sk::TileOverride tile_guard(o.sketch_tile);
   const int64_t r = std::min<int64_t>((int64_t)o.k_max + o.oversample, m);
   if (r > 256) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_factor: r = min(k_max + oversample, m) must be <= 256");
   if (!o.omega) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_factor: omega must be supplied");
@@ -1017,14 +1034,22 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   hipLaunchKernelGGL((k_dp_partial<zw, zw>), dim3((unsigned)tiles, (unsigned)p, (unsigned)F), dim3(DP_ROWS), 0, s,
                      Bh, (const zw*)h->W, T, (int)l, (int)p, (int)r, kcap, partial);
   RT_LAUNCH_OK();
-  RT_ALLOC(bnd, double, groups, sc);
+  // the bounds ride in the selection kernel's arguments for up to 16 groups, else in device memory
+  Vals16 bnd_args = {};
+  double* bnd = nullptr;
+  if (groups <= 16) {
+    for (int g = 0; g < groups; ++g) bnd_args.v[g] = bounds[g];
+  } else {
+    bnd = sc.template get<double>(groups);
+    if (!bnd) return fail(RTSVD_E_NOMEM, "device allocation failed: bnd");
+    RT_TRY(upload_doubles(bnd, bounds.data(), groups, s));
+  }
   RT_ALLOC(rho_tmp, double, (int64_t)groups * kcap, sc);
-  RT_TRY(upload_doubles(bnd, bounds.data(), groups, s));
   hipLaunchKernelGGL(k_dp_rho, dim3((unsigned)(groups * kcap)), dim3(DP_RHO_THREADS), 0, s, partial, (int)F, tiles,
                      (int)p, kcap, (int)n, groups, resid_out, rho_tmp);
   RT_LAUNCH_OK();
-  hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(256), 0, s, kcap, groups, (const double*)bnd, k_start, (const double*)rho_tmp,
-                     k_out, status_out);
+  hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(DP_SELECT_THREADS), 0, s, kcap, groups, (const double*)bnd, bnd_args,
+                     k_start, (const double*)rho_tmp, k_out, status_out);
   RT_LAUNCH_OK();
   // X-hat = V T', T' = T with rows >= k zeroed; X = inverse DFT
   hipLaunchKernelGGL(k_mask_coeffs, dim3(nblocks(F * r * p)), dim3(256), 0, s, T, D, k_out, groups, (int)r, (int)p,

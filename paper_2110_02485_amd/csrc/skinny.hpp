@@ -535,7 +535,18 @@ static inline bool aligned_elems(const void* p, int64_t a, int64_t b, int64_t c,
 }
 
 // column tiles of 16 per block
-template <class P> static inline int nt_for(int N) { return N <= 16 ? 1 : (N <= 32 ? 2 : (N <= 64 ? 4 : 8)); }
+// sixteen-column tiles per workgroup: by N, unless a factor call set its sketch_tile option for
+// the products it issues from this host thread (packing, workspace size and launch all read it)
+inline thread_local int tile_override = 0;
+struct TileOverride {
+  int saved;
+  explicit TileOverride(int nt) : saved(tile_override) { tile_override = nt; }
+  ~TileOverride() { tile_override = saved; }
+};
+template <class P> static inline int nt_for(int N) {
+  if (tile_override > 0) return tile_override;
+  return N <= 16 ? 1 : (N <= 32 ? 2 : (N <= 64 ? 4 : 8));
+}
 
 template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, bool UTRI, typename TA, typename TX, typename TC, int NT>
 static int sk_launch_nt(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const void* X, int64_t ldx,

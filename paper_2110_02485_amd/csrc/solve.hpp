@@ -80,6 +80,7 @@ k_dp_rho(const double* __restrict__ partial, int F, int tiles, int p, int kcap, 
   const int c0 = groups == 1 ? 0 : g, nc = groups == 1 ? p : 1;
   const int cnt = F * tiles;
   double s = 0.0;
+#pragma unroll 4
   for (int e = threadIdx.x; e < cnt; e += DP_RHO_THREADS) {
     const int fi = e / tiles, t = e - fi * tiles;
     const double w = (fi == 0 || 2 * fi == n) ? 1.0 : 2.0;
@@ -101,19 +102,32 @@ k_dp_rho(const double* __restrict__ partial, int F, int tiles, int p, int kcap, 
   }
 }
 
-// The first k >= k_start with rho_k <= eta delta of each group (one block).  k_start >= 1.
-__global__ void k_dp_select(int kcap, int groups, const double* __restrict__ bound /* eta*delta per group */,
-                            int k_start, const double* __restrict__ rho_tmp, int* __restrict__ k_out,
-                            int* __restrict__ status_out) {
+// The first k >= k_start with rho_k <= eta delta of each group (one block; k_start >= 1).  One
+// wave per group: its lanes test 64 consecutive orders at once and the lowest lane that meets
+// the bound gives k, so a group costs one load round per 64 orders.  bound_args holds the bounds
+// when groups <= 16 (then `bound` may be null), else they are read from `bound`.
+constexpr int DP_SELECT_THREADS = 256;
+__global__ void __launch_bounds__(DP_SELECT_THREADS)
+k_dp_select(int kcap, int groups, const double* __restrict__ bound /* eta*delta per group */, Vals16 bound_args,
+            int k_start, const double* __restrict__ rho_tmp, int* __restrict__ k_out, int* __restrict__ status_out) {
   __shared__ int any_fail;
   if (threadIdx.x == 0) any_fail = 0;
   __syncthreads();
-  for (int g = threadIdx.x; g < groups; g += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
+  for (int g = wave; g < groups; g += nw) {
+    const double b = groups <= 16 ? bound_args.v[g] : bound[g];
     int kk = -1;
-    for (int k = k_start; k <= kcap; ++k)
-      if (rho_tmp[g * kcap + k - 1] <= bound[g]) { kk = k; break; }
-    if (kk < 0) { kk = kcap; atomicOr(&any_fail, 1); }
-    k_out[g] = kk;
+    for (int k0 = k_start; k0 <= kcap && kk < 0; k0 += 64) {
+      const int k = k0 + lane;
+      const bool ok = k <= kcap && rho_tmp[(int64_t)g * kcap + k - 1] <= b;
+      const unsigned long long hit = __ballot(ok);
+      if (hit) kk = k0 + __builtin_ctzll(hit);
+    }
+    if (kk < 0) {
+      kk = kcap;
+      if (lane == 0) atomicOr(&any_fail, 1);
+    }
+    if (lane == 0) k_out[g] = kk;
   }
   __syncthreads();
   if (threadIdx.x == 0 && status_out) *status_out = any_fail ? RTSVD_W_DP_NOT_MET : RTSVD_OK;
@@ -141,6 +155,8 @@ k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __r
   __shared__ double rows[HEEV_RMAX_SOLVE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double s = 0.0;
+  // unrolled so that each lane's loads are all in flight together (same summation order)
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < nsumsq; i += blockDim.x) s += sumsq[i];
   s = wave_sum(s);
   if (lane == 0) red[wave] = s;
@@ -150,8 +166,10 @@ k_eta_prefix(const double* __restrict__ sumsq, int64_t nsumsq, const double* __r
   for (int j0 = 0; j0 < r; j0 += per) {
     const int j = j0 + jl;
     double t = 0.0;
-    if (j < r)
+    if (j < r) {
+#pragma unroll 9
       for (int f = sub; f < F; f += 8) t += ((f == 0 || 2 * f == n) ? 1.0 : 2.0) * rn[(int64_t)f * sf + (int64_t)j * sj];
+    }
     t += dpp<DPP_XOR1>(t);
     t += dpp<DPP_XOR2>(t);
     t += __shfl_xor(t, 4, 64);

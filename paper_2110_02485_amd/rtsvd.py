@@ -37,7 +37,8 @@ class RtsvdError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("omega", ctypes.c_void_p),
-                ("eps", ctypes.c_double), ("adaptive", ctypes.c_int32), ("face_groups", ctypes.c_int32)]
+                ("eps", ctypes.c_double), ("adaptive", ctypes.c_int32), ("face_groups", ctypes.c_int32),
+                ("sketch_tile", ctypes.c_int32)]
 
 
 _lib = None
@@ -154,7 +155,7 @@ class Factor:
     @classmethod
     def rtsvd(cls, A: torch.Tensor, k_max: int, oversample: int, power_iters: int = 0, precision: str = "fp64",
               omega: torch.Tensor | None = None, eps: float = 0.0, seed: int = 0,
-              adaptive: bool = False, face_groups: int = 0) -> "Factor":
+              adaptive: bool = False, face_groups: int = 0, sketch_tile: int = 0) -> "Factor":
         lib = load()
         A = _dev(A, "A")
         n, m, l = A.shape
@@ -165,7 +166,7 @@ class Factor:
         if tuple(omega.shape) != (n, r, m) or omega.dtype != A.dtype:
             raise ValueError(f"omega must have shape {(n, r, m)} and dtype {A.dtype}")
         opts = _Opts(k_max, oversample, power_iters, PRECISIONS[precision], seed, omega.data_ptr(), eps,
-                     1 if adaptive else 0, face_groups)
+                     1 if adaptive else 0, face_groups, sketch_tile)
         h = ctypes.c_void_p()
         _check(lib.rtsvd_factor(A.data_ptr(), l, m, n, _dtype_code(A), ctypes.byref(opts), _stream(),
                                 ctypes.byref(h)), "rtsvd_factor")
@@ -251,11 +252,12 @@ def trim() -> None:
 
 
 def factor(A, k_max, oversample, power_iters=0, precision="fp64", omega=None, eps=0.0, adaptive=False,
-           face_groups=0) -> Factor:
+           face_groups=0, sketch_tile=0) -> Factor:
     """R-tSVD factor of A (see Factor.rtsvd); adaptive=True with eps > 0: Alg. 6's fixed-precision rank;
-    face_groups: 0 automatic, 1..3 (the result does not depend on it)."""
+    face_groups: 0 automatic, 1..3; sketch_tile: 0 automatic, 1, 2, 4 or 8 sixteen-column tiles per
+    workgroup in the A-hat products (the result depends on neither)."""
     return Factor.rtsvd(A, k_max, oversample, power_iters, precision, omega, eps, adaptive=adaptive,
-                        face_groups=face_groups)
+                        face_groups=face_groups, sketch_tile=sketch_tile)
 
 
 def ttsvd_factor(A, k_max, precision="fp64") -> Factor:

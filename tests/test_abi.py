@@ -55,6 +55,9 @@ def test_argument_errors_without_gpu():
     grp = rt._Opts(5, 2, 0, 0, 0, ctypes.c_void_p(16), 0.0, 0, 4)
     assert lib.rtsvd_factor(ctypes.c_void_p(16), 8, 8, 4, 0, ctypes.byref(grp), None, ctypes.byref(h)) == rt.E_ARG
     assert b"face_groups" in lib.rtsvd_last_error()
+    tile = rt._Opts(5, 2, 0, 0, 0, ctypes.c_void_p(16), 0.0, 0, 0, 3)
+    assert lib.rtsvd_factor(ctypes.c_void_p(16), 8, 8, 4, 0, ctypes.byref(tile), None, ctypes.byref(h)) == rt.E_ARG
+    assert b"sketch_tile" in lib.rtsvd_last_error()
     assert lib.tprod(None, None, None, 1, 1, 1, 1, 0, None) == rt.E_ARG
     assert lib.tprod(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 1, 1, 1, 7, None) == rt.E_ARG
     assert b"dtype" in lib.rtsvd_last_error()

@@ -245,6 +245,31 @@ def test_face_groups_give_identical_factors(precision):
         assert np.array_equal(eta_, outs[0][2]) and np.array_equal(sig_, outs[0][3])
 
 
+@pytest.mark.parametrize("precision,r_cols", [("mixed", 30), ("mixed", 120), ("fp32", 120), ("fp64", 30)])
+def test_sketch_tiles_give_identical_factors(precision, r_cols):
+    # 1, 2, 4 or 8 sixteen-column MFMA tiles per workgroup in the factor's A-hat products: only the
+    # work split changes (no sum changes order), so factor and solution agree bit for bit
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    k_max = r_cols - 10
+    A, X, B, Om, delta = blur_problem(256, 16, 2.0, 8, 1, 1e-2, k_max, 10, seed=67)
+    dt = "float64" if precision == "fp64" else "float32"
+    At, Bt, Omt = _t(A, dt), _t(B, dt), _t(Om, dt)
+    outs = []
+    for tile in (0, 1, 2, 4, 8):
+        print(f"[sketch_tile] {precision} r={r_cols} tile={tile}", flush=True)
+        f = rt.factor(At, k_max, 10, 1, precision, Omt, sketch_tile=tile)
+        res = f.solve(Bt, delta, 1.01, 1)
+        torch.cuda.synchronize()
+        info = f.info()
+        outs.append((_np(res.X), int(res.k[0]), info[2], info[4]))
+        f.close()
+    for X_, k_, eta_, sig_ in outs[1:]:
+        assert k_ == outs[0][1]
+        assert np.array_equal(X_, outs[0][0])
+        assert np.array_equal(eta_, outs[0][2]) and np.array_equal(sig_, outs[0][3])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solve_captured_in_a_graph_replays_like_eager(precision):
     # rtsvd_solve keeps k, residuals and status on the device and launches kernels only, so after a
