@@ -78,11 +78,11 @@ def stage_model(w, precision):
 # calibration 1 GiB -> FETCH_SIZE 524302.3 KiB (factor 1.99995), WRITE_SIZE 1048576 KiB (factor 1.0).
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
-                         "sha256": "40c9478d914fb9f45e25e7f3eb93a953b8339e7af2e41935913b0ce9a3a31999",
-                         "bytes_per_launch": 677414042},
+                         "sha256": "23a4052b1d6fb1baf6c640ead9a475a772c67677a20dcd79596192923a7393e0",
+                         "bytes_per_launch": 677413206},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
-                        "sha256": "4f12bda3afa189baf3e1124acd8506f672530ac28b332b7565fec7991a8398c1",
-                        "bytes_per_launch": 35824387},
+                        "sha256": "c10a9b5ae77b9c9de712ab0032bd96a2dae5f6c6d508c6cf882bada06bd8b7d8",
+                        "bytes_per_launch": 34691400},
 }
 
 
