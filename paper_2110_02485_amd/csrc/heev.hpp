@@ -120,6 +120,14 @@ __device__ __forceinline__ double inv_d(double x) {
   return y;
 }
 
+// 1/sqrt(x) for normal x > 0: v_rsq_f64 refined by two Newton steps, y <- y + y (1 - x y^2) / 2
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 // number of eigenvalues of the tridiagonal (d, e) strictly below x (Sturm sequence)
 __device__ __forceinline__ int sturm_count_fast(const double* d, const double* e2, int r, double x, double pivmin) {
   int cnt = 0;
@@ -961,8 +969,22 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
         const zd ac = a[sl];
         const double dd = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ac.re), c + 16 * cs),
                                            __builtin_amdgcn_readlane(__double2loint(ac.re), c + 16 * cs));
-        const double pv = (c >= kb) ? 1.0 : ((dd > tol && dd > 0.0) ? sqrt(dd) : 0.0);
-        const double ipv = pv > 0.0 ? 1.0 / pv : 0.0;
+        // pivot sqrt(dd) and its inverse: one reciprocal square root (dd is wave-uniform), the
+        // IEEE square root and division only for pivots near the bottom of the normal range
+        const bool live = c < kb && dd > tol && dd > 0.0;
+        double pv = 1.0, ipv = 1.0;
+        if (c < kb) {
+          if (!live) {
+            pv = 0.0;
+            ipv = 0.0;
+          } else if (dd > 1e-280) {
+            ipv = rsqrt_d(dd);
+            pv = dd * ipv;
+          } else {
+            pv = sqrt(dd);
+            ipv = 1.0 / pv;
+          }
+        }
         myipv = (rho == c) ? ipv : myipv;
         const zd acn = zsel(g != cs || rho < c, ac, zsel(rho == c, mk(pv, 0.0), cscale(ac, ipv)));
         a[sl] = acn;

@@ -14,8 +14,11 @@
 //    relabelling of k (lane group g = lane/16 holds k = KL*g + e), applied identically to X.
 //  * With RT = 2 the two row tiles of a wave interleave (row 2*rho + t), so a lane's outputs are
 //    8 consecutive rows of one column and are written with 16-byte stores.
-//  * Complex arithmetic is four real MFMA products on split planes:
-//      Re C += Ar Xr + (-Ai) Xi,   Im C += Ar Xi + Ai Xr   (conjugation of A folded into Ai).
+//  * Complex arithmetic on split planes (conjugation of A folded into Ai):
+//      bf16: four real MFMA products,  Re C += Ar Xr + (-Ai) Xi,  Im C += Ar Xi + Ai Xr;
+//      FP32 and FP64: three (Gauss), P1 += Ar Xr, P2 += Ai Xi, P3 += (Ar + Ai)(Xr + Xi), and at the
+//      end Re C = P1 - P2, Im C = (P3 - P1) - P2 -- a quarter fewer MFMAs for the MFMA-bound
+//      products; the operand sums are formed in registers (in bf16 they would not be exact).
 //  * The blocks of one face run on one XCD (block id congruent mod 8), sharing X in that L2.
 // MFMA output layouts (16 x 16 tile, element v < 4 of lane l, column l % 16): f32 accumulators
 // row 4*(l/16) + v; f64 accumulators row (l/16) + 4*v.
@@ -346,13 +349,16 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
     }
   };
 
-  V accr[RT][NT], acci[RT][NT];
+  // bf16: accr, acci are Re C, Im C.  FP32 / FP64: accr, acci, accs hold P1, P2, P3 (combined
+  // into Re C, Im C before the store)
+  constexpr bool GAUSS = !std::is_same<P, B16>::value;
+  V accr[RT][NT], acci[RT][NT], accs[RT][NT];
 #pragma unroll
   for (int tt = 0; tt < RT; ++tt)
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { accr[tt][c][v] = 0; acci[tt][c][v] = 0; }
+      for (int v = 0; v < 4; ++v) { accr[tt][c][v] = 0; acci[tt][c][v] = 0; accs[tt][c][v] = 0; }
 
   // one k-group from an LDS buffer
   // UTRI: X is upper triangular (X[k][n] = 0 for k > n), so column tile c skips k-groups that
@@ -419,7 +425,8 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
         }
       }
     } else {
-      Acc xr[RT][KL], xi[RT][KL], xn[RT][KL];
+      // three real products: P1 = Ar Xr, P2 = Ai Xi, P3 = (Ar + Ai)(Xr + Xi)
+      Acc xr[RT][KL], xi[RT][KL], xs[RT][KL];
 #pragma unroll
       for (int tt = 0; tt < RT; ++tt)
 #pragma unroll
@@ -427,14 +434,16 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
           const cplx<Acc> v = ld<Acc>(ra[tt][e]);
           xr[tt][e] = v.re;
           xi[tt][e] = CN ? -v.im : v.im;
-          xn[tt][e] = -xi[tt][e];
+          xs[tt][e] = xr[tt][e] + xi[tt][e];
         }
-      E br[NT][KL], bi[NT][KL];
+      E br[NT][KL], bi[NT][KL], bs[NT][KL];
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
         const E* bp = Bc + (cw + 16 * c + rho) * ROWE + KL * g;
         vload<E, KL>(bp, br[c]);
         vload<E, KL>(bp + XPLANE, bi[c]);
+#pragma unroll
+        for (int e = 0; e < KL; ++e) bs[c][e] = br[c][e] + bi[c][e];
       }
 #pragma unroll
       for (int e = 0; e < KL; ++e) {
@@ -444,16 +453,8 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
 #pragma unroll
           for (int tt = 0; tt < RT; ++tt) {
             accr[tt][c] = mma(xr[tt][e], br[c][e], accr[tt][c]);
-            acci[tt][c] = mma(xr[tt][e], bi[c][e], acci[tt][c]);
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-          if ((LOWER && n0 + cw + 16 * c > wmax) || skip(kc, c)) continue;
-#pragma unroll
-          for (int tt = 0; tt < RT; ++tt) {
-            accr[tt][c] = mma(xn[tt][e], bi[c][e], accr[tt][c]);
-            acci[tt][c] = mma(xi[tt][e], br[c][e], acci[tt][c]);
+            acci[tt][c] = mma(xi[tt][e], bi[c][e], acci[tt][c]);
+            accs[tt][c] = mma(xs[tt][e], bs[c][e], accs[tt][c]);
           }
         }
       }
@@ -495,6 +496,18 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
   }
 
   // ---- store ----
+  if constexpr (GAUSS) {
+#pragma unroll
+    for (int tt = 0; tt < RT; ++tt)
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const Acc p1 = accr[tt][c][v], p2 = acci[tt][c][v], p3 = accs[tt][c][v];
+          accr[tt][c][v] = p1 - p2;
+          acci[tt][c][v] = (p3 - p1) - p2;
+        }
+  }
 #pragma unroll
   for (int c = 0; c < NT; ++c) {
     if (LOWER && n0 + cw + 16 * c > wmax) continue;
