@@ -74,15 +74,18 @@ def stage_model(w, precision):
 # HBM traffic of a kernel from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE per dispatch, each
 # scaled by the ratio of known bytes to the counter's reading for a plain device copy); valid only
 # while the kernel's source is the one that was measured (sha256 of the source file)
-# Measured on the blur1024 workload (profiles/w_mma_cholinv_blur1024_hbm_counters.md): copy
+# Measured on the blur1024 workload (profiles/w_mma_cholinv_gram_blur1024_hbm_counters.md): copy
 # calibration 1 GiB -> FETCH_SIZE 524302.3 KiB (factor 1.99995), WRITE_SIZE 1048576 KiB (factor 1.0).
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
-                         "sha256": "23a4052b1d6fb1baf6c640ead9a475a772c67677a20dcd79596192923a7393e0",
-                         "bytes_per_launch": 677413206},
+                         "sha256": "bd60979bbd2bf7281d1036402afeaeafd15eee157d2f0a07b2e92ec86c1cae10",
+                         "bytes_per_launch": 677418415},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
-                        "sha256": "c10a9b5ae77b9c9de712ab0032bd96a2dae5f6c6d508c6cf882bada06bd8b7d8",
-                        "bytes_per_launch": 34691400},
+                        "sha256": "0521275def9093121b981db92449edf2f55e3c4b4b23f40e64fbe3a7962ca85a",
+                        "bytes_per_launch": 34710293},
+    ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
+                        "sha256": "b61971c1e72b84752d3b98d02af13ea5bdf58f73ddb2da4648d8e3a988a54c0c",
+                        "bytes_per_launch": 76487003},
 }
 
 

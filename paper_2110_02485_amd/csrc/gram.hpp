@@ -21,12 +21,20 @@ constexpr int GRAM_THREADS = 512;
 constexpr int GRAM_WAVES = GRAM_THREADS / 64;
 typedef double gr_f64x4 __attribute__((ext_vector_type(4)));
 
+// Grid: 8 ceil(P batch / 8) blocks in one dimension (P lower tiles per face).  The hardware hands
+// block b to XCD b % 8; block b takes work item (b % 8) S + b / 8 (S = ceil(P batch / 8)), item
+// = face * P + tile, so each XCD works through a contiguous run of faces and reads each face's
+// panels into its own L2 once instead of every XCD fetching every face.
 template <typename TY>
 __global__ void __launch_bounds__(GRAM_THREADS)
-k_gram_lower(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY, zd* __restrict__ G) {
+k_gram_lower(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY, zd* __restrict__ G, int P,
+             int batch) {
   __shared__ gr_f64x4 red[GRAM_WAVES - 1][2][64];
-  const int f = blockIdx.y;
-  const int p = blockIdx.x;
+  const int items = P * batch, per_xcd = (items + 7) / 8;
+  const int item = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (item >= items) return;   // uniform per block
+  const int f = item / P;
+  const int p = item - f * P;
   // lower tile (I, J) from its index p = I (I + 1) / 2 + J
   int I = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= p) ++I;
@@ -220,8 +228,9 @@ template <typename TY>
 int gram_lower(const TY* Y, int rows, int r, int64_t ldy, int64_t sY, int batch, zd* G, hipStream_t s) {
   if (r <= 0 || batch <= 0) return 0;
   const int T = (r + 15) / 16, P = T * (T + 1) / 2;
-  hipLaunchKernelGGL((k_gram_lower<TY>), dim3((unsigned)P, (unsigned)batch), dim3(GRAM_THREADS), 0, s,
-                     Y, rows, r, ldy, sY, G);
+  const int64_t per_xcd = ((int64_t)P * batch + 7) / 8;
+  hipLaunchKernelGGL((k_gram_lower<TY>), dim3((unsigned)(8 * per_xcd)), dim3(GRAM_THREADS), 0, s,
+                     Y, rows, r, ldy, sY, G, P, batch);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
