@@ -51,19 +51,50 @@ k_gram_lower(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY,
   // three independent accumulators (P1, P2, P3) so that consecutive MFMAs never wait on each
   // other's results
   gr_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0;
-  // unconditional loads at clamped rows (in bounds), masked afterwards; the next 16 rows are
-  // loaded while the current ones are multiplied
-  TY ra[4], rb[4];
-  auto load = [&](int kb) {
+  auto mfma_step = [&](const zd* a, const zd* bv) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int kc = min(kb + 4 * q + s, rows - 1);
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].re, bv[s].re, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].im, bv[s].im, acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].re - a[s].im, bv[s].re + bv[s].im, acc2, 0, 0, 0);
+    }
+  };
+  int kb = k0;
+  // tiles with all 16 + 16 columns inside r, whole steps of 16 rows: no clamps or masks (block-
+  // and wave-uniform conditions)
+  const int kfull = k0 + (k1 > k0 ? (k1 - k0) / 16 * 16 : 0);
+  if (16 * I + 16 <= r && 16 * J + 16 <= r && kfull > k0) {
+    const TY* __restrict__ pa = ya + k0 + 4 * q;
+    const TY* __restrict__ pb = yb + k0 + 4 * q;
+    TY na[4], nb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { na[s] = pa[s]; nb[s] = pb[s]; }
+    for (; kb < kfull; kb += 16) {
+      zd a[4], bv[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) { a[s] = ld<double>(na[s]); bv[s] = ld<double>(nb[s]); }
+      pa += 16;
+      pb += 16;
+      if (kb + 16 < kfull) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) { na[s] = pa[s]; nb[s] = pb[s]; }
+      }
+      mfma_step(a, bv);
+    }
+  }
+  // edge tiles and the last partial step: loads at clamped rows (in bounds), masked afterwards;
+  // the next 16 rows are loaded while the current ones are multiplied
+  TY ra[4], rb[4];
+  auto load = [&](int kr) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kc = min(kr + 4 * q + s, rows - 1);
       ra[s] = ya[kc];
       rb[s] = yb[kc];
     }
   };
-  load(k0);
-  for (int kb = k0; kb < k1; kb += 16) {
+  if (kb < k1) load(kb);
+  for (; kb < k1; kb += 16) {
     zd a[4], bv[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -73,12 +104,7 @@ k_gram_lower(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY,
       bv[s] = mk((okb && in) ? vb.re : 0.0, (okb && in) ? vb.im : 0.0);
     }
     load(kb + 16);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].re, bv[s].re, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].im, bv[s].im, acc1, 0, 0, 0);
-      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].re - a[s].im, bv[s].re + bv[s].im, acc2, 0, 0, 0);
-    }
+    mfma_step(a, bv);
   }
   gr_f64x4 accr = acc0 + acc1, acci = acc2 - acc0 + acc1;
   if (w > 0) {
