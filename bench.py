@@ -84,8 +84,8 @@ TRAFFIC = {
                         "sha256": "0521275def9093121b981db92449edf2f55e3c4b4b23f40e64fbe3a7962ca85a",
                         "bytes_per_launch": 34710293},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
-                        "sha256": "b61971c1e72b84752d3b98d02af13ea5bdf58f73ddb2da4648d8e3a988a54c0c",
-                        "bytes_per_launch": 76487003},
+                        "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
+                        "bytes_per_launch": 76505844},
 }
 
 
