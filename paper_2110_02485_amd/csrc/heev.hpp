@@ -853,12 +853,13 @@ k_heev_backtr(const zd* __restrict__ gpk, const zd* __restrict__ taus, const dou
 // Blocked by 16 columns.  Per diagonal block K, one wave factors the 16 x 16 block and inverts it
 // in registers (lane (i, j) layout, column data exchanged by cross-lane shuffles); the panel below
 // is G_panel D^H (D = L_KK^{-1}) and the trailing update is S -= P P^H, both on FP64 MFMA 16x16x4
-// tiles spread over the waves.  The inverse runs over the diagonal blocks backwards:
-//   Linv(J1:, J) = -Linv(J1:, J1:) X D_J,  X = L(J1:, J)  (MFMA tiles, three barriers per block).
+// tiles spread over the waves.  L^{-1} is formed by block rows during the same sweep:
+//   Linv(K, J) = -D_K sum_{J <= M < K} L(K, M) Linv(M, J)  (MFMA tiles),  Linv(K, K) = D_K,
+// by waves 1.. while wave 0 factors the next diagonal block, and written over L's block row K.
 // A pivot at or below tol_rel * max diag marks a dependent column: its row and column of L^{-1}
 // are zero and flags gets bit 0.  The packed lower triangle lives in LDS when it fits (else in
 // `gpk`, global scratch of packed_size(r) per face); `gdi` (F x ceil(r/16) x 256) keeps the block
-// inverses between the two sweeps.  Guarded operand loads read a clamped in-range element and
+// inverses D_K for the block rows of L^{-1}.  Guarded operand loads read a clamped in-range element and
 // select zero by value: a conditional between an LDS element and a zero object would become a
 // generic (flat) load, whose wait also covers the wave's outstanding global stores.
 // ---------------------------------------------------------------------------------------------
@@ -942,10 +943,64 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
   __syncthreads();
   const double tol = H.tol;
 
+  // ---- L^{-1} by block rows, beside the factorization ----
+  // Block row Kp of L^{-1}: Linv(Kp, jt) = -D_Kp sum_{jt <= mb < Kp} L(Kp, mb) Linv(mb, jt) for
+  // jt < Kp, and Linv(Kp, Kp) = D_Kp.  It needs only L's block row Kp (final once the panel of
+  // step Kp - 1 is written) and block rows < Kp of L^{-1}, so waves 1.. compute it in registers
+  // while wave 0 factors the next diagonal block, and store it over L's block row Kp in the next
+  // panel phase.  D_Kp is read back from GD.  An MFMA output tile (lane: rows 4 v + g of column
+  // rho) is laid out as the B operand of the next product, so T = sum L Linv feeds D T directly.
+  constexpr int LT_MAX = IN_LDS ? 1 : 3;   // tiles per wave: r <= 128 in LDS (<= 7), else <= 15
+  ch_f64x4 lr[LT_MAX], li[LT_MAX];
+  const int nlw = nw - 1;                  // waves 1 .. nw - 1 compute the block rows
+  auto linv_tiles = [&](int Kp) {
+    const int row = CH_NB * Kp + rho, rowc = min(row, r - 1);
+#pragma unroll
+    for (int u = 0; u < LT_MAX; ++u) {
+      const int jt = (wave - 1) + nlw * u;
+      lr[u] = (ch_f64x4){0, 0, 0, 0};
+      li[u] = lr[u];
+      if (jt >= Kp) continue;                // uniform per wave
+      ch_f64x4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+      const int col = CH_NB * jt + rho;
+      for (int mb = jt; mb < Kp; ++mb) {
+#pragma unroll
+        for (int kg = 0; kg < 4; ++kg) {
+          const int k = CH_NB * mb + 4 * kg + g;                  // < CH_NB Kp <= rowc
+          const zd av = zsel(row < r, at(rowc, k), zero);          // L(row, k)
+          const zd bv = zsel(k >= col, at(k, min(col, k)), zero);  // Linv(k, col), lower
+          ch_cmma(av, bv, tr, ti);
+        }
+      }
+      const zd* __restrict__ Dg = GD + Kp * CH_NB * CH_NB;
+#pragma unroll
+      for (int kg = 0; kg < 4; ++kg) ch_cmma(Dg[rho * CH_NB + 4 * kg + g], mk(tr[kg], ti[kg]), lr[u], li[u]);
+    }
+  };
+  auto linv_store = [&](int Kp) {
+    if (wave > 0) {
+#pragma unroll
+      for (int u = 0; u < LT_MAX; ++u) {
+        const int jt = (wave - 1) + nlw * u;
+        if (jt >= Kp) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = CH_NB * Kp + 4 * v + g;
+          if (i < r) at(i, CH_NB * jt + rho) = mk(-lr[u][v], -li[u][v]);
+        }
+      }
+    }
+    for (int q = tid; q < CH_NB * CH_NB; q += blockDim.x) {
+      const int i = q / CH_NB, c = q % CH_NB;
+      if (i >= c && CH_NB * Kp + i < r) at(CH_NB * Kp + i, CH_NB * Kp + c) = GD[Kp * CH_NB * CH_NB + q];
+    }
+  };
+
   RT_PHASE(8);
   // ---- blocked right-looking Cholesky ----
   for (int K = 0; K < r; K += CH_NB) {
     const int kb = min(CH_NB, r - K), K1 = K + kb, m = r - K1;
+    const int Kb = K / CH_NB;
     // (a) wave 0: factor the diagonal block and invert it; lane holds (i, j_s), i = rho, j_s = g + 4 s.
     // A block narrower than 16 is padded with the identity (its extra pivots are 1), so the
     // unrolled column loop has no bound tests; only rows and columns < kb are written back.
@@ -1037,9 +1092,12 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
         DI[rho * CH_PS + j] = dv;
         GD[(K / CH_NB) * CH_NB * CH_NB + rho * CH_NB + j] = dv;
       }
+    } else if (Kb >= 1) {
+      linv_tiles(Kb - 1);
     }
     __syncthreads();
     if (K == 0) RT_PHASE(12);
+    if (Kb >= 1) linv_store(Kb - 1);   // rows of block Kb - 1: disjoint from the panel below
     // (b) panel P(i, c) = sum_t G(i, K + t) conj(D(c, t)), rows i >= K1, 16-row MFMA tiles
     for (int ti = wave; ti * 16 < m; ti += nw) {
       const int i0 = K1 + 16 * ti;
@@ -1089,61 +1147,12 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
     if (K == 0) RT_PHASE(14);
   }
   RT_PHASE(9);
-  // ---- in-place inverse of L, diagonal blocks from the last to the first ----
-  const int nblk = (r + CH_NB - 1) / CH_NB;
-  for (int Jb = nblk - 1; Jb >= 0; --Jb) {
-    const int J = Jb * CH_NB, kb = min(CH_NB, r - J), J1 = J + kb, m = r - J1;
-    // (d) block inverse D_J back from global; panel X = L(J1:, J) copied into P
-    for (int q = tid; q < CH_NB * CH_NB; q += blockDim.x) DI[(q / CH_NB) * CH_PS + q % CH_NB] = GD[Jb * CH_NB * CH_NB + q];
-    for (int q = tid; q < m * kb; q += blockDim.x) {
-      const int k = J1 + q / kb, c = q % kb;
-      P[(size_t)k * CH_PS + c] = at(k, J + c);
-    }
+  // the last block row of L^{-1}
+  {
+    const int nblk = (r + CH_NB - 1) / CH_NB;
+    if (wave > 0) linv_tiles(nblk - 1);
     __syncthreads();
-    // (e) T = Linv(J1:, J1:) X, written over the panel slots (X is safe in P)
-    for (int ti = wave; ti * 16 < m; ti += nw) {
-      const int i0 = J1 + 16 * ti;
-      ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      for (int tk = 0; tk <= ti; ++tk) {
-#pragma unroll
-        for (int kg = 0; kg < 4; ++kg) {
-          const int kk = J1 + 16 * tk + 4 * kg + g;
-          const int i = i0 + rho;
-          const int ic = min(i, r - 1);
-          const zd av = zsel(i < r && kk <= i, at(ic, min(kk, ic)), zero);
-          const zd bv = zsel(kk < r && rho < kb, P[(size_t)min(kk, r - 1) * CH_PS + rho], zero);
-          ch_cmma(av, bv, cr, ci);
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + g + 4 * v;
-        if (i < r && rho < kb) at(i, J + rho) = mk(cr[v], ci[v]);
-      }
-    }
-    __syncthreads();
-    // (f) Linv(i, J + c) = -sum_t T(i, t) D(t, c) (each wave reads back only its own row tiles);
-    // the diagonal block becomes D
-    for (int ti = wave; ti * 16 < m; ti += nw) {
-      const int i0 = J1 + 16 * ti;
-      ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-#pragma unroll
-      for (int kg = 0; kg < 4; ++kg) {
-        const int t = 4 * kg + g;
-        const zd av = zsel(i0 + rho < r && t < kb, at(min(i0 + rho, r - 1), J + min(t, kb - 1)), zero);
-        const zd bv = zsel(t < kb && rho < kb, DI[t * CH_PS + rho], zero);
-        ch_cmma(av, bv, cr, ci);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + g + 4 * v;
-        if (i < r && rho < kb) at(i, J + rho) = mk(-cr[v], -ci[v]);
-      }
-    }
-    for (int q = tid; q < kb * kb; q += blockDim.x) {
-      const int i = q / kb, c = q % kb;
-      if (i >= c) at(J + i, J + c) = DI[i * CH_PS + c];
-    }
+    linv_store(nblk - 1);
     __syncthreads();
   }
   RT_PHASE(10);

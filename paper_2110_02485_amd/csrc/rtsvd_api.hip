@@ -306,6 +306,9 @@ static int launch_cholinv(const zd* G, int r, int64_t F, zd* Rinv, int* flags, S
   const size_t full = chol_lds_bytes(r, true);
   const bool in_lds = (int64_t)full <= (int64_t)max_lds_per_block();
   const size_t bytes = in_lds ? full : chol_lds_bytes(r, false);
+  // the kernel's waves 1..7 hold at most 1 (LDS variant) or 3 tiles each of a block row of L^{-1}
+  if ((in_lds && r > 128) || r > HEEV_RMAX)
+    return fail(RTSVD_E_UNSUPPORTED, "Cholesky inverse: r beyond the kernel's block-row capacity");
   zd* gpk = nullptr;
   if (!in_lds) {
     gpk = sc.get<zd>(F * packed_size(r));
