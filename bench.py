@@ -79,13 +79,13 @@ def stage_model(w, precision):
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
                          "sha256": "bd60979bbd2bf7281d1036402afeaeafd15eee157d2f0a07b2e92ec86c1cae10",
-                         "bytes_per_launch": 677418415},
+                         "bytes_per_launch": 677418838},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
-                        "sha256": "0521275def9093121b981db92449edf2f55e3c4b4b23f40e64fbe3a7962ca85a",
-                        "bytes_per_launch": 34710293},
+                        "sha256": "9e90a094b8e9ed452f281851b088a0fb2c12d8e8a494a1e7275411de90a2b108",
+                        "bytes_per_launch": 34664793},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
                         "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
-                        "bytes_per_launch": 76505844},
+                        "bytes_per_launch": 76506075},
 }
 
 
