@@ -93,6 +93,26 @@ def test_rtsvd_fp64_random_ragged(q):
     np.testing.assert_allclose(_np(res.resid)[0], orc["res"][:, 0], rtol=1e-11)
 
 
+@pytest.mark.parametrize("r_cols,precision,tol", [(200, "fp64", 1e-10), (256, "fp64", 1e-10), (200, "fp32", 2e-5)])
+def test_rtsvd_wide_sketch(r_cols, precision, tol):
+    # sketch widths above 128: the Cholesky factor and its block-row inverse run from global
+    # scratch (up to three tiles of an L^{-1} block row per wave; r = 256 is the largest r), and
+    # the eigensolver takes its one-kernel path; q = 1, ragged l, several RHS
+    l, m, n, p, rho = 271, 256, 4, 2, 10
+    k_max = r_cols - rho
+    A, B, Om = random_problem(l, m, n, p, r_cols, seed=r_cols)
+    delta = 0.5 * np.linalg.norm(B)
+    orc = _oracle_rtsvd(A, B, Om, delta, 1.05, k_max, 1)
+    dt = "float64" if precision == "fp64" else "float32"
+    f, res = _gpu_rtsvd(A, B, Om, delta, 1.05, k_max, rho, 1, precision, dt)
+    r, faces, eta, r_eps, sig, flags = f.info()
+    assert r == r_cols and flags == 0
+    assert int(res.k[0]) == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= tol
+    kk = orc["k"]
+    np.testing.assert_allclose(_np(res.resid)[0][:kk], orc["res"][:kk, 0], rtol=tol)
+
+
 def test_rtsvd_per_slice_and_paper_mode():
     w = wl.WORKLOADS["blur64"]
     A, X, B, Om, delta = blur_problem(48, 10, 2.0, 6, 3, 1e-2, 12, 6, seed=3, video=True)
