@@ -163,8 +163,13 @@ __global__ void k_pack_slabs(const TX* __restrict__ X, int64_t ldx, int64_t sX, 
 // Both paths are branch-free inside the k loop.  LOWER: skip column tiles strictly above the
 // diagonal (Hermitian Gram).  vec_c: the host has checked the alignment of 16-byte stores.
 // k-groups past kend see X = 0 (packed X is zero-padded, raw X is zeroed while staging).
+// waves per SIMD the register allocation must allow: four (two workgroups per CU, so one
+// workgroup's MFMAs run while the other waits at its k-group barrier) for the unchecked FP32
+// products, two for the others
+template <class P, bool SAFE> constexpr int sk_min_waves() { return (std::is_same<P, F32>::value && !SAFE) ? 4 : 2; }
+
 template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, bool UTRI, typename TA, typename TX, typename TC, int NB>
-__global__ void __launch_bounds__(SK_THREADS, 2)
+__global__ void __launch_bounds__(SK_THREADS, (sk_min_waves<P, SAFE>()))
 k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA, const void* __restrict__ Xv,
          int64_t ldx, int64_t sX, TC* __restrict__ C, int64_t ldc, int64_t sC, int batch, int mtiles, int ntiles,
          int kchunk, int64_t sCsplit, int vec_c) {
