@@ -78,14 +78,14 @@ def stage_model(w, precision):
 # calibration 1 GiB -> FETCH_SIZE 524302.3 KiB (factor 1.99995), WRITE_SIZE 1048576 KiB (factor 1.0).
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
-                         "sha256": "bd60979bbd2bf7281d1036402afeaeafd15eee157d2f0a07b2e92ec86c1cae10",
-                         "bytes_per_launch": 677418838},
+                         "sha256": "efa161e1a25a8f71d90fc684f4494d856d69a500af82f1698b05f9530812bf65",
+                         "bytes_per_launch": 681677920},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
                         "sha256": "9e90a094b8e9ed452f281851b088a0fb2c12d8e8a494a1e7275411de90a2b108",
-                        "bytes_per_launch": 34664793},
+                        "bytes_per_launch": 34664265},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
                         "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
-                        "bytes_per_launch": 76506075},
+                        "bytes_per_launch": 76505883},
 }
 
 
