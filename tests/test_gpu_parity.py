@@ -129,6 +129,26 @@ def test_rtsvd_per_slice_and_paper_mode():
     assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-11
 
 
+@pytest.mark.parametrize("p", [16, 17, 24])
+def test_rtsvd_per_slice_many_slices(p):
+    # one discrepancy bound per lateral slice: up to 16 bounds ride in the selection kernel's
+    # arguments, more come from device memory.  Slice-dependent levels (some met at small k, slice
+    # 5 never met), search from k = 3; k per slice, status, X and residuals against the oracle
+    A, X, B, Om, delta = blur_problem(48, 10, 2.0, 6, p, 1e-2, 14, 6, seed=p, video=True)
+    Bm = wl.to_math(B)
+    fac = [0.005 + 0.03 * ((7 * j) % 11) / 10.0 for j in range(p)]
+    fac[5] = 1e-14
+    deltas = [fac[j] * float(np.linalg.norm(Bm[:, j])) for j in range(p)]
+    orc = _oracle_rtsvd(A, B, Om, deltas, 1.01, 14, 0, k_start=3, per_slice=True)
+    f, res = _gpu_rtsvd(A, B, Om, deltas, 1.01, 14, 6, 0, "fp64", "float64", k_start=3)
+    assert [int(v) for v in res.k.cpu()] == orc["k"]
+    assert int(res.status[0]) == orc["status"] == 1
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-11
+    got = _np(res.resid)
+    for j in range(p):
+        np.testing.assert_allclose(got[j][:14], orc["res"][:14, j], rtol=1e-10)
+
+
 @pytest.mark.parametrize("q", [0, 1])
 def test_rtsvd_fixed_precision_adaptive(q):
     # Alg. 6's fixed-precision rank: the factor keeps r_eps = first j with eta^[j] < eps^2 sketch
