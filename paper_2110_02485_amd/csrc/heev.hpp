@@ -1243,12 +1243,18 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
     double beta = alpha.re;
     zd tau = mk(0.0, 0.0), sc = mk(0.0, 0.0);
     if (active) {
-      const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn);
+      // the norm, 1/beta and 1/|alpha - beta|^2 by Newton-refined hardware estimates (the values
+      // are wave-uniform, so the branch to the IEEE operations near the bottom of the normal
+      // range is uniform too)
+      const double nn = alpha.re * alpha.re + alpha.im * alpha.im + xn;
+      const bool normal = nn > 1e-280;
+      const double nrm = normal ? nn * rsqrt_d(nn) : sqrt(nn);
       beta = alpha.re >= 0.0 ? -nrm : nrm;
-      const double ib = 1.0 / beta;
+      const double ib = normal ? inv_d(beta) : 1.0 / beta;
       tau = mk((beta - alpha.re) * ib, -alpha.im * ib);
       const zd den = mk(alpha.re - beta, alpha.im);
-      const double idd = 1.0 / cabs2(den);
+      const double dd2 = cabs2(den);
+      const double idd = normal ? inv_d(dd2) : 1.0 / dd2;
       sc = mk(den.re * idd, -den.im * idd);
     }
 #pragma unroll
