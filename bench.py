@@ -79,13 +79,13 @@ def stage_model(w, precision):
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
                          "sha256": "efa161e1a25a8f71d90fc684f4494d856d69a500af82f1698b05f9530812bf65",
-                         "bytes_per_launch": 681677920},
+                         "bytes_per_launch": 681678432},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
-                        "sha256": "9e90a094b8e9ed452f281851b088a0fb2c12d8e8a494a1e7275411de90a2b108",
+                        "sha256": "3123ec9af2958fd33f0593ec2c55eac4f6ac81b95e04e0ff6c8b14746769f10b",
                         "bytes_per_launch": 34664265},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
                         "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
-                        "bytes_per_launch": 76505883},
+                        "bytes_per_launch": 76505867},
 }
 
 
