@@ -357,7 +357,7 @@ def cpu_baseline(w, wl):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU; the library has no multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
