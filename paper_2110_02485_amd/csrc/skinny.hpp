@@ -129,30 +129,41 @@ template <class P, bool CN, typename TA> constexpr int lds_bytes(int NB, int BM)
 // Packed X in slab-major order, so that one slab of one block column is a single contiguous run:
 //   Xp[f][block column nt][slab s][plane][n < NP][kl < KSL],  k = s KSL + kl,  n = nt NP + n,
 // plane 0 real, 1 imaginary, zero outside K x N.  X_f is column-major K x N (leading dimension ldx).
+// One thread per PV = 16 / sizeof(E) consecutive kl of one column: one 16-byte store per plane
+// (Xp 16-byte aligned; KSL is a multiple of PV).
+template <typename E> constexpr int pack_vec() { return 16 / (int)sizeof(E); }
 template <typename TX, typename E, int KSL>
 __global__ void k_pack_slabs(const TX* __restrict__ X, int64_t ldx, int64_t sX, int K, int N, E* __restrict__ Xp,
                              int KP, int NP, int ntiles, int batch) {
+  constexpr int PV = pack_vec<E>(), KV = KSL / PV;
+  static_assert(KSL % PV == 0, "a slab row holds whole 16-byte vectors");
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int nsl = KP / KSL;
-  const int64_t total = (int64_t)batch * ntiles * nsl * NP * KSL;
+  const int64_t total = (int64_t)batch * ntiles * nsl * NP * KV;
   if (idx >= total) return;
-  const int kl = (int)(idx % KSL);
-  int64_t t1 = idx / KSL;
+  const int kv = (int)(idx % KV);
+  int64_t t1 = idx / KV;
   const int nl = (int)(t1 % NP);
   t1 /= NP;
   const int sl = (int)(t1 % nsl);
   t1 /= nsl;
   const int nt = (int)(t1 % ntiles);
   const int64_t f = t1 / ntiles;
-  const int k = sl * KSL + kl, n = nt * NP + nl;
-  double re = 0.0, im = 0.0;
-  if (n < N && k < K) {
-    const cplx<double> v = ld<double>(X[f * sX + k + (int64_t)n * ldx]);
-    re = v.re; im = v.im;
+  const int k0 = sl * KSL + kv * PV, n = nt * NP + nl;
+  E re[PV], im[PV];
+#pragma unroll
+  for (int e = 0; e < PV; ++e) {
+    double vr = 0.0, vi = 0.0;
+    if (n < N && k0 + e < K) {
+      const cplx<double> v = ld<double>(X[f * sX + k0 + e + (int64_t)n * ldx]);
+      vr = v.re; vi = v.im;
+    }
+    re[e] = cvt_e<E>(vr);
+    im[e] = cvt_e<E>(vi);
   }
-  E* out = Xp + (((f * ntiles + nt) * nsl + sl) * 2 * NP + nl) * KSL + kl;
-  out[0] = cvt_e<E>(re);
-  out[(int64_t)NP * KSL] = cvt_e<E>(im);
+  E* out = Xp + (((f * ntiles + nt) * nsl + sl) * 2 * NP + nl) * KSL + kv * PV;
+  vstore<E, PV>(out, re);
+  vstore<E, PV>(out + (int64_t)NP * KSL, im);
 }
 
 // C_f (+ split * sCsplit) = op(A_f) X_f, M x N, contraction length K.
@@ -655,7 +666,8 @@ static int skinny_pack(int N, int K, const TX* X, int64_t ldx, int64_t sX, int b
   const int NPt = (int)(ceil_div(N, NP) * NP);
   constexpr int KSL = kslab<P>();
   const int64_t total = (int64_t)NPt * KP * batch;
-  hipLaunchKernelGGL((k_pack_slabs<TX, E, KSL>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, X, ldx, sX, K, N,
+  hipLaunchKernelGGL((k_pack_slabs<TX, E, KSL>), dim3((unsigned)ceil_div(total / pack_vec<E>(), 256)), dim3(256), 0, s,
+                     X, ldx, sX, K, N,
                      static_cast<E*>(ws), KP, NP, NPt / NP, batch);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
