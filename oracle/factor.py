@@ -138,10 +138,14 @@ def rtsvd_face(A_i: np.ndarray, O_i: np.ndarray, power_iters: int = 0) -> dict:
     return {"Q": q, "C": c, "Ub": u, "s": sv, "Vh": vh}
 
 
-def solution_face(fc: dict, b_i: np.ndarray, k: int) -> np.ndarray:
+def solution_face(fc: dict, b_i: np.ndarray, k: int, cut: float = 0.0) -> np.ndarray:
     """Face i of the truncated solution X_k = V_k * S_k^{-1} * U_k^T * B (Section 4.2) from one
-    face's factor: V[:, :k] diag(1/s[:k]) U-breve[:, :k]^H Q^H b_i (b_i: l x p)."""
-    t = (fc["Ub"][:, :k].conj().T @ (fc["Q"].conj().T @ b_i)) / fc["s"][:k][:, None]
+    face's factor: V[:, :k] diag(1/s[:k]) U-breve[:, :k]^H Q^H b_i (b_i: l x p).  Singular values
+    at or below `cut` (the all-face cutoff of solve.pinv_cut) count as zero (Moore-Penrose)."""
+    d = fc["Ub"][:, :k].conj().T @ (fc["Q"].conj().T @ b_i)
+    s = fc["s"][:k]
+    t = np.zeros_like(d)
+    t[s > cut] = d[s > cut] / s[s > cut][:, None]
     return fc["Vh"][:k, :].conj().T @ t
 
 

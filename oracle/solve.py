@@ -17,14 +17,32 @@ OK = 0
 DP_NOT_MET = 1
 
 
+def pinv_cut(s: np.ndarray) -> float:
+    """Numerical-rank cutoff of the truncated pseudo-inverse: sqrt(4 r eps) times the largest
+    singular value over all faces (r = number of singular values per face, eps = 2^-52).  The
+    inverse of S_k in X_k = V_k * S_k^{-1} * U_k^T * B is read as the Moore-Penrose inverse of the
+    block-diagonal Fourier form of S_k with this tolerance: a face of A that is zero (or zero up to
+    rounding) contributes nothing instead of 1/0."""
+    return float(np.sqrt(4.0 * s.shape[0] * np.finfo(np.float64).eps) * s.max(initial=0.0))
+
+
+def pinv_scale(d: np.ndarray, s: np.ndarray, cut: float = 0.0) -> np.ndarray:
+    """diag(s)^+ d: rows divided by the singular values, rows of singular values <= cut set to zero."""
+    out = np.zeros_like(d)
+    nz = s > cut
+    out[nz] = d[nz] / s[nz][:, None]
+    return out
+
+
 def coefficients_rtsvd(f: dict, b: np.ndarray) -> np.ndarray:
     """T_i = diag(1/s_i) U-breve_i^H Q_i^H B-hat_i for every face (r x p x n)."""
     bh = fft_tubes(b)
     n = bh.shape[2]
+    cut = pinv_cut(f["s"])
     out = np.empty((f["s"].shape[0], b.shape[1], n), dtype=complex)
     for i in range(n):
         d = f["Ub"][:, :, i].conj().T @ (f["Q"][:, :, i].conj().T @ bh[:, :, i])
-        out[:, :, i] = d / f["s"][:, i][:, None]
+        out[:, :, i] = pinv_scale(d, f["s"][:, i], cut)
     return out
 
 
@@ -32,9 +50,10 @@ def coefficients_tsvd(f: dict, b: np.ndarray) -> np.ndarray:
     """T_i = diag(1/s_i) U_i^H B-hat_i for every face (eq. (14))."""
     bh = fft_tubes(b)
     n = bh.shape[2]
+    cut = pinv_cut(f["s"])
     out = np.empty((f["s"].shape[0], b.shape[1], n), dtype=complex)
     for i in range(n):
-        out[:, :, i] = (f["U"][:, :, i].conj().T @ bh[:, :, i]) / f["s"][:, i][:, None]
+        out[:, :, i] = pinv_scale(f["U"][:, :, i].conj().T @ bh[:, :, i], f["s"][:, i], cut)
     return out
 
 
