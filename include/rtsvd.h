@@ -49,6 +49,7 @@ extern "C" {
 #define RTSVD_W_DP_NOT_MET 1       /* no k in [k_start, k_cap] met the discrepancy principle   */
 #define RTSVD_W_RANK_DEFICIENT 2   /* a sketch column fell below the breakdown threshold        */
 #define RTSVD_E_ARG (-1)           /* invalid argument (sizes, null pointers, eta_dp <= 1, ...) */
+#define RTSVD_E_NOTFINITE (-2)     /* an input holds NaN or infinity (detected on the device)      */
 #define RTSVD_E_HIP (-3)           /* a HIP runtime call failed                                 */
 #define RTSVD_E_NOMEM (-4)         /* device memory could not be obtained                       */
 #define RTSVD_E_UNSUPPORTED (-5)   /* valid but unsupported configuration (e.g. r > 256)        */
@@ -60,9 +61,11 @@ typedef struct {
   int32_t oversample;   /* rho >= 0 (Section 4.2, r = k + rho): r = min(k_max + rho, m) <= 256  */
   int32_t power_iters;  /* q >= 0 range refinements A-hat A-hat^H; q = 0 is Alg. 6 as printed   */
   int32_t precision;    /* RTSVD_P_FP64 | RTSVD_P_FP32 | RTSVD_P_BF16                           */
-  uint64_t seed;        /* seed of the on-device Gaussian generator, used when omega == NULL    */
-  const void* omega;    /* optional DEVICE real m x r x n Gaussian tensor (dtype of A); the r   */
-                        /* tensor columns play the role of the Gaussian slices G of Alg. 6      */
+  uint64_t seed;        /* key of the on-device Gaussian generator, used when omega == NULL: the */
+                        /* tensor rtsvd_gaussian(seed, m, r, n, dtype of A) writes is drawn on   */
+                        /* the device and used as omega (Alg. 6, "generate a Gaussian tensor")   */
+  const void* omega;    /* optional DEVICE real m x r x n Gaussian tensor (dtype of A, finite);  */
+                        /* the r tensor columns play the role of the Gaussian slices G of Alg. 6 */
   double eps;           /* > 0: also report r_eps = min{ j : eta^[j] < eps^2 } (Alg. 6 stopping */
                         /* rule, Thm 4.2); <= 0: not used                                        */
   int32_t adaptive;     /* nonzero (with eps > 0): the fixed-precision R-tSVD of Alg. 6 -- the  */
@@ -96,8 +99,11 @@ typedef struct {
  * Errors: RTSVD_E_ARG (l < m, n < 1, k_max < 1, k_max > m, oversample < 0,
  * power_iters < 0, bad precision, face_groups outside 0..3, sketch_tile not 0, 1, 2, 4 or 8,
  * null A/opts/out),
- * RTSVD_E_UNSUPPORTED (r > 256), RTSVD_E_HIP (the library's streams could not be created).
- * Warning RTSVD_W_RANK_DEFICIENT is reported later by rtsvd_factor_info.                      */
+ * RTSVD_E_UNSUPPORTED (r > 256), RTSVD_E_HIP (the library's streams could not be created),
+ * RTSVD_E_NOMEM.  Conditions found on the device are reported later, without a synchronization
+ * here: RTSVD_W_RANK_DEFICIENT (a sketch column broke down, Alg. 3) and RTSVD_E_NOTFINITE (A holds
+ * NaN or infinity, or ||A||_F^2 overflows: the factor is then formed from a zero A-hat and is
+ * unusable) by rtsvd_factor_info, and RTSVD_E_NOTFINITE again in rtsvd_solve's status_out.     */
 int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype,
                  const rtsvd_opts* opts, void* stream, rtsvd_handle* out);
 
@@ -113,7 +119,11 @@ int ttsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype, int3
  *            (Thm 4.2); eta[r] = ||A - Q * B-tilde||_F^2 (Thm 4.1)
  *   r_eps  : smallest j with eta^[j] < eps^2, or -1 (eps <= 0 or never reached)
  *   sigma  : HOST array r x faces, sigma[i*r + j] = j-th singular value of face i
- *   flags  : bit 0 = a Gram pivot fell below the breakdown threshold (rank-deficient sketch)   */
+ *   flags  : bit 0 = a Gram pivot fell below the breakdown threshold (rank-deficient sketch),
+ *            bit 1 = A is not finite
+ * Returns RTSVD_OK, RTSVD_W_RANK_DEFICIENT (flag bit 0) or RTSVD_E_NOTFINITE (flag bit 1; the
+ * outputs are still written).  r_eps is the first j >= 1 with eta^[j] < eps^2, as Alg. 6 tests
+ * the indicator after each new column.                                                         */
 int rtsvd_factor_info(rtsvd_handle f, int32_t* r, int32_t* faces, double* eta, int32_t* r_eps,
                       double* sigma, int32_t* flags);
 
@@ -133,24 +143,28 @@ int rtsvd_trim(void);
 
 /* Truncated R-tSVD / T-tSVD solution with the discrepancy principle (eq. (disp), eq. (kinit)):
  *   X_k = V_k * S_k^{-1} * U_k^T * B,  U_k = Q * U-tilde(:, 1:k, :)   (Section 4.2)
- * B: DEVICE l x p x n (dtype); X: DEVICE m x p x n (dtype), caller-allocated.
+ * B: DEVICE l x p x n (dtype; l and n those of the factor's A, p >= 1 any); X: DEVICE m x p x n
+ * (dtype), caller-allocated.  The library reads l p n elements of B and writes m p n of X.
  * delta: HOST array; n_delta = 1 -> one noise bound for all of B, joint k (the single k of the
  *        RT-tSVD rows of the paper's tables); n_delta = p -> lateral slice j is its own problem
  *        with bound delta[j] and its own k_j.
  * eta_dp > 1 is the discrepancy factor (tau of eq. (disp)).
  * k_start >= 1: the first k tried (1 = the literal principle, smallest k > 0); k_start = 0: the
  *        experiments' rule k_init = max(1, r - rho), increased up to r (eq. (kinit)).
- * k_cap = k_max for k_start >= 1 and r for k_start = 0.  The residual used is the exact
+ * k_start <= min(k_max, r) (an adaptive factor may keep r < k_max columns).
+ * k_cap = min(k_max, r) for k_start >= 1 and r for k_start = 0.  The residual used is the exact
  *        ||B - A * X_k||_F (Fourier domain, FP64 sums).
  * k_out:     DEVICE int32[n_delta]: chosen k (k_cap when the principle is not met).
  * resid_out: DEVICE double[n_delta * k_cap] or NULL: resid_out[g*k_cap + k-1] = ||B_g - A*X_k||_F.
- * status_out: DEVICE int32[1] or NULL: RTSVD_OK or RTSVD_W_DP_NOT_MET (set on the device).
+ * status_out: DEVICE int32[1] or NULL: RTSVD_OK, RTSVD_W_DP_NOT_MET, or RTSVD_E_NOTFINITE when B
+ *        or the factor's A is not finite (any residual not finite; k_out then holds k_cap and X
+ *        is unspecified).  Set on the device.
  * The call only launches kernels on `stream` (no synchronization, no host copies, outputs stay
  * on the device), so it can be captured in a HIP graph and replayed for new contents of the same
  * B buffer: make one call on the capturing stream first (its workspace comes from that stream's
  * cache, so the captured call allocates nothing), keep the handle alive while the graph is used.
  * Errors: RTSVD_E_ARG (null handle/B/X/delta/k_out, p < 1, n_delta not 1 or p, eta_dp <= 1,
- *         k_start < 0 or > k_max, dtype mismatch with the factor's caller dtype).             */
+ *         k_start < 0 or > min(k_max, r), dtype mismatch with the factor's caller dtype).     */
 int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype,
                 const double* delta, int32_t n_delta, double eta_dp, int32_t k_start,
                 void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
@@ -263,6 +277,17 @@ int rtsvd_solve_vjp(const void* A, const void* dA, const void* B, const void* om
 #define RTSVD_T_TLANCZOS 16  /* whole tlanczos_solve                                         */
 int rtsvd_timer_enable(int on);
 int rtsvd_timer_read(int tag, double* total_ms, int32_t* launches);
+
+/* Gaussian test tensor of Alg. 6 ("generate a Gaussian random tensor"), drawn on the device:
+ * out = DEVICE m x r x n (column-major, dtype), element e = i + m j + m r t standard normal.
+ * Generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) keyed by (seed mod 2^32,
+ * seed div 2^32) on the counter (q mod 2^32, q div 2^32, 0, 0) of the pair q = floor(e / 2); its
+ * output words (x0, x1, x2, x3) give u1 = (((x1 x0) >> 11) + 1/2) 2^-53 and u2 = ((x3 x2) >> 11)
+ * 2^-53 (64-bit words formed high:low), and the Box-Muller pair sqrt(-2 ln u1) cos(2 pi u2)
+ * (element 2q), sqrt(-2 ln u1) sin(2 pi u2) (element 2q + 1), computed in FP64 and rounded once.
+ * rtsvd_factor with omega == NULL uses exactly this tensor.  Errors: RTSVD_E_ARG (null out,
+ * sizes < 1, bad dtype), RTSVD_E_UNSUPPORTED (more than 2^32 elements), RTSVD_E_HIP.          */
+int rtsvd_gaussian(uint64_t seed, int64_t m, int64_t r, int64_t n, int dtype, void* out, void* stream);
 
 /* Human-readable status text. */
 const char* rtsvd_status_string(int status);

@@ -342,7 +342,10 @@ inline int ilog2_exact(int64_t n) {
   int l = 0; while ((1LL << l) < n) ++l; return l;
 }
 
-// per-device cache of twiddle tables (kept for the life of the process; a few KB each)
+// per-device cache of twiddle tables (kept for the life of the process; a few KB each).  A table
+// is published only once its fill kernel has completed (the calling thread waits for it), so any
+// stream may read a cached table without an event.  The first use of a length n on a device must
+// therefore not happen while the stream is being captured into a graph (nullptr is returned then).
 template <typename T>
 const cplx<T>* twiddles(int n, hipStream_t s) {
   static std::mutex mu;
@@ -353,9 +356,15 @@ const cplx<T>* twiddles(int n, hipStream_t s) {
   auto key = std::make_pair(dev, n);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return nullptr;
   cplx<T>* tw = nullptr;
   if (hipMalloc(&tw, sizeof(cplx<T>) * (size_t)std::max(1, n / 2)) != hipSuccess) return nullptr;
   hipLaunchKernelGGL((k_twiddle_table<T>), dim3((unsigned)((n / 2 + 255) / 256 + 1)), dim3(256), 0, s, tw, n);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(tw);
+    return nullptr;
+  }
   cache[key] = tw;
   return tw;
 }

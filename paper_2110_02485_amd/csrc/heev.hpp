@@ -1183,6 +1183,12 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
 constexpr int TRD_R = 128;
 constexpr int TRD_THREADS = 512;
 constexpr int TRD_WAVES = TRD_THREADS / 64;
+// LDS vectors are stored with one padding entry after every 8 (index t -> t + t/8): the 16 lanes
+// of a row group read 8 consecutive entries each, 128 bytes apart without padding, which puts all
+// of them on the same banks; with the padding their 16-byte reads start 144 bytes apart and fall on
+// distinct banks.
+constexpr int TRD_RP = TRD_R + TRD_R / 8;
+__device__ __forceinline__ int trd_p(int t) { return t + (t >> 3); }
 
 __device__ __forceinline__ zd shfl_xor_z(zd v, int o) { return mk(__shfl_xor(v.re, o, 64), __shfl_xor(v.im, o, 64)); }
 
@@ -1190,10 +1196,10 @@ __device__ __forceinline__ zd shfl_xor_z(zd v, int o) { return mk(__shfl_xor(v.r
 __global__ void __launch_bounds__(TRD_THREADS)
 k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __restrict__ taus,
             zd* __restrict__ gpk) {
-  __shared__ zd xcol[2][TRD_R];
-  __shared__ zd xsh[2][TRD_R];
+  __shared__ zd xcol[2][TRD_RP];
+  __shared__ zd xsh[2][TRD_RP];
   __shared__ zd xv[2][TRD_WAVES];
-  __shared__ zd vpriv[TRD_WAVES][TRD_R];
+  __shared__ zd vpriv[TRD_WAVES][TRD_RP];
   const int f = blockIdx.x;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int a = 4 * w + (l >> 4), b = l & 15;
@@ -1225,7 +1231,7 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
       for (int jj = 0; jj < 8; ++jj)
         if (jk == jj) {
 #pragma unroll
-          for (int ii = 0; ii < 4; ++ii) xcol[par][r0 + ii] = A[ii][jj];
+          for (int ii = 0; ii < 4; ++ii) xcol[par][trd_p(r0 + ii)] = A[ii][jj];
         }
     }
     __syncthreads();
@@ -1234,11 +1240,11 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
 #pragma unroll
     for (int t0 = 0; t0 < TRD_R; t0 += 64) {
       const int t = t0 + l;
-      const zd xt = xcol[par][t];
+      const zd xt = xcol[par][trd_p(t)];
       xn += (t >= k + 2 && t < r) ? cabs2(xt) : 0.0;
     }
     xn = wave_sum(xn);
-    const zd alpha = xcol[par][k + 1];
+    const zd alpha = xcol[par][trd_p(k + 1)];
     const bool active = (xn > 0.0 || alpha.im != 0.0);   // uniform
     double beta = alpha.re;
     zd tau = mk(0.0, 0.0), sc = mk(0.0, 0.0);
@@ -1260,13 +1266,13 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
 #pragma unroll
     for (int t0 = 0; t0 < TRD_R; t0 += 64) {
       const int t = t0 + l;
-      const zd sv = cmul(xcol[par][t], sc);
+      const zd sv = cmul(xcol[par][trd_p(t)], sc);
       const zd vt = zsel(t == k + 1, mk(1.0, 0.0), zsel(t > k + 1 && t < r && active, sv, mk(0.0, 0.0)));
-      vp[t] = vt;
+      vp[trd_p(t)] = vt;
       if (w == 0 && t > k && t < r) S[pk_off(k, r) + (t - k)] = vt;
     }
     if (w == 0 && l == 0) {
-      dout[k] = xcol[par][k].re;
+      dout[k] = xcol[par][trd_p(k)].re;
       eout[k] = beta;
       taus[(int64_t)f * r + k] = tau;
     }
@@ -1279,7 +1285,7 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
       for (int ii = 0; ii < 4; ++ii) sp[ii] = mk(0.0, 0.0);
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
-        const zd vj = vp[c0 + jj];
+        const zd vj = vp[trd_p(c0 + jj)];
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) sp[ii] = zfma(A[ii][jj], vj, sp[ii]);
       }
@@ -1296,8 +1302,8 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
       zd x = cmul(tau, qv);
       if (myrow <= k || myrow >= r) x = mk(0.0, 0.0);
       const bool writer = (l & 3) == 0;
-      zd c = writer ? cmulc(x, vp[myrow]) : mk(0.0, 0.0);   // conj(x) v
-      if (writer) xsh[par][myrow] = x;
+      zd c = writer ? cmulc(x, vp[trd_p(myrow)]) : mk(0.0, 0.0);   // conj(x) v
+      if (writer) xsh[par][trd_p(myrow)] = x;
       c = wave_sum(c);
       if (l == 0) xv[par][w] = c;
     }
@@ -1317,14 +1323,14 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
       zd vi[4], wi[4];
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
-        vi[ii] = vp[r0 + ii];
-        wi[ii] = cadd(xsh[par][r0 + ii], cmul(a2, vi[ii]));
+        vi[ii] = vp[trd_p(r0 + ii)];
+        wi[ii] = cadd(xsh[par][trd_p(r0 + ii)], cmul(a2, vi[ii]));
       }
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
-        const zd vj = vp[c0 + jj];
+        const zd vj = vp[trd_p(c0 + jj)];
         const zd vcc = cconj(vj);
-        const zd xj = xsh[par][c0 + jj];
+        const zd xj = xsh[par][trd_p(c0 + jj)];
         const zd wcc = cconj(cadd(zsel(c0 + jj > k, xj, mk(0.0, 0.0)), cmul(a2, vj)));
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) A[ii][jj] = zfms(wi[ii], vcc, zfms(vi[ii], wcc, A[ii][jj]));

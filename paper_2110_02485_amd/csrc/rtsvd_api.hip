@@ -14,6 +14,7 @@
 
 #include "common.hpp"
 #include "fft.hpp"
+#include "gauss.hpp"
 #include "gram.hpp"
 #include "gemm.hpp"
 #include "skinny.hpp"
@@ -648,9 +649,21 @@ static int eta_from_gram(const double* sumsq, int64_t nblk, const zd* G, int64_t
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// After the tube DFT of A: flag bit 1 when ||A||_F^2 is not finite (a NaN or infinite entry, or an
+// overflowing norm) and, in that case only, zero A-hat so that the rest of the factor runs on the
+// zero operator (outputs unspecified; rtsvd_factor_info and rtsvd_solve report RTSVD_E_NOTFINITE).
+template <typename Tw>
+static int finite_guard(const double* sumsq, int64_t nblk, int* flags, cplx<Tw>* Ah, int64_t count, zb* Ah16,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_finite_check, dim3(1), dim3(FIN_THREADS), 0, s, sumsq, nblk, flags);
+  if (hipGetLastError() != hipSuccess) return -1;
+  if (launch_zero_if_nonfinite<cplx<Tw>>(Ah, count, flags, s)) return -1;
+  return launch_zero_if_nonfinite<zb>(Ah16, count, flags, s);
+}
+
 template <typename Tin, typename Tw>
-static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int64_t n, int64_t r, int precision,
-                       int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd_mode, double adapt_eps = 0.0,
+static int factor_impl(const Tin* A, const Tin* omega, uint64_t seed, int64_t l, int64_t m, int64_t n, int64_t r,
+                       int precision, int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd_mode, double adapt_eps = 0.0,
                        int groups_req = 0) {
   typedef cplx<Tw> zw;
   const int64_t F = n / 2 + 1;
@@ -665,6 +678,13 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     Omh = sc.get<zw>(F * m * r);
     if (!Omh) return fail(RTSVD_E_NOMEM, "device allocation failed: Omh");
   }
+  // Gaussian tensor of the sketch: the caller's, or drawn on the device from `seed`
+  Tin* omg = nullptr;
+  if (!tsvd_mode && !omega) {
+    omg = sc.get<Tin>(m * r * n);
+    if (!omg) return fail(RTSVD_E_NOMEM, "device allocation failed: Gaussian tensor");
+    omega = omg;
+  }
   if (groups > 1) {
     fs = face_streams(groups);
     if (!fs) return fail(RTSVD_E_HIP, "rtsvd_factor: creating the face-group streams failed");
@@ -672,6 +692,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     // the tube DFT of Omega on group 0's stream, beside that of A on the caller's stream
     RT_CHECK_HIP(hipEventRecord(fs->start, s));
     RT_CHECK_HIP(hipStreamWaitEvent(fs->st[0], fs->start, 0));
+    if (omg) RT_TRY(launch_gaussian<Tin>(seed, m * r * n, omg, fs->st[0]));
     RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr,
                                  fs->st[0])));
     RT_CHECK_HIP(hipEventRecord(fs->omega_done, fs->st[0]));
@@ -684,11 +705,15 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     if (!Ah16) return fail(RTSVD_E_NOMEM, "device allocation failed: Ah16");
   }
   RT_ALLOC(sumsq, double, ceil_div(l * m, 2) + 1, sc);
+  RT_ALLOC(flags, int, 1, sc);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, flags, 0);
+  RT_LAUNCH_OK();
   int64_t nblk = 0;
   {
     RT_TIMED(RTSVD_T_FFT_A);
     RT_TRY((launch_rfft<Tin, Tw>(A, l * m, (int)n, Ah, l * m, Ah16, sumsq, &nblk, s)));
   }
+  RT_TRY(finite_guard(sumsq, nblk, flags, Ah, F * l * m, Ah16, s));
 
   // outputs owned by the handle
   zw* Qo = nullptr;  // Q (R-tSVD) or U (T-tSVD), l x r per face
@@ -696,8 +721,6 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
   RT_ALLOC(V, zd, F * m * r, sc);
   RT_ALLOC(Wo, zw, F * l * r, sc);
   RT_ALLOC(eta, double, r + 1, sc);
-  RT_ALLOC(flags, int, 1, sc);
-  RT_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
   zd* Ub = nullptr;
 
   RT_ALLOC(G, zd, F * r * r, sc);
@@ -715,6 +738,7 @@ static int factor_impl(const Tin* A, const Tin* omega, int64_t l, int64_t m, int
     RT_ALLOC(Ubs, zd, F * r * r, sc);
     if (groups == 1) {
       RT_TIMED(RTSVD_T_FFT_OMEGA);
+      if (omg) RT_TRY(launch_gaussian<Tin>(seed, m * r * n, omg, s));
       RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
     }
     FaceBufs<Tw> fb{Ah, Ah16, Omh, Y, tmp, Zb, G, Rinv, Ch, Ub, Ubs, lam, sigma, V, Wo, flags};
@@ -824,21 +848,21 @@ static void free_handle(rtsvd_factor_s* h) {
   delete h;
 }
 
-static int dispatch_factor(const void* A, const void* omega, int dtype, int64_t l, int64_t m, int64_t n, int64_t r,
-                           int precision, int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd, double ae = 0.0,
-                           int groups = 0) {
+static int dispatch_factor(const void* A, const void* omega, uint64_t seed, int dtype, int64_t l, int64_t m,
+                           int64_t n, int64_t r, int precision, int q, rtsvd_factor_s* h, hipStream_t s, bool tsvd,
+                           double ae = 0.0, int groups = 0) {
   if (dtype == RTSVD_F64) {
     if (work_is_double(precision))
-      return factor_impl<double, double>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd,
-                                         ae, groups);
-    return factor_impl<double, float>((const double*)A, (const double*)omega, l, m, n, r, precision, q, h, s, tsvd,
-                                      ae, groups);
+      return factor_impl<double, double>((const double*)A, (const double*)omega, seed, l, m, n, r, precision, q, h, s,
+                                         tsvd, ae, groups);
+    return factor_impl<double, float>((const double*)A, (const double*)omega, seed, l, m, n, r, precision, q, h, s,
+                                      tsvd, ae, groups);
   }
   if (work_is_double(precision))
-    return factor_impl<float, double>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd, ae,
-                                      groups);
-  return factor_impl<float, float>((const float*)A, (const float*)omega, l, m, n, r, precision, q, h, s, tsvd, ae,
-                                     groups);
+    return factor_impl<float, double>((const float*)A, (const float*)omega, seed, l, m, n, r, precision, q, h, s, tsvd,
+                                      ae, groups);
+  return factor_impl<float, float>((const float*)A, (const float*)omega, seed, l, m, n, r, precision, q, h, s, tsvd,
+                                   ae, groups);
 }
 
 extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int dtype, const rtsvd_opts* opts,
@@ -860,13 +884,12 @@ extern "C" int rtsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int 
   sk::TileOverride tile_guard(o.sketch_tile);
   const int64_t r = std::min<int64_t>((int64_t)o.k_max + o.oversample, m);
   if (r > 256) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_factor: r = min(k_max + oversample, m) must be <= 256");
-  if (!o.omega) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_factor: omega must be supplied");
   hipStream_t s = (hipStream_t)stream;
   rtsvd_factor_s* h = new rtsvd_factor_s();
   h->l = l; h->m = m; h->n = n; h->F = n / 2 + 1; h->r = r; h->dtype = dtype; h->precision = o.precision;
   h->kind = 0; h->k_max = o.k_max; h->oversample = o.oversample; h->eps = o.eps; h->stream = s;
   const double ae = (o.adaptive && o.eps > 0.0) ? o.eps : 0.0;
-  const int rc = dispatch_factor(A, o.omega, dtype, l, m, n, r, o.precision, o.power_iters, h, s, false, ae,
+  const int rc = dispatch_factor(A, o.omega, o.seed, dtype, l, m, n, r, o.precision, o.power_iters, h, s, false, ae,
                                  o.face_groups);
   if (rc != 0) { delete h; return rc; }
   *out = h;
@@ -888,7 +911,7 @@ extern "C" int ttsvd_factor(const void* A, int64_t l, int64_t m, int64_t n, int 
   rtsvd_factor_s* h = new rtsvd_factor_s();
   h->l = l; h->m = m; h->n = n; h->F = n / 2 + 1; h->r = m; h->dtype = dtype; h->precision = precision;
   h->kind = 1; h->k_max = k_max; h->oversample = 0; h->stream = s;
-  const int rc = dispatch_factor(A, nullptr, dtype, l, m, n, m, precision, 0, h, s, true);
+  const int rc = dispatch_factor(A, nullptr, 0, dtype, l, m, n, m, precision, 0, h, s, true);
   if (rc != 0) { delete h; return rc; }
   *out = h;
   return RTSVD_OK;
@@ -905,19 +928,21 @@ static int tevd_impl(const Tin* A, int64_t m, int64_t n, rtsvd_factor_s* h, hipS
   Scratch sc(s);
   RT_ALLOC(Ah, zw, F * m * m, sc);
   RT_ALLOC(sumsq, double, ceil_div(m * m, 2) + 1, sc);
+  RT_ALLOC(flags, int, 1, sc);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, flags, 0);
+  RT_LAUNCH_OK();
   int64_t nblk = 0;
   {
     RT_TIMED(RTSVD_T_FFT_A);
     RT_TRY((launch_rfft<Tin, Tw>(A, m * m, (int)n, Ah, m * m, (zb*)nullptr, sumsq, &nblk, s)));
   }
+  RT_TRY(finite_guard<Tw>(sumsq, nblk, flags, Ah, F * m * m, (zb*)nullptr, s));
   RT_ALLOC(sigma, double, F * r, sc);
   RT_ALLOC(s2, double, F * r, sc);
   RT_ALLOC(V, zd, F * m * r, sc);
   RT_ALLOC(Uo, zw, F * m * r, sc);
   RT_ALLOC(Wo, zw, F * m * r, sc);
   RT_ALLOC(eta, double, r + 1, sc);
-  RT_ALLOC(flags, int, 1, sc);
-  RT_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
   RT_ALLOC(G, zd, F * m * m, sc);
   RT_ALLOC(Ve, zd, F * m * m, sc);
   RT_ALLOC(lam, double, F * r, sc);
@@ -1000,17 +1025,24 @@ extern "C" int rtsvd_factor_info(rtsvd_handle f, int32_t* r, int32_t* faces, dou
   if (eta) std::copy(e.begin(), e.end(), eta);
   if (flags) *flags = fl;
   if (r_eps) {
+    // Alg. 6 tests eta after each new column: the first j >= 1 (as the fixed-precision factor uses)
     *r_eps = -1;
     if (f->eps > 0.0)
-      for (int64_t j = 0; j <= f->r; ++j)
+      for (int64_t j = 1; j <= f->r; ++j)
         if (e[j] < f->eps * f->eps) { *r_eps = (int32_t)j; break; }
   }
-  return RTSVD_OK;
+  if (fl & 2) return fail(RTSVD_E_NOTFINITE, "rtsvd_factor_info: A is not finite (||A||_F^2 overflowed or is NaN)");
+  return (fl & 1) ? RTSVD_W_RANK_DEFICIENT : RTSVD_OK;
 }
 
 // ---------------------------------------------------------------------------------------------
 // solve: coefficients, discrepancy principle, truncated solution, inverse DFT
 // ---------------------------------------------------------------------------------------------
+// Relative numerical-rank cutoff of the truncated pseudo-inverse: singular values at or below
+// sqrt(4 r eps) sigma_max (eps = 2^-52) are taken as zero -- the accuracy floor of singular values
+// obtained from the eigenvalues of C C^H (the eigensolver's relative cutoff 4 r eps, squared).
+static double pinv_rel(int64_t r) { return std::sqrt(4.0 * (double)r * 2.220446049250313e-16); }
+
 template <typename Tio, typename Tw>
 static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vector<double>& bounds, int k_start,
                       int kcap, Tio* X, int* k_out, double* resid_out, int* status_out, hipStream_t s) {
@@ -1029,7 +1061,8 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   if (h->Ub)
     RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)p, (int)r, h->Ub, r, r * r, D, r, r * p, T, r, r * p,
                                      (int)F, 1.0, false, s)));
-  hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(F * r * p)), dim3(256), 0, s, T, h->sigma, (int)r, (int)p, (int)F);
+  hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(F * r * p)), dim3(256), 0, s, T, h->sigma, (int)r, (int)p, (int)F,
+                     pinv_rel(r));
   RT_LAUNCH_OK();
   // residual norms for k = 1..kcap, then the first k meeting the principle
   const int tiles = (int)ceil_div(l, DP_ROWS);
@@ -1052,7 +1085,7 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
                      (int)p, kcap, (int)n, groups, resid_out, rho_tmp);
   RT_LAUNCH_OK();
   hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(DP_SELECT_THREADS), 0, s, kcap, groups, (const double*)bnd, bnd_args,
-                     k_start, (const double*)rho_tmp, k_out, status_out);
+                     k_start, (const double*)rho_tmp, (const int*)h->flags, k_out, status_out);
   RT_LAUNCH_OK();
   // X-hat = V T', T' = T with rows >= k zeroed; X = inverse DFT
   hipLaunchKernelGGL(k_mask_coeffs, dim3(nblocks(F * r * p)), dim3(256), 0, s, T, D, k_out, groups, (int)r, (int)p,
@@ -1074,7 +1107,8 @@ extern "C" int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype, 
   if (dtype != f->dtype) return fail(RTSVD_E_ARG, "rtsvd_solve: dtype differs from the factor's");
   if (n_delta != 1 && n_delta != p) return fail(RTSVD_E_ARG, "rtsvd_solve: n_delta must be 1 or p");
   if (!(eta_dp > 1.0)) return fail(RTSVD_E_ARG, "rtsvd_solve: eta_dp must be > 1");
-  if (k_start < 0 || k_start > f->k_max) return fail(RTSVD_E_ARG, "rtsvd_solve: need 0 <= k_start <= k_max");
+  if (k_start < 0 || k_start > std::min<int64_t>(f->k_max, f->r))
+    return fail(RTSVD_E_ARG, "rtsvd_solve: need 0 <= k_start <= min(k_max, r)");
   for (int i = 0; i < n_delta; ++i)
     if (!(delta[i] >= 0.0)) return fail(RTSVD_E_ARG, "rtsvd_solve: delta must be >= 0");
   int ks = k_start, kcap = std::min<int>(f->k_max, (int)f->r);
@@ -1741,12 +1775,31 @@ extern "C" int rtsvd_solve_vjp(const void* A, const void* dA, const void* B, con
 }
 
 // ---------------------------------------------------------------------------------------------
+// Gaussian tensor of the sketch (the one rtsvd_factor draws when omega == NULL)
+// ---------------------------------------------------------------------------------------------
+extern "C" int rtsvd_gaussian(uint64_t seed, int64_t m, int64_t r, int64_t n, int dtype, void* out, void* stream) {
+  g_last_error.clear();
+  if (!out) return fail(RTSVD_E_ARG, "rtsvd_gaussian: null output");
+  if (m < 1 || r < 1 || n < 1) return fail(RTSVD_E_ARG, "rtsvd_gaussian: sizes must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t count = m * r * n;
+  if ((count + 1) / 2 > GAUSS_MAX_PAIRS) return fail(RTSVD_E_UNSUPPORTED, "rtsvd_gaussian: more than 2^32 elements");
+  int rc;
+  if (dtype == RTSVD_F64) rc = launch_gaussian<double>(seed, count, (double*)out, s);
+  else if (dtype == RTSVD_F32) rc = launch_gaussian<float>(seed, count, (float*)out, s);
+  else return fail(RTSVD_E_ARG, "rtsvd_gaussian: bad dtype");
+  if (rc) return fail(RTSVD_E_HIP, "rtsvd_gaussian: launch failed");
+  return RTSVD_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
 extern "C" const char* rtsvd_status_string(int status) {
   switch (status) {
     case RTSVD_OK: return "ok";
     case RTSVD_W_DP_NOT_MET: return "warning: discrepancy principle not met within k_cap";
     case RTSVD_W_RANK_DEFICIENT: return "warning: rank-deficient sketch (breakdown threshold reached)";
     case RTSVD_E_ARG: return "error: invalid argument";
+    case RTSVD_E_NOTFINITE: return "error: non-finite input (NaN or infinity)";
     case RTSVD_E_HIP: return "error: HIP runtime failure";
     case RTSVD_E_NOMEM: return "error: out of device memory";
     case RTSVD_E_UNSUPPORTED: return "error: unsupported configuration";

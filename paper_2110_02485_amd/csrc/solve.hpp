@@ -18,15 +18,27 @@ constexpr int DP_KCH = 64;         // residual orders per transposition chunk
 constexpr int DP_SEL_THREADS = 1024;
 constexpr int HEEV_RMAX_SOLVE = 256;  // largest r (the eigensolver's limit)
 
-// T = diag(1/sigma) E, zero where sigma <= 0 (dependent columns excluded from the pseudo-inverse)
-__global__ void k_scale_rows(zd* __restrict__ T, const double* __restrict__ sigma, int r, int p, int F) {
+// T = diag(sigma)^+ E: rows divided by the singular values; a singular value at or below
+// rel * sigma_max, sigma_max the largest over all faces (sigma[f * r] is face f's largest), counts
+// as zero and its row is zeroed (numerical rank of the pseudo-inverse of the block-diagonal Fourier
+// form of A; this also drops dependent sketch columns and faces of A that are zero up to rounding).
+// Launched with 256 threads per block.
+__global__ void __launch_bounds__(256) k_scale_rows(zd* __restrict__ T, const double* __restrict__ sigma, int r, int p,
+                                                    int F, double rel) {
+  __shared__ double red[4];
+  double mx = 0.0;
+  for (int f = threadIdx.x; f < F; f += blockDim.x) mx = fmax(mx, sigma[(int64_t)f * r]);
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  const double cut = rel * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)F * r * p;
   if (idx >= total) return;
   const int j = (int)(idx % r);
   const int64_t f = idx / ((int64_t)r * p);
   const double s = sigma[f * r + j];
-  T[idx] = s > 0.0 ? cscale(T[idx], 1.0 / s) : mk(0.0, 0.0);
+  T[idx] = s > cut ? cscale(T[idx], 1.0 / s) : mk(0.0, 0.0);
 }
 
 // partial[((f * tiles + tile) * p + c) * kcap + (k-1)] = sum over the tile's rows of
@@ -96,7 +108,8 @@ k_dp_rho(const double* __restrict__ partial, int F, int tiles, int p, int kcap, 
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < DP_RHO_THREADS / 64; ++w) t += red[w];
-    const double rho = sqrt(fmax(t / (double)n, 0.0));
+    const double q = t / (double)n;
+    const double rho = q < 0.0 ? 0.0 : sqrt(q);     // a NaN sum stays NaN (fmax would drop it)
     rho_tmp[idx] = rho;
     if (resid_out) resid_out[idx] = rho;
   }
@@ -109,13 +122,21 @@ k_dp_rho(const double* __restrict__ partial, int F, int tiles, int p, int kcap, 
 constexpr int DP_SELECT_THREADS = 256;
 __global__ void __launch_bounds__(DP_SELECT_THREADS)
 k_dp_select(int kcap, int groups, const double* __restrict__ bound /* eta*delta per group */, Vals16 bound_args,
-            int k_start, const double* __restrict__ rho_tmp, int* __restrict__ k_out, int* __restrict__ status_out) {
-  __shared__ int any_fail;
-  if (threadIdx.x == 0) any_fail = 0;
+            int k_start, const double* __restrict__ rho_tmp, const int* __restrict__ fflags, int* __restrict__ k_out,
+            int* __restrict__ status_out) {
+  __shared__ int any_fail, non_finite;
+  if (threadIdx.x == 0) {
+    any_fail = 0;
+    non_finite = (fflags && (*fflags & 2)) ? 1 : 0;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
   for (int g = wave; g < groups; g += nw) {
     const double b = groups <= 16 ? bound_args.v[g] : bound[g];
+    // a non-finite residual (B, or the factor, not finite) fails every test below and is reported
+    bool bad = false;
+    for (int k = 1 + lane; k <= kcap; k += 64) bad |= !isfinite(rho_tmp[(int64_t)g * kcap + k - 1]);
+    if (__ballot(bad) && lane == 0) atomicOr(&non_finite, 1);
     int kk = -1;
     for (int k0 = k_start; k0 <= kcap && kk < 0; k0 += 64) {
       const int k = k0 + lane;
@@ -130,7 +151,8 @@ k_dp_select(int kcap, int groups, const double* __restrict__ bound /* eta*delta 
     if (lane == 0) k_out[g] = kk;
   }
   __syncthreads();
-  if (threadIdx.x == 0 && status_out) *status_out = any_fail ? RTSVD_W_DP_NOT_MET : RTSVD_OK;
+  if (threadIdx.x == 0 && status_out)
+    *status_out = non_finite ? RTSVD_E_NOTFINITE : (any_fail ? RTSVD_W_DP_NOT_MET : RTSVD_OK);
 }
 
 // T'[f][j][c] = T[f][j][c] if j < k of column c's group, else 0

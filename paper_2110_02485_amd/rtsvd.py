@@ -19,13 +19,13 @@ LIB_PATH = os.path.join(_HERE, "librtsvd.so")
 F64, F32 = 0, 1
 P_FP64, P_FP32, P_BF16 = 0, 1, 2
 OK, W_DP_NOT_MET, W_RANK_DEFICIENT = 0, 1, 2
-E_ARG, E_HIP, E_NOMEM, E_UNSUPPORTED = -1, -3, -4, -5
+E_ARG, E_NOTFINITE, E_HIP, E_NOMEM, E_UNSUPPORTED = -1, -2, -3, -4, -5
 
 PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
            "tprod", "tprod_adjoint", "tgkb_solve", "nested_tgkb_solve", "ttevd_factor", "tlanczos_solve", "rtsvd_status_string", "rtsvd_last_error",
-           "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim"]
+           "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim", "rtsvd_gaussian"]
 
 
 class RtsvdError(RuntimeError):
@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rtsvd_timer_enable.argtypes = [ctypes.c_int]
     lib.rtsvd_timer_read.argtypes = [ctypes.c_int, pdbl, pi32]
     lib.rtsvd_trim.argtypes = []
+    lib.rtsvd_gaussian.argtypes = [ctypes.c_uint64, i64, i64, i64, ctypes.c_int, vp, vp]
     _lib = lib
     return lib
 
@@ -107,6 +108,19 @@ def _dev(t: torch.Tensor, name: str) -> torch.Tensor:
 
 def _stream() -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def gaussian(seed: int, m: int, r: int, n: int, dtype=torch.float64, device="cuda") -> torch.Tensor:
+    """The Gaussian test tensor (m x r x n, storage shape (n, r, m)) that rtsvd_factor draws on the
+    device from `seed` when no omega is given (Philox4x32-10 + Box-Muller, see include/rtsvd.h)."""
+    lib = load()
+    out = torch.empty((n, r, m), dtype=dtype, device=device)
+    code = F64 if dtype == torch.float64 else F32 if dtype == torch.float32 else None
+    if code is None:
+        raise TypeError(f"unsupported dtype {dtype}")
+    _check(lib.rtsvd_gaussian(int(seed) & ((1 << 64) - 1), m, r, n, code, out.data_ptr(), _stream()),
+           "rtsvd_gaussian")
+    return out
 
 
 def tprod(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
@@ -147,10 +161,12 @@ class SolveResult:
 class Factor:
     """An R-tSVD (or T-tSVD) factor held by the library; solve() may be called many times."""
 
-    def __init__(self, handle: int, dtype: torch.dtype, device, m: int, k_max: int, r: int, oversample: int):
+    def __init__(self, handle: int, dtype: torch.dtype, device, l: int, m: int, n: int, k_max: int, r: int,
+                 oversample: int):
         self._h = ctypes.c_void_p(handle)
         self.dtype, self.device = dtype, device
-        self.m, self.k_max, self.r, self.oversample = m, k_max, r, oversample
+        self.l, self.m, self.n = l, m, n
+        self.k_max, self.r, self.oversample = k_max, r, oversample
 
     @classmethod
     def rtsvd(cls, A: torch.Tensor, k_max: int, oversample: int, power_iters: int = 0, precision: str = "fp64",
@@ -160,17 +176,18 @@ class Factor:
         A = _dev(A, "A")
         n, m, l = A.shape
         r = min(k_max + oversample, m)
-        if omega is None:
-            raise ValueError("omega (storage shape (n, r, m)) must be supplied")
-        omega = _dev(omega, "omega")
-        if tuple(omega.shape) != (n, r, m) or omega.dtype != A.dtype:
-            raise ValueError(f"omega must have shape {(n, r, m)} and dtype {A.dtype}")
-        opts = _Opts(k_max, oversample, power_iters, PRECISIONS[precision], seed, omega.data_ptr(), eps,
+        optr = None
+        if omega is not None:     # else: drawn on the device from `seed` (rtsvd_gaussian)
+            omega = _dev(omega, "omega")
+            if tuple(omega.shape) != (n, r, m) or omega.dtype != A.dtype or omega.device != A.device:
+                raise ValueError(f"omega must have shape {(n, r, m)}, dtype {A.dtype} and A's device")
+            optr = omega.data_ptr()
+        opts = _Opts(k_max, oversample, power_iters, PRECISIONS[precision], int(seed) & ((1 << 64) - 1), optr, eps,
                      1 if adaptive else 0, face_groups, sketch_tile)
         h = ctypes.c_void_p()
         _check(lib.rtsvd_factor(A.data_ptr(), l, m, n, _dtype_code(A), ctypes.byref(opts), _stream(),
                                 ctypes.byref(h)), "rtsvd_factor")
-        f = cls(h.value, A.dtype, A.device, m, k_max, r, oversample)
+        f = cls(h.value, A.dtype, A.device, l, m, n, k_max, r, oversample)
         f._keep = omega  # the factor reads omega asynchronously
         if adaptive and eps > 0.0:
             f.r = f.info()[0]   # the fixed-precision factor keeps r_eps columns (the call synchronized)
@@ -184,7 +201,7 @@ class Factor:
         h = ctypes.c_void_p()
         _check(lib.ttsvd_factor(A.data_ptr(), l, m, n, _dtype_code(A), PRECISIONS[precision], k_max, _stream(),
                                 ctypes.byref(h)), "ttsvd_factor")
-        return cls(h.value, A.dtype, A.device, m, k_max, m, 0)
+        return cls(h.value, A.dtype, A.device, l, m, n, k_max, m, 0)
 
     @classmethod
     def ttevd(cls, A: torch.Tensor, k_max: int, precision: str = "fp64") -> "Factor":
@@ -197,24 +214,49 @@ class Factor:
         h = ctypes.c_void_p()
         _check(lib.ttevd_factor(A.data_ptr(), m, n, _dtype_code(A), PRECISIONS[precision], k_max, _stream(),
                                 ctypes.byref(h)), "ttevd_factor")
-        return cls(h.value, A.dtype, A.device, m, k_max, m, 0)
+        return cls(h.value, A.dtype, A.device, m, m, n, k_max, m, 0)
 
-    def info(self):
-        """(r, faces, eta (r+1), r_eps, sigma (faces, r), flags); synchronizes."""
+    def info(self, with_status: bool = False):
+        """(r, faces, eta (r+1), r_eps, sigma (faces, r), flags) and, with_status, the call's status
+        (OK, W_RANK_DEFICIENT or E_NOTFINITE: a non-finite A is reported, not raised); synchronizes."""
         import numpy as np
         lib = load()
         r, faces, r_eps, flags = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         lib.rtsvd_factor_info(self._h, ctypes.byref(r), ctypes.byref(faces), None, None, None, None)
         eta = np.zeros(r.value + 1)
         sig = np.zeros(r.value * faces.value)
-        _check(lib.rtsvd_factor_info(self._h, ctypes.byref(r), ctypes.byref(faces),
-                                     eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(r_eps),
-                                     sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(flags)),
-               "rtsvd_factor_info")
-        return r.value, faces.value, eta, r_eps.value, sig.reshape(faces.value, r.value), flags.value
+        rc = lib.rtsvd_factor_info(self._h, ctypes.byref(r), ctypes.byref(faces),
+                                   eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(r_eps),
+                                   sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(flags))
+        if rc != E_NOTFINITE:
+            _check(rc, "rtsvd_factor_info")
+        out = (r.value, faces.value, eta, r_eps.value, sig.reshape(faces.value, r.value), flags.value)
+        return out + (rc,) if with_status else out
 
     def k_cap(self, k_start: int) -> int:
         return self.r if k_start == 0 else min(self.k_max, self.r)
+
+    def check_solve_args(self, shape, dtype, device, groups: int, k_start: int, out=None) -> None:
+        """Raise ValueError unless B (storage shape `shape`) and the optional output buffers fit this
+        factor: the library reads l p n elements of B and writes m p n of X, sizes it takes from the
+        factor, so a mismatch must be caught before the call."""
+        n, p, l = shape
+        if (n, l) != (self.n, self.l) or dtype != self.dtype or device != self.device:
+            raise ValueError(f"B must have storage shape ({self.n}, p, {self.l}), dtype {self.dtype} and the "
+                             f"factor's device; got {tuple(shape)} {dtype} {device}")
+        if groups not in (1, p):
+            raise ValueError(f"delta must hold 1 or p = {p} values, got {groups}")
+        if not 0 <= k_start <= min(self.k_max, self.r):
+            raise ValueError(f"k_start must be in [0, min(k_max, r)] = [0, {min(self.k_max, self.r)}]")
+        if out is None:
+            return
+        kcap = self.k_cap(k_start)
+        want = {"X": ((n, p, self.m), dtype), "k": ((groups,), torch.int32),
+                "resid": ((groups, kcap), torch.float64), "status": ((1,), torch.int32)}
+        for name, (shp, dt) in want.items():
+            t = getattr(out, name)
+            if tuple(t.shape) != shp or t.dtype != dt or t.device != self.device or not t.is_contiguous():
+                raise ValueError(f"out.{name} must be a contiguous {dt} tensor of shape {shp} on the factor's device")
 
     def solve(self, B: torch.Tensor, delta, eta: float, k_start: int = 1, out: SolveResult | None = None) -> SolveResult:
         lib = load()
@@ -223,6 +265,7 @@ class Factor:
         deltas = [float(d) for d in (delta if hasattr(delta, "__len__") else [delta])]
         groups = len(deltas)
         kcap = self.k_cap(k_start)
+        self.check_solve_args(tuple(B.shape), B.dtype, B.device, groups, k_start, out)
         if out is None:
             out = SolveResult(X=torch.empty((n, p, self.m), dtype=B.dtype, device=B.device),
                               k=torch.empty(groups, dtype=torch.int32, device=B.device),
@@ -252,11 +295,12 @@ def trim() -> None:
 
 
 def factor(A, k_max, oversample, power_iters=0, precision="fp64", omega=None, eps=0.0, adaptive=False,
-           face_groups=0, sketch_tile=0) -> Factor:
-    """R-tSVD factor of A (see Factor.rtsvd); adaptive=True with eps > 0: Alg. 6's fixed-precision rank;
+           face_groups=0, sketch_tile=0, seed=0) -> Factor:
+    """R-tSVD factor of A (see Factor.rtsvd); omega None: the Gaussian tensor is drawn on the device from
+    `seed` (see gaussian()); adaptive=True with eps > 0: Alg. 6's fixed-precision rank;
     face_groups: 0 automatic, 1..3; sketch_tile: 0 automatic, 1, 2, 4 or 8 sixteen-column tiles per
     workgroup in the A-hat products (the result depends on neither)."""
-    return Factor.rtsvd(A, k_max, oversample, power_iters, precision, omega, eps, adaptive=adaptive,
+    return Factor.rtsvd(A, k_max, oversample, power_iters, precision, omega, eps, seed=seed, adaptive=adaptive,
                         face_groups=face_groups, sketch_tile=sketch_tile)
 
 
@@ -331,6 +375,13 @@ def solve_vjp(A: torch.Tensor, dA, B: torch.Tensor, omega: torch.Tensor, gX: tor
     A, B, omega, gX = _dev(A, "A"), _dev(B, "B"), _dev(omega, "omega"), _dev(gX, "gX")
     n, m, l = A.shape
     _, p, _ = B.shape
+    r = min(k + oversample, m)
+    for name, t, shape in (("B", B, (n, p, l)), ("omega", omega, (n, r, m)), ("gX", gX, (n, p, m))):
+        if tuple(t.shape) != shape or t.dtype != A.dtype or t.device != A.device:
+            raise ValueError(f"{name} must have storage shape {shape}, dtype {A.dtype} and A's device; "
+                             f"got {tuple(t.shape)} {t.dtype}")
+    if dA is not None and (tuple(dA.shape) != tuple(A.shape) or dA.dtype != A.dtype or dA.device != A.device):
+        raise ValueError("dA must match A in shape, dtype and device")
     gB = torch.empty_like(B)
     gdot = None
     dptr = None

@@ -106,3 +106,51 @@ def test_bench_refuses_several_gpus():
                          text=True, timeout=60)
     assert out.returncode == 2
     assert "one GPU" in out.stdout
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librtsvd.so not built")
+def test_gaussian_argument_errors_without_gpu():
+    from paper_2110_02485_amd import rtsvd as rt
+    lib = rt.load()
+    assert lib.rtsvd_gaussian(1, 4, 4, 4, 0, None, None) == rt.E_ARG
+    assert lib.rtsvd_gaussian(1, 0, 4, 4, 0, ctypes.c_void_p(16), None) == rt.E_ARG
+    assert lib.rtsvd_gaussian(1, 4, 4, 4, 9, ctypes.c_void_p(16), None) == rt.E_ARG
+    assert lib.rtsvd_gaussian(1, 1 << 20, 1 << 12, 1 << 10, 0, ctypes.c_void_p(16), None) == rt.E_UNSUPPORTED
+    assert lib.rtsvd_status_string(rt.E_NOTFINITE) is not None
+
+
+def test_solve_arguments_are_checked_before_the_call():
+    # Factor.solve validates B and the output buffers against the factor's sizes (the library reads
+    # l p n elements of B and writes m p n of X with the factor's l, m, n): mismatches raise before
+    # any launch
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    f = rt.Factor.__new__(rt.Factor)
+    f._h = None
+    f.dtype, f.device = torch.float64, torch.device("cuda", 0)
+    f.l, f.m, f.n, f.k_max, f.r, f.oversample = 40, 32, 16, 10, 14, 4
+    dev = torch.device("cuda", 0)
+    f.check_solve_args((16, 3, 40), torch.float64, dev, 1, 1)            # fits
+    f.check_solve_args((16, 3, 40), torch.float64, dev, 3, 0)
+    with pytest.raises(ValueError):
+        f.check_solve_args((8, 3, 40), torch.float64, dev, 1, 1)         # fewer tubes than the factor's n
+    with pytest.raises(ValueError):
+        f.check_solve_args((16, 3, 39), torch.float64, dev, 1, 1)        # rows differ from l
+    with pytest.raises(ValueError):
+        f.check_solve_args((16, 3, 40), torch.float32, dev, 1, 1)        # dtype
+    with pytest.raises(ValueError):
+        f.check_solve_args((16, 3, 40), torch.float64, torch.device("cuda", 1), 1, 1)
+    with pytest.raises(ValueError):
+        f.check_solve_args((16, 3, 40), torch.float64, dev, 2, 1)        # 2 bounds for 3 slices
+    with pytest.raises(ValueError):
+        f.check_solve_args((16, 3, 40), torch.float64, dev, 1, 11)       # k_start > min(k_max, r)
+
+    class Out:
+        pass
+    out = Out()
+    out.X = torch.empty((16, 3, 31), dtype=torch.float64)                # m is 32
+    out.k = torch.empty(1, dtype=torch.int32)
+    out.resid = torch.empty((1, 10), dtype=torch.float64)
+    out.status = torch.empty(1, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        f.check_solve_args((16, 3, 40), torch.float64, dev, 1, 1, out)
