@@ -169,6 +169,19 @@ int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype,
                 const double* delta, int32_t n_delta, double eta_dp, int32_t k_start,
                 void* X, int32_t* k_out, double* resid_out, int32_t* status_out, void* stream);
 
+/* rtsvd_solve without device allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results (bit for bit) and errors as rtsvd_solve.  Its scratch (B-hat, coefficients, residual
+ * sums, X-hat: about F (l p cs + 2 r p 16 + ceil(l/64) p k_cap 8 + m p 16) bytes, cs = 8 for
+ * FP32/BF16 work, 16 for FP64) is a fixed 64 MiB device array of the library, one per device,
+ * held until the process ends; a solve that needs more returns RTSVD_E_UNSUPPORTED before any
+ * work is issued.  Every call on a device uses the same array: calls that overlap on one device
+ * (concurrent streams or threads) race and must be serialized by the caller.  Nothing in the
+ * array needs to start at zero (every slice is written before it is read).                   */
+int rtsvd_solve_noalloc(rtsvd_handle f, const void* B, int64_t p, int dtype, const double* delta,
+                        int32_t n_delta, double eta_dp, int32_t k_start, void* X, int32_t* k_out,
+                        double* resid_out, int32_t* status_out, void* stream);
+
 /* t-product C = A * B (Definition 2.1 via the tube DFT, Section 2).
  * A: l x m x n, B: m x p x n, C: l x p x n, all DEVICE, same dtype.  Computed in the dtype. */
 int tprod(const void* A, const void* B, void* C, int64_t l, int64_t m, int64_t p, int64_t n,

@@ -346,6 +346,18 @@ inline int ilog2_exact(int64_t n) {
 // is published only once its fill kernel has completed (the calling thread waits for it), so any
 // stream may read a cached table without an event.  The first use of a length n on a device must
 // therefore not happen while the stream is being captured into a graph (nullptr is returned then).
+// While a TwiddleLookupOnly guard lives on the calling thread, twiddles() only looks tables up
+// and never creates one (callers that must not allocate device memory).
+inline bool& twiddle_lookup_only() {
+  static thread_local bool v = false;
+  return v;
+}
+struct TwiddleLookupOnly {
+  bool prev;
+  TwiddleLookupOnly() : prev(twiddle_lookup_only()) { twiddle_lookup_only() = true; }
+  ~TwiddleLookupOnly() { twiddle_lookup_only() = prev; }
+};
+
 template <typename T>
 const cplx<T>* twiddles(int n, hipStream_t s) {
   static std::mutex mu;
@@ -356,6 +368,7 @@ const cplx<T>* twiddles(int n, hipStream_t s) {
   auto key = std::make_pair(dev, n);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
+  if (twiddle_lookup_only()) return nullptr;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return nullptr;
   cplx<T>* tw = nullptr;
@@ -367,6 +380,14 @@ const cplx<T>* twiddles(int n, hipStream_t s) {
   }
   cache[key] = tw;
   return tw;
+}
+
+// creates the tables a solve with tube length n uses (forward DFT of B in T, inverse DFT in FP64),
+// so that later solves, also allocation-free ones, find them
+template <typename T>
+inline int ensure_solve_twiddles(int n, hipStream_t s) {
+  if (ilog2_exact(n) < 0 || n < 2) return 0;   // direct DFT: no table
+  return (twiddles<T>(n, s) && twiddles<double>(n, s)) ? 0 : -1;
 }
 
 template <typename T>

@@ -131,6 +131,22 @@ struct Scratch {
   }
 };
 
+// bump allocator over a fixed device region (the allocation-free entry point): hands out
+// 256-byte aligned slices in request order, nullptr once the region is exhausted; allocates nothing
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t cap = 0, used = 0;
+  static size_t round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+  template <typename T> T* get(int64_t count) {
+    if (count <= 0) count = 1;
+    const size_t bytes = round((size_t)count * sizeof(T));
+    if (!base || used + bytes > cap) return nullptr;
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
 #define RT_ALLOC(var, type, count, sc)                                             \
   type* var = (sc).template get<type>(count);                                      \
   if (!var) return fail(RTSVD_E_NOMEM, "device allocation failed: " #var)
@@ -669,6 +685,7 @@ static int factor_impl(const Tin* A, const Tin* omega, uint64_t seed, int64_t l,
   const int64_t F = n / 2 + 1;
   const bool bf16 = (precision == RTSVD_P_BF16);
   Scratch sc(s);
+  if (ensure_solve_twiddles<Tw>((int)n, s)) return fail(RTSVD_E_HIP, "rtsvd_factor: twiddle tables");
   // face groups (R-tSVD, fixed rank, no stage timers): see rtsvd_faces_qc / QcGroup
   const int groups = (tsvd_mode || adapt_eps > 0.0 || timers_on()) ? 1 : face_groups(F, groups_req);
   FaceStreams* fs = nullptr;
@@ -926,6 +943,7 @@ static int tevd_impl(const Tin* A, int64_t m, int64_t n, rtsvd_factor_s* h, hipS
   typedef cplx<Tw> zw;
   const int64_t F = n / 2 + 1, r = m;
   Scratch sc(s);
+  if (ensure_solve_twiddles<Tw>((int)n, s)) return fail(RTSVD_E_HIP, "ttevd_factor: twiddle tables");
   RT_ALLOC(Ah, zw, F * m * m, sc);
   RT_ALLOC(sumsq, double, ceil_div(m * m, 2) + 1, sc);
   RT_ALLOC(flags, int, 1, sc);
@@ -1043,13 +1061,25 @@ extern "C" int rtsvd_factor_info(rtsvd_handle f, int32_t* r, int32_t* faces, dou
 // obtained from the eigenvalues of C C^H (the eigensolver's relative cutoff 4 r eps, squared).
 static double pinv_rel(int64_t r) { return std::sqrt(4.0 * (double)r * 2.220446049250313e-16); }
 
-template <typename Tio, typename Tw>
+// Device scratch of one solve, in the order solve_impl requests it (each slice 256-byte aligned).
+static size_t solve_scratch_bytes(const rtsvd_factor_s* h, int64_t p, int groups, int kcap) {
+  const size_t cw = work_is_double(h->precision) ? 16 : 8;
+  const int64_t tiles = ceil_div(h->l, DP_ROWS);
+  size_t b = Arena::round((size_t)(h->F * h->l * p) * cw);                 // B-hat
+  b += 2 * Arena::round((size_t)(h->F * h->r * p) * 16);                   // D, T
+  b += Arena::round((size_t)(h->F * tiles * p * kcap) * 8);                // residual partial sums
+  if (groups > 16) b += Arena::round((size_t)groups * 8);                  // bounds in device memory
+  b += Arena::round((size_t)groups * kcap * 8);                            // rho
+  b += Arena::round((size_t)(h->F * h->m * p) * 16);                       // X-hat
+  return b;
+}
+
+template <typename Tio, typename Tw, typename SC>
 static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vector<double>& bounds, int k_start,
-                      int kcap, Tio* X, int* k_out, double* resid_out, int* status_out, hipStream_t s) {
+                      int kcap, Tio* X, int* k_out, double* resid_out, int* status_out, hipStream_t s, SC& sc) {
   typedef cplx<Tw> zw;
   const int64_t l = h->l, m = h->m, n = h->n, F = h->F, r = h->r;
   const int groups = (int)bounds.size();
-  Scratch sc(s);
   RT_TIMED(RTSVD_T_SOLVE);
   RT_ALLOC(Bh, zw, F * l * p, sc);
   RT_TRY((launch_rfft<Tio, Tw>(B, l * p, (int)n, Bh, l * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
@@ -1098,10 +1128,10 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   return 0;
 }
 
-extern "C" int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype, const double* delta, int32_t n_delta,
-                           double eta_dp, int32_t k_start, void* X, int32_t* k_out, double* resid_out,
-                           int32_t* status_out, void* stream) {
-  g_last_error.clear();
+// argument checks, truncation range and bounds shared by rtsvd_solve and rtsvd_solve_noalloc
+static int solve_setup(rtsvd_handle f, const void* B, int64_t p, int dtype, const double* delta, int32_t n_delta,
+                       double eta_dp, int32_t k_start, const void* X, const int32_t* k_out, int* ks, int* kcap,
+                       std::vector<double>& bounds) {
   if (!f || !B || !X || !delta || !k_out) return fail(RTSVD_E_ARG, "rtsvd_solve: null argument");
   if (p < 1) return fail(RTSVD_E_ARG, "rtsvd_solve: p must be >= 1");
   if (dtype != f->dtype) return fail(RTSVD_E_ARG, "rtsvd_solve: dtype differs from the factor's");
@@ -1111,25 +1141,97 @@ extern "C" int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype, 
     return fail(RTSVD_E_ARG, "rtsvd_solve: need 0 <= k_start <= min(k_max, r)");
   for (int i = 0; i < n_delta; ++i)
     if (!(delta[i] >= 0.0)) return fail(RTSVD_E_ARG, "rtsvd_solve: delta must be >= 0");
-  int ks = k_start, kcap = std::min<int>(f->k_max, (int)f->r);
+  *ks = k_start;
+  *kcap = std::min<int>(f->k_max, (int)f->r);
   if (k_start == 0) {
-    ks = std::max<int>(1, (int)f->r - f->oversample);
-    kcap = (int)f->r;
+    *ks = std::max<int>(1, (int)f->r - f->oversample);
+    *kcap = (int)f->r;
   }
-  std::vector<double> bounds(n_delta);
+  bounds.resize(n_delta);
   for (int i = 0; i < n_delta; ++i) bounds[i] = eta_dp * delta[i];
-  hipStream_t s = (hipStream_t)stream;
+  return 0;
+}
+
+template <typename SC>
+static int solve_dispatch(rtsvd_handle f, const void* B, int64_t p, const std::vector<double>& bounds, int ks,
+                          int kcap, void* X, int32_t* k_out, double* resid_out, int32_t* status_out, hipStream_t s,
+                          SC& sc) {
   if (f->dtype == RTSVD_F64) {
     if (work_is_double(f->precision))
       return solve_impl<double, double>(f, (const double*)B, p, bounds, ks, kcap, (double*)X, k_out, resid_out,
-                                        status_out, s);
+                                        status_out, s, sc);
     return solve_impl<double, float>(f, (const double*)B, p, bounds, ks, kcap, (double*)X, k_out, resid_out,
-                                     status_out, s);
+                                     status_out, s, sc);
   }
   if (work_is_double(f->precision))
     return solve_impl<float, double>(f, (const float*)B, p, bounds, ks, kcap, (float*)X, k_out, resid_out, status_out,
-                                     s);
-  return solve_impl<float, float>(f, (const float*)B, p, bounds, ks, kcap, (float*)X, k_out, resid_out, status_out, s);
+                                     s, sc);
+  return solve_impl<float, float>(f, (const float*)B, p, bounds, ks, kcap, (float*)X, k_out, resid_out, status_out, s,
+                                  sc);
+}
+
+extern "C" int rtsvd_solve(rtsvd_handle f, const void* B, int64_t p, int dtype, const double* delta, int32_t n_delta,
+                           double eta_dp, int32_t k_start, void* X, int32_t* k_out, double* resid_out,
+                           int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  int ks = 0, kcap = 0;
+  std::vector<double> bounds;
+  const int rc = solve_setup(f, B, p, dtype, delta, n_delta, eta_dp, k_start, X, k_out, &ks, &kcap, bounds);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Scratch sc(s);
+  return solve_dispatch(f, B, p, bounds, ks, kcap, X, k_out, resid_out, status_out, s, sc);
+}
+
+// ---------------------------------------------------------------------------------------------
+// rtsvd_solve without device allocation: its scratch is a fixed device array of the library
+// ---------------------------------------------------------------------------------------------
+// `scratch` is a host-side stand-in for the array in host code; its device address is obtained
+// once per device with hipGetSymbolAddress and used everywhere instead of the name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_noalloc_mu;
+static unsigned char* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of this device's copy of `scratch` (looked up on the first call on the device)
+static unsigned char* noalloc_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_noalloc_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  return g_noalloc_ptr[dev];
+}
+
+extern "C" int rtsvd_solve_noalloc(rtsvd_handle f, const void* B, int64_t p, int dtype, const double* delta,
+                                   int32_t n_delta, double eta_dp, int32_t k_start, void* X, int32_t* k_out,
+                                   double* resid_out, int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  int ks = 0, kcap = 0;
+  std::vector<double> bounds;
+  const int rc = solve_setup(f, B, p, dtype, delta, n_delta, eta_dp, k_start, X, k_out, &ks, &kcap, bounds);
+  if (rc) return rc;
+  const size_t need = solve_scratch_bytes(f, p, (int)bounds.size(), kcap);
+  if (need > NOALLOC_SCRATCH_BYTES) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "rtsvd_solve_noalloc: the solve needs %zu bytes of scratch, above the %zu-byte "
+             "maximum (use rtsvd_solve)", need, NOALLOC_SCRATCH_BYTES);
+    return fail(RTSVD_E_UNSUPPORTED, buf);
+  }
+  Arena arena;
+  arena.base = noalloc_scratch();
+  if (!arena.base) return fail(RTSVD_E_HIP, "rtsvd_solve_noalloc: hipGetSymbolAddress of the scratch array failed");
+  arena.cap = NOALLOC_SCRATCH_BYTES;
+  TwiddleLookupOnly no_new_tables;   // the factor created every table this solve uses
+  return solve_dispatch(f, B, p, bounds, ks, kcap, X, k_out, resid_out, status_out, (hipStream_t)stream, arena);
 }
 
 // ---------------------------------------------------------------------------------------------

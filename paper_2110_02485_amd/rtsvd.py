@@ -25,7 +25,8 @@ PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
            "tprod", "tprod_adjoint", "tgkb_solve", "nested_tgkb_solve", "ttevd_factor", "tlanczos_solve", "rtsvd_status_string", "rtsvd_last_error",
-           "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim", "rtsvd_gaussian"]
+           "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim", "rtsvd_gaussian",
+           "rtsvd_solve_noalloc"]
 
 
 class RtsvdError(RuntimeError):
@@ -60,6 +61,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rtsvd_factor_destroy.argtypes = [vp]
     lib.rtsvd_factor_destroy.restype = None
     lib.rtsvd_solve.argtypes = [vp, vp, i64, ctypes.c_int, pdbl, i32, dbl, i32, vp, vp, vp, vp, vp]
+    lib.rtsvd_solve_noalloc.argtypes = [vp, vp, i64, ctypes.c_int, pdbl, i32, dbl, i32, vp, vp, vp, vp, vp]
     lib.tprod.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int, vp]
     lib.tprod_adjoint.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int, vp]
     if hasattr(lib, "tgkb_solve"):
@@ -258,7 +260,11 @@ class Factor:
             if tuple(t.shape) != shp or t.dtype != dt or t.device != self.device or not t.is_contiguous():
                 raise ValueError(f"out.{name} must be a contiguous {dt} tensor of shape {shp} on the factor's device")
 
-    def solve(self, B: torch.Tensor, delta, eta: float, k_start: int = 1, out: SolveResult | None = None) -> SolveResult:
+    def solve(self, B: torch.Tensor, delta, eta: float, k_start: int = 1, out: SolveResult | None = None,
+              no_alloc: bool = False) -> SolveResult:
+        """Truncated solution with the discrepancy principle.  no_alloc: rtsvd_solve_noalloc (the
+        library's fixed scratch array instead of device allocations; pass `out` as well for a call
+        that allocates nothing at all)."""
         lib = load()
         B = _dev(B, "B")
         n, p, l = B.shape
@@ -272,9 +278,9 @@ class Factor:
                               resid=torch.empty((groups, kcap), dtype=torch.float64, device=B.device),
                               status=torch.empty(1, dtype=torch.int32, device=B.device))
         arr = (ctypes.c_double * groups)(*deltas)
-        _check(lib.rtsvd_solve(self._h, B.data_ptr(), p, _dtype_code(B), arr, groups, eta, k_start,
-                               out.X.data_ptr(), out.k.data_ptr(), out.resid.data_ptr(), out.status.data_ptr(),
-                               _stream()), "rtsvd_solve")
+        fn, name = (lib.rtsvd_solve_noalloc, "rtsvd_solve_noalloc") if no_alloc else (lib.rtsvd_solve, "rtsvd_solve")
+        _check(fn(self._h, B.data_ptr(), p, _dtype_code(B), arr, groups, eta, k_start, out.X.data_ptr(),
+                  out.k.data_ptr(), out.resid.data_ptr(), out.status.data_ptr(), _stream()), name)
         return out
 
     def close(self):
