@@ -193,6 +193,7 @@ class Workload:
     video: bool = False
     problems: list = field(default_factory=list)  # per-problem frame counts (differentiable batch)
     symmetric: bool = False  # circularly symmetric blur tube (A^T = A)
+    seed_name: str = ""      # draw the inputs of this workload (same X_true, noise direction, Omega)
 
     @property
     def r(self) -> int:
@@ -206,6 +207,9 @@ class Workload:
 WORKLOADS = {
     "blur64": Workload("blur64", 64, 16, 2.0, 6, 1, 20, 10, 0, 1e-2, precision="fp64"),
     "blur256": Workload("blur256", 256, 256, 3.0, 10, 1, 60, 10, 0, 1e-3, precision="fp32", squares=3),
+    # the same image and noise direction at the second noise level of the 256-wide comparison
+    "blur256n2": Workload("blur256n2", 256, 256, 3.0, 10, 1, 60, 10, 0, 1e-2, precision="fp32", squares=3,
+                          seed_name="blur256"),
     "video512": Workload("video512", 512, 64, 3.0, 10, 64, 80, 10, 0, 1e-2, precision="fp32", video=True),
     "blur1024": Workload("blur1024", 1024, 128, 3.0, 10, 1, 100, 20, 1, 1e-3, precision="mixed"),
     # differentiable batch: 16 clips of uneven frame counts (4 to 32) restored in one call
@@ -229,14 +233,15 @@ def make_inputs(w: Workload, dtype=np.float64, seed_extra: int = 0):
     their choice.
     """
     A = blur_operator(w.size, w.n, w.sigma, w.band, dtype=np.float64, symmetric=w.symmetric)
-    rx = rng_for(w.name, "xtrue", seed_extra)
+    key = w.seed_name or w.name
+    rx = rng_for(key, "xtrue", seed_extra)
     if w.video:
         frames = moving_blob_video(w.size, w.n, max(w.p, 1), rx)
         X = lateral_slices(frames)
     else:
         X = lateral_slices(blob_image(w.size, w.n, rx, squares=w.squares)[None])
-    E0 = noise_direction((w.n, X.shape[1], w.size), rng_for(w.name, "noise", seed_extra))
-    Om = gaussian_omega(w.size, w.r, w.n, rng_for(w.name, "omega", seed_extra))
+    E0 = noise_direction((w.n, X.shape[1], w.size), rng_for(key, "noise", seed_extra))
+    Om = gaussian_omega(w.size, w.r, w.n, rng_for(key, "omega", seed_extra))
     return A.astype(dtype), X.astype(dtype), E0, Om.astype(dtype)
 
 
