@@ -36,6 +36,9 @@ TAGS = {1: "fft_A", 2: "fft_omega", 3: "sketch", 4: "power", 5: "project", 6: "W
 # the others bracket several kernels (packing passes, the four eigensolver kernels, the solve)
 SINGLE_KERNEL = {"fft_A": "k_rfft_reg", "fft_omega": "k_rfft_reg", "gram": "k_gram_lower", "chol": "k_cholinv",
                  "W_mma": "k_skinny (FP32 MFMA, W = A-hat V)"}
+# FP32/FP64 skinny products issue three real MFMA products per complex multiply-add (6 real
+# flops for the standard count of 8): the issued MFMA rate is 3/4 of the effective one
+ISSUED_FRACTION = {"W_mma": 0.75, "W": 0.75}
 # stages whose brackets in one step are different kernels (svd_aux: the Gram C C^H, V and the error
 # indicator): their model is the work of the whole step, priced against the step's summed time
 PER_STEP = {"svd_aux"}
@@ -135,6 +138,10 @@ def parse():
                          "the symmetric-A methods on sym256)")
     ap.add_argument("--krylov-only", action="store_true",
                     help="only the comparison methods (colour-image Krylov timing, symmetric-A comparison)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (256-wide method comparison at two noise levels, the "
+                         "512-wide video restoration with graph replay, the differentiable 16-clip batch)")
+    ap.add_argument("--configs-only", action="store_true", help="only the other configurations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM counters against known bytes)")
     return ap.parse_args()
@@ -233,18 +240,43 @@ def time_steps(torch, rt, prob, w, precision, steps, warmup, timers=False, split
     out = {"X": res.X, "k": int(res.k[0]), "status": int(res.status[0])}
     last.close()
     if timers:
-        import ctypes
-        stages = {}
-        for tag, name in TAGS.items():
-            tot, cnt = ctypes.c_double(), ctypes.c_int32()
-            lib.rtsvd_timer_read(tag, ctypes.byref(tot), ctypes.byref(cnt))
-            if cnt.value:
-                stages[name] = {"ms_per_step": tot.value / steps, "launches_per_step": cnt.value / steps,
-                                "avg_launch_us": 1e3 * tot.value / cnt.value,
-                                **roofline_of(name, tot.value / steps, cnt.value / steps, w, precision)}
+        out["stages"] = read_stages(lib, steps, w, precision)
         lib.rtsvd_timer_enable(0)
-        out["stages"] = stages
     return ev_ms / steps, wall, out
+
+
+def read_stages(lib, steps, w, precision):
+    """Per-stage times of the last `steps` steps from the library's stage timers, with rooflines."""
+    import ctypes
+    stages = {}
+    for tag, name in TAGS.items():
+        tot, cnt = ctypes.c_double(), ctypes.c_int32()
+        lib.rtsvd_timer_read(tag, ctypes.byref(tot), ctypes.byref(cnt))
+        if cnt.value:
+            stages[name] = {"ms_per_step": tot.value / steps, "launches_per_step": cnt.value / steps,
+                            "avg_launch_us": 1e3 * tot.value / cnt.value,
+                            **roofline_of(name, tot.value / steps, cnt.value / steps, w, precision)}
+    return stages
+
+
+def dominant_roofline(stages, precision):
+    """Roofline object of the single-kernel stage with the most time per step, plus the fraction
+    of the MFMA rate actually issued (three real products per complex multiply-add in FP32/FP64)
+    and the stages below 60 % of their bound."""
+    single = [k for k in stages if k in SINGLE_KERNEL]
+    if not single:
+        return None
+    dom = max(single, key=lambda k: stages[k]["ms_per_step"])
+    st = stages[dom]
+    out = {"kernel": SINGLE_KERNEL[dom], "stage": dom, "bound": st["bound"], "achieved": st["achieved"],
+           "peak": st["peak"], "unit": st["unit"], "frac": st["frac"], "traffic": traffic_of(dom, precision),
+           "avg_launch_us": st["avg_launch_us"], "launches_per_step": st["launches_per_step"]}
+    if dom in ISSUED_FRACTION and st["unit"] == "TFLOP/s":
+        out["rate"] = "effective (8 flops per complex multiply-add)"
+        out["issued_frac"] = st["frac"] * ISSUED_FRACTION[dom]
+    out["stages_below_0.6"] = {k: round(v["frac"], 3) for k, v in stages.items() if v["frac"] < 0.6}
+    out["lowest_stage"] = min(stages, key=lambda k: stages[k]["frac"])
+    return out
 
 
 def time_krylov(torch, rt, wl, steps):
@@ -312,46 +344,331 @@ def time_symmetric(torch, rt, wl, steps):
     return out
 
 
-def cpu_baseline(w, wl):
-    """Time the FP64 oracle on a bounded sample of the same workload and scale to one solve."""
-    import threading
+# ---------------------------------------------------------------------------------------------
+# other configurations: 256-wide method comparison, 512-wide video with graph replay, adjoint
+# ---------------------------------------------------------------------------------------------
+def _events_ms(torch, fn, steps):
+    """Average ms of `fn` over `steps` calls issued back to back between two events on the current
+    stream (one warm-up call first)."""
+    fn()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def _rel_err(torch, X, x_true):
+    return float(torch.linalg.norm(X.double() - x_true) / torch.linalg.norm(x_true))
+
+
+def time_comparison_256(torch, rt, wl, steps):
+    """The 256 x 256 x 256 comparison (FP32): R-tSVD (r = 60 + 10), T-tSVD and tGKB restorations per
+    second at relative noise 1e-3 and 1e-2 (Section 5's noise of eq. (e1)), k and relative error to
+    X_true.  Returns (entries, GPU results for the CPU-baseline leg's oracle comparison)."""
+    out, gpu = {}, {}
+    dev = torch.device("cuda:0")
+    for name in ("blur256", "blur256n2"):
+        w = wl.WORKLOADS[name]
+        prob = make_problem(w, dev, torch, rt, wl)
+        At, Bd, Omt, x_true, delta = prob["A32"], prob["B32"], prob["Om32"], prob["X64"], prob["delta"]
+        entry = {"l": w.size, "m": w.size, "n": w.n, "k_max": w.k_max, "oversample": w.oversample,
+                 "noise": w.noise, "eta": w.eta, "precision": "fp32"}
+        print(f"[bench] 256-wide comparison, noise {w.noise}", file=sys.stderr, flush=True)
+
+        def rtsvd_run():
+            f = rt.factor(At, w.k_max, w.oversample, 0, "fp32", Omt)
+            r = f.solve(Bd, delta, w.eta, 1)
+            f.close()
+            return r
+
+        def ttsvd_run():
+            f = rt.ttsvd_factor(At, w.k_max, "fp32")
+            r = f.solve(Bd, delta, w.eta, 1)
+            f.close()
+            return r
+        res = {}
+        for meth, run, st in (("rtsvd", rtsvd_run, steps), ("ttsvd", ttsvd_run, max(2, steps // 3))):
+            ms = _events_ms(torch, run, st)
+            r = run()
+            torch.cuda.synchronize()
+            entry[meth] = {"value": 1000.0 / ms, "unit": "restorations/s", "ms_per_step": ms, "k": int(r.k[0]),
+                           "dp_status": int(r.status[0]), "rel_error": _rel_err(torch, r.X, x_true)}
+            res[meth] = (r.X.double().cpu().numpy(), int(r.k[0]))
+        # the Krylov call waits on the device's progress: wall clock around complete calls
+        rt.tgkb_solve(At, Bd, delta, w.eta, w.k_max)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            Xk, kk, _, st = rt.tgkb_solve(At, Bd, delta, w.eta, w.k_max)
+        torch.cuda.synchronize()
+        ms_g = (time.perf_counter() - t0) * 1e3 / 3
+        entry["tgkb"] = {"value": 1000.0 / ms_g, "unit": "solves/s", "ms_per_step": ms_g, "k": int(kk[0]),
+                         "dp_status": int(st[0]), "rel_error": _rel_err(torch, Xk, x_true),
+                         "timing": "host wall clock per call (the step loop waits on device progress)"}
+        res["tgkb"] = (Xk.double().cpu().numpy(), int(kk[0]))
+        entry["rtsvd_speedup_over_ttsvd"] = entry["ttsvd"]["ms_per_step"] / entry["rtsvd"]["ms_per_step"]
+        out[f"noise_{w.noise:g}"] = entry
+        gpu[name] = res
+    return out, gpu
+
+
+def _capture(torch, fn, stream):
+    """HIP graph of fn() captured on `stream` (after one eager call there, which fills the stream's
+    workspace cache so that the captured call allocates nothing)."""
+    with torch.cuda.stream(stream):
+        fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream, capture_error_mode="relaxed"):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def time_video_512(torch, rt, wl, steps, tune_enabled=True):
+    """The 512 x 512 x 64 video restoration (FP32, 64 frames as lateral slices, joint k): one
+    restoration (factor + solve) eager and replayed from a HIP graph, the solve alone with a cached
+    factor (eager and replayed), frames per second, and the stages with their rooflines.  Returns
+    (entry, GPU result for the CPU-baseline leg)."""
+    w = wl.WORKLOADS["video512"]
+    dev = torch.device("cuda:0")
+    prob = make_problem(w, dev, torch, rt, wl)
+    At, Bd, Omt, x_true, delta = prob["A32"], prob["B32"], prob["Om32"], prob["X64"], prob["delta"]
+    p = Bd.shape[1]
+    print("[bench] 512-wide video restoration", file=sys.stderr, flush=True)
+    tuned = tuned_split(torch, prob, w, "fp32", tune_enabled)
+    split = tuned or {}
+    groups, tile = split.get("face_groups", 0), split.get("sketch_tile", 0)
+
+    def make_restore(state):
+        def restore():
+            f = rt.factor(At, w.k_max, w.oversample, 0, "fp32", Omt, face_groups=groups, sketch_tile=tile)
+            state["res"] = f.solve(Bd, delta, w.eta, 1, out=state.get("res"))
+            if "f" in state:
+                state["f"].close()     # its buffers go back to the stream's cache (host side)
+            state["f"] = f
+        return restore
+    state = {}
+    ms_eager = _events_ms(torch, make_restore(state), steps)
+    res = state["res"]
+    k, status = int(res.k[0]), int(res.status[0])
+    X_eager = res.X.clone()
+    # one restoration replayed from a graph captured on a stream of its own; the captured factor
+    # handle stays alive and is rewritten by every replay
+    gstate = {}
+    graph_note = "captured: factor (face groups on the library's streams) + solve"
+    try:
+        g = _capture(torch, make_restore(gstate), torch.cuda.Stream())
+        ms_graph = _events_ms(torch, g.replay, steps)
+        graph_identical = bool(torch.equal(gstate["res"].X, X_eager))
+    except Exception as e:  # capture refused: reported, eager figures stand
+        ms_graph, graph_identical, graph_note = None, None, f"capture failed: {e}"
+    f = state["f"]
+    sstate = {}
+
+    def solve_only():
+        sstate["res"] = f.solve(Bd, delta, w.eta, 1, out=sstate.get("res"))
+    ms_solve = _events_ms(torch, solve_only, steps)
+    try:
+        g2 = _capture(torch, solve_only, torch.cuda.Stream())
+        ms_solve_graph = _events_ms(torch, g2.replay, steps)
+    except Exception as e:
+        ms_solve_graph = None
+        graph_note += f"; solve capture failed: {e}"
+    # stages (one face group, full-size launches) with their rooflines
+    lib = rt.load()
+    lib.rtsvd_timer_enable(1)
+    for _ in range(3):
+        ff = rt.factor(At, w.k_max, w.oversample, 0, "fp32", Omt)
+        ff.solve(Bd, delta, w.eta, 1)
+        ff.close()
+    torch.cuda.synchronize()
+    stages = read_stages(lib, 3, w, "fp32")
+    lib.rtsvd_timer_enable(0)
+    best = min(v for v in (ms_eager, ms_graph) if v is not None)
+    best_solve = min(v for v in (ms_solve, ms_solve_graph) if v is not None)
+    entry = {"l": w.size, "m": w.size, "n": w.n, "p": p, "k_max": w.k_max, "oversample": w.oversample,
+             "noise": w.noise, "eta": w.eta, "precision": "fp32",
+             "tuning": ({"face_groups": groups, "sketch_tile": tile, "candidates_ms": tuned["table"]}
+                        if tuned else "automatic"),
+             "value": 1000.0 / best, "unit": "restorations/s", "frames_per_s": p * 1000.0 / best,
+             "ms_restoration_eager": ms_eager, "ms_restoration_graph": ms_graph, "graph": graph_note,
+             "graph_identical_to_eager": graph_identical,
+             "ms_solve_cached_factor_eager": ms_solve, "ms_solve_cached_factor_graph": ms_solve_graph,
+             "solves_per_s_cached_factor": 1000.0 / best_solve, "frames_per_s_cached_factor": p * 1000.0 / best_solve,
+             "k": k, "dp_status": status, "rel_error": _rel_err(torch, X_eager, x_true),
+             "roofline": dominant_roofline(stages, "fp32"),
+             "stages": {kk: {a: (round(b, 4) if isinstance(b, float) else b) for a, b in v.items()}
+                        for kk, v in stages.items()}}
+    return entry, {"rtsvd": (X_eager.double().cpu().numpy(), k)}
+
+
+def time_adjoint_512(torch, rt, wl, steps):
+    """The differentiable 16-clip batch (512 x 512 x 64, 4 to 32 frames per clip, 260 lateral
+    slices, FP32, k = 80): forward (factor + fixed-k solve) and forward + backward (hand-written
+    adjoint, factor recomputed) per batch."""
+    from paper_2110_02485_amd import autograd as ag
+    w = wl.WORKLOADS["diff512"]
+    dev = torch.device("cuda:0")
+    A, dA, X, E0, Om, off = wl.make_clip_inputs(w)
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
+    At, dAt, Omt, Xt = f32(A), f32(dA), f32(Om), f32(X)
+    Bt = rt.tprod(At, Xt)
+    B = Bt.clone()
+    for j in range(len(w.problems)):
+        e = f32(E0[j])
+        sl = slice(int(off[j]), int(off[j + 1]))
+        B[:, sl, :] += w.noise * e / torch.linalg.norm(e) * torch.linalg.norm(Bt[:, sl, :])
+    print("[bench] differentiable 16-clip batch", file=sys.stderr, flush=True)
+
+    def fwd():
+        s = torch.tensor(w.sigma, dtype=torch.float32, device=dev)
+        return ag.restore(B, s, At, None, Omt, w.k_max, w.oversample)
+
+    def fwd_bwd():
+        Bg = B.clone().requires_grad_(True)
+        s = torch.tensor(w.sigma, dtype=torch.float32, device=dev, requires_grad=True)
+        Xr = ag.restore(Bg, s, At, dAt, Omt, w.k_max, w.oversample)
+        L = 0.5 * ((Xr - Xt) ** 2).sum()
+        L.backward()
+        return L
+    ms_f = _events_ms(torch, fwd, steps)
+    ms_fb = _events_ms(torch, fwd_bwd, steps)
+    return {"l": w.size, "m": w.size, "n": w.n, "clips": len(w.problems), "slices": int(off[-1]),
+            "k": w.k_max, "oversample": w.oversample, "precision": "fp32",
+            "ms_forward": ms_f, "ms_forward_backward": ms_fb, "ms_backward": ms_fb - ms_f,
+            "batches_per_s_forward_backward": 1000.0 / ms_fb}
+
+
+# ---------------------------------------------------------------------------------------------
+# CPU-baseline leg: the FP64 oracle timed on the host on bounded samples, its per-face solutions
+# compared with the GPU's results on the same faces.  The only place the benchmark runs the oracle.
+# ---------------------------------------------------------------------------------------------
+def _oracle_problem(w, wl):
+    """Math-order inputs of workload w with B formed by the oracle's t-product (never the GPU's)."""
+    from oracle import tproduct as tp
+    A, X, E0, Om = wl.make_inputs(w)
+    Am, Xm = wl.to_math(A), wl.to_math(X)
+    ah = tp.fft_tubes(Am)
+    bt = tp.tprod_hat(ah, Xm)
+    E = wl.scale_noise(wl.to_math(E0), bt, w.noise)
+    return Am, ah, bt + E, wl.to_math(Om)
+
+
+def _face_diff(Xg_storage, faces, oracle_face):
+    """sqrt(sum_i ||X-hat_i(GPU) - X-hat_i(oracle)||^2 / sum_i ||X-hat_i(oracle)||^2) over `faces`."""
+    xh = np.fft.fft(np.asarray(Xg_storage).transpose(2, 1, 0), axis=2)
+    num = den = 0.0
+    for i in faces:
+        xo = oracle_face(i)
+        num += float(np.linalg.norm(xh[:, :, i] - xo) ** 2)
+        den += float(np.linalg.norm(xo) ** 2)
+    return float(np.sqrt(num / den))
+
+
+def _oracle_faces(w, ah, bh, om_h, method, k, faces):
+    """The oracle's X-hat faces of `method` at truncation k (FP64, one face at a time)."""
+    from oracle import factor as fa, tgkb as tg
+    out = {}
+    if method == "tgkb":
+        Wf, Qf, cf, zf = tg.tgkb_faces(ah[:, :, faces], bh[:, 0, faces], k)
+        xs = tg.tgkb_solution(Wf, cf, zf, k)
+        return {i: xs[:, :, j] for j, i in enumerate(faces)}
+    for i in faces:
+        A_i, O_i = ah[:, :, i], om_h[:, :, i]
+        if i == (w.n - i) % w.n:
+            A_i, O_i = A_i.real, O_i.real
+        if method == "ttsvd":
+            u, sv, vh = np.linalg.svd(A_i, full_matrices=False)
+            out[i] = vh[:k].conj().T @ ((u[:, :k].conj().T @ bh[:, :, i]) / sv[:k, None])
+        else:
+            out[i] = fa.solution_face(fa.rtsvd_face(A_i, O_i, w.power_iters), bh[:, :, i], k)
+    return out
+
+
+def cpu_baseline_configs(wl, gpu_256, gpu_video):
+    """Oracle per-face solutions on sampled faces of the 256-wide comparison (both noise levels,
+    three methods) and of the video restoration, against the GPU's results at the GPU's k."""
+    out = {}
+    for name, res in list(gpu_256.items()) + [("video512", gpu_video)]:
+        w = wl.WORKLOADS[name]
+        t0 = time.perf_counter()
+        Am, ah, bm, om = _oracle_problem(w, wl)
+        bh, om_h = np.fft.fft(bm, axis=2), np.fft.fft(om, axis=2)
+        faces = sorted({0, 1, w.faces // 2, w.faces - 1})
+        entry = {"faces": faces}
+        for meth, (Xg, k) in res.items():
+            of = _oracle_faces(w, ah, bh, om_h, meth, k, faces)
+            entry[meth] = {"k": k, "oracle_rel_diff_sampled_faces": _face_diff(Xg, faces, lambda i: of[i])}
+        entry["cpu_seconds"] = time.perf_counter() - t0
+        out[name] = entry
+    return out
+
+
+def cpu_baseline(w, wl, X_gpu=None, k_gpu=None):
+    """Time the FP64 oracle on a bounded sample of the headline workload and scale to one solve:
+    the tube DFT of A, the per-face factor of two sampled faces and three literal discrepancy
+    residuals; one warm-up, then the median of three runs, with every host core and with one
+    (BLAS threads; numpy's FFT is single-threaded).  With the GPU's X, also the relative
+    difference between the oracle's and the GPU's solution on four sampled faces at the GPU's k."""
+    from threadpoolctl import threadpool_limits
     from oracle import tproduct as tp, factor as fa, solve as so
     cores = len(os.sched_getaffinity(0))
     A, X, E0, Om = wl.make_inputs(w)
     Am, Xm, Omm = wl.to_math(A), wl.to_math(X), wl.to_math(Om)
-    t0 = time.perf_counter()
-    ah = tp.fft_tubes(Am)                                   # full tube DFT of A
-    t_fft = time.perf_counter() - t0
-    bt = tp.tprod_hat(ah, Xm)
-    E = wl.scale_noise(wl.to_math(E0), bt, w.noise)
-    b = bt + E
-    oh = tp.fft_tubes(Omm)
     faces = w.n // 2 + 1
-    sample_faces = [0, 1, faces // 2, faces - 1]
-    t0 = time.perf_counter()
-    for i in sample_faces:                                   # per-face factor work, as rtsvd_block
-        A_i, O_i = ah[:, :, i], oh[:, :, i]
-        q, _ = fa.qr_positive(A_i @ O_i)
-        for _ in range(w.power_iters):
-            qz, _ = fa.qr_positive(A_i.conj().T @ q)
-            q, _ = fa.qr_positive(A_i @ qz)
-        c = q.conj().T @ A_i
-        np.linalg.svd(c, full_matrices=False)
-    t_face = (time.perf_counter() - t0) / len(sample_faces)
-    # discrepancy search: one literal residual ||B - A * X_k|| per k tried (all k up to k_cap when
-    # the principle is not met); three k timed
-    V = np.zeros((w.size, w.r, w.n), dtype=complex)
-    T = np.zeros((w.r, 1, w.n), dtype=complex)
-    t0 = time.perf_counter()
-    for k in (1, 2, 3):
-        so.residual(ah, b, so.x_of_k(V, T, k))
-    t_k = (time.perf_counter() - t0) / 3
-    t_solve = t_fft + faces * t_face + min(w.k_max, w.r) * t_k
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": (f"FP64 numpy oracle: full tube DFT of A ({t_fft:.2f} s), per-face factor on "
-                       f"{len(sample_faces)} of {faces} faces ({t_face:.2f} s/face), 3 literal "
-                       f"discrepancy residuals ({t_k:.2f} s each) scaled to {min(w.k_max, w.r)}; "
-                       f"one solve = {t_solve:.1f} s")}
+    sample_faces = [1, faces // 2]
+    kcap = min(w.k_max, w.r)
+
+    def sample():
+        t0 = time.perf_counter()
+        ah = tp.fft_tubes(Am)                                   # full tube DFT of A
+        t_fft = time.perf_counter() - t0
+        oh = tp.fft_tubes(Omm)
+        t0 = time.perf_counter()
+        for i in sample_faces:                                  # per-face factor work (rtsvd_face)
+            fa.rtsvd_face(ah[:, :, i], oh[:, :, i], w.power_iters)
+        t_face = (time.perf_counter() - t0) / len(sample_faces)
+        # discrepancy search: one literal residual ||B - A * X_k|| per k tried (all k up to k_cap
+        # when the principle is not met); three k timed
+        V = np.zeros((w.size, w.r, w.n), dtype=complex)
+        T = np.zeros((w.r, 1, w.n), dtype=complex)
+        b = np.zeros((w.size, 1, w.n))
+        t0 = time.perf_counter()
+        for k in (1, 2, 3):
+            so.residual(ah, b, so.x_of_k(V, T, k))
+        t_k = (time.perf_counter() - t0) / 3
+        return t_fft + faces * t_face + kcap * t_k, (t_fft, t_face, t_k)
+
+    result = {"unit": "solves/s", "kind": "oracle", "cores": cores}
+    for label, limit in (("all_cores", cores), ("one_core", 1)):
+        with threadpool_limits(limits=limit):
+            sample()                                            # warm-up
+            runs = sorted(sample() for _ in range(3))
+        t_solve, (t_fft, t_face, t_k) = runs[1]
+        result[label] = {"value": 1.0 / t_solve, "seconds_per_solve": t_solve, "threads": limit,
+                         "tube_dft_s": t_fft, "per_face_s": t_face, "per_residual_s": t_k}
+    result["value"] = result["all_cores"]["value"]
+    result["sample"] = (f"FP64 numpy oracle, median of 3 after a warm-up: full tube DFT of A, per-face factor on "
+                        f"{len(sample_faces)} of {faces} faces scaled to {faces}, 3 literal discrepancy "
+                        f"residuals scaled to {kcap}; value with every host core ({cores}), one_core with one "
+                        f"BLAS thread")
+    if X_gpu is not None:
+        t0 = time.perf_counter()
+        ah = tp.fft_tubes(Am)
+        bm = tp.tprod_hat(ah, Xm)
+        bm = bm + wl.scale_noise(wl.to_math(E0), bm, w.noise)
+        bh, om_h = np.fft.fft(bm, axis=2), tp.fft_tubes(Omm)
+        fs = sorted({0, 1, faces // 2, faces - 1})
+        of = _oracle_faces(w, ah, bh, om_h, "rtsvd", k_gpu, fs)
+        result["oracle_rel_diff_sampled_faces"] = _face_diff(X_gpu, fs, lambda i: of[i])
+        result["oracle_faces"] = fs
+        result["oracle_check_s"] = time.perf_counter() - t0
+    return result
 
 
 def main():
@@ -376,6 +693,13 @@ def main():
     if args.krylov_only:
         print(json.dumps({"krylov": time_krylov(torch, rt, wl, args.steps),
                           "symmetric": time_symmetric(torch, rt, wl, args.steps)}), flush=True)
+        return
+    if args.configs_only:
+        cfg = time_configs(torch, rt, wl, args)
+        gpu_cfg = cfg.pop("_gpu")
+        if not args.no_cpu_baseline:
+            cfg["cpu_baseline_configs"] = cpu_baseline_configs(wl, gpu_cfg["c256"], gpu_cfg["video"])
+        print(json.dumps(cfg), flush=True)
         return
     w = wl.WORKLOADS[args.workload]
     precision = args.precision or w.precision
@@ -406,13 +730,7 @@ def main():
     }
     stages = out.get("stages", {})
     if stages:
-        single = [k for k in stages if k in SINGLE_KERNEL]
-        dom = max(single, key=lambda k: stages[k]["ms_per_step"])
-        st = stages[dom]
-        result["roofline"] = {"kernel": SINGLE_KERNEL[dom], "stage": dom, "bound": st["bound"],
-                              "achieved": st["achieved"], "peak": st["peak"], "unit": st["unit"], "frac": st["frac"],
-                              "traffic": traffic_of(dom, precision), "avg_launch_us": st["avg_launch_us"],
-                              "launches_per_step": st["launches_per_step"]}
+        result["roofline"] = dominant_roofline(stages, precision)
         result["stages"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                             for k, v in stages.items()}
     if not args.no_fp64 and precision != "fp64":
@@ -446,10 +764,28 @@ def main():
         result["krylov"] = time_krylov(torch, rt, wl, 3)
         print("[bench] symmetric-A comparison (T-tEVD, t-Lanczos, tGKB, T-tSVD, RT-tSVD)", file=sys.stderr, flush=True)
         result["symmetric"] = time_symmetric(torch, rt, wl, 3)
+    gpu_cfg = None
+    if not args.no_configs:
+        cfg = time_configs(torch, rt, wl, args)
+        gpu_cfg = cfg.pop("_gpu")
+        result.update(cfg)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(w, wl)
+        result["cpu_baseline"] = cpu_baseline(w, wl, out["X"].double().cpu().numpy(), out["k"])
+        if gpu_cfg:
+            print("[bench] oracle on sampled faces of the other configurations", file=sys.stderr, flush=True)
+            result["cpu_baseline"]["configs"] = cpu_baseline_configs(wl, gpu_cfg["c256"], gpu_cfg["video"])
     print(json.dumps(result), flush=True)
+
+
+def time_configs(torch, rt, wl, args):
+    """The other configurations: the 256-wide method comparison at two noise levels, the 512-wide
+    video restoration (graph replay, cached-factor solve) and the differentiable 16-clip batch."""
+    c256, gpu256 = time_comparison_256(torch, rt, wl, args.steps)
+    video, gpuvid = time_video_512(torch, rt, wl, args.steps, not args.no_tune)
+    adj = time_adjoint_512(torch, rt, wl, max(3, args.steps // 2))
+    return {"comparison_256": c256, "video_512": video, "adjoint_512": adj,
+            "_gpu": {"c256": gpu256, "video": gpuvid}}
 
 
 if __name__ == "__main__":

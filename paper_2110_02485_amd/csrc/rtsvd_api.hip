@@ -357,20 +357,22 @@ static int gram(const TY* Y, int64_t rows, int64_t r, int64_t F, zd* G, Scratch&
 // C_f = op(A_f) X_f on MFMA, X packed into pool scratch first
 // ktag: optional timer tag for the product kernel alone (without the packing pass);
 // utri: X is upper triangular (its zero blocks are skipped)
-template <typename TA, typename TX, typename TC>
+// P: MFMA precision (default: that of A's type; sk::F64 with an FP32 A gives FP64 accumulation)
+template <typename TA, typename TX, typename TC, typename SC = Scratch, class P = typename sk::PrecOf<TA>::P>
 static int skinny(bool conjA, int64_t M, int64_t N, int64_t K, const TA* A, int64_t lda, int64_t sA, const TX* X,
-                  int64_t ldx, int64_t sX, TC* C, int64_t ldc, int64_t sC, int64_t F, Scratch& sc, hipStream_t s,
+                  int64_t ldx, int64_t sX, TC* C, int64_t ldc, int64_t sC, int64_t F, SC& sc, hipStream_t s,
                   int ktag = 0, int utri = 0) {
   if (M <= 0 || N <= 0 || F <= 0) return 0;
   if (K <= 0) return fail(RTSVD_E_ARG, "skinny product: K must be positive");
-  unsigned char* ws = sc.get<unsigned char>(sk::skinny_ws_bytes<TA>((int)K, (int)N, (int)F));
+  unsigned char* ws = sc.template get<unsigned char>(sk::skinny_ws_bytes<TA, P>((int)K, (int)N, (int)F));
   if (!ws) return fail(RTSVD_E_NOMEM, "device allocation failed: packed operand");
-  if (sk::skinny_pack<TA, TX>((int)N, (int)K, X, ldx, sX, (int)F, ws, s)) return fail(RTSVD_E_HIP, "skinny pack launch");
+  if (sk::skinny_pack<TA, TX, P>((int)N, (int)K, X, ldx, sX, (int)F, ws, s))
+    return fail(RTSVD_E_HIP, "skinny pack launch");
   if (ktag) {
     RT_TIMED(ktag);
-    return sk::skinny_run<TA, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri);
+    return sk::skinny_run<TA, TC, P>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri);
   }
-  return sk::skinny_run<TA, TC>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri);
+  return sk::skinny_run<TA, TC, P>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1062,15 +1064,29 @@ extern "C" int rtsvd_factor_info(rtsvd_handle f, int32_t* r, int32_t* faces, dou
 static double pinv_rel(int64_t r) { return std::sqrt(4.0 * (double)r * 2.220446049250313e-16); }
 
 // Device scratch of one solve, in the order solve_impl requests it (each slice 256-byte aligned).
+// right-hand sides above which the solve's products run on MFMA (k_skinny) instead of the
+// matrix-vector kernels
+constexpr int SOLVE_MFMA_P = GEMV_NP;
+// columns of B summed per residual partial (joint principle)
+static int dp_cols_per_block(int groups, int64_t p) { return (groups == 1 && p >= 8) ? 8 : 1; }
+
 static size_t solve_scratch_bytes(const rtsvd_factor_s* h, int64_t p, int groups, int kcap) {
-  const size_t cw = work_is_double(h->precision) ? 16 : 8;
+  const bool dbl = work_is_double(h->precision);
+  const size_t cw = dbl ? 16 : 8;
   const int64_t tiles = ceil_div(h->l, DP_ROWS);
+  const int64_t pg = ceil_div(p, dp_cols_per_block(groups, p));
+  const int l = (int)h->l, r = (int)h->r, F = (int)h->F;
   size_t b = Arena::round((size_t)(h->F * h->l * p) * cw);                 // B-hat
   b += 2 * Arena::round((size_t)(h->F * h->r * p) * 16);                   // D, T
-  b += Arena::round((size_t)(h->F * tiles * p * kcap) * 8);                // residual partial sums
+  if (p > SOLVE_MFMA_P) {                                                  // packed operands of the products
+    b += Arena::round((size_t)(dbl ? sk::skinny_ws_bytes<zd>(l, (int)p, F) : sk::skinny_ws_bytes<zf, sk::F64>(l, (int)p, F)));
+    if (h->Ub) b += Arena::round((size_t)sk::skinny_ws_bytes<zd>(r, (int)p, F));
+  }
+  b += Arena::round((size_t)(h->F * tiles * pg * kcap) * 8);               // residual partial sums
   if (groups > 16) b += Arena::round((size_t)groups * 8);                  // bounds in device memory
   b += Arena::round((size_t)groups * kcap * 8);                            // rho
   b += Arena::round((size_t)(h->F * h->m * p) * 16);                       // X-hat
+  if (p > SOLVE_MFMA_P) b += Arena::round((size_t)sk::skinny_ws_bytes<zd>(r, (int)p, F));
   return b;
 }
 
@@ -1085,20 +1101,37 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   RT_TRY((launch_rfft<Tio, Tw>(B, l * p, (int)n, Bh, l * p, (zb*)nullptr, (double*)nullptr, nullptr, s)));
   RT_ALLOC(D, zd, F * r * p, sc);
   RT_ALLOC(T, zd, F * r * p, sc);
-  // D = Q^H B-hat (T-tSVD: U^H B-hat); T = U-breve^H D
-  RT_TRY((cgemm<zw, zw, zd, double>(true, false, (int)r, (int)p, (int)l, (const zw*)h->Q, l, l * r, Bh, l, l * p,
-                                   h->Ub ? D : T, r, r * p, (int)F, 1.0, false, s)));
-  if (h->Ub)
-    RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)p, (int)r, h->Ub, r, r * r, D, r, r * p, T, r, r * p,
-                                     (int)F, 1.0, false, s)));
+  // D = Q^H B-hat (T-tSVD: U^H B-hat); T = U-breve^H D.  Few right-hand sides: matrix-vector
+  // kernels (one pass over Q, FP64 sums); more: FP64 MFMA products (FP32 Q and B-hat converted on
+  // the way to the MFMA operands), so the sums are FP64 either way
+  const bool mfma = p > SOLVE_MFMA_P;
+  if (mfma)
+    RT_TRY((skinny<zw, zw, zd, SC, sk::F64>(true, r, p, l, (const zw*)h->Q, l, l * r, Bh, l, l * p, h->Ub ? D : T,
+                                            r, r * p, F, sc, s)));
+  else
+    RT_TRY((cgemm<zw, zw, zd, double>(true, false, (int)r, (int)p, (int)l, (const zw*)h->Q, l, l * r, Bh, l, l * p,
+                                     h->Ub ? D : T, r, r * p, (int)F, 1.0, false, s)));
+  if (h->Ub) {
+    if (mfma)
+      RT_TRY((skinny<zd, zd, zd, SC>(true, r, p, r, h->Ub, r, r * r, D, r, r * p, T, r, r * p, F, sc, s)));
+    else
+      RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)p, (int)r, h->Ub, r, r * r, D, r, r * p, T, r,
+                                       r * p, (int)F, 1.0, false, s)));
+  }
   hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(F * r * p)), dim3(256), 0, s, T, h->sigma, (int)r, (int)p, (int)F,
                      pinv_rel(r));
   RT_LAUNCH_OK();
   // residual norms for k = 1..kcap, then the first k meeting the principle
   const int tiles = (int)ceil_div(l, DP_ROWS);
-  RT_ALLOC(partial, double, F * tiles * p * kcap, sc);
-  hipLaunchKernelGGL((k_dp_partial<zw, zw>), dim3((unsigned)tiles, (unsigned)p, (unsigned)F), dim3(DP_ROWS), 0, s,
-                     Bh, (const zw*)h->W, T, (int)l, (int)p, (int)r, kcap, partial);
+  const int cpb = dp_cols_per_block(groups, p);
+  const int64_t pg = ceil_div(p, cpb);
+  RT_ALLOC(partial, double, F * tiles * pg * kcap, sc);
+  if (cpb == 8)
+    hipLaunchKernelGGL((k_dp_partial<8, zw, zw>), dim3((unsigned)tiles, (unsigned)pg, (unsigned)F), dim3(DP_ROWS), 0,
+                       s, Bh, (const zw*)h->W, T, (int)l, (int)p, (int)r, kcap, partial);
+  else
+    hipLaunchKernelGGL((k_dp_partial<1, zw, zw>), dim3((unsigned)tiles, (unsigned)p, (unsigned)F), dim3(DP_ROWS), 0,
+                       s, Bh, (const zw*)h->W, T, (int)l, (int)p, (int)r, kcap, partial);
   RT_LAUNCH_OK();
   // the bounds ride in the selection kernel's arguments for up to 16 groups, else in device memory
   Vals16 bnd_args = {};
@@ -1112,7 +1145,7 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
   }
   RT_ALLOC(rho_tmp, double, (int64_t)groups * kcap, sc);
   hipLaunchKernelGGL(k_dp_rho, dim3((unsigned)(groups * kcap)), dim3(DP_RHO_THREADS), 0, s, partial, (int)F, tiles,
-                     (int)p, kcap, (int)n, groups, resid_out, rho_tmp);
+                     (int)pg, kcap, (int)n, groups, resid_out, rho_tmp);
   RT_LAUNCH_OK();
   hipLaunchKernelGGL(k_dp_select, dim3(1), dim3(DP_SELECT_THREADS), 0, s, kcap, groups, (const double*)bnd, bnd_args,
                      k_start, (const double*)rho_tmp, (const int*)h->flags, k_out, status_out);
@@ -1122,8 +1155,11 @@ static int solve_impl(rtsvd_factor_s* h, const Tio* B, int64_t p, const std::vec
                      (int)F);
   RT_LAUNCH_OK();
   RT_ALLOC(Xh, zd, F * m * p, sc);
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)p, (int)r, h->V, m, m * r, D, r, r * p, Xh, m, m * p,
-                                   (int)F, 1.0, false, s)));
+  if (mfma)
+    RT_TRY((skinny<zd, zd, zd, SC>(false, m, p, r, h->V, m, m * r, D, r, r * p, Xh, m, m * p, F, sc, s)));
+  else
+    RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)p, (int)r, h->V, m, m * r, D, r, r * p, Xh, m,
+                                     m * p, (int)F, 1.0, false, s)));
   RT_TRY((launch_irfft<double, Tio>(Xh, m * p, m * p, (int)n, X, s)));
   return 0;
 }
@@ -1729,6 +1765,39 @@ extern "C" int tlanczos_solve(const void* A, const void* B, int64_t m, int64_t n
 
 
 // ---------------------------------------------------------------------------------------------
+// batched complex products of the adjoint: FP64 MFMA (k_skinny, FP32 operands converted on the
+// way to the MFMA operands, FP64 sums); C = alpha P or C += alpha P through a compact temporary
+// ---------------------------------------------------------------------------------------------
+template <typename TC>
+__global__ void k_axpby(TC* __restrict__ C, int64_t ldc, int64_t sC, const zd* __restrict__ P, int M, int N, int F,
+                        double alpha, int accumulate) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)F * M * N) return;
+  const int i = (int)(idx % M), j = (int)((idx / M) % N);
+  const int64_t f = idx / ((int64_t)M * N);
+  TC& c = C[f * sC + i + (int64_t)j * ldc];
+  const zd v = cscale(P[idx], alpha);
+  st(c, accumulate ? cadd(ld<double>(c), v) : v);
+}
+
+template <typename TA, typename TB, typename TC>
+static int mprod(bool conjA, bool conjB, int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const TB* B,
+                 int64_t ldb, int64_t sB, TC* C, int64_t ldc, int64_t sC, int F, double alpha, bool accumulate,
+                 Scratch& sc, hipStream_t s) {
+  if (conjB) return cgemm<TA, TB, TC, double>(conjA, conjB, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, F, alpha,
+                                              accumulate, s);
+  if (!accumulate && alpha == 1.0)
+    return skinny<TA, TB, TC, Scratch, sk::F64>(conjA, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, F, sc, s);
+  RT_ALLOC(tmp, zd, (int64_t)F * M * N, sc);
+  RT_TRY((skinny<TA, TB, zd, Scratch, sk::F64>(conjA, M, N, K, A, lda, sA, B, ldb, sB, tmp, M, (int64_t)M * N, F,
+                                               sc, s)));
+  hipLaunchKernelGGL((k_axpby<TC>), dim3(nblocks((int64_t)F * M * N)), dim3(256), 0, s, C, ldc, sC, (const zd*)tmp, M,
+                     N, F, alpha, (int)accumulate);
+  RT_LAUNCH_OK();
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------------------
 // gradients of the fixed-k truncated R-tSVD restoration (q = 0), factor recomputed
 // ---------------------------------------------------------------------------------------------
 template <typename T>
@@ -1769,90 +1838,97 @@ static int vjp_impl(const T* A, const T* dA, const T* B, const T* omega, const T
   RT_ALLOC(Gk, zd, F * r * r, sc);
   hipLaunchKernelGGL(k_scale_inv_eigs, dim3(nblocks(F * r * r)), dim3(256), 0, s, U, Uphi, lam, (int)r, k, (int)F);
   RT_LAUNCH_OK();
-  RT_TRY((cgemm<zd, zd, zd, double>(false, true, (int)r, (int)r, (int)r, Uphi, r, r * r, U, r, r * r, Gk, r, r * r,
-                                   (int)F, 1.0, false, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, true, (int)r, (int)r, (int)r, Uphi, r, r * r, U, r, r * r, Gk, r, r * r,
+                                   (int)F, 1.0, false, sc, s)));
   // dL/dB = Q G_k^+ C G  (face by face), then the inverse DFT
   RT_ALLOC(t1, zd, F * r * p, sc);
   RT_ALLOC(t2, zd, F * r * p, sc);
   RT_ALLOC(gBh, zt, F * l * p, sc);
-  RT_TRY((cgemm<zd, zt, zd, double>(true, false, (int)r, (int)p, (int)m, Ch, m, m * r, Gh, m, m * p, t1, r, r * p,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, t1, r, r * p, t2, r, r * p,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zt, zd, zt, double>(false, false, (int)l, (int)p, (int)r, Q, l, l * r, t2, r, r * p, gBh, l, l * p,
-                                   (int)F, 1.0, false, s)));
+  RT_TRY((mprod<zd, zt, zd>(true, false, (int)r, (int)p, (int)m, Ch, m, m * r, Gh, m, m * p, t1, r, r * p,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, t1, r, r * p, t2, r, r * p,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zt, zd, zt>(false, false, (int)l, (int)p, (int)r, Q, l, l * r, t2, r, r * p, gBh, l, l * p,
+                                   (int)F, 1.0, false, sc, s)));
   RT_TRY((launch_irfft<T, T>(gBh, l * p, l * p, (int)n, gB, s)));
   if (!dA || !gdot) return 0;
   // forward-mode derivative along dA
   RT_ALLOC(dAh, zt, F * l * m, sc);
   RT_TRY((launch_rfft<T, T>(dA, l * m, (int)n, dAh, l * m, (zb*)nullptr, (double*)nullptr, nullptr, s)));
   RT_ALLOC(dY, zd, F * l * r, sc);
-  RT_TRY((cgemm<zt, zt, zd, double>(false, false, (int)l, (int)r, (int)m, dAh, l, l * m, Omh, m, m * r, dY, l, l * r,
-                                   (int)F, 1.0, false, s)));
+  RT_TRY((mprod<zt, zt, zd>(false, false, (int)l, (int)r, (int)m, dAh, l, l * m, Omh, m, m * r, dY, l, l * r,
+                                   (int)F, 1.0, false, sc, s)));
   RT_ALLOC(T1, zd, F * r * r, sc);   // Q^H dY
   RT_ALLOC(Mq, zd, F * r * r, sc);
   RT_ALLOC(Xq, zd, F * r * r, sc);
-  RT_TRY((cgemm<zt, zd, zd, double>(true, false, (int)r, (int)r, (int)l, Q, l, l * r, dY, l, l * r, T1, r, r * r,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)r, (int)r, T1, r, r * r, Ry, r, r * r, Mq, r, r * r,
-                                   (int)F, 1.0, false, s)));
+  RT_TRY((mprod<zt, zd, zd>(true, false, (int)r, (int)r, (int)l, Q, l, l * r, dY, l, l * r, T1, r, r * r,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)r, (int)r, (int)r, T1, r, r * r, Ry, r, r * r, Mq, r, r * r,
+                                   (int)F, 1.0, false, sc, s)));
   hipLaunchKernelGGL(k_skew_lower, dim3(nblocks(F * r * r)), dim3(256), 0, s, Mq, Xq, (int)r, (int)F);
   RT_LAUNCH_OK();
   // P = dY - Q T1 (in place in dY), dQ = Q Xq + P R^{-1}
-  RT_TRY((cgemm<zt, zd, zd, double>(false, false, (int)l, (int)r, (int)r, Q, l, l * r, T1, r, r * r, dY, l, l * r,
-                                   (int)F, -1.0, true, s)));
+  RT_TRY((mprod<zt, zd, zd>(false, false, (int)l, (int)r, (int)r, Q, l, l * r, T1, r, r * r, dY, l, l * r,
+                                   (int)F, -1.0, true, sc, s)));
   RT_ALLOC(dQ, zd, F * l * r, sc);
-  RT_TRY((cgemm<zt, zd, zd, double>(false, false, (int)l, (int)r, (int)r, Q, l, l * r, Xq, r, r * r, dQ, l, l * r,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)l, (int)r, (int)r, dY, l, l * r, Ry, r, r * r, dQ, l, l * r,
-                                   (int)F, 1.0, true, s)));
+  RT_TRY((mprod<zt, zd, zd>(false, false, (int)l, (int)r, (int)r, Q, l, l * r, Xq, r, r * r, dQ, l, l * r,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)l, (int)r, (int)r, dY, l, l * r, Ry, r, r * r, dQ, l, l * r,
+                                   (int)F, 1.0, true, sc, s)));
   // dC^H = A-hat^H dQ + dA-hat^H Q
   RT_ALLOC(dCh, zd, F * m * r, sc);
-  RT_TRY((cgemm<zt, zd, zd, double>(true, false, (int)m, (int)r, (int)l, Ah, l, l * m, dQ, l, l * r, dCh, m, m * r,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zt, zt, zd, double>(true, false, (int)m, (int)r, (int)l, dAh, l, l * m, Q, l, l * r, dCh, m, m * r,
-                                   (int)F, 1.0, true, s)));
+  RT_TRY((mprod<zt, zd, zd>(true, false, (int)m, (int)r, (int)l, Ah, l, l * m, dQ, l, l * r, dCh, m, m * r,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zt, zt, zd>(true, false, (int)m, (int)r, (int)l, dAh, l, l * m, Q, l, l * r, dCh, m, m * r,
+                                   (int)F, 1.0, true, sc, s)));
   // dG = dC C^H + C dC^H  = (dC^H)^H C^H + (C^H)^H dC^H
   RT_ALLOC(dG, zd, F * r * r, sc);
-  RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)m, dCh, m, m * r, Ch, m, m * r, dG, r, r * r,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)m, Ch, m, m * r, dCh, m, m * r, dG, r, r * r,
-                                   (int)F, 1.0, true, s)));
+  RT_TRY((mprod<zd, zd, zd>(true, false, (int)r, (int)r, (int)m, dCh, m, m * r, Ch, m, m * r, dG, r, r * r,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(true, false, (int)r, (int)r, (int)m, Ch, m, m * r, dCh, m, m * r, dG, r, r * r,
+                                   (int)F, 1.0, true, sc, s)));
   // d(G_k^+) = U (Phi o (U^H dG U)) U^H
   RT_ALLOC(E1, zd, F * r * r, sc);
   RT_ALLOC(E2, zd, F * r * r, sc);
-  RT_TRY((cgemm<zd, zd, zd, double>(true, false, (int)r, (int)r, (int)r, U, r, r * r, dG, r, r * r, E1, r, r * r,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)r, (int)r, E1, r, r * r, U, r, r * r, E2, r, r * r,
-                                   (int)F, 1.0, false, s)));
+  RT_TRY((mprod<zd, zd, zd>(true, false, (int)r, (int)r, (int)r, U, r, r * r, dG, r, r * r, E1, r, r * r,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)r, (int)r, (int)r, E1, r, r * r, U, r, r * r, E2, r, r * r,
+                                   (int)F, 1.0, false, sc, s)));
   hipLaunchKernelGGL(k_phi_hadamard, dim3(nblocks(F * r * r)), dim3(256), 0, s, E2, lam, (int)r, k, (int)F);
   RT_LAUNCH_OK();
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)r, (int)r, U, r, r * r, E2, r, r * r, E1, r, r * r,
-                                   (int)F, 1.0, false, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)r, (int)r, (int)r, U, r, r * r, E2, r, r * r, E1, r, r * r,
+                                   (int)F, 1.0, false, sc, s)));
   RT_ALLOC(dGk, zd, F * r * r, sc);
-  RT_TRY((cgemm<zd, zd, zd, double>(false, true, (int)r, (int)r, (int)r, E1, r, r * r, U, r, r * r, dGk, r, r * r,
-                                   (int)F, 1.0, false, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, true, (int)r, (int)r, (int)r, E1, r, r * r, U, r, r * r, dGk, r, r * r,
+                                   (int)F, 1.0, false, sc, s)));
   // d = Q^H B-hat, dd = dQ^H B-hat, dX-hat = dC^H G_k^+ d + C^H dG_k^+ d + C^H G_k^+ dd
   RT_ALLOC(d, zd, F * r * p, sc);
   RT_ALLOC(dd, zd, F * r * p, sc);
   RT_ALLOC(e, zd, F * r * p, sc);
-  RT_TRY((cgemm<zt, zt, zd, double>(true, false, (int)r, (int)p, (int)l, Q, l, l * r, Bh, l, l * p, d, r, r * p,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zt, zd, double>(true, false, (int)r, (int)p, (int)l, dQ, l, l * r, Bh, l, l * p, dd, r, r * p,
-                                   (int)F, 1.0, false, s)));
+  RT_TRY((mprod<zt, zt, zd>(true, false, (int)r, (int)p, (int)l, Q, l, l * r, Bh, l, l * p, d, r, r * p,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zt, zd>(true, false, (int)r, (int)p, (int)l, dQ, l, l * r, Bh, l, l * p, dd, r, r * p,
+                                   (int)F, 1.0, false, sc, s)));
   RT_ALLOC(dXh, zd, F * m * p, sc);
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, d, r, r * p, e, r, r * p,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)p, (int)r, dCh, m, m * r, e, r, r * p, dXh, m, m * p,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)p, (int)r, dGk, r, r * r, d, r, r * p, e, r, r * p,
-                                   (int)F, 1.0, false, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, dd, r, r * p, e, r, r * p,
-                                   (int)F, 1.0, true, s)));
-  RT_TRY((cgemm<zd, zd, zd, double>(false, false, (int)m, (int)p, (int)r, Ch, m, m * r, e, r, r * p, dXh, m, m * p,
-                                   (int)F, 1.0, true, s)));
-  hipLaunchKernelGGL((k_weighted_inner<zt>), dim3(1), dim3(256), 0, s, Gh, dXh, m * p, (int)F, (int)n, gdot);
-  RT_LAUNCH_OK();
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, d, r, r * p, e, r, r * p,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)m, (int)p, (int)r, dCh, m, m * r, e, r, r * p, dXh, m, m * p,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)r, (int)p, (int)r, dGk, r, r * r, d, r, r * p, e, r, r * p,
+                                   (int)F, 1.0, false, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)r, (int)p, (int)r, Gk, r, r * r, dd, r, r * p, e, r, r * p,
+                                   (int)F, 1.0, true, sc, s)));
+  RT_TRY((mprod<zd, zd, zd>(false, false, (int)m, (int)p, (int)r, Ch, m, m * r, e, r, r * p, dXh, m, m * p,
+                                   (int)F, 1.0, true, sc, s)));
+  {
+    const int64_t blocks = ceil_div(F * m * p, (int64_t)WI_THREADS * WI_ITEMS);
+    RT_ALLOC(wpart, double, blocks, sc);
+    hipLaunchKernelGGL((k_weighted_inner_part<zt>), dim3((unsigned)blocks), dim3(WI_THREADS), 0, s, Gh, dXh, m * p,
+                       (int)F, (int)n, wpart);
+    RT_LAUNCH_OK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, (const double*)wpart, blocks, 1.0 / (double)n, gdot);
+    RT_LAUNCH_OK();
+  }
   return 0;
 }
 

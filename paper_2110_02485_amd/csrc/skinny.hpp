@@ -650,16 +650,16 @@ template <class P> static inline int64_t packed_elems(int K, int N, int batch) {
   const int64_t NPt = ceil_div(N, NP) * NP;
   return 2 * NPt * KP * batch;
 }
-template <typename TA> static inline int64_t skinny_ws_bytes(int K, int N, int batch) {
-  typedef typename PrecOf<TA>::P P;
+// P: the MFMA precision, by default the streamed operand's own (FP64 may also take an FP32 A,
+// converted on its way from LDS to the MFMA operands: FP32 data with FP64 accumulation)
+template <typename TA, class P = typename PrecOf<TA>::P> static inline int64_t skinny_ws_bytes(int K, int N, int batch) {
   return packed_elems<P>(K, N, batch) * (int64_t)sizeof(typename P::E);
 }
 
 // C_f = op(A_f) X_f with X packed into `ws` (skinny_ws_bytes<TA>(K, N, batch) bytes) first:
 // skinny_pack, then skinny_run (split so that the caller can time the product kernel alone).
-template <typename TA, typename TX>
+template <typename TA, typename TX, class P = typename PrecOf<TA>::P>
 static int skinny_pack(int N, int K, const TX* X, int64_t ldx, int64_t sX, int batch, void* ws, hipStream_t s) {
-  typedef typename PrecOf<TA>::P P;
   typedef typename P::E E;
   const int NP = 16 * nt_for<P>(N);
   const int KP = packed_kp<P>(K);
@@ -672,10 +672,9 @@ static int skinny_pack(int N, int K, const TX* X, int64_t ldx, int64_t sX, int b
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename TA, typename TC>
+template <typename TA, typename TC, class P = typename PrecOf<TA>::P>
 static int skinny_run(bool conjA, int M, int N, int K, const TA* A, int64_t lda, int64_t sA, TC* C, int64_t ldc,
                       int64_t sC, int batch, const void* ws, hipStream_t s, int utri = 0) {
-  typedef typename PrecOf<TA>::P P;
   typedef typename P::E E;
   const int NP = 16 * nt_for<P>(N);
   const int KP = packed_kp<P>(K);

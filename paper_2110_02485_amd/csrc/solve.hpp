@@ -41,33 +41,48 @@ __global__ void __launch_bounds__(256) k_scale_rows(zd* __restrict__ T, const do
   T[idx] = s > cut ? cscale(T[idx], 1.0 / s) : mk(0.0, 0.0);
 }
 
-// partial[((f * tiles + tile) * p + c) * kcap + (k-1)] = sum over the tile's rows of
-// |B-hat - W[:, :k] T[:k, c]|^2, FP64.  Block = one wave = one 64-row tile of one column.  The
-// residual is updated one rank-1 term at a time; the 64 row values of each order k are summed
-// through an LDS transposition (lane kk sums row kk of a 64 x 64 chunk), so there is no
-// per-order cross-lane reduction chain.
-template <typename TBh, typename TW>
+// partial[((f * tiles + tile) * pg + g) * kcap + (k-1)] = sum over the tile's rows and over the
+// columns c of column group g (columns g*CPB .. g*CPB + CPB - 1 that exist; pg = ceil(p / CPB)) of
+// |B-hat - W[:, :k] T[:k, c]|^2, FP64.  Block = one wave = one 64-row tile of one column group.
+// The residuals are updated one rank-1 term at a time (each W entry is loaded once for the CPB
+// columns); the 64 row values of each order k are summed through an LDS transposition (lane kk
+// sums row kk of a 64 x 64 chunk), so there is no per-order cross-lane reduction chain.  CPB = 1
+// keeps one column per partial (per-slice discrepancy principle); a joint principle sums every
+// column and may take CPB = 8.
+template <int CPB, typename TBh, typename TW>
 __global__ void __launch_bounds__(DP_ROWS)
 k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __restrict__ T,
              int l, int p, int r, int kcap, double* __restrict__ partial) {
-  const int tile = blockIdx.x, c = blockIdx.y, f = blockIdx.z;
-  const int tiles = gridDim.x;
+  const int tile = blockIdx.x, g = blockIdx.y, f = blockIdx.z;
+  const int tiles = gridDim.x, pg = gridDim.y;
   const int lane = threadIdx.x;
   const int row = tile * DP_ROWS + lane;
+  const int c0 = g * CPB;
   __shared__ double sq[DP_KCH][DP_ROWS + 1];
   const bool on = row < l;
-  zd R = mk(0.0, 0.0);
-  if (on) R = ld<double>(Bh[(int64_t)f * l * p + (int64_t)c * l + row]);
+  zd R[CPB];
+#pragma unroll
+  for (int j = 0; j < CPB; ++j) {
+    R[j] = mk(0.0, 0.0);
+    if (on && c0 + j < p) R[j] = ld<double>(Bh[(int64_t)f * l * p + (int64_t)(c0 + j) * l + row]);
+  }
   const TW* __restrict__ wf = W + (int64_t)f * l * r + (on ? row : 0);
-  const zd* __restrict__ tf = T + (int64_t)f * r * p + (int64_t)c * r;
-  double* __restrict__ out = partial + (((int64_t)f * tiles + tile) * p + c) * kcap;
+  const zd* __restrict__ tf = T + (int64_t)f * r * p;
+  double* __restrict__ out = partial + (((int64_t)f * tiles + tile) * pg + g) * kcap;
   for (int k0 = 0; k0 < kcap; k0 += DP_KCH) {
     const int kn = min(DP_KCH, kcap - k0);
-#pragma unroll 8
+#pragma unroll 4
     for (int kk = 0; kk < kn; ++kk) {
       const int k = k0 + kk;                       // order k+1 uses column k
-      R = csub(R, cmul(ld<double>(wf[(int64_t)k * l]), tf[k]));
-      sq[kk][lane] = on ? cabs2(R) : 0.0;
+      const zd wk = ld<double>(wf[(int64_t)k * l]);
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < CPB; ++j) {
+        const zd t = (c0 + j < p) ? tf[(int64_t)(c0 + j) * r + k] : mk(0.0, 0.0);
+        R[j] = csub(R[j], cmul(wk, t));
+        acc += cabs2(R[j]);
+      }
+      sq[kk][lane] = on ? acc : 0.0;
     }
     __syncthreads();
     if (lane < kn) {
@@ -89,6 +104,7 @@ k_dp_rho(const double* __restrict__ partial, int F, int tiles, int p, int kcap, 
   __shared__ double red[DP_RHO_THREADS / 64];
   const int idx = blockIdx.x;
   const int g = idx / kcap, k = idx % kcap;
+  // p: partial columns per tile (column groups of the joint principle, or the slices)
   const int c0 = groups == 1 ? 0 : g, nc = groups == 1 ? p : 1;
   const int cnt = F * tiles;
   double s = 0.0;
@@ -268,29 +284,51 @@ __global__ void k_scale_inv_eigs(const zd* __restrict__ U, zd* __restrict__ Uphi
   Uphi[idx] = (j < k && lj > 0.0) ? cscale(U[idx], 1.0 / lj) : mk(0.0, 0.0);
 }
 
-// out[0] = (1/n) sum_f w_f sum Re(conj(G) dX)  (one block, fixed summation order per thread)
+// Weighted real inner product over the half spectrum, (1/n) sum_f w_f Re <G_f, D_f> (w_f = 1 for
+// faces 0 and n/2, else 2), in two fixed-order passes: k_weighted_inner_part gives every workgroup a
+// contiguous run of the F x per_face elements (WI_ITEMS per thread), k_sum_partials adds the
+// workgroup sums in order.
+constexpr int WI_THREADS = 256;
+constexpr int WI_ITEMS = 16;
 template <typename TG>
-__global__ void k_weighted_inner(const TG* __restrict__ G, const zd* __restrict__ D, int64_t per_face, int F, int n,
-                                 double* __restrict__ out) {
-  __shared__ double red[256];
+__global__ void __launch_bounds__(WI_THREADS)
+k_weighted_inner_part(const TG* __restrict__ G, const zd* __restrict__ D, int64_t per_face, int F, int n,
+                      double* __restrict__ part) {
+  __shared__ double red[WI_THREADS / 64];
+  const int64_t total = (int64_t)F * per_face;
+  const int64_t base = (int64_t)blockIdx.x * WI_THREADS * WI_ITEMS;
   double s = 0.0;
-  for (int f = 0; f < F; ++f) {
-    const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
-    double t = 0.0;
-    for (int64_t i = threadIdx.x; i < per_face; i += blockDim.x) {
-      const zd g = ld<double>(G[(int64_t)f * per_face + i]);
-      const zd d = D[(int64_t)f * per_face + i];
-      t += g.re * d.re + g.im * d.im;
+#pragma unroll 4
+  for (int it = 0; it < WI_ITEMS; ++it) {
+    const int64_t i = base + (int64_t)it * WI_THREADS + threadIdx.x;
+    if (i < total) {
+      const int f = (int)(i / per_face);
+      const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
+      const zd g = ld<double>(G[i]);
+      const zd d = D[i];
+      s += w * (g.re * d.re + g.im * d.im);
     }
-    s += w * t;
   }
-  red[threadIdx.x] = s;
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < WI_THREADS / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
   }
-  if (threadIdx.x == 0) out[0] = red[0] / (double)n;
+}
+
+// out[0] = scale * sum of part[0 .. count) in a fixed order (one workgroup of 256 threads)
+__global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ part, int64_t count, double scale,
+                                                      double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) s += part[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = scale * (((red[0] + red[1]) + red[2]) + red[3]);
 }
 
 }  // namespace rt
