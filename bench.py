@@ -322,6 +322,7 @@ def time_symmetric(torch, rt, wl, steps):
     methods = (
         ("ttevd", factor_run(lambda: rt.ttevd_factor(A, w.k_max, "fp64"))),
         ("tlanczos", lambda: rt.tlanczos_solve(A, B, delta, w.eta, w.k_max)),
+        ("tlanczos_tik", lambda: (lambda r: (r[0], r[1], r[4]))(rt.tlanczos_tik_solve(A, B, delta, w.eta, w.k_max))),
         ("tgkb", lambda: rt.tgkb_solve(A, B, delta, w.eta, w.k_max)),
         ("ttsvd", factor_run(lambda: rt.ttsvd_factor(A, w.k_max, "fp64"))),
         ("rtsvd", factor_run(lambda: rt.factor(A, w.k_max, w.oversample, w.power_iters, "fp64", Om))),
@@ -410,6 +411,17 @@ def time_comparison_256(torch, rt, wl, steps):
                          "dp_status": int(st[0]), "rel_error": _rel_err(torch, Xk, x_true),
                          "timing": "host wall clock per call (the step loop waits on device progress)"}
         res["tgkb"] = (Xk.double().cpu().numpy(), int(kk[0]))
+        # Tikhonov on the tGKB space, mu by bisection on the paper's interval [1e1, 1e7]
+        rt.tgkt_solve(At, Bd, delta, w.eta, w.k_max)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            Xt_, kt_, mut_, _, stt_ = rt.tgkt_solve(At, Bd, delta, w.eta, w.k_max)
+        torch.cuda.synchronize()
+        ms_t = (time.perf_counter() - t0) * 1e3 / 3
+        entry["tgkt"] = {"value": 1000.0 / ms_t, "unit": "solves/s", "ms_per_step": ms_t, "k": int(kt_[0]),
+                         "mu": float(mut_[0]), "dp_status": int(stt_[0]), "rel_error": _rel_err(torch, Xt_, x_true),
+                         "mu_interval": [1e1, 1e7], "timing": "host wall clock per call"}
         entry["rtsvd_speedup_over_ttsvd"] = entry["ttsvd"]["ms_per_step"] / entry["rtsvd"]["ms_per_step"]
         out[f"noise_{w.noise:g}"] = entry
         gpu[name] = res

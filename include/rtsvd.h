@@ -227,6 +227,32 @@ int nested_tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, int64_
                       int32_t k_init, void* X, int32_t* k_out, double* resid_out, int32_t* status_out,
                       void* stream);
 
+/* tGKT_p: Tikhonov regularization on the t-Krylov space of Alg. 7 (Sections 4.3 and 5 compare the
+ * truncated iterations with it; the paper gives the Tikhonov parameter mu by bisection on an
+ * interval).  Per lateral slice j: k = tGKB_p's discrepancy index (the first k whose projected
+ * least-squares residual is <= eta_dp delta_j, k_max if none), then
+ *   X_j = W_k * Y,  Y = argmin ||P-bar_k y - z_1 e_1||^2 + (1/mu_j) ||y||^2  face by face,
+ * i.e. min ||A * X - B_j||_F^2 + (1/mu_j) ||X||_F^2 over the t-Krylov space, with mu_j from
+ * bisection in log mu on [mu_lo, mu_hi] (50 halvings) for ||B_j - A * X_j||_F = eta_dp delta_j
+ * (the returned mu_j meets the principle: its residual is <= eta_dp delta_j).  If mu_hi leaves the
+ * residual above the bound, mu_j = mu_hi; if mu_lo already meets it, mu_j = mu_lo.  The projected
+ * problems are solved from the Givens QR of P-bar_k kept by the step loop (real banded normal
+ * equations, FP64).  Arguments as tgkb_solve, and mu_lo, mu_hi (0 < mu_lo < mu_hi, finite), mu_out:
+ * DEVICE double[p]; resid_out: DEVICE double[p] or NULL, ||B_j - A * X_j||_F at mu_j; status_out:
+ * RTSVD_W_DP_NOT_MET when a slice reached k_max unmet or mu_hi could not meet its bound.
+ * Errors: RTSVD_E_ARG, RTSVD_E_UNSUPPORTED (l > 8192).                                          */
+int tgkt_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p, int dtype,
+               const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, double mu_lo, double mu_hi,
+               void* X, int32_t* k_out, double* mu_out, double* resid_out, int32_t* status_out, void* stream);
+
+/* t-LanczosTik_p: as tgkt_solve on the t-Lanczos space of Alg. 4 for a symmetric A (the
+ * (k+1) x k tridiagonal T-bar_k of eq. (9t) in place of P-bar_k; k = t-Lanczos_p's discrepancy
+ * index), X_j = Q_k * Y.  Arguments as tlanczos_solve and tgkt_solve.                          */
+int tlanczos_tik_solve(const void* A, const void* B, int64_t m, int64_t n, int64_t p, int dtype,
+                       const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, double mu_lo,
+                       double mu_hi, void* X, int32_t* k_out, double* mu_out, double* resid_out,
+                       int32_t* status_out, void* stream);
+
 /* T-tEVD factor of a symmetric tensor (Alg. 2, Section 3.1): A in R^{m x m x n} with A^T = A, i.e.
  * every DFT face A-hat_i Hermitian (the faces' lower triangles are read; symmetry is the caller's
  * promise, not checked).  Facewise FP64 Hermitian eigendecomposition, eigenpairs ordered by

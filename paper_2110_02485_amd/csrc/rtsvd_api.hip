@@ -1427,10 +1427,42 @@ static int await_progress(const Progress& pr, int i, int ahead, const int* remai
 // steps in flight beyond the last one known to be finished
 constexpr int KRYLOV_AHEAD = 2;
 
+// Tikhonov variants (tGKT_p, t-LanczosTik_p): mu interval, outputs and the scratch the tail fills
+struct TikArgs {
+  double mu_lo, mu_hi;
+  double* mu_out;    // DEVICE [p]
+  double* res_out;   // DEVICE [p] or NULL: ||B_c - A * X_c|| at mu
+  double* y;         // scratch: F x p x kmax coefficients (filled by tikhonov_tail)
+  int* fail;         // scratch: mu_hi could not meet a bound
+};
+
+// mu by bisection and the coefficients y of every (face, slice) from the Givens QR histories of the
+// step loop (k_tik_mu); allocates tik.y and tik.fail from sc
+template <bool LANCZOS>
+static int tikhonov_tail(const double* ha, const double* hb, const double* hc, const double* phi, const double* beta,
+                         const int* kin, int kmax, int64_t p, int64_t F, int64_t n, const double* bnd, TikArgs& tik,
+                         Scratch& sc, hipStream_t s) {
+  tik.y = sc.get<double>(F * p * kmax);
+  tik.fail = sc.get<int>(1);
+  if (!tik.y || !tik.fail) return fail(RTSVD_E_NOMEM, "device allocation failed: Tikhonov scratch");
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, tik.fail, 0);
+  RT_LAUNCH_OK();
+  // 4 k_max doubles of LDS per thread, at most 150 KB per workgroup
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(TIK_MAX_THREADS, (150 * 1024) / (32 * (int64_t)kmax)));
+  const size_t lds = (size_t)nt * 4 * kmax * sizeof(double);
+  auto kern = k_tik_mu<LANCZOS>;
+  if (lds > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)lds));
+  hipLaunchKernelGGL(kern, dim3((unsigned)p), dim3(nt), lds, s, ha, hb, hc, phi, beta, kin, kmax, (int)p, (int)F,
+                     (int)n, bnd, tik.mu_lo, tik.mu_hi, tik.mu_out, tik.res_out, tik.y, tik.fail);
+  RT_LAUNCH_OK();
+  return 0;
+}
+
 template <typename T>
 static int tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, int64_t p,
                      const std::vector<double>& bounds, int kmax, T* X, int* k_out, double* resid_out, int* status_out,
-                     hipStream_t s) {
+                     hipStream_t s, TikArgs* tik = nullptr) {
   typedef cplx<T> zt;
   const int64_t F = n / 2 + 1;
   const double tol = 64.0 * (sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.960464477539063e-08);
@@ -1466,6 +1498,12 @@ static int tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, in
   hipLaunchKernelGGL((k_gkb_init<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, Bh, l * p, (int)l, (int)p, Qb,
                      ldq, zc, phibar, cprev, 0.0);
   RT_LAUNCH_OK();
+  double* beta = nullptr;   // ||b-hat|| per (face, slice), for the Tikhonov residuals
+  if (tik) {
+    beta = sc.get<double>(cnt);
+    if (!beta) return fail(RTSVD_E_NOMEM, "device allocation failed: beta");
+    RT_CHECK_HIP(hipMemcpyAsync(beta, phibar, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+  }
   Progress prog;
   if (!progress_open(prog)) return fail(RTSVD_E_NOMEM, "tgkb_solve: pinned host memory");
   for (int i = 1; i <= kmax; ++i) {
@@ -1501,11 +1539,21 @@ static int tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, in
   }
   // solution at each slice's k (k_max where the principle was not met)
   RT_ALLOC(Xh, zt, F * m * p, sc);
-  hipLaunchKernelGGL((k_gkb_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), (size_t)kmax * sizeof(double), s,
-                     Wb, ldw, (int)m, kin, kmax, (int)p, rho_h, s_h, phi_h, alpha_h, Xh);
+  if (tik) {
+    RT_TRY(tikhonov_tail<false>(rho_h, s_h, alpha_h, phi_h, beta, kin, kmax, p, F, n, bnd, *tik, sc, s));
+    hipLaunchKernelGGL((k_basis_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, (const zt*)Wb, ldw,
+                       (int)m, (const int*)kin, kmax, (int)p, (const double*)tik->y, Xh);
+  } else {
+    hipLaunchKernelGGL((k_gkb_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), (size_t)kmax * sizeof(double),
+                       s, Wb, ldw, (int)m, kin, kmax, (int)p, rho_h, s_h, phi_h, alpha_h, Xh);
+  }
   RT_LAUNCH_OK();
   RT_TRY((launch_irfft<T, T>(Xh, m * p, m * p, (int)n, X, s)));
-  hipLaunchKernelGGL(k_gkb_finish, dim3(1), dim3(64), 0, s, kin, (int)p, kmax, k_out, status_out);
+  if (tik)
+    hipLaunchKernelGGL(k_tik_finish, dim3(1), dim3(64), 0, s, kin, (int)p, kmax, (const int*)tik->fail, k_out,
+                       status_out);
+  else
+    hipLaunchKernelGGL(k_gkb_finish, dim3(1), dim3(64), 0, s, kin, (int)p, kmax, k_out, status_out);
   RT_LAUNCH_OK();
   return 0;
 }
@@ -1534,6 +1582,54 @@ extern "C" int tgkb_solve(const void* A, const void* B, int64_t l, int64_t m, in
     return tgkb_impl<float>((const float*)A, (const float*)B, l, m, n, p, bounds, k_max, (float*)X, k_out, resid_out,
                             status_out, s);
   return fail(RTSVD_E_ARG, "tgkb_solve: bad dtype");
+}
+
+// shared argument checks of the Krylov entry points: bounds eta_dp * delta per slice
+static int krylov_bounds(const char* who, const double* delta, int32_t n_delta, int64_t p, double eta_dp,
+                         std::vector<double>& bounds) {
+  char buf[160];
+  if (n_delta != 1 && n_delta != p) {
+    snprintf(buf, sizeof(buf), "%s: n_delta must be 1 or p", who);
+    return fail(RTSVD_E_ARG, buf);
+  }
+  if (!(eta_dp > 1.0)) {
+    snprintf(buf, sizeof(buf), "%s: eta_dp must be > 1", who);
+    return fail(RTSVD_E_ARG, buf);
+  }
+  bounds.resize(p);
+  for (int64_t c = 0; c < p; ++c) {
+    const double d = delta[n_delta == 1 ? 0 : c];
+    if (!(d >= 0.0)) {
+      snprintf(buf, sizeof(buf), "%s: delta must be >= 0", who);
+      return fail(RTSVD_E_ARG, buf);
+    }
+    bounds[c] = eta_dp * d;
+  }
+  return 0;
+}
+
+extern "C" int tgkt_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p, int dtype,
+                          const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, double mu_lo,
+                          double mu_hi, void* X, int32_t* k_out, double* mu_out, double* resid_out,
+                          int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !X || !delta || !k_out || !mu_out) return fail(RTSVD_E_ARG, "tgkt_solve: null argument");
+  if (l < 1 || m < 1 || n < 1 || p < 1 || l < m) return fail(RTSVD_E_ARG, "tgkt_solve: need l >= m >= 1, n >= 1, p >= 1");
+  if (k_max < 1 || k_max > m) return fail(RTSVD_E_ARG, "tgkt_solve: need 1 <= k_max <= m");
+  if (!(mu_lo > 0.0) || !(mu_hi > mu_lo) || !std::isfinite(mu_hi))
+    return fail(RTSVD_E_ARG, "tgkt_solve: need 0 < mu_lo < mu_hi < inf");
+  if (l > 8192) return fail(RTSVD_E_UNSUPPORTED, "tgkt_solve: l must be <= 8192");
+  std::vector<double> bounds;
+  RT_TRY(krylov_bounds("tgkt_solve", delta, n_delta, p, eta_dp, bounds));
+  hipStream_t s = (hipStream_t)stream;
+  TikArgs tik{mu_lo, mu_hi, mu_out, resid_out, nullptr, nullptr};
+  if (dtype == RTSVD_F64)
+    return tgkb_impl<double>((const double*)A, (const double*)B, l, m, n, p, bounds, k_max, (double*)X, k_out, nullptr,
+                             status_out, s, &tik);
+  if (dtype == RTSVD_F32)
+    return tgkb_impl<float>((const float*)A, (const float*)B, l, m, n, p, bounds, k_max, (float*)X, k_out, nullptr,
+                            status_out, s, &tik);
+  return fail(RTSVD_E_ARG, "tgkt_solve: bad dtype");
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1659,7 +1755,8 @@ extern "C" int nested_tgkb_solve(const void* A, const void* B, int64_t l, int64_
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 static int tlanczos_impl(const T* A, const T* B, int64_t m, int64_t n, int64_t p, const std::vector<double>& bounds,
-                         int kmax, T* X, int* k_out, double* resid_out, int* status_out, hipStream_t s) {
+                         int kmax, T* X, int* k_out, double* resid_out, int* status_out, hipStream_t s,
+                         TikArgs* tik = nullptr) {
   typedef cplx<T> zt;
   const int64_t F = n / 2 + 1;
   const double tol = 64.0 * (sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.960464477539063e-08);
@@ -1694,6 +1791,12 @@ static int tlanczos_impl(const T* A, const T* B, int64_t m, int64_t n, int64_t p
   hipLaunchKernelGGL((k_gkb_init<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, Bh, m * p, (int)m, (int)p, Qb,
                      ldq, zc, phibar, cprev, 0.0);
   RT_LAUNCH_OK();
+  double* beta = nullptr;   // ||b-hat|| per (face, slice), for the Tikhonov residuals
+  if (tik) {
+    beta = sc.get<double>(cnt);
+    if (!beta) return fail(RTSVD_E_NOMEM, "device allocation failed: beta");
+    RT_CHECK_HIP(hipMemcpyAsync(beta, phibar, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+  }
   double* l1c = rot4;
   double* l1s = rot4 + cnt;
   double* l2c = rot4 + 2 * cnt;
@@ -1727,11 +1830,21 @@ static int tlanczos_impl(const T* A, const T* B, int64_t m, int64_t n, int64_t p
     }
   }
   RT_ALLOC(Xh, zt, F * m * p, sc);
-  hipLaunchKernelGGL((k_tlan_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), (size_t)kmax * sizeof(double), s,
-                     Qb, ldq, (int)m, kin, kmax, (int)p, rho_h, r1_h, r2_h, phi_h, Xh);
+  if (tik) {
+    RT_TRY(tikhonov_tail<true>(rho_h, r1_h, r2_h, phi_h, beta, kin, kmax, p, F, n, bnd, *tik, sc, s));
+    hipLaunchKernelGGL((k_basis_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, (const zt*)Qb, ldq,
+                       (int)m, (const int*)kin, kmax, (int)p, (const double*)tik->y, Xh);
+  } else {
+    hipLaunchKernelGGL((k_tlan_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), (size_t)kmax * sizeof(double),
+                       s, Qb, ldq, (int)m, kin, kmax, (int)p, rho_h, r1_h, r2_h, phi_h, Xh);
+  }
   RT_LAUNCH_OK();
   RT_TRY((launch_irfft<T, T>(Xh, m * p, m * p, (int)n, X, s)));
-  hipLaunchKernelGGL(k_gkb_finish, dim3(1), dim3(64), 0, s, kin, (int)p, kmax, k_out, status_out);
+  if (tik)
+    hipLaunchKernelGGL(k_tik_finish, dim3(1), dim3(64), 0, s, kin, (int)p, kmax, (const int*)tik->fail, k_out,
+                       status_out);
+  else
+    hipLaunchKernelGGL(k_gkb_finish, dim3(1), dim3(64), 0, s, kin, (int)p, kmax, k_out, status_out);
   RT_LAUNCH_OK();
   return 0;
 }
@@ -1760,6 +1873,30 @@ extern "C" int tlanczos_solve(const void* A, const void* B, int64_t m, int64_t n
     return tlanczos_impl<float>((const float*)A, (const float*)B, m, n, p, bounds, k_max, (float*)X, k_out, resid_out,
                                 status_out, s);
   return fail(RTSVD_E_ARG, "tlanczos_solve: bad dtype");
+}
+
+extern "C" int tlanczos_tik_solve(const void* A, const void* B, int64_t m, int64_t n, int64_t p, int dtype,
+                                  const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, double mu_lo,
+                                  double mu_hi, void* X, int32_t* k_out, double* mu_out, double* resid_out,
+                                  int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !X || !delta || !k_out || !mu_out) return fail(RTSVD_E_ARG, "tlanczos_tik_solve: null argument");
+  if (m < 1 || n < 1 || p < 1) return fail(RTSVD_E_ARG, "tlanczos_tik_solve: need m >= 1, n >= 1, p >= 1");
+  if (k_max < 1 || k_max > m) return fail(RTSVD_E_ARG, "tlanczos_tik_solve: need 1 <= k_max <= m");
+  if (!(mu_lo > 0.0) || !(mu_hi > mu_lo) || !std::isfinite(mu_hi))
+    return fail(RTSVD_E_ARG, "tlanczos_tik_solve: need 0 < mu_lo < mu_hi < inf");
+  if (m > 8192) return fail(RTSVD_E_UNSUPPORTED, "tlanczos_tik_solve: m must be <= 8192");
+  std::vector<double> bounds;
+  RT_TRY(krylov_bounds("tlanczos_tik_solve", delta, n_delta, p, eta_dp, bounds));
+  hipStream_t s = (hipStream_t)stream;
+  TikArgs tik{mu_lo, mu_hi, mu_out, resid_out, nullptr, nullptr};
+  if (dtype == RTSVD_F64)
+    return tlanczos_impl<double>((const double*)A, (const double*)B, m, n, p, bounds, k_max, (double*)X, k_out, nullptr,
+                                 status_out, s, &tik);
+  if (dtype == RTSVD_F32)
+    return tlanczos_impl<float>((const float*)A, (const float*)B, m, n, p, bounds, k_max, (float*)X, k_out, nullptr,
+                                status_out, s, &tik);
+  return fail(RTSVD_E_ARG, "tlanczos_tik_solve: bad dtype");
 }
 
 

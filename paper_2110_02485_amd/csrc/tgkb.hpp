@@ -535,6 +535,199 @@ __global__ void k_gkb_finish(const int* __restrict__ kin, int p, int kmax, int* 
 }
 
 // ---------------------------------------------------------------------------------------------
+// Tikhonov on the t-Krylov space (tGKT_p on Alg. 7's space, t-LanczosTik_p on Alg. 4's)
+// ---------------------------------------------------------------------------------------------
+// After the step loop every (face, slice) holds the Givens QR of its projected matrix,
+// Qbar^T [P-bar_k | z_1 e_1] = [R f; 0 phi-bar_{k+1}], R upper triangular with at most two
+// superdiagonals (tGKB: diagonal rho_j, R(j, j+1) = s_j alpha_{j+1}; t-Lanczos: rho_j, r1_{j+1},
+// r2_{j+2}).  For any y, ||P-bar_k y - z_1 e_1||^2 = ||R y - f||^2 + phi-bar_{k+1}^2 with
+// phi-bar_{k+1}^2 = z_1^2 - ||f||^2, so the Tikhonov solution for lam = 1/mu solves the banded
+// normal equations (R^T R + lam I) y = R^T f (Cholesky with bandwidth 2, real arithmetic).
+// k_tik_mu: one workgroup per slice c; its threads take the faces in turn and keep the Cholesky
+// bands and the solution in LDS (4 k_max doubles per thread).  mu by bisection in log mu on
+// [mu_lo, mu_hi] for (1/n) sum_f w_f (||R_f y_f - f_f||^2 + phi-bar_f^2) = bound_c^2: the bracket
+// keeps res(lo) > bound >= res(hi) and mu = hi after the last halving; mu_hi that leaves the
+// residual above the bound gives mu = mu_hi and a failure flag, mu_lo that meets it gives mu_lo.
+// Outputs: mu[c], the final residual, y per (face, slice) for k_basis_solution.
+constexpr int TIK_MAX_THREADS = 64;
+constexpr int TIK_STEPS = 50;
+
+// R(j, j), R(j, j+1), R(j, j+2) of the face's history arrays (a, b, c: see above)
+template <bool LANCZOS>
+__device__ __forceinline__ void tik_band(const double* __restrict__ ha, const double* __restrict__ hb,
+                                         const double* __restrict__ hc, int j, int k, double& d0, double& d1,
+                                         double& d2) {
+  d0 = ha[j];
+  if (LANCZOS) {
+    d1 = (j + 1 < k) ? hb[j + 1] : 0.0;
+    d2 = (j + 2 < k) ? hc[j + 2] : 0.0;
+  } else {
+    d1 = (j + 1 < k) ? hb[j] * hc[j + 1] : 0.0;   // s_j alpha_{j+1}
+    d2 = 0.0;
+  }
+}
+
+// ||R y - f||^2 (+ nothing else) of one face at lam, y left in ys.  M = R^T R + lam I:
+//   M(i, i)   = d0_i^2 + d1_{i-1}^2 + d2_{i-2}^2 + lam
+//   M(i+1, i) = d1_i d0_i + d2_{i-1} d1_{i-1},   M(i+2, i) = d2_i d0_i
+// L L^T = M with L(i, i) = g_i, L(i+1, i) = u_i, L(i+2, i) = v_i:
+//   v_i = M(i+2, i) / g_i,  u_i = (M(i+1, i) - u_{i-1} v_{i-1}) / g_i,
+//   g_i = sqrt(M(i, i) - u_{i-1}^2 - v_{i-2}^2); forward then backward substitution of R^T f.
+template <bool LANCZOS>
+__device__ double tik_face(const double* __restrict__ ha, const double* __restrict__ hb, const double* __restrict__ hc,
+                           const double* __restrict__ fv, int k, double lam, double* __restrict__ g,
+                           double* __restrict__ u, double* __restrict__ v, double* __restrict__ ys) {
+  double d1m1 = 0.0, d2m1 = 0.0, d2m2 = 0.0;   // d1_{i-1}, d2_{i-1}, d2_{i-2}
+  double fm1 = 0.0, fm2 = 0.0;                 // f_{i-1}, f_{i-2}
+  for (int i = 0; i < k; ++i) {
+    double d0, d1, d2;
+    tik_band<LANCZOS>(ha, hb, hc, i, k, d0, d1, d2);
+    const double fi = fv[i];
+    const double um1 = i >= 1 ? u[i - 1] : 0.0, vm2 = i >= 2 ? v[i - 2] : 0.0, vm1 = i >= 1 ? v[i - 1] : 0.0;
+    const double mii = fma(d0, d0, fma(d1m1, d1m1, fma(d2m2, d2m2, lam)));
+    const double gi = sqrt(fmax(mii - um1 * um1 - vm2 * vm2, 0.0));
+    const double ig = gi > 0.0 ? 1.0 / gi : 0.0;
+    g[i] = gi;
+    u[i] = (fma(d1, d0, d2m1 * d1m1) - um1 * vm1) * ig;   // L(i+1, i); u_{i-1} v_{i-1} = L(i+1,i-1) L(i,i-1)
+    v[i] = d2 * d0 * ig;                                  // L(i+2, i)
+    // forward: z_i = ((R^T f)_i - u_{i-1} z_{i-1} - v_{i-2} z_{i-2}) / g_i
+    const double rt = fma(d0, fi, fma(d1m1, fm1, d2m2 * fm2));
+    double z = rt;
+    if (i >= 1) z = fma(-um1, ys[i - 1], z);
+    if (i >= 2) z = fma(-vm2, ys[i - 2], z);
+    ys[i] = z * ig;
+    d2m2 = d2m1;
+    d1m1 = d1;
+    d2m1 = d2;
+    fm2 = fm1;
+    fm1 = fi;
+  }
+  // backward: y_i = (z_i - u_i y_{i+1} - v_i y_{i+2}) / g_i
+  double y1 = 0.0, y2 = 0.0;
+  for (int i = k - 1; i >= 0; --i) {
+    const double ig = g[i] > 0.0 ? 1.0 / g[i] : 0.0;
+    const double yi = (ys[i] - u[i] * y1 - v[i] * y2) * ig;
+    ys[i] = yi;
+    y2 = y1;
+    y1 = yi;
+  }
+  // ||R y - f||^2
+  double rr = 0.0;
+  for (int i = 0; i < k; ++i) {
+    double d0, d1, d2;
+    tik_band<LANCZOS>(ha, hb, hc, i, k, d0, d1, d2);
+    double e = d0 * ys[i] - fv[i];
+    if (i + 1 < k) e = fma(d1, ys[i + 1], e);
+    if (i + 2 < k) e = fma(d2, ys[i + 2], e);
+    rr = fma(e, e, rr);
+  }
+  return rr;
+}
+
+// ha, hb, hc: the histories (tGKB: rho, s, alpha; t-Lanczos: rho, r1, r2), phi: f, beta: z_1 per
+// (face, slice) (index f * p + c, histories with stride kmax).  kin[c] <= 0: k = kmax.
+template <bool LANCZOS>
+__global__ void __launch_bounds__(TIK_MAX_THREADS)
+k_tik_mu(const double* __restrict__ ha, const double* __restrict__ hb, const double* __restrict__ hc,
+         const double* __restrict__ phi, const double* __restrict__ beta, const int* __restrict__ kin, int kmax, int p,
+         int F, int n, const double* __restrict__ bound, double mu_lo, double mu_hi, double* __restrict__ mu_out,
+         double* __restrict__ res_out, double* __restrict__ y_out, int* __restrict__ fail) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[TIK_MAX_THREADS];
+  __shared__ double sh_res;
+  const int c = blockIdx.x, tid = threadIdx.x, nt = (int)blockDim.x;
+  double* base = reinterpret_cast<double*>(smem_raw) + (size_t)tid * 4 * kmax;
+  double *g = base, *u = base + kmax, *v = base + 2 * kmax, *ys = base + 3 * kmax;
+  const int k = kin[c] > 0 ? kin[c] : kmax;
+  const double b2 = bound[c] * bound[c];
+  // residual^2 of the Tikhonov solution at lam (all faces), written to y_out when `keep`
+  auto residual2 = [&](double lam, bool keep) -> double {
+    double acc = 0.0;
+    for (int f = tid; f < F; f += nt) {
+      const int64_t idx = (int64_t)f * p + c;
+      const double* fa = ha + idx * kmax;
+      const double* fb = hb + idx * kmax;
+      const double* fc = hc + idx * kmax;
+      const double* fv = phi + idx * kmax;
+      double ff = 0.0;
+      for (int i = 0; i < k; ++i) ff = fma(fv[i], fv[i], ff);
+      const double bt = beta[idx];
+      const double pb2 = fmax(bt * bt - ff, 0.0);          // phi-bar_{k+1}^2
+      const double rr = tik_face<LANCZOS>(fa, fb, fc, fv, k, lam, g, u, v, ys);
+      const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
+      acc = fma(w, rr + pb2, acc);
+      if (keep)
+        for (int i = 0; i < kmax; ++i) y_out[idx * kmax + i] = i < k ? ys[i] : 0.0;
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int i = 0; i < nt; ++i) t += red[i];
+      sh_res = t / (double)n;
+    }
+    __syncthreads();
+    return sh_res;
+  };
+  double mu;
+  int failed = 0;
+  if (residual2(1.0 / mu_hi, false) > b2) {
+    mu = mu_hi;
+    failed = 1;
+  } else if (residual2(1.0 / mu_lo, false) <= b2) {
+    mu = mu_lo;
+  } else {
+    double lo = log(mu_lo), hi = log(mu_hi);
+    for (int it = 0; it < TIK_STEPS; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (residual2(exp(-mid), false) > b2) lo = mid;
+      else hi = mid;
+    }
+    mu = exp(hi);
+  }
+  const double r2 = residual2(1.0 / mu, true);
+  if (tid == 0) {
+    mu_out[c] = mu;
+    if (res_out) res_out[c] = sqrt(r2);
+    if (failed) atomicOr(fail, 1);
+  }
+}
+
+// X-hat(:, c) of face f = basis_k y (basis vectors of length len, stride len, per (f, c) at
+// basis + (f p + c) ld_basis); one workgroup per (c, f)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_basis_solution(const cplx<T>* __restrict__ basis, int64_t ld_basis, int len, const int* __restrict__ kin, int kmax,
+                 int p, const double* __restrict__ y_in, cplx<T>* __restrict__ Xh) {
+  const int c = blockIdx.x, f = blockIdx.y;
+  const int64_t idx = (int64_t)f * p + c;
+  const int k = kin[c] > 0 ? kin[c] : kmax;
+  const cplx<T>* B = basis + idx * ld_basis;
+  const double* y = y_in + idx * kmax;
+  for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    zd acc = mk(0.0, 0.0);
+    for (int j = 0; j < k; ++j) acc = cadd(acc, cscale(ld<double>(B[(int64_t)j * len + i]), y[j]));
+    Xh[(int64_t)f * len * p + (int64_t)c * len + i] = mk((T)acc.re, (T)acc.im);
+  }
+}
+
+// k_out, status of a Tikhonov solve: not met when the truncated index reached k_max or mu_hi
+// could not bring the residual down to the bound
+__global__ void k_tik_finish(const int* __restrict__ kin, int p, int kmax, const int* __restrict__ fail,
+                             int* __restrict__ kout, int* __restrict__ status) {
+  __shared__ int fail_any;
+  if (threadIdx.x == 0) fail_any = *fail;
+  __syncthreads();
+  for (int c = threadIdx.x; c < p; c += blockDim.x) {
+    const int k = kin[c];
+    if (k <= 0) atomicOr(&fail_any, 1);
+    kout[c] = k > 0 ? k : kmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && status) *status = fail_any ? RTSVD_W_DP_NOT_MET : RTSVD_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
 // nested_tGKB_p (Alg. 8): one basis, started from B_1, shared by every lateral slice
 // ---------------------------------------------------------------------------------------------
 // The bidiagonal P-bar_k and its Givens rotations belong to the basis alone (one set per face);

@@ -26,7 +26,7 @@ PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
            "tprod", "tprod_adjoint", "tgkb_solve", "nested_tgkb_solve", "ttevd_factor", "tlanczos_solve", "rtsvd_status_string", "rtsvd_last_error",
            "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim", "rtsvd_gaussian",
-           "rtsvd_solve_noalloc"]
+           "rtsvd_solve_noalloc", "tgkt_solve", "tlanczos_tik_solve"]
 
 
 class RtsvdError(RuntimeError):
@@ -81,6 +81,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rtsvd_timer_read.argtypes = [ctypes.c_int, pdbl, pi32]
     lib.rtsvd_trim.argtypes = []
     lib.rtsvd_gaussian.argtypes = [ctypes.c_uint64, i64, i64, i64, ctypes.c_int, vp, vp]
+    lib.tgkt_solve.argtypes = [vp, vp, i64, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, dbl, dbl, vp, vp, vp, vp,
+                               vp, vp]
+    lib.tlanczos_tik_solve.argtypes = [vp, vp, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, dbl, dbl, vp, vp, vp,
+                                       vp, vp, vp]
     _lib = lib
     return lib
 
@@ -355,6 +359,42 @@ def tgkb_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int):
     _check(lib.tgkb_solve(A.data_ptr(), B.data_ptr(), l, m, n, p, _dtype_code(A), arr, len(deltas), eta, k_max,
                           X.data_ptr(), k.data_ptr(), resid.data_ptr(), status.data_ptr(), _stream()), "tgkb_solve")
     return X, k, resid, status
+
+
+def _tikhonov(fn_name, A, B, delta, eta, k_max, mu_lo, mu_hi, square):
+    lib = load()
+    A, B = _dev(A, "A"), _dev(B, "B")
+    n, m, l = A.shape
+    if square and l != m:
+        raise ValueError("t-Lanczos needs a square (symmetric) tensor")
+    n2, p, l2 = B.shape
+    if (n2, l2) != (n, l) or B.dtype != A.dtype or B.device != A.device:
+        raise ValueError("B must have storage shape (n, p, l) of A, A's dtype and device")
+    deltas = [float(d) for d in (delta if hasattr(delta, "__len__") else [delta])]
+    arr = (ctypes.c_double * len(deltas))(*deltas)
+    X = torch.empty((n, p, m), dtype=A.dtype, device=A.device)
+    k = torch.empty(p, dtype=torch.int32, device=A.device)
+    mu = torch.empty(p, dtype=torch.float64, device=A.device)
+    resid = torch.empty(p, dtype=torch.float64, device=A.device)
+    status = torch.empty(1, dtype=torch.int32, device=A.device)
+    fn = getattr(lib, fn_name)
+    dims = (m, n, p) if square else (l, m, n, p)
+    _check(fn(A.data_ptr(), B.data_ptr(), *dims, _dtype_code(A), arr, len(deltas), eta, k_max, mu_lo, mu_hi,
+              X.data_ptr(), k.data_ptr(), mu.data_ptr(), resid.data_ptr(), status.data_ptr(), _stream()), fn_name)
+    return X, k, mu, resid, status
+
+
+def tgkt_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int, mu_lo: float = 1e1,
+               mu_hi: float = 1e7):
+    """tGKT_p restoration (Tikhonov on the tGKB space, mu by bisection on [mu_lo, mu_hi]); returns
+    (X, k (device int32 [p]), mu (device [p]), residual at mu (device [p]), status)."""
+    return _tikhonov("tgkt_solve", A, B, delta, eta, k_max, mu_lo, mu_hi, False)
+
+
+def tlanczos_tik_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int, mu_lo: float = 1e1,
+                       mu_hi: float = 1e7):
+    """t-LanczosTik_p restoration of a symmetric A; returns (X, k, mu, residual at mu, status)."""
+    return _tikhonov("tlanczos_tik_solve", A, B, delta, eta, k_max, mu_lo, mu_hi, True)
 
 
 def nested_tgkb_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int, k_init: int = 2):
