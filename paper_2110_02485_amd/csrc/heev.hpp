@@ -23,10 +23,13 @@ constexpr int HEEV_THREADS = 1024;
 
 #ifdef RTSVD_PHASE_CLOCKS
 // phase timestamps of block 0 (profiling builds only)
-__device__ unsigned long long rt_phase_clock[16];
+__device__ unsigned long long rt_phase_clock[24];
 #define RT_PHASE(i) do { __syncthreads(); if (blockIdx.x == 0 && threadIdx.x == 0) rt_phase_clock[i] = wall_clock64(); } while (0)
+// timestamp of one wave's progress (its lane 0), no synchronization
+#define RT_MARK(i) do { if (blockIdx.x == 0 && (threadIdx.x & 63) == 0) rt_phase_clock[i] = wall_clock64(); } while (0)
 #else
 #define RT_PHASE(i) do { } while (0)
+#define RT_MARK(i) do { } while (0)
 #endif
 constexpr int HEEV_RMAX = 256;
 
@@ -401,6 +404,10 @@ __device__ __forceinline__ zd zfms(zd a, zd b, zd acc) {
 }
 __device__ __forceinline__ zd zcfma(zd a, zd b, zd acc) {
   return mk(fma(a.re, b.re, fma(a.im, b.im, acc.re)), fma(a.re, b.im, fma(-a.im, b.re, acc.im)));
+}
+// acc - a conj(b)
+__device__ __forceinline__ zd zfms_conj(zd a, zd b, zd acc) {
+  return mk(fma(-a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(-a.im, b.re, acc.im)));
 }
 
 constexpr int HEEV_UREG = 16;   // rows per lane of the register-resident back-transformation (r <= 128)
@@ -865,12 +872,13 @@ k_heev_backtr(const zd* __restrict__ gpk, const zd* __restrict__ taus, const dou
 // ---------------------------------------------------------------------------------------------
 constexpr int CH_NB = 16, CH_PS = CH_NB + 1;  // block width, padded row stride of the panel buffers
 constexpr int CH_THREADS = 512;
+constexpr int CH_LOAD_COLS = 16;
+          // columns per wave and load round (all of r <= 128 at once)
 
 struct CholHdr {
   double tol;
   int bad;
   int pad_;
-  double ipiv[HEEV_RMAX];   // 1 / L(j, j), 0 for a dependent column
 };
 
 inline size_t chol_lds_bytes(int r, bool packed_in_lds) {
@@ -924,181 +932,112 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
   const int nw = (int)blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, rho = lane & 15;   // MFMA lane coordinates
-  __shared__ zd chx[2][CH_NB];                // wave 0's column / row exchange (double-buffered)
-  __shared__ zd chl[CH_NB][CH_NB + 1];        // the factored diagonal block
+  const int nblk = (r + CH_NB - 1) / CH_NB;
+  __shared__ zd chx[2][CH_NB];                // column c of L (double-buffered)
+  __shared__ zd LT[CH_NB][CH_NB];             // LT[c][t] = conj(L(t, c)) for t > c, LT[c][c] = 1 / L(c, c)
+  __shared__ int tq;                          // next trailing-update tile of the step
   // packed lower storage, column j at j r - j (j - 1) / 2
   auto at = [&](int i, int j) -> zd& { return S[j * r - (j * (j - 1)) / 2 + (i - j)]; };  // i >= j
-  const zd zero = mk(0.0, 0.0);
 
-  RT_PHASE(7);
-  load_lower_packed(G, r, S, tid, blockDim.x);
-  if (tid == 0) H.bad = 0;
-  __syncthreads();
-  if (wave == 0) {
-    double mx = 0.0;
-    for (int j = lane; j < r; j += 64) mx = fmax(mx, at(j, j).re);
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
-    if (lane == 0) H.tol = tol_rel * mx;
-  }
-  __syncthreads();
-  const double tol = H.tol;
-
-  // ---- L^{-1} by block rows, beside the factorization ----
-  // Block row Kp of L^{-1}: Linv(Kp, jt) = -D_Kp sum_{jt <= mb < Kp} L(Kp, mb) Linv(mb, jt) for
-  // jt < Kp, and Linv(Kp, Kp) = D_Kp.  It needs only L's block row Kp (final once the panel of
-  // step Kp - 1 is written) and block rows < Kp of L^{-1}, so waves 1.. compute it in registers
-  // while wave 0 factors the next diagonal block, and store it over L's block row Kp in the next
-  // panel phase.  D_Kp is read back from GD.  An MFMA output tile (lane: rows 4 v + g of column
-  // rho) is laid out as the B operand of the next product, so T = sum L Linv feeds D T directly.
-  constexpr int LT_MAX = IN_LDS ? 1 : 3;   // tiles per wave: r <= 128 in LDS (<= 7), else <= 15
-  ch_f64x4 lr[LT_MAX], li[LT_MAX];
-  const int nlw = nw - 1;                  // waves 1 .. nw - 1 compute the block rows
-  auto linv_tiles = [&](int Kp) {
-    const int row = CH_NB * Kp + rho, rowc = min(row, r - 1);
+  // ---- wave 0: factor a diagonal block held in registers ----
+  // Lane (rho, g) holds entries (i, j_s) = (rho, g + 4 s) of the block (identity-padded when it
+  // is narrower than 16, so its extra pivots are 1).  Column c is exchanged through LDS once its
+  // pivot is known; the entries right of column c then take the rank-one update, slots whose
+  // columns are all done being skipped.  Entries above the diagonal are never read.  A pivot at
+  // or below tol marks a dependent column: its column of L is zero and H.bad is set.  Writes LT.
+  auto factor_core = [&](int Kb, zd (&a)[4], double tl, auto tiny_range) {
+    constexpr bool TINY = decltype(tiny_range)::value;   // tol may be at or below 1e-280
+    const int K = CH_NB * Kb, kb = min(CH_NB, r - K);
+    double myipv = 1.0;    // 1 / L(rho, rho) once column rho is factored
 #pragma unroll
-    for (int u = 0; u < LT_MAX; ++u) {
-      const int jt = (wave - 1) + nlw * u;
-      lr[u] = (ch_f64x4){0, 0, 0, 0};
-      li[u] = lr[u];
-      if (jt >= Kp) continue;                // uniform per wave
-      ch_f64x4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
-      const int col = CH_NB * jt + rho;
-      for (int mb = jt; mb < Kp; ++mb) {
-#pragma unroll
-        for (int kg = 0; kg < 4; ++kg) {
-          const int k = CH_NB * mb + 4 * kg + g;                  // < CH_NB Kp <= rowc
-          const zd av = zsel(row < r, at(rowc, k), zero);          // L(row, k)
-          const zd bv = zsel(k >= col, at(k, min(col, k)), zero);  // Linv(k, col), lower
-          ch_cmma(av, bv, tr, ti);
-        }
+    for (int c = 0; c < CH_NB; ++c) {
+      const int cs = c & 3, sl = c >> 2;
+      const zd ac = a[sl];
+      const double dd = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ac.re), c + 16 * cs),
+                                         __builtin_amdgcn_readlane(__double2loint(ac.re), c + 16 * cs));
+      // 1 / sqrt(dd) without branches (dd is wave-uniform): one reciprocal square root; only when
+      // tol is that small can a live pivot lie near the bottom of the normal range, and then dd
+      // is scaled by 2^600 first.  A dependent or padding column gets 0 or 1.
+      const bool live = c < kb && dd > tl && dd > 0.0;
+      double ipv0;
+      if constexpr (TINY) {
+        const bool tiny = dd <= 1e-280;
+        const double y = rsqrt_d(tiny ? dd * 0x1p+600 : dd);
+        ipv0 = tiny ? y * 0x1p+300 : y;
+      } else {
+        ipv0 = rsqrt_d(dd);
       }
-      const zd* __restrict__ Dg = GD + Kp * CH_NB * CH_NB;
-#pragma unroll
-      for (int kg = 0; kg < 4; ++kg) ch_cmma(Dg[rho * CH_NB + 4 * kg + g], mk(tr[kg], ti[kg]), lr[u], li[u]);
-    }
-  };
-  auto linv_store = [&](int Kp) {
-    if (wave > 0) {
-#pragma unroll
-      for (int u = 0; u < LT_MAX; ++u) {
-        const int jt = (wave - 1) + nlw * u;
-        if (jt >= Kp) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = CH_NB * Kp + 4 * v + g;
-          if (i < r) at(i, CH_NB * jt + rho) = mk(-lr[u][v], -li[u][v]);
-        }
-      }
-    }
-    for (int q = tid; q < CH_NB * CH_NB; q += blockDim.x) {
-      const int i = q / CH_NB, c = q % CH_NB;
-      if (i >= c && CH_NB * Kp + i < r) at(CH_NB * Kp + i, CH_NB * Kp + c) = GD[Kp * CH_NB * CH_NB + q];
-    }
-  };
-
-  RT_PHASE(8);
-  // ---- blocked right-looking Cholesky ----
-  for (int K = 0; K < r; K += CH_NB) {
-    const int kb = min(CH_NB, r - K), K1 = K + kb, m = r - K1;
-    const int Kb = K / CH_NB;
-    // (a) wave 0: factor the diagonal block and invert it; lane holds (i, j_s), i = rho, j_s = g + 4 s.
-    // A block narrower than 16 is padded with the identity (its extra pivots are 1), so the
-    // unrolled column loop has no bound tests; only rows and columns < kb are written back.
-    if (wave == 0) {
-      zd a[4], d[4];
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        const int j = g + 4 * s2;
-        const bool in = rho < kb && j < kb && rho >= j;
-        const zd diag = mk(rho == j ? 1.0 : 0.0, 0.0);
-        const int ic = min(K + rho, r - 1), jc = min(K + j, ic);   // in range when !in
-        a[s2] = zsel(in, at(ic, jc), diag);
-        d[s2] = diag;
-      }
-      double myipv = 1.0;   // 1 / L(rho, rho) once column rho is factored
-      // column exchange through LDS (one write, broadcast reads; the wave's LDS operations run in
-      // order) and pivots read from a fixed lane as scalars: no chains of cross-lane permutes
-#pragma unroll
-      for (int c = 0; c < CH_NB; ++c) {
-        const int cs = c & 3, sl = c >> 2;
-        const zd ac = a[sl];
-        const double dd = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ac.re), c + 16 * cs),
-                                           __builtin_amdgcn_readlane(__double2loint(ac.re), c + 16 * cs));
-        // pivot sqrt(dd) and its inverse: one reciprocal square root (dd is wave-uniform), the
-        // IEEE square root and division only for pivots near the bottom of the normal range
-        const bool live = c < kb && dd > tol && dd > 0.0;
-        double pv = 1.0, ipv = 1.0;
-        if (c < kb) {
-          if (!live) {
-            pv = 0.0;
-            ipv = 0.0;
-          } else if (dd > 1e-280) {
-            ipv = rsqrt_d(dd);
-            pv = dd * ipv;
-          } else {
-            pv = sqrt(dd);
-            ipv = 1.0 / pv;
-          }
-        }
-        myipv = (rho == c) ? ipv : myipv;
-        const zd acn = zsel(g != cs || rho < c, ac, zsel(rho == c, mk(pv, 0.0), cscale(ac, ipv)));
-        a[sl] = acn;
-        if (g == cs) chx[c & 1][rho] = acn;   // column c of L (rows < c hold the upper part, unused)
-        __builtin_amdgcn_wave_barrier();
-        const zd lic = chx[c & 1][rho];        // L(rho, c)
-        zd ljc[4];
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) ljc[s2] = chx[c & 1][g + 4 * s2];   // L(j_s, c)
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) {
-          const int j = g + 4 * s2;
-          const zd upd = csub(a[s2], cmul(lic, cconj(ljc[s2])));
-          a[s2] = zsel(j > c && rho >= j, upd, a[s2]);
-        }
-      }
-      // the factored block to LDS for the substitution below
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) chl[rho][g + 4 * s2] = a[s2];
+      const double ipv = c < kb ? (live ? ipv0 : 0.0) : 1.0;
+      myipv = (rho == c) ? ipv : myipv;
+      // column c of L: the lanes holding it scale it (its diagonal entry and the rows above are
+      // never read again)
+      const zd acn = zsel(g == cs, cscale(ac, ipv), ac);
+      a[sl] = acn;
+      if (g == cs) chx[c & 1][rho] = acn;
       __builtin_amdgcn_wave_barrier();
-      if (g == 0 && rho < kb) {
-        H.ipiv[K + rho] = myipv;
-        if (myipv == 0.0) H.bad = 1;
-      }
-      // D = L_KK^{-1}: forward substitution, row t final then eliminated from the rows below
-#pragma unroll
-      for (int t = 0; t < CH_NB; ++t) {
-        const double sc = (rho == t) ? myipv : 1.0;   // branch-free: the arrays stay in registers
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) d[s2] = cscale(d[s2], sc);
-        // row t of D is final: publish it, then eliminate it from the rows below
-        if (rho == t) {
-#pragma unroll
-          for (int s2 = 0; s2 < 4; ++s2) chx[t & 1][g + 4 * s2] = d[s2];
-        }
-        __builtin_amdgcn_wave_barrier();
-        const zd lit = chl[rho][t];                 // L(rho, t)
-        const zd lm = zsel(rho > t, lit, zero);
-        zd dtj[4];
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) dtj[s2] = chx[t & 1][g + 4 * s2];   // D(t, j_s)
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) d[s2] = csub(d[s2], cmul(lm, dtj[s2]));
-      }
+      const zd lic = chx[c & 1][rho];          // L(rho, c)
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
-        const int j = g + 4 * s2;
-        if (rho < kb && j < kb && rho >= j) at(K + rho, K + j) = a[s2];
-        const zd dv = zsel(rho < kb && j < kb, d[s2], zero);
-        DI[rho * CH_PS + j] = dv;
-        GD[(K / CH_NB) * CH_NB * CH_NB + rho * CH_NB + j] = dv;
+        if (s2 < sl) continue;                 // columns g + 4 s2 < c: done
+        const zd ljc = chx[c & 1][g + 4 * s2];  // L(j_s, c)
+        const zd upd2 = zfms_conj(lic, ljc, a[s2]);
+        a[s2] = (s2 == sl) ? zsel(g + 4 * s2 > c, upd2, a[s2]) : upd2;
       }
-    } else if (Kb >= 1) {
-      linv_tiles(Kb - 1);
     }
-    __syncthreads();
-    if (K == 0) RT_PHASE(12);
-    if (Kb >= 1) linv_store(Kb - 1);   // rows of block Kb - 1: disjoint from the panel below
-    // (b) panel P(i, c) = sum_t G(i, K + t) conj(D(c, t)), rows i >= K1, 16-row MFMA tiles
+    if (rho < kb && myipv == 0.0) H.bad = 1;   // a dependent column
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int j = g + 4 * s2;
+      if (rho > j) LT[j][rho] = cconj(a[s2]);
+      if (rho == j) LT[j][j] = mk(myipv, 0.0);
+    }
+  };
+  auto factor_block = [&](int Kb, zd (&a)[4], double tl) {
+    if (tl > 1e-280) factor_core(Kb, a, tl, std::false_type{});
+    else factor_core(Kb, a, tl, std::true_type{});
+  };
+
+  // ---- wave 0: D_Kb = L_KK^{-1} from the factored block in LT ----
+  // Sixteen rows, the identity rows e_i', solve x L_KK^H = e_i', so x = row i' of L_KK^{-H} and
+  // D(:, i') = conj(x).  Four lanes per row (lane 4 i' + h holds columns h + 4 s).  Columns left to
+  // right: the owner of column c scales it, x_c = g_c / L(c, c), and passes it to its quad by DPP;
+  // columns t > c subtract x_c conj(L(t, c)).  A dependent column has 1 / L(c, c) = 0 and gives a
+  // zero row and column of D.  D goes to DI (for the panel) and GD (for L^{-1}), zero outside kb.
+  auto diag_inverse = [&](int Kb) {
+    const zd zero = mk(0.0, 0.0);
+    const int K = CH_NB * Kb, kb = min(CH_NB, r - K);
+    const int id = lane >> 2, gq = lane & 3;
+    zd gv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) gv[s] = mk(gq + 4 * s == id ? 1.0 : 0.0, 0.0);
+    static_for<0, CH_NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value, cs = c & 3, sl = c >> 2;
+      const zd own = cscale(gv[sl], LT[c][c].re);
+      const zd p = dpp<cs * 0x55>(own);                     // quad_perm [cs, cs, cs, cs]
+      {
+        const zd u = zfms(p, LT[c][gq + 4 * sl], gv[sl]);
+        gv[sl] = zsel(gq == cs, p, zsel(gq > cs, u, gv[sl]));
+      }
+      static_for<sl + 1, 4>([&](auto ss) {
+        constexpr int s = decltype(ss)::value;
+        gv[s] = zfms(p, LT[c][gq + 4 * s], gv[s]);
+      });
+    });
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int t = gq + 4 * s;
+      const zd dv = zsel(t < kb && id < kb, cconj(gv[s]), zero);   // D(t, id)
+      DI[t * CH_PS + id] = dv;
+      GD[Kb * CH_NB * CH_NB + t * CH_NB + id] = dv;
+    }
+  };
+
+  // ---- panel of step Kb: P(i, c) = sum_t S(i, K + t) conj(D(c, t)), rows i >= K1 ----
+  // 16-row MFMA tiles over the waves; the panel goes over the block column of S (it is L's) and
+  // into P for the trailing update.
+  auto panel = [&](int Kb) {
+    const zd zero = mk(0.0, 0.0);
+    const int K = CH_NB * Kb, kb = min(CH_NB, r - K), K1 = K + kb, m = r - K1;
     for (int ti = wave; ti * 16 < m; ti += nw) {
       const int i0 = K1 + 16 * ti;
       ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
@@ -1119,48 +1058,222 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
         }
       }
     }
-    __syncthreads();
-    if (K == 0) RT_PHASE(13);
-    // (c) trailing update S(i, j) -= sum_c P(i, c) conj(P(j, c)), lower 16 x 16 tiles
-    const int T = (m + 15) / 16;
-    for (int q = wave; q < T * (T + 1) / 2; q += nw) {
-      int ti = (int)((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
-      while (ti * (ti + 1) / 2 > q) --ti;
-      while ((ti + 1) * (ti + 2) / 2 <= q) ++ti;
-      const int tj = q - ti * (ti + 1) / 2;
-      const int i0 = K1 + 16 * ti, j0 = K1 + 16 * tj;
-      ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  };
+
+  // ---- L^{-1} by block rows, beside the factorization ----
+  // Block row Kp of L^{-1}: Linv(Kp, jt) = -D_Kp sum_{jt <= mb < Kp} L(Kp, mb) Linv(mb, jt) for
+  // jt < Kp, and Linv(Kp, Kp) = D_Kp.  It needs only L's block row Kp (final once the panel of
+  // step Kp - 1 is written) and block rows < Kp of L^{-1}, so waves 1.. compute it in registers
+  // in the update phase of step Kp and store it in the panel phase of step Kp + 1, over L's block
+  // row Kp, and its conjugate transpose into Rinv's block column Kp.  D_Kp is read back from GD.
+  // An MFMA output tile (lane: rows 4 v + g of column rho) is laid out as the B operand of the
+  // next product, so T = sum L Linv feeds D T directly.
+  constexpr int LT_MAX = IN_LDS ? 1 : 3;   // tiles per wave: r <= 128 in LDS (<= 7), else <= 15
+  ch_f64x4 lr[LT_MAX], li[LT_MAX];
+  const int nlw = nw - 1;                  // waves 1 .. nw - 1 compute the block rows
+  // first tile column of this wave: waves 1, 2, 3, 5, 6, 7 take 0 .. 5 (the longest rows on
+  // distinct SIMDs), wave 4 the last: it shares its SIMD with wave 0, whose factorization is the
+  // step's critical path, so it takes no other work
+  const int ljt = wave < 4 ? wave - 1 : (wave == 4 ? nw - 2 : wave - 2);
+  auto linv_tiles = [&](int Kp) {
+    const zd zero = mk(0.0, 0.0);
+    const int row = CH_NB * Kp + rho, rowc = min(row, r - 1);
 #pragma unroll
-      for (int kg = 0; kg < 4; ++kg) {
-        const int k = 4 * kg + g;
-        const zd av = zsel(i0 + rho < r && k < kb, P[(size_t)min(i0 + rho, r - 1) * CH_PS + k], zero);
-        const zd bv = zsel(j0 + rho < r && k < kb, cconj(P[(size_t)min(j0 + rho, r - 1) * CH_PS + k]), zero);
-        ch_cmma(av, bv, cr, ci);
+    for (int u = 0; u < LT_MAX; ++u) {
+      const int jt = ljt + nlw * u;
+      lr[u] = (ch_f64x4){0, 0, 0, 0};
+      li[u] = lr[u];
+      if (jt >= Kp) continue;                // uniform per wave
+      ch_f64x4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+      const int col = CH_NB * jt + rho;
+      for (int mb = jt; mb < Kp; ++mb) {
+#pragma unroll
+        for (int kg = 0; kg < 4; ++kg) {
+          const int k = CH_NB * mb + 4 * kg + g;                  // < CH_NB Kp <= rowc
+          const zd av = zsel(row < r, at(rowc, k), zero);          // L(row, k)
+          const zd bv = zsel(k >= col, at(k, min(col, k)), zero);  // Linv(k, col), lower
+          ch_cmma(av, bv, tr, ti);
+        }
       }
+      const zd* __restrict__ Dg = GD + Kp * CH_NB * CH_NB;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + g + 4 * v, j = j0 + rho;
-        if (i < r && j < r && i >= j) at(i, j) = csub(at(i, j), mk(cr[v], ci[v]));
+      for (int kg = 0; kg < 4; ++kg) ch_cmma(Dg[rho * CH_NB + 4 * kg + g], mk(tr[kg], ti[kg]), lr[u], li[u]);
+    }
+  };
+  // block row Kp of L^{-1} over L's, Rinv(:, block Kp) = its conjugate transpose, zero below
+  auto linv_store = [&](int Kp) {
+    const zd zero = mk(0.0, 0.0);
+    const int K = CH_NB * Kp, kb = min(CH_NB, r - K);
+    if (wave > 0) {
+#pragma unroll
+      for (int u = 0; u < LT_MAX; ++u) {
+        const int jt = ljt + nlw * u;
+        if (jt >= Kp) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = K + 4 * v + g, c = CH_NB * jt + rho;
+          if (i < r) {
+            at(i, c) = mk(-lr[u][v], -li[u][v]);
+            R[(int64_t)i * r + c] = mk(-lr[u][v], li[u][v]);
+          }
+        }
+      }
+    }
+    for (int q = tid; q < CH_NB * CH_NB; q += blockDim.x) {
+      const int i = q / CH_NB, c = q % CH_NB;
+      if (i < kb && c < kb) {
+        const zd dv = GD[Kp * CH_NB * CH_NB + q];
+        if (i >= c) at(K + i, K + c) = dv;
+        R[(int64_t)(K + i) * r + K + c] = cconj(dv);   // zero for c > i
+      }
+    }
+    const int below = r - (K + kb);
+    for (int q = tid; q < kb * below; q += blockDim.x) {
+      const int c = q / below, i = K + kb + q % below;
+      R[(int64_t)(K + c) * r + i] = zero;
+    }
+  };
+
+  RT_PHASE(7);
+  if (wave == 0) {
+    // tol from the diagonal of G, and diagonal block 0 straight from G, factored while the other
+    // waves load the lower triangle
+    if (lane == 0) H.bad = 0;
+    const int kb0 = min(CH_NB, r);
+    double mx = 0.0;
+    for (int j = lane; j < r; j += 64) mx = fmax(mx, G[(int64_t)j * r + j].re);
+    zd a[4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int j = g + 4 * s2;
+      const bool in = rho < kb0 && j < kb0 && rho >= j;
+      zd v = mk(rho == j ? 1.0 : 0.0, 0.0);
+      if (in) v = G[(int64_t)j * r + rho];
+      a[s2] = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    const double tl = tol_rel * mx;
+    if (lane == 0) H.tol = tl;
+    factor_block(0, a, tl);
+    diag_inverse(0);
+  } else {
+    // lower triangle, column by column (rows j.. of column j are contiguous in G and in S), all
+    // loads of a round in flight together
+    const int lw = wave - 1, nlw_ = nw - 1;
+    for (int j0 = lw; j0 < r; j0 += CH_LOAD_COLS * nlw_) {
+      zd v[CH_LOAD_COLS][2];
+#pragma unroll
+      for (int u = 0; u < CH_LOAD_COLS; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = j0 + nlw_ * u, i = j + lane + 64 * h;
+          v[u][h] = (j < r && i < r) ? G[(int64_t)j * r + i] : mk(0.0, 0.0);
+        }
+#pragma unroll
+      for (int u = 0; u < CH_LOAD_COLS; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = j0 + nlw_ * u, i = j + lane + 64 * h;
+          if (j < r && i < r) at(i, j) = v[u][h];
+        }
+      for (int u = 0; u < CH_LOAD_COLS; ++u) {   // columns longer than 128 rows (r > 128 only)
+        const int j = j0 + nlw_ * u;
+        for (int i = j + lane + 128; j < r && i < r; i += 64) at(i, j) = G[(int64_t)j * r + i];
+      }
+    }
+  }
+  __syncthreads();
+  const double tol = H.tol;
+  RT_PHASE(8);
+  RT_PHASE(12);
+
+  // ---- blocked right-looking Cholesky with look-ahead ----
+  for (int Kb = 0; Kb < nblk; ++Kb) {
+    const int K = CH_NB * Kb, kb = min(CH_NB, r - K), K1 = K + kb, m = r - K1;
+    // (b) block row Kb - 1 of L^{-1} out of the registers, the panel of block Kb and D_Kb
+    if (Kb >= 1) linv_store(Kb - 1);   // rows of block Kb - 1: disjoint from the panel below
+    if (tid == 0) tq = 1;              // tile 0 of the trailing update is wave 0's
+    panel(Kb);
+    __syncthreads();
+    if (Kb == 0) RT_PHASE(13);
+    if (Kb == 3) RT_PHASE(15);
+    // (c) trailing update S(i, j) -= sum_c P(i, c) conj(P(j, c)), lower 16 x 16 tiles: wave 0
+    // takes the first diagonal tile in registers and factors it (the next step's diagonal block);
+    // waves 1.. take the other tiles, then block row Kb of L^{-1}
+    if (wave == 0) {
+      if (Kb + 1 < nblk) {
+        // diagonal block Kb + 1 with the update of this step's panel: lane (rho, g) gets
+        // T(rho, j_s) of T = P P^H as entry s of an MFMA tile with operands conj(P) and P, the
+        // products and their order being those of the other tiles
+        const int Kn = K1, kbn = min(CH_NB, r - Kn);
+        zd a[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int j = g + 4 * s2;
+          const bool in = rho < kbn && j < kbn && rho >= j;
+          const int ic = min(Kn + rho, r - 1), jc = min(Kn + j, ic);   // in range when !in
+          a[s2] = zsel(in, at(ic, jc), mk(rho == j ? 1.0 : 0.0, 0.0));
+        }
+        ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        const zd* Prow = P + (size_t)min(Kn + rho, r - 1) * CH_PS;
+#pragma unroll
+        for (int kg = 0; kg < 4; ++kg) {
+          const zd b = Prow[4 * kg + g];
+          cr = ch_mma(b.re, b.re, cr);
+          cr = ch_mma(b.im, b.im, cr);
+          ci = ch_mma(-b.im, b.re, ci);
+          ci = ch_mma(b.re, b.im, ci);
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int j = g + 4 * s2;
+          const bool in = rho < kbn && j < kbn && rho >= j;
+          a[s2] = zsel(in, csub(a[s2], mk(cr[s2], ci[s2])), a[s2]);
+        }
+        if (Kb == 3) RT_MARK(18);
+        factor_block(Kb + 1, a, tol);
+        diag_inverse(Kb + 1);
+        if (Kb == 3) RT_MARK(19);
+      }
+    } else {
+      const zd zero = mk(0.0, 0.0);
+      const int T = (m + 15) / 16, ntile = T * (T + 1) / 2;
+      linv_tiles(Kb);
+      // the trailing tiles other than the first come from a queue: waves with short or no rows
+      // of L^{-1} take more of them
+      for (; wave != 4;) {
+        int q0 = 0;
+        if (lane == 0) q0 = atomicAdd(&tq, 1);
+        const int q = __builtin_amdgcn_readfirstlane(q0);
+        if (q >= ntile) break;
+        int ti = (int)((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
+        while (ti * (ti + 1) / 2 > q) --ti;
+        while ((ti + 1) * (ti + 2) / 2 <= q) ++ti;
+        const int tj = q - ti * (ti + 1) / 2;
+        const int i0 = K1 + 16 * ti, j0 = K1 + 16 * tj;
+        ch_f64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+        for (int kg = 0; kg < 4; ++kg) {
+          const int k = 4 * kg + g;
+          const zd av = zsel(i0 + rho < r && k < kb, P[(size_t)min(i0 + rho, r - 1) * CH_PS + k], zero);
+          const zd bv = zsel(j0 + rho < r && k < kb, cconj(P[(size_t)min(j0 + rho, r - 1) * CH_PS + k]), zero);
+          ch_cmma(av, bv, cr, ci);
+        }
+        static_for<0, 4>([&](auto vv) {
+          constexpr int v = decltype(vv)::value;
+          const int i = i0 + g + 4 * v, j = j0 + rho;
+          if (i < r && j < r && i >= j) at(i, j) = csub(at(i, j), mk(cr[v], ci[v]));
+        });
       }
     }
     __syncthreads();
-    if (K == 0) RT_PHASE(14);
+    if (Kb == 0) RT_PHASE(14);
+    if (Kb == 2) RT_PHASE(16);
+    if (Kb == 3) RT_PHASE(17);
   }
   RT_PHASE(9);
-  // the last block row of L^{-1}
-  {
-    const int nblk = (r + CH_NB - 1) / CH_NB;
-    if (wave > 0) linv_tiles(nblk - 1);
-    __syncthreads();
-    linv_store(nblk - 1);
-    __syncthreads();
-  }
+  linv_store(nblk - 1);
   RT_PHASE(10);
-  // Rinv(i, j) = conj(Linv(j, i)) for i <= j, zero below the diagonal
-  for (int idx = tid; idx < r * r; idx += blockDim.x) {
-    const int i = idx % r, j = idx / r;
-    R[idx] = (i <= j) ? cconj(at(j, i)) : zero;
-  }
   RT_PHASE(11);
   if (tid == 0 && flags && H.bad) atomicOr(flags, 1);
 }
