@@ -422,12 +422,14 @@ constexpr int HEEV_UREG = 16;   // rows per lane of the register-resident back-t
 // tri holds d (r) then e (r) per face, taus the reflector scalars, gpk the reflectors; the kernel
 // starts at the eigenvalues.  MODE 2: in addition the eigenvalues (lamout) and the eigenvectors of
 // the tridiagonal (zs, stride r + 1) were computed by k_tri_stein; the kernel starts at the
-// re-orthogonalization of clusters.
+// re-orthogonalization of clusters.  MODES 2 and 3 stop before the back-transformation, which
+// k_heev_backtr does; MODE 3 runs from G (as MODE 0) and writes lamout and the reflector scalars
+// (taus_out, F x r) for it.
 template <bool IN_LDS, int MODE = 0>
 __global__ void __launch_bounds__(HEEV_THREADS)
 k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restrict__ lamout,
        zd* __restrict__ gpk, double* __restrict__ zs, double* __restrict__ lu,
-       const double* __restrict__ tri, const zd* __restrict__ taus) {
+       const double* __restrict__ tri, const zd* __restrict__ taus, zd* __restrict__ taus_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   HeevLds& L = *reinterpret_cast<HeevLds*>(smem_raw);
   const int f = blockIdx.x;
@@ -444,7 +446,7 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   RT_PHASE(0);
   for (int j = tid; j <= r; j += blockDim.x) L.cb[j] = (int)pk_off(j, r);
   if (tid < 2) { L.acc[tid] = 0.0; L.accre[tid] = 0.0; L.accim[tid] = 0.0; }
-  constexpr bool FROM_TRI = MODE >= 1;
+  constexpr bool FROM_TRI = MODE == 1 || MODE == 2;
   if constexpr (FROM_TRI) {
     for (int j = tid; j < r; j += blockDim.x) {
       L.d[j] = tri[(int64_t)f * 2 * r + j];
@@ -546,7 +548,7 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   // ---- eigenvalues of T: multisection, 8 lanes per eigenvalue ------------------------------
   const TriBounds tb = tri_bounds(L.d, L.e, L.e2, r);
   const double tnorm = tb.tnorm;
-  if constexpr (MODE < 2) {
+  if constexpr (MODE != 2) {
     for (int base = 0; base < r; base += ngrp) {
       const int j = base + grp;                      // j-th largest eigenvalue
       const bool on = j < r;
@@ -571,7 +573,7 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
   else Zp = Z;
 
   // ---- eigenvectors of T: inverse iteration, one thread per eigenvalue ---------------------------
-  if constexpr (MODE < 2) {
+  if constexpr (MODE != 2) {
     for (int j = tid; j < r; j += blockDim.x)
       tri_invit(L.d, L.e, r, L.lam[j], tnorm, j, lu + ((int64_t)f * r + j) * 5 * r, Zp + (int64_t)j * zst);
   } else if constexpr (IN_LDS) {
@@ -640,8 +642,14 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
     }
   }
   __syncthreads();
-  if constexpr (MODE == 2) {
+  if constexpr (MODE >= 2) {
     // the back-transformation runs in k_heev_backtr
+    if constexpr (MODE == 3) {
+      for (int j = tid; j < r; j += blockDim.x) {
+        taus_out[(int64_t)f * r + j] = L.tau[j];
+        lamout[(int64_t)f * r + j] = L.lam[j];
+      }
+    }
     if constexpr (IN_LDS) {
       for (int64_t i = tid; i < (int64_t)r * zst; i += blockDim.x) Z[i] = Zp[i];
     }
@@ -794,11 +802,17 @@ k_tri_stein(const double* __restrict__ tri, int r, double* __restrict__ lamout, 
 constexpr int BT_COLS = 32;
 constexpr int BT_THREADS = 8 * BT_COLS;
 constexpr int BT_CH = 32;
-constexpr int BT_RP = 8 * HEEV_UREG;   // padded rows (128)
+// UREG rows per lane (r <= 8 UREG), CH reflectors per LDS chunk: (16, 32) for r <= 128 and
+// (32, 15) for r <= 256 (the chunk of dense reflector rows stays under 64 KB)
+constexpr int BT_UREG_WIDE = 32, BT_CH_WIDE = 15;
 
+template <int UREG, int CH>
 __global__ void __launch_bounds__(BT_THREADS)
 k_heev_backtr(const zd* __restrict__ gpk, const zd* __restrict__ taus, const double* __restrict__ zs, int r,
               zd* __restrict__ Uout) {
+  constexpr int BT_RP = 8 * UREG;   // padded rows
+  constexpr int BT_CH = CH;
+  constexpr int HEEV_UREG = UREG;
   __shared__ zd vbuf[BT_CH][BT_RP];
   __shared__ zd tbuf[BT_CH];
   const int f = blockIdx.y;

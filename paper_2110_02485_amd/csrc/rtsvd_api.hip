@@ -304,17 +304,31 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
     auto kern = in_lds ? k_heev<true, 2> : k_heev<false, 2>;
     if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
-                       (const double*)tri, (const zd*)taus);
+                       (const double*)tri, (const zd*)taus, (zd*)nullptr);
     RT_LAUNCH_OK();
-    hipLaunchKernelGGL(k_heev_backtr, dim3((unsigned)ceil_div(r, BT_COLS), (unsigned)F), dim3(BT_THREADS), 0, s,
-                       (const zd*)gpk, (const zd*)taus, (const double*)zs, r, U);
+    hipLaunchKernelGGL((k_heev_backtr<HEEV_UREG, BT_CH>), dim3((unsigned)ceil_div(r, BT_COLS), (unsigned)F),
+                       dim3(BT_THREADS), 0, s, (const zd*)gpk, (const zd*)taus, (const double*)zs, r, U);
+    RT_LAUNCH_OK();
+    return 0;
+  }
+  if (r <= 8 * BT_UREG_WIDE) {
+    // the whole solver but the back-transformation, then the register-resident back-transformation
+    zd* taus = sc.get<zd>(F * (int64_t)r);
+    if (!taus) return fail(RTSVD_E_NOMEM, "device allocation failed: heev reflector scalars");
+    auto kern = in_lds ? k_heev<true, 3> : k_heev<false, 3>;
+    if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
+                       (const double*)nullptr, (const zd*)nullptr, taus);
+    RT_LAUNCH_OK();
+    hipLaunchKernelGGL((k_heev_backtr<BT_UREG_WIDE, BT_CH_WIDE>), dim3((unsigned)ceil_div(r, BT_COLS), (unsigned)F),
+                       dim3(BT_THREADS), 0, s, (const zd*)gpk, (const zd*)taus, (const double*)zs, r, U);
     RT_LAUNCH_OK();
     return 0;
   }
   auto kern = in_lds ? k_heev<true> : k_heev<false>;
   if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
-                     (const double*)nullptr, (const zd*)nullptr);
+                     (const double*)nullptr, (const zd*)nullptr, (zd*)nullptr);
   RT_LAUNCH_OK();
   return 0;
 }
