@@ -81,14 +81,14 @@ def stage_model(w, precision):
 # calibration 1 GiB -> FETCH_SIZE 524302.3 KiB (factor 1.99995), WRITE_SIZE 1048576 KiB (factor 1.0).
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
-                         "sha256": "eb1e5a0aa9d67c8af1d2b0ad2d0e0595d663416025f12059306b16798c0c8a2f",
-                         "bytes_per_launch": 681662561},
+                         "sha256": "0f263c4a58d3d8eeff383dfae4dcad517867cd4708c34282cd3781b1e25bd07f",
+                         "bytes_per_launch": 681669192},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
                         "sha256": "3123ec9af2958fd33f0593ec2c55eac4f6ac81b95e04e0ff6c8b14746769f10b",
                         "bytes_per_launch": 34664265},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
                         "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
-                        "bytes_per_launch": 76505883},
+                        "bytes_per_launch": 76505536},
 }
 
 
