@@ -16,7 +16,7 @@ import numpy as np
 
 from .tproduct import fft_tubes, ifft_tubes, tprod, tprod_hat, ttranspose, fro
 from .factor import normalize, normalize_tol
-from .solve import discrepancy
+from .solve import discrepancy, pinv_cut, pinv_scale
 
 OK = 0
 DP_NOT_MET = 1
@@ -56,12 +56,20 @@ def spatial_tevd(f: dict):
 
 
 def coefficients_tevd(f: dict, b: np.ndarray) -> np.ndarray:
-    """T_i = diag(1/d_i) W_i^H B-hat_i for every face, so that X_k = W_k * T_k is eq. (6) / (61)."""
+    """T_i = diag(1/d_i) W_i^H B-hat_i for every face, so that X_k = W_k * T_k is eq. (6) / (61).
+
+    diag(d)^{-1} is read as the pseudo-inverse with the tolerance of the truncated SVD solution
+    (`solve.pinv_cut` on |d|, the singular values of a Hermitian face): an eigenvalue at or below
+    sqrt(4 r eps) max |d| over all faces contributes nothing, so that on a symmetric A the T-tEVD
+    solution equals the T-tSVD one also when a face is (nearly) singular."""
     bh = fft_tubes(b)
     n = bh.shape[2]
+    ad = np.abs(f["d"])
+    cut = pinv_cut(ad)
     out = np.empty((f["d"].shape[0], b.shape[1], n), dtype=complex)
     for i in range(n):
-        out[:, :, i] = (f["W"][:, :, i].conj().T @ bh[:, :, i]) / f["d"][:, i][:, None]
+        sgn = np.where(f["d"][:, i] < 0.0, -1.0, 1.0)
+        out[:, :, i] = pinv_scale(f["W"][:, :, i].conj().T @ bh[:, :, i], ad[:, i], cut) * sgn[:, None]
     return out
 
 

@@ -69,6 +69,46 @@ def test_tevd_restore_equals_tsvd_restore_for_symmetric_a(per_slice):
     np.testing.assert_allclose(e["res"], s["res"], rtol=1e-10, atol=1e-12 * np.linalg.norm(b))
 
 
+def _singular_face_sym(m, n, seed, c0):
+    """A^(t) = c_t T with T random symmetric and the symmetric tube c = (1/2, -1/4, 0, ..., 0, -1/4)
+    + c0 / n: face f is c-hat_f T with c-hat_f = (1 - cos(2 pi f / n)) / 2 + c0, so face 0 is
+    c0 T (exactly zero for c0 = 0) and the others are well conditioned."""
+    rng = np.random.default_rng(seed)
+    t = rng.standard_normal((m, m))
+    t = t + t.T
+    c = np.zeros(n)
+    c[0], c[1], c[-1] = 0.5, -0.25, -0.25
+    c = c + c0 / n
+    return c[None, None, :] * t[:, :, None]
+
+
+@pytest.mark.parametrize("c0", [0.0, 1e-13])
+def test_tevd_singular_face_matches_tsvd_and_drops_the_face(c0):
+    # a symmetric A with a zero (or numerically zero) Fourier face: T-tEVD reads diag(d)^{-1} as the
+    # pseudo-inverse with the truncated SVD's tolerance, so it equals T-tSVD and the face
+    # contributes nothing; without the cutoff face 0 would carry 1/c0 or 1/0
+    m, n = 6, 8
+    a = _singular_face_sym(m, n, 31, c0)
+    assert np.abs(tp.fft_tubes(a)[:, :, 0]).max() <= max(c0, 1e-15) * 100 * np.abs(a).max() * n
+    b = np.random.default_rng(32).standard_normal((m, 2, n))
+    delta = 1e-3 * np.linalg.norm(b)
+    e = sy.tevd_restore(a, b, delta, 1.01, m)
+    s = so.tsvd_restore(a, b, delta, 1.01, m)
+    assert e["k"] == s["k"]
+    np.testing.assert_allclose(e["X"], s["X"], atol=1e-9 * np.abs(s["X"]).max())
+    np.testing.assert_allclose(e["res"], s["res"], rtol=1e-9, atol=1e-12 * np.linalg.norm(b))
+    xh = tp.fft_tubes(e["X"])
+    assert np.abs(xh[:, :, 0]).max() <= 1e-13 * np.abs(xh).max()   # zero up to the DFT round trip
+    # every other face: the per-face solution of the full-rank Hermitian system truncated at k
+    f = sy.tevd(a)
+    bh = tp.fft_tubes(b)
+    k = e["k"]
+    for i in range(1, n):
+        W, d = f["W"][:, :k, i], f["d"][:k, i]
+        np.testing.assert_allclose(xh[:, :, i], W @ ((W.conj().T @ bh[:, :, i]) / d[:, None]),
+                                   atol=1e-9 * np.abs(xh).max())
+
+
 def test_tlanczos_literal_equals_facewise():
     a = _sym(6, 5, 5)
     b = np.random.default_rng(6).standard_normal((6, 1, 5))
