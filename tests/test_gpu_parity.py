@@ -390,6 +390,36 @@ def test_ttevd_symmetric_blur_fp64():
     _check_eigs(f, orc["factor"], 7, 1e-10)
 
 
+def test_ttevd_nearly_singular_faces_fp64():
+    # the symmetric blur with the wide tube (sigma_c = 2): its DFT falls to 4e-5 of the largest
+    # face, so 85 of the 640 face eigenvalues (times the blur's own small ones) lie below the
+    # pseudo-inverse tolerance sqrt(4 r eps) max |d| (r = m here, every eigenvalue kept on both
+    # sides); the GPU's k, X and residuals must follow the oracle's reading of diag(d)^{-1}
+    from oracle import symmetric as sy
+    m, n = 40, 16
+    A = wl.blur_operator(m, n, 2.0, 6, sigma_c=2.0, symmetric=True)
+    Am = wl.to_math(A)
+    fo = sy.tevd(Am)
+    ad = np.abs(fo["d"])
+    assert (ad <= so.pinv_cut(ad)).sum() > 50     # many eigenvalues below the tolerance
+    rx = wl.rng_for("parity", "xtrue", 41)
+    X = wl.lateral_slices(wl.blob_image(m, n, rx)[None])
+    Bt = tp.tprod(Am, wl.to_math(X))
+    E = wl.scale_noise(wl.noise_direction(Bt.shape, wl.rng_for("parity", "noise", 41)), Bt, 1e-3)
+    Bm = Bt + E
+    delta = float(np.linalg.norm(E))
+    orc = sy.tevd_restore(Am, Bm, delta, 1.01, m)
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    f = rt.ttevd_factor(_t(A), m, "fp64")
+    res = f.solve(_t(wl.to_storage(Bm)), delta, 1.01, 1)
+    torch.cuda.synchronize()
+    assert int(res.k[0]) == orc["k"]
+    assert _rel(_np(res.X), wl.to_storage(orc["X"])) <= 1e-9
+    kk = orc["k"]
+    np.testing.assert_allclose(_np(res.resid)[0, :kk], orc["res"][:kk, 0], rtol=1e-9)
+
+
 def test_ttevd_indefinite_per_slice_odd_n():
     # random t-symmetric A with eigenvalues of both signs, odd n, two slices with their own k
     from oracle import symmetric as sy
