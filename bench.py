@@ -259,16 +259,31 @@ def read_stages(lib, steps, w, precision):
     return stages
 
 
-def dominant_roofline(stages, precision):
+def fft_kernel_name(n, precision):
+    """The forward tube-DFT kernel the library launches for tube length n."""
+    pow2 = n >= 2 and n & (n - 1) == 0
+    if pow2 and 4 <= n <= (64 if precision == "fp64" else 128):
+        return "k_rfft_reg"
+    if pow2:
+        return "k_rfft_pow2"
+    m = n
+    for p in (2, 3, 5, 7, 11, 13):
+        while m % p == 0:
+            m //= p
+    return "k_rfft_mixed" if m == 1 else "k_rdft_direct"
+
+
+def dominant_roofline(stages, precision, n=None):
     """Roofline object of the single-kernel stage with the most time per step, plus the fraction
     of the MFMA rate actually issued (three real products per complex multiply-add in FP32/FP64)
-    and the stages below 60 % of their bound."""
+    and the stages below 60 % of their bound.  n: the tube length (names the DFT kernel)."""
     single = [k for k in stages if k in SINGLE_KERNEL]
     if not single:
         return None
     dom = max(single, key=lambda k: stages[k]["ms_per_step"])
     st = stages[dom]
-    out = {"kernel": SINGLE_KERNEL[dom], "stage": dom, "bound": st["bound"], "achieved": st["achieved"],
+    kernel = fft_kernel_name(n, precision) if (n and dom in ("fft_A", "fft_omega")) else SINGLE_KERNEL[dom]
+    out = {"kernel": kernel, "stage": dom, "bound": st["bound"], "achieved": st["achieved"],
            "peak": st["peak"], "unit": st["unit"], "frac": st["frac"], "traffic": traffic_of(dom, precision),
            "avg_launch_us": st["avg_launch_us"], "launches_per_step": st["launches_per_step"]}
     if dom in ISSUED_FRACTION and st["unit"] == "TFLOP/s":
@@ -517,6 +532,53 @@ def time_video_512(torch, rt, wl, steps, tune_enabled=True):
              "stages": {kk: {a: (round(b, 4) if isinstance(b, float) else b) for a, b in v.items()}
                         for kk, v in stages.items()}}
     return entry, {"rtsvd": (X_eager.double().cpu().numpy(), k)}
+
+
+def time_video_240(torch, rt, wl, steps):
+    """Section 5's grey-scale video shape (240 x 240 x 240, six frames, FP32, r = 81, q = 0): one
+    restoration (factor + solve) and the solve alone with a cached factor, frames per second, and
+    the stages with their rooflines (the tube DFT of A at n = 240 takes the mixed-radix kernel)."""
+    w = wl.WORKLOADS["video240"]
+    dev = torch.device("cuda:0")
+    prob = make_problem(w, dev, torch, rt, wl)
+    At, Bd, Omt, x_true, delta = prob["A32"], prob["B32"], prob["Om32"], prob["X64"], prob["delta"]
+    p = Bd.shape[1]
+    print("[bench] 240-length video restoration", file=sys.stderr, flush=True)
+    state = {}
+
+    def restore():
+        f = rt.factor(At, w.k_max, w.oversample, w.power_iters, "fp32", Omt)
+        state["res"] = f.solve(Bd, delta, w.eta, 1, out=state.get("res"))
+        if "f" in state:
+            state["f"].close()
+        state["f"] = f
+    ms = _events_ms(torch, restore, steps)
+    res = state["res"]
+    k, status = int(res.k[0]), int(res.status[0])
+    X = res.X.clone()
+    f = state["f"]
+    sstate = {}
+
+    def solve_only():
+        sstate["res"] = f.solve(Bd, delta, w.eta, 1, out=sstate.get("res"))
+    ms_solve = _events_ms(torch, solve_only, steps)
+    lib = rt.load()
+    lib.rtsvd_timer_enable(1)
+    for _ in range(3):
+        ff = rt.factor(At, w.k_max, w.oversample, w.power_iters, "fp32", Omt)
+        ff.solve(Bd, delta, w.eta, 1)
+        ff.close()
+    torch.cuda.synchronize()
+    stages = read_stages(lib, 3, w, "fp32")
+    lib.rtsvd_timer_enable(0)
+    return {"l": w.size, "m": w.size, "n": w.n, "p": p, "k_max": w.k_max, "oversample": w.oversample,
+            "power_iters": w.power_iters, "noise": w.noise, "eta": w.eta, "precision": "fp32",
+            "value": 1000.0 / ms, "unit": "restorations/s", "frames_per_s": p * 1000.0 / ms,
+            "ms_restoration": ms, "ms_solve_cached_factor": ms_solve,
+            "k": k, "dp_status": status, "rel_error": _rel_err(torch, X, x_true),
+            "roofline": dominant_roofline(stages, "fp32", w.n),
+            "stages": {kk: {a: (round(b, 4) if isinstance(b, float) else b) for a, b in v.items()}
+                       for kk, v in stages.items()}}
 
 
 def time_adjoint_512(torch, rt, wl, steps):
@@ -792,11 +854,13 @@ def main():
 
 def time_configs(torch, rt, wl, args):
     """The other configurations: the 256-wide method comparison at two noise levels, the 512-wide
-    video restoration (graph replay, cached-factor solve) and the differentiable 16-clip batch."""
+    video restoration (graph replay, cached-factor solve), Section 5's 240-length video shape and
+    the differentiable 16-clip batch."""
     c256, gpu256 = time_comparison_256(torch, rt, wl, args.steps)
     video, gpuvid = time_video_512(torch, rt, wl, args.steps, not args.no_tune)
+    video240 = time_video_240(torch, rt, wl, args.steps)
     adj = time_adjoint_512(torch, rt, wl, max(3, args.steps // 2))
-    return {"comparison_256": c256, "video_512": video, "adjoint_512": adj,
+    return {"comparison_256": c256, "video_512": video, "video_240": video240, "adjoint_512": adj,
             "_gpu": {"c256": gpu256, "video": gpuvid}}
 
 

@@ -9,6 +9,8 @@
 // are packed into one complex sequence (z = x + i y), a radix-2 Stockham FFT runs in LDS,
 // and the two spectra are separated with X_f = (Z_f + conj Z_{n-f})/2,
 // Y_f = (Z_f - conj Z_{n-f})/(2i).  Stores of one face for TB tubes are contiguous again.
+// Tube lengths whose prime factors are all at most 13 (the paper's n = 240, 300 and 500 among
+// them) take the same layout with a mixed-radix Stockham FFT; other lengths a direct DFT.
 #pragma once
 #include "common.hpp"
 #include <map>
@@ -45,11 +47,127 @@ __device__ cplx<T>* stockham_lds(cplx<T>* b0, cplx<T>* b1, const cplx<T>* tw, in
   return b0;
 }
 
-// twiddle table in global memory: tw[k] = exp(-2 pi i k / n), k < n/2, computed in FP64
+// Mixed-radix Stockham passes (the autosorting formulation of Govindaraju et al., SC 2008, with a
+// radix per pass).  n = p_1 p_2 ... p_P; pass j with radix p and Ns = p_1 ... p_{j-1} maps, for
+// every butterfly index b < n / p (k = b mod Ns):
+//   v_r = in[b + r n/p] exp(sign 2 pi i r k / (Ns p)),  r < p
+//   out[(b - k) p + k + q Ns] = sum_r v_r exp(sign 2 pi i r q / p),  q < p
+// which leaves the DFT in natural order after the last pass.  tw holds exp(-2 pi i t / n) for
+// t < n (conjugated for the inverse); both exponents above are exact multiples of 1/n, and
+// r k n / (Ns p) < n.  The radices are 2, 3, 4, 5, 7, 11 and 13 (FFT_RMAX).
+constexpr int FFT_RMAX = 13;
+constexpr int FFT_MAXPASS = 24;
+struct RadixPlan {
+  int np;
+  int r[FFT_MAXPASS];
+};
+
+// radices of n: fours, then a two, then 3, 5, 7, 11, 13; false when another prime divides n
+inline bool radix_plan(int64_t n, RadixPlan& pl) {
+  pl.np = 0;
+  if (n < 2) return false;
+  int64_t m = n;
+  auto take = [&](int p) {
+    while (m % p == 0) {
+      if (pl.np == FFT_MAXPASS) return false;
+      pl.r[pl.np++] = p;
+      m /= p;
+    }
+    return true;
+  };
+  const int radices[] = {4, 2, 3, 5, 7, 11, 13};
+  for (int p : radices)
+    if (!take(p)) return false;
+  return m == 1;
+}
+
+// One pass of radix P (compile time).  Thread mapping: item idx = b nseq + sq (sequence sq
+// fastest, as the buffers are laid out), advanced by blockDim.x without divisions in the loop.
+// The P-point DFT takes its roots exp(sign 2 pi i e / P) from the table once per pass (radices 2
+// and 4 use the exact +-1, +-i forms).
+template <int P, typename T>
+__device__ __forceinline__ void stockham_pass(const cplx<T>* b0, cplx<T>* b1, const cplx<T>* tw, int n, int Ns,
+                                              int nseq, int sign) {
+  const int m = n / P, stride = n / (Ns * P), total = m * nseq;
+  cplx<T> root[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    cplx<T> w = tw[e * m];
+    if (sign > 0) w.im = -w.im;
+    root[e] = w;
+  }
+  const int step = blockDim.x, db = step / nseq, dsq = step - db * nseq;
+  int b = threadIdx.x / nseq, sq = threadIdx.x - b * nseq;
+  for (int idx = threadIdx.x; idx < total; idx += step) {
+    const int k = b % Ns;
+    cplx<T> v[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      cplx<T> x = b0[(b + r * m) * nseq + sq];
+      if (r > 0) {
+        cplx<T> w = tw[r * k * stride];
+        if (sign > 0) w.im = -w.im;
+        x = cmul(x, w);
+      }
+      v[r] = x;
+    }
+    cplx<T>* o = b1 + ((b - k) * P + k) * nseq + sq;
+    const int os = Ns * nseq;
+    if constexpr (P == 2) {
+      o[0] = cadd(v[0], v[1]);
+      o[os] = csub(v[0], v[1]);
+    } else if constexpr (P == 4) {
+      const cplx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+      const cplx<T> s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+      // forward: y1 = d02 - i d13, y3 = d02 + i d13 (the inverse swaps them)
+      const cplx<T> mi = mk((T)sign * -d13.im, (T)sign * d13.re);   // sign * i * d13
+      o[0] = cadd(s02, s13);
+      o[os] = cadd(d02, mi);
+      o[2 * os] = csub(s02, s13);
+      o[3 * os] = csub(d02, mi);
+    } else {
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        cplx<T> y = v[0];
+#pragma unroll
+        for (int r = 1; r < P; ++r) y = cadd(y, cmul(v[r], root[(r * q) % P]));
+        o[q * os] = y;
+      }
+    }
+    b += db;
+    sq += dsq;
+    if (sq >= nseq) { sq -= nseq; ++b; }
+  }
+}
+
 template <typename T>
-__global__ void k_twiddle_table(cplx<T>* tw, int n) {
+__device__ cplx<T>* stockham_mixed(cplx<T>* b0, cplx<T>* b1, const cplx<T>* tw, int n, const RadixPlan& plan,
+                                   int nseq, int sign) {
+  int Ns = 1;
+  for (int pass = 0; pass < plan.np; ++pass) {
+    const int p = plan.r[pass];
+    switch (p) {
+      case 2: stockham_pass<2>(b0, b1, tw, n, Ns, nseq, sign); break;
+      case 3: stockham_pass<3>(b0, b1, tw, n, Ns, nseq, sign); break;
+      case 4: stockham_pass<4>(b0, b1, tw, n, Ns, nseq, sign); break;
+      case 5: stockham_pass<5>(b0, b1, tw, n, Ns, nseq, sign); break;
+      case 7: stockham_pass<7>(b0, b1, tw, n, Ns, nseq, sign); break;
+      case 11: stockham_pass<11>(b0, b1, tw, n, Ns, nseq, sign); break;
+      default: stockham_pass<13>(b0, b1, tw, n, Ns, nseq, sign); break;
+    }
+    __syncthreads();
+    cplx<T>* tmp = b0; b0 = b1; b1 = tmp;
+    Ns *= p;
+  }
+  return b0;
+}
+
+// twiddle table in global memory: tw[k] = exp(-2 pi i k / n), k < cnt (n/2 for the radix-2
+// passes, n for the mixed-radix ones), computed in FP64
+template <typename T>
+__global__ void k_twiddle_table(cplx<T>* tw, int n, int cnt) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n / 2) {
+  if (k < cnt) {
     double s, c;
     sincospi(-2.0 * (double)k / (double)n, &s, &c);
     tw[k] = mk((T)c, (T)s);
@@ -57,8 +175,69 @@ __global__ void k_twiddle_table(cplx<T>* tw, int n) {
 }
 
 template <typename T>
-__device__ void fill_twiddles(cplx<T>* tw, const cplx<T>* __restrict__ gtw, int n) {
-  for (int k = threadIdx.x; k < n / 2; k += blockDim.x) tw[k] = gtw[k];
+__device__ void fill_twiddles(cplx<T>* tw, const cplx<T>* __restrict__ gtw, int cnt) {
+  for (int k = threadIdx.x; k < cnt; k += blockDim.x) tw[k] = gtw[k];
+}
+
+// Staging of a workgroup's TB tubes (tube0 .. tube0 + TB - 1): element t of tube tube0 + i comes
+// from in[tube0 + i + ntubes t] (TB consecutive tubes per element: contiguous) and goes to the
+// packed complex sequence s = i mod TH (TH = TB / 2), b[t TH + s].re for i < TH, .im otherwise.
+// FFT_LB loads per thread are issued before their LDS stores, so that many loads are in flight.
+// Returns the thread's sum of squared samples (FP64).
+constexpr int FFT_LB = 8;
+template <typename Tin, typename T>
+__device__ double stage_real_tubes(const Tin* __restrict__ in, int64_t ntubes, int n, int TB, int64_t tube0,
+                                   cplx<T>* b) {
+  const int TH = TB / 2, total = n * TB;
+  double acc = 0.0;
+  for (int base = threadIdx.x; base < total; base += FFT_LB * blockDim.x) {
+    T v[FFT_LB];
+#pragma unroll
+    for (int u = 0; u < FFT_LB; ++u) {
+      const int idx = base + u * blockDim.x;
+      const int t = idx / TB, i = idx - t * TB;
+      const int64_t g = tube0 + i;
+      v[u] = (idx < total && g < ntubes) ? (T)in[g + ntubes * (int64_t)t] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < FFT_LB; ++u) {
+      const int idx = base + u * blockDim.x;
+      if (idx < total) {
+        const int t = idx / TB, i = idx - t * TB;
+        acc += (double)v[u] * (double)v[u];
+        cplx<T>& z = b[t * TH + (i % TH)];
+        if (i < TH) z.re = v[u]; else z.im = v[u];
+      }
+    }
+  }
+  return acc;
+}
+// Staging of the half spectra of TB tubes for the inverse: face f < F of tube tube0 + i from
+// in[f face_stride + tube0 + i] to b[f TB + i] (imaginary parts of faces 0 and n/2 dropped).
+template <typename T>
+__device__ void stage_half_spectra(const cplx<T>* __restrict__ in, int64_t face_stride, int64_t ntubes, int n,
+                                   int TB, int64_t tube0, cplx<T>* b) {
+  const int F = n / 2 + 1, total = F * TB;
+  for (int base = threadIdx.x; base < total; base += FFT_LB * blockDim.x) {
+    cplx<T> v[FFT_LB];
+#pragma unroll
+    for (int u = 0; u < FFT_LB; ++u) {
+      const int idx = base + u * blockDim.x;
+      const int f = idx / TB, i = idx - f * TB;
+      const int64_t g = tube0 + i;
+      v[u] = (idx < total && g < ntubes) ? in[f * face_stride + g] : mk((T)0, (T)0);
+    }
+#pragma unroll
+    for (int u = 0; u < FFT_LB; ++u) {
+      const int idx = base + u * blockDim.x;
+      if (idx < total) {
+        const int f = idx / TB, i = idx - f * TB;
+        cplx<T> w = v[u];
+        if (f == 0 || 2 * f == n) w.im = 0;
+        b[f * TB + i] = w;
+      }
+    }
+  }
 }
 
 // forward: real tubes (input type Tin) -> half spectrum in working precision T, optional bf16 copy.
@@ -74,16 +253,8 @@ k_rfft_pow2(const Tin* __restrict__ in, int64_t ntubes, int n, int log2n, int TB
   cplx<T>* b0 = tw + n / 2;
   cplx<T>* b1 = b0 + (size_t)(n + 2) * TH;
   const int64_t tube0 = (int64_t)blockIdx.x * TB;
-  fill_twiddles(tw, gtw, n);
-  double acc = 0.0;
-  for (int idx = threadIdx.x; idx < n * TB; idx += blockDim.x) {
-    const int t = idx / TB, i = idx % TB;
-    const int64_t g = tube0 + i;
-    T v = 0;
-    if (g < ntubes) { v = (T)in[g + ntubes * (int64_t)t]; acc += (double)v * (double)v; }
-    cplx<T>& z = b0[t * TH + (i % TH)];
-    if (i < TH) z.re = v; else z.im = v;
-  }
+  fill_twiddles(tw, gtw, n / 2);
+  const double acc = stage_real_tubes(in, ntubes, n, TB, tube0, b0);
   __syncthreads();
   cplx<T>* res = stockham_lds(b0, b1, tw, n, log2n, TH, -1);
   const int F = n / 2 + 1;
@@ -233,16 +404,9 @@ k_irfft_pow2(const cplx<T>* __restrict__ in, int64_t face_stride, int64_t ntubes
   cplx<T>* b0 = tw + n / 2;
   cplx<T>* b1 = b0 + (size_t)(n + 2) * TH;
   const int64_t tube0 = (int64_t)blockIdx.x * TB;
-  fill_twiddles(tw, gtw, n);
+  fill_twiddles(tw, gtw, n / 2);
   // stage X_f (tubes 0..TH-1) and Y_f (tubes TH..TB-1) for f < F in b1: b1[f*TB + i]
-  for (int idx = threadIdx.x; idx < F * TB; idx += blockDim.x) {
-    const int f = idx / TB, i = idx % TB;
-    const int64_t g = tube0 + i;
-    cplx<T> v = mk((T)0, (T)0);
-    if (g < ntubes) v = in[f * face_stride + g];
-    if (f == 0 || 2 * f == n) v.im = 0;
-    b1[f * TB + i] = v;
-  }
+  stage_half_spectra(in, face_stride, ntubes, n, TB, tube0, b1);
   __syncthreads();
   // Z_f = X_f + i Y_f for every f of the full spectrum (Hermitian extension of X and Y)
   for (int idx = threadIdx.x; idx < n * TH; idx += blockDim.x) {
@@ -264,7 +428,99 @@ k_irfft_pow2(const cplx<T>* __restrict__ in, int64_t face_stride, int64_t ntubes
   }
 }
 
-// Direct DFT for tube lengths that are not powers of two (one thread per tube, twiddles in LDS).
+// Mixed-radix forward and inverse transforms: the layout of k_rfft_pow2 / k_irfft_pow2 (TB tubes
+// per workgroup, two real tubes per complex sequence) with the passes of stockham_mixed and a
+// twiddle table of n entries.  Tube groups are spread so that consecutive groups run on one XCD
+// (the hardware hands block b to XCD b mod 8): a group's rows are TB elements wide, so the groups
+// of one cache line then share that XCD's L2.
+constexpr int FFT_MIXED_THREADS = 512;
+__device__ __forceinline__ int64_t fft_group_of_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  if (nb % 8) return b;
+  const int64_t per = nb / 8;
+  return (b % 8) * per + b / 8;
+}
+
+template <typename Tin, typename T>
+__global__ void __launch_bounds__(FFT_MIXED_THREADS)
+k_rfft_mixed(const Tin* __restrict__ in, int64_t ntubes, int n, RadixPlan plan, int TB,
+             cplx<T>* __restrict__ out, int64_t face_stride, zb* __restrict__ out16,
+             double* __restrict__ sumsq, const cplx<T>* __restrict__ gtw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int TH = TB / 2;
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw + n;
+  cplx<T>* b1 = b0 + (size_t)(n + 2) * TH;
+  const int64_t grp = fft_group_of_block();
+  const int64_t tube0 = grp * TB;
+  fill_twiddles(tw, gtw, n);
+  const double acc = stage_real_tubes(in, ntubes, n, TB, tube0, b0);
+  __syncthreads();
+  cplx<T>* res = stockham_mixed(b0, b1, tw, n, plan, TH, -1);
+  const int F = n / 2 + 1;
+  for (int idx = threadIdx.x; idx < F * TB; idx += blockDim.x) {
+    const int f = idx / TB, i = idx % TB;
+    const int sq = i % TH;
+    const int64_t g = tube0 + i;
+    if (g >= ntubes) continue;
+    const cplx<T> zf = res[f * TH + sq];
+    const cplx<T> zn = cconj(res[(f == 0 ? 0 : n - f) * TH + sq]);
+    cplx<T> v;
+    if (i < TH) v = cscale(cadd(zf, zn), (T)0.5);
+    else { cplx<T> d = csub(zf, zn); v = mk((T)0.5 * d.im, (T)-0.5 * d.re); }
+    if (f == 0 || 2 * f == n) v.im = 0;
+    out[f * face_stride + g] = v;
+    if (out16) st(out16[f * face_stride + g], v);
+  }
+  if (sumsq) {
+    __shared__ double red[FFT_MIXED_THREADS];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int sh = blockDim.x / 2; sh > 0; sh >>= 1) {
+      if ((int)threadIdx.x < sh) red[threadIdx.x] += red[threadIdx.x + sh];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) sumsq[blockIdx.x] = red[0];
+  }
+}
+
+template <typename T, typename Tout>
+__global__ void __launch_bounds__(FFT_MIXED_THREADS)
+k_irfft_mixed(const cplx<T>* __restrict__ in, int64_t face_stride, int64_t ntubes, int n, RadixPlan plan,
+              int TB, Tout* __restrict__ out, const cplx<T>* __restrict__ gtw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int TH = TB / 2;
+  const int F = n / 2 + 1;
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw + n;
+  cplx<T>* b1 = b0 + (size_t)(n + 2) * TH;
+  const int64_t grp = fft_group_of_block();
+  const int64_t tube0 = grp * TB;
+  fill_twiddles(tw, gtw, n);
+  // X_f (tubes 0..TH-1) and Y_f (tubes TH..TB-1), f < F, staged in b1: b1[f*TB + i]
+  stage_half_spectra(in, face_stride, ntubes, n, TB, tube0, b1);
+  __syncthreads();
+  // Z_f = X_f + i Y_f over the full spectrum (Hermitian extension of X and Y)
+  for (int idx = threadIdx.x; idx < n * TH; idx += blockDim.x) {
+    const int f = idx / TH, sq = idx % TH;
+    cplx<T> x, y;
+    if (f < F) { x = b1[f * TB + sq]; y = b1[f * TB + sq + TH]; }
+    else { x = cconj(b1[(n - f) * TB + sq]); y = cconj(b1[(n - f) * TB + sq + TH]); }
+    b0[f * TH + sq] = mk(x.re - y.im, x.im + y.re);
+  }
+  __syncthreads();
+  cplx<T>* res = stockham_mixed(b0, b1, tw, n, plan, TH, +1);
+  const T inv = (T)1 / (T)n;
+  for (int idx = threadIdx.x; idx < n * TB; idx += blockDim.x) {
+    const int t = idx / TB, i = idx % TB;
+    const int64_t g = tube0 + i;
+    if (g >= ntubes) continue;
+    const cplx<T> z = res[t * TH + (i % TH)];
+    out[g + ntubes * (int64_t)t] = (Tout)((i < TH ? z.re : z.im) * inv);
+  }
+}
+
+// Direct DFT for the other tube lengths (one thread per tube, twiddles in LDS).
 template <typename Tin, typename T>
 __global__ void k_rdft_direct(const Tin* __restrict__ in, int64_t ntubes, int n,
                               cplx<T>* __restrict__ out, int64_t face_stride, zb* __restrict__ out16,
@@ -371,9 +627,11 @@ const cplx<T>* twiddles(int n, hipStream_t s) {
   if (twiddle_lookup_only()) return nullptr;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return nullptr;
+  // n/2 entries for the radix-2 passes, n for the mixed-radix ones
+  const int cnt = ilog2_exact(n) >= 0 ? n / 2 : n;
   cplx<T>* tw = nullptr;
-  if (hipMalloc(&tw, sizeof(cplx<T>) * (size_t)std::max(1, n / 2)) != hipSuccess) return nullptr;
-  hipLaunchKernelGGL((k_twiddle_table<T>), dim3((unsigned)((n / 2 + 255) / 256 + 1)), dim3(256), 0, s, tw, n);
+  if (hipMalloc(&tw, sizeof(cplx<T>) * (size_t)std::max(1, cnt)) != hipSuccess) return nullptr;
+  hipLaunchKernelGGL((k_twiddle_table<T>), dim3((unsigned)((cnt + 255) / 256 + 1)), dim3(256), 0, s, tw, n, cnt);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     (void)hipFree(tw);
     return nullptr;
@@ -386,9 +644,33 @@ const cplx<T>* twiddles(int n, hipStream_t s) {
 // so that later solves, also allocation-free ones, find them
 template <typename T>
 inline int ensure_solve_twiddles(int n, hipStream_t s) {
-  if (ilog2_exact(n) < 0 || n < 2) return 0;   // direct DFT: no table
+  RadixPlan pl;
+  if (n < 2 || (ilog2_exact(n) < 0 && !radix_plan(n, pl))) return 0;   // direct DFT: no table
   return (twiddles<T>(n, s) && twiddles<double>(n, s)) ? 0 : -1;
 }
+
+// tubes per workgroup of the mixed-radix kernels: the largest even count (at most 256) whose two
+// LDS buffers of (n + 2) TB / 2 complex values and n twiddles fit in 60 KB; 0 if none does
+template <typename T>
+inline int fft_tile_mixed(int n) {
+  const int64_t budget = 60 * 1024 / (int64_t)sizeof(cplx<T>);
+  const int64_t tb = (budget - n) / (n + 2);
+  if (tb < 2) return 0;
+  return (int)std::min<int64_t>(256, tb / 2 * 2);
+}
+template <typename T>
+inline size_t fft_lds_mixed(int n, int TB) {
+  return (size_t)((int64_t)(n + 2) * TB + n) * sizeof(cplx<T>);
+}
+// workgroups of a mixed-radix launch: the tube groups, rounded up to a multiple of 8 so that
+// fft_group_of_block can keep neighbouring groups on one XCD
+inline int64_t fft_blocks_mixed(int64_t ntubes, int TB) {
+  const int64_t groups = ceil_div(ntubes, TB);
+  return groups >= 8 ? ceil_div(groups, 8) * 8 : groups;
+}
+// bound on the workgroup count of a forward launch (entries of its sumsq partials): every path
+// takes at least two tubes per workgroup, and the mixed-radix one rounds up by at most 7
+inline int64_t rfft_max_blocks(int64_t ntubes) { return ceil_div(ntubes, 2) + 8; }
 
 template <typename T>
 inline int fft_tile(int n) {
@@ -438,10 +720,22 @@ int launch_rfft(const Tin* in, int64_t ntubes, int n, cplx<T>* out, int64_t face
                        in, ntubes, n, lg, TB, out, face_stride, out16, sumsq, tw);
     if (nblocks_out) *nblocks_out = blocks;
   } else {
-    const int64_t blocks = ceil_div(ntubes, FFT_THREADS);
-    hipLaunchKernelGGL((k_rdft_direct<Tin, T>), dim3((unsigned)blocks), dim3(FFT_THREADS),
-                       (size_t)n * sizeof(cplx<T>), s, in, ntubes, n, out, face_stride, out16, sumsq);
-    if (nblocks_out) *nblocks_out = blocks;
+    // mixed radix when n factors into radices <= 13 and its table exists (an allocation-free or
+    // captured caller that finds none takes the direct DFT), else the direct DFT
+    RadixPlan pl;
+    const int TB = lg < 0 && radix_plan(n, pl) ? fft_tile_mixed<T>(n) : 0;
+    const cplx<T>* tw = TB ? twiddles<T>(n, s) : nullptr;
+    if (tw) {
+      const int64_t blocks = fft_blocks_mixed(ntubes, TB);
+      hipLaunchKernelGGL((k_rfft_mixed<Tin, T>), dim3((unsigned)blocks), dim3(FFT_MIXED_THREADS), fft_lds_mixed<T>(n, TB),
+                         s, in, ntubes, n, pl, TB, out, face_stride, out16, sumsq, tw);
+      if (nblocks_out) *nblocks_out = blocks;
+    } else {
+      const int64_t blocks = ceil_div(ntubes, FFT_THREADS);
+      hipLaunchKernelGGL((k_rdft_direct<Tin, T>), dim3((unsigned)blocks), dim3(FFT_THREADS),
+                         (size_t)n * sizeof(cplx<T>), s, in, ntubes, n, out, face_stride, out16, sumsq);
+      if (nblocks_out) *nblocks_out = blocks;
+    }
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -458,9 +752,17 @@ int launch_irfft(const cplx<T>* in, int64_t face_stride, int64_t ntubes, int n, 
     hipLaunchKernelGGL((k_irfft_pow2<T, Tout>), dim3((unsigned)blocks), dim3(FFT_THREADS), lds, s,
                        in, face_stride, ntubes, n, lg, TB, out, tw);
   } else {
-    const int64_t blocks = ceil_div(ntubes, FFT_THREADS);
-    hipLaunchKernelGGL((k_irdft_direct<T, Tout>), dim3((unsigned)blocks), dim3(FFT_THREADS),
-                       (size_t)n * sizeof(cplx<T>), s, in, face_stride, ntubes, n, out);
+    RadixPlan pl;
+    const int TB = lg < 0 && radix_plan(n, pl) ? fft_tile_mixed<T>(n) : 0;
+    const cplx<T>* tw = TB ? twiddles<T>(n, s) : nullptr;
+    if (tw) {
+      hipLaunchKernelGGL((k_irfft_mixed<T, Tout>), dim3((unsigned)fft_blocks_mixed(ntubes, TB)), dim3(FFT_MIXED_THREADS),
+                         fft_lds_mixed<T>(n, TB), s, in, face_stride, ntubes, n, pl, TB, out, tw);
+    } else {
+      const int64_t blocks = ceil_div(ntubes, FFT_THREADS);
+      hipLaunchKernelGGL((k_irdft_direct<T, Tout>), dim3((unsigned)blocks), dim3(FFT_THREADS),
+                         (size_t)n * sizeof(cplx<T>), s, in, face_stride, ntubes, n, out);
+    }
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -737,7 +737,7 @@ static int factor_impl(const Tin* A, const Tin* omega, uint64_t seed, int64_t l,
     Ah16 = sc.get<zb>(F * l * m);
     if (!Ah16) return fail(RTSVD_E_NOMEM, "device allocation failed: Ah16");
   }
-  RT_ALLOC(sumsq, double, ceil_div(l * m, 2) + 1, sc);
+  RT_ALLOC(sumsq, double, rfft_max_blocks(l * m), sc);
   RT_ALLOC(flags, int, 1, sc);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, flags, 0);
   RT_LAUNCH_OK();
@@ -961,7 +961,7 @@ static int tevd_impl(const Tin* A, int64_t m, int64_t n, rtsvd_factor_s* h, hipS
   Scratch sc(s);
   if (ensure_solve_twiddles<Tw>((int)n, s)) return fail(RTSVD_E_HIP, "ttevd_factor: twiddle tables");
   RT_ALLOC(Ah, zw, F * m * m, sc);
-  RT_ALLOC(sumsq, double, ceil_div(m * m, 2) + 1, sc);
+  RT_ALLOC(sumsq, double, rfft_max_blocks(m * m), sc);
   RT_ALLOC(flags, int, 1, sc);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, flags, 0);
   RT_LAUNCH_OK();

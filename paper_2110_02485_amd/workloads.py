@@ -212,6 +212,9 @@ WORKLOADS = {
                           seed_name="blur256"),
     "video512": Workload("video512", 512, 64, 3.0, 10, 64, 80, 10, 0, 1e-2, precision="fp32", video=True),
     "blur1024": Workload("blur1024", 1024, 128, 3.0, 10, 1, 100, 20, 1, 1e-3, precision="mixed"),
+    # Section 5's grey-scale video example: 240 x 240 x 240, six frames as lateral slices, band 12,
+    # sigma 2.5, eta 1.2, r = 81 at relative noise 1e-3; tube length 240 = 2^4 3 5 (mixed-radix DFT)
+    "video240": Workload("video240", 240, 240, 2.5, 12, 6, 71, 10, 0, 1e-3, eta=1.2, precision="fp32", video=True),
     # differentiable batch: 16 clips of uneven frame counts (4 to 32) restored in one call
     "diff512": Workload("diff512", 512, 64, 3.0, 10, 260, 80, 10, 0, 1e-2, precision="fp32", video=True,
                         problems=[4, 32, 9, 17, 6, 25, 12, 30, 5, 20, 14, 28, 8, 11, 23, 16]),
