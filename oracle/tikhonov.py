@@ -21,13 +21,20 @@ lateral slice B_j at a time, as the p-methods):
     meets it, mu = mu_lo.
 The residual of the projected problem is the literal one: B_j lies in the span of the first
 basis tube (Q_1 = B_j normalized), so ||B_j - A * W_k * Y|| = ||P-bar_k Y - z_1 e_1|| face by face.
+
+nested_tGKT_p (the nested t-Krylov subspace method with Tikhonov regularization, which the paper
+cites and compares): the same reading on the one t-Krylov space of nested_tGKB_p (Alg. 8), grown
+from B_1.  Per slice j: k_j = nested_tGKB_p's index (the projected discrepancy principle, slices in
+order, k never decreasing); Y_mu = argmin ||P-bar_k y - g_j||^2 + (1/mu) ||y||^2 face by face with
+g_j = Q_{k+1}^H b-hat_j (complex), X_mu = W_k * Y_mu; mu by the same bisection for the projected
+residual (the one Alg. 8 tests) = eta delta_j.  For j = 1 this is tGKT_p on B_1 (g_1 = z_1 e_1).
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .tproduct import fft_tubes, ifft_tubes, tprod_hat, fro
-from .tgkb import tgkb_faces, tgkb_solution, bidiag
+from .tgkb import tgkb_faces, tgkb_solution, bidiag, nested_tgkb_restore
 from .symmetric import tlanczos_faces, tlanczos_solution, tridiag
 
 OK = 0
@@ -126,3 +133,56 @@ def tlanczos_tik_restore(a: np.ndarray, b: np.ndarray, delta, eta: float, k_max:
     """t-LanczosTik_p for a symmetric A: as tgkt_restore on the t-Lanczos space of Alg. 4 with the
     tridiagonal T-bar_k of eq. (9t)."""
     return _restore(a, b, delta, eta, k_max, mu_lo, mu_hi, lanczos=True)
+
+
+def tikhonov_face_rhs(P: np.ndarray, g: np.ndarray, lam: float):
+    """argmin_y ||P y - g||^2 + lam ||y||^2 for a general (complex) right-hand side g, as the
+    stacked least-squares problem [P; sqrt(lam) I] y ~ [g; 0]; returns (y, ||P y - g||)."""
+    k1, k = P.shape
+    M = np.vstack([P, np.sqrt(lam) * np.eye(k)]).astype(complex)
+    rhs = np.concatenate([np.asarray(g, dtype=complex), np.zeros(k, dtype=complex)])
+    y, *_ = np.linalg.lstsq(M, rhs, rcond=None)
+    return y, float(np.linalg.norm(P @ y - g))
+
+
+def nested_tikhonov_slice(W, Q, c, z, bhj, k: int, lam: float):
+    """Tikhonov solution of one slice (b-hat_j, l x n) on the first k vectors of the nested space:
+    per face y = argmin ||P-bar_k y - Q_{k+1}^H b-hat_j||^2 + lam ||y||^2, x-hat = W_k y.  Returns
+    (x-hat (m x n), projected residual sqrt((1/n) sum_f ||P-bar_k y - g||^2))."""
+    m, _, n = W.shape
+    xh = np.zeros((m, n), dtype=complex)
+    tot = 0.0
+    for f in range(n):
+        P = bidiag(c, z, k, f)
+        g = Q[:, :k + 1, f].conj().T @ bhj[:, f]
+        y, r = tikhonov_face_rhs(P, g, lam)
+        xh[:, f] = W[:, :k, f] @ y
+        tot += r * r
+    return xh, float(np.sqrt(tot / n))
+
+
+def nested_tgkt_restore(a: np.ndarray, b: np.ndarray, delta, eta: float, k_max: int, mu_lo: float, mu_hi: float,
+                        k_init: int = 2):
+    """nested_tGKT_p: k_j from nested_tGKB_p (Alg. 8), then Tikhonov on its nested t-Krylov space
+    with mu_j from bisection for the projected residual (module docstring).  Returns k, mu, X, the
+    projected residuals at mu and the status."""
+    l, p, n = b.shape
+    deltas = np.broadcast_to(np.asarray(delta, dtype=np.float64), (p,))
+    base = nested_tgkb_restore(a, b, delta, eta, k_max, k_init)
+    ah = fft_tubes(a)
+    bh = fft_tubes(b)
+    W, Q, c, z = tgkb_faces(ah, bh[:, 0, :], k_max)
+    X = np.zeros((a.shape[1], p, n))
+    mus, res = [], []
+    status = base["status"]
+    for j in range(p):
+        k = base["k"][j]
+        bound = eta * deltas[j]
+        mu, st_mu = bisect_mu(lambda mu: nested_tikhonov_slice(W, Q, c, z, bh[:, j, :], k, 1.0 / mu)[1], bound,
+                              mu_lo, mu_hi)
+        xh, r = nested_tikhonov_slice(W, Q, c, z, bh[:, j, :], k, 1.0 / mu)
+        X[:, j, :] = ifft_tubes(xh[:, None, :])[:, 0, :]
+        mus.append(mu)
+        res.append(r)
+        status = max(status, st_mu)
+    return {"k": list(base["k"]), "mu": mus, "X": X, "res": res, "status": status}

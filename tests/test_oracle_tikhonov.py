@@ -110,3 +110,86 @@ def test_restore_meets_the_discrepancy_equation(lanczos):
     # an interval that cannot reach the bound: mu_hi returned, status DP_NOT_MET
     out2 = fn(a, b, deltas, 1.1, 20, 1e-6, 1e-4)
     assert out2["mu"] == [1e-4, 1e-4] and out2["status"] == tk.DP_NOT_MET
+
+
+# ----------------------------------------------------------------------------------------------
+# nested_tGKT_p: Tikhonov on the nested t-Krylov space of Alg. 8
+# ----------------------------------------------------------------------------------------------
+def test_nested_tikhonov_full_space_equals_direct_for_every_slice():
+    # k = m: the nested space is the whole space on every face and range(A_f) lies in the span of
+    # Q_{m+1}, so for every slice (not only the one that started the basis) the projected Tikhonov
+    # solution is the direct (A_f^H A_f + lam I)^{-1} A_f^H b-hat_{j,f}
+    a, b = _small(seed=7)
+    m, n = a.shape[1], a.shape[2]
+    ah, bh = tp.fft_tubes(a), tp.fft_tubes(b)
+    W, Q, c, z = tg.tgkb_faces(ah, bh[:, 0, :], m)
+    lam = 0.05
+    for j in range(b.shape[1]):
+        xh, _ = tk.nested_tikhonov_slice(W, Q, c, z, bh[:, j, :], m, lam)
+        for f in range(n):
+            A = ah[:, :, f]
+            direct = np.linalg.solve(A.conj().T @ A + lam * np.eye(m), A.conj().T @ bh[:, j, f])
+            np.testing.assert_allclose(xh[:, f], direct, rtol=1e-8, atol=1e-10)
+
+
+def test_nested_tikhonov_limits_and_monotone_residual():
+    # lam -> 0: the truncated solution of nested_tGKB_p (projected least squares) with its
+    # projected residual; lam -> infinity: X -> 0 and the residual -> ||Q_{k+1}^H b_j||; the
+    # residual grows with lam in between
+    a, b = _small(seed=9)
+    ah, bh = tp.fft_tubes(a), tp.fft_tubes(b)
+    k, n = 4, a.shape[2]
+    W, Q, c, z = tg.tgkb_faces(ah, bh[:, 0, :], k)
+    bj = bh[:, 1, :]
+    xt, rt = tg.projected_lsq(W, Q, c, z, bj, k)
+    x0, r0 = tk.nested_tikhonov_slice(W, Q, c, z, bj, k, 1e-14)
+    np.testing.assert_allclose(x0, xt, rtol=1e-6, atol=1e-9)
+    assert r0 == pytest.approx(rt, rel=1e-8)
+    xi, ri = tk.nested_tikhonov_slice(W, Q, c, z, bj, k, 1e14)
+    assert np.abs(xi).max() < 1e-10 * np.abs(xt).max()
+    g2 = sum(float(np.sum(np.abs(Q[:, :k + 1, f].conj().T @ bj[:, f]) ** 2)) for f in range(n))
+    assert ri == pytest.approx(np.sqrt(g2 / n), rel=1e-9)
+    res = [tk.nested_tikhonov_slice(W, Q, c, z, bj, k, lam)[1] for lam in np.logspace(-8, 8, 17)]
+    assert all(r1 <= r2 + 1e-14 for r1, r2 in zip(res, res[1:]))
+
+
+def _blur_pair(seed_name, p=3, noise=1e-2):
+    size, n = 24, 8
+    A = wl.blur_operator(size, n, 2.0, 5)
+    X = wl.lateral_slices(wl.moving_blob_video(size, n, p, wl.rng_for(seed_name, "xtrue")))
+    a, x = wl.to_math(A), wl.to_math(X)
+    bt = tp.tprod(a, x)
+    E = wl.scale_noise(wl.noise_direction(bt.shape, wl.rng_for(seed_name, "noise")), bt, noise)
+    return a, bt + E, [float(np.linalg.norm(E[:, j, :])) for j in range(p)]
+
+
+def test_nested_tgkt_meets_the_projected_discrepancy_equation():
+    a, b, deltas = _blur_pair("ntik")
+    out = tk.nested_tgkt_restore(a, b, deltas, 1.1, 20, 1e-2, 1e8)
+    base = tg.nested_tgkb_restore(a, b, deltas, 1.1, 20)
+    assert out["k"] == base["k"] and out["status"] == tk.OK
+    ah, bh = tp.fft_tubes(a), tp.fft_tubes(b)
+    W, Q, c, z = tg.tgkb_faces(ah, bh[:, 0, :], 20)
+    for j in range(3):
+        bound = 1.1 * deltas[j]
+        assert 1e-2 < out["mu"][j] < 1e8
+        # the returned mu meets the principle, a slightly smaller one does not (bisection bracket)
+        assert out["res"][j] <= bound * (1 + 1e-12) and out["res"][j] == pytest.approx(bound, rel=1e-8)
+        r_below = tk.nested_tikhonov_slice(W, Q, c, z, bh[:, j, :], out["k"][j], 1.0 / (out["mu"][j] * 0.999))[1]
+        assert r_below > bound
+        # X is the Tikhonov solution at that mu
+        xh, _ = tk.nested_tikhonov_slice(W, Q, c, z, bh[:, j, :], out["k"][j], 1.0 / out["mu"][j])
+        np.testing.assert_allclose(out["X"][:, j, :], tp.ifft_tubes(xh[:, None, :])[:, 0, :], rtol=1e-12, atol=1e-14)
+    out2 = tk.nested_tgkt_restore(a, b, deltas, 1.1, 20, 1e-6, 1e-4)
+    assert out2["mu"] == [1e-4] * 3 and out2["status"] == tk.DP_NOT_MET
+
+
+def test_nested_tgkt_first_slice_is_tgkt():
+    # slice 1 started the basis (g_1 = z_1 e_1) and, with k_init = 1, takes tGKB_p's index, so it
+    # is tGKT_p on B_1: same k, mu and X
+    a, b, deltas = _blur_pair("ntik1")
+    nt = tk.nested_tgkt_restore(a, b, deltas, 1.1, 20, 1e-2, 1e8, k_init=1)
+    t1 = tk.tgkt_restore(a, b[:, :1, :], deltas[:1], 1.1, 20, 1e-2, 1e8)
+    assert nt["k"][0] == t1["k"][0]
+    assert nt["mu"][0] == pytest.approx(t1["mu"][0], rel=1e-9)
+    np.testing.assert_allclose(nt["X"][:, 0, :], t1["X"][:, 0, :], rtol=1e-8, atol=1e-12)
