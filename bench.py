@@ -295,7 +295,8 @@ def dominant_roofline(stages, precision, n=None):
 
 
 def time_krylov(torch, rt, wl, steps):
-    """tGKB_p and nested_tGKB_p (FP64) on the colour-image workload: solves/s, k per slice, error."""
+    """tGKB_p, nested_tGKB_p and their Tikhonov variants tGKT_p and nested_tGKT_p (FP64, mu on
+    [1e1, 1e7]) on the colour-image workload: solves/s, k (and mu) per slice, error."""
     w = wl.WORKLOADS["rgb256"]
     prob = make_problem(w, torch.device("cuda:0"), torch, rt, wl)
     A, B, x_true = prob["A64"], prob["B64"], prob["X64"]
@@ -304,17 +305,22 @@ def time_krylov(torch, rt, wl, steps):
     out = {"workload": w.name, "l": w.size, "m": w.size, "n": w.n, "p": B.shape[1], "k_max": w.k_max,
            "noise": w.noise, "eta": w.eta, "precision": "fp64"}
     for name, fn in (("tgkb_p", lambda: rt.tgkb_solve(A, B, deltas, w.eta, w.k_max)),
-                     ("nested_tgkb_p", lambda: rt.nested_tgkb_solve(A, B, deltas, w.eta, w.k_max))):
+                     ("nested_tgkb_p", lambda: rt.nested_tgkb_solve(A, B, deltas, w.eta, w.k_max)),
+                     ("tgkt_p", lambda: rt.tgkt_solve(A, B, deltas, w.eta, w.k_max)),
+                     ("nested_tgkt_p", lambda: rt.nested_tgkt_solve(A, B, deltas, w.eta, w.k_max))):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            X, k, resid, status = fn()
+            res = fn()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
+        X, k, status = res[0], res[1], res[-1]
         err = float(torch.linalg.norm(X - x_true) / torch.linalg.norm(x_true))
         out[name] = {"value": 1000.0 / ms, "unit": "solves/s", "ms_per_step": ms,
                      "k": [int(v) for v in k.cpu()], "dp_status": int(status[0]), "rel_error": err}
+        if len(res) == 5:
+            out[name]["mu"] = [float(v) for v in res[2].cpu()]
     return out
 
 

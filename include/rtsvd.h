@@ -245,6 +245,25 @@ int tgkt_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, in
                const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, double mu_lo, double mu_hi,
                void* X, int32_t* k_out, double* mu_out, double* resid_out, int32_t* status_out, void* stream);
 
+/* nested_tGKT_p: Tikhonov regularization on the nested t-Krylov space of Alg. 8 (the nested method
+ * with Tikhonov regularization that Sections 4.3 and 5 compare).  Per lateral slice j: k_j =
+ * nested_tGKB_p's index (as nested_tgkb_solve: one basis from B_1, slices in order, k_init), then
+ *   X_j = W_k * Y,  Y = argmin ||P-bar_k y - Q_{k+1}^T * B_j||^2 + (1/mu_j) ||y||^2  face by face
+ * (complex projected right-hand side), with mu_j from bisection in log mu on [mu_lo, mu_hi] (50
+ * halvings) for the projected residual ||P-bar_k Y - Q_{k+1}^T * B_j||_F = eta_dp delta_j (the one
+ * Alg. 8 tests; the returned mu_j meets it).  If mu_hi leaves the residual above the bound,
+ * mu_j = mu_hi; if mu_lo already meets it, mu_j = mu_lo.  The projected problems are solved from
+ * the basis' Givens QR (real banded normal equations for the real and imaginary parts, FP64).
+ * Arguments as nested_tgkb_solve, and mu_lo, mu_hi (0 < mu_lo < mu_hi, finite), mu_out: DEVICE
+ * double[p]; resid_out: DEVICE double[p] or NULL, the projected residual at mu_j; status_out:
+ * RTSVD_W_DP_NOT_MET when a slice reached k_max unmet or mu_hi could not meet its bound.
+ * Errors: RTSVD_E_ARG (as nested_tgkb_solve, and the mu interval), RTSVD_E_UNSUPPORTED
+ * (l > 8192).                                                                                   */
+int nested_tgkt_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p, int dtype,
+                      const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, int32_t k_init,
+                      double mu_lo, double mu_hi, void* X, int32_t* k_out, double* mu_out, double* resid_out,
+                      int32_t* status_out, void* stream);
+
 /* t-LanczosTik_p: as tgkt_solve on the t-Lanczos space of Alg. 4 for a symmetric A (the
  * (k+1) x k tridiagonal T-bar_k of eq. (9t) in place of P-bar_k; k = t-Lanczos_p's discrepancy
  * index), X_j = Q_k * Y.  Arguments as tlanczos_solve and tgkt_solve.                          */

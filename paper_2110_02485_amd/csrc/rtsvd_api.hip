@@ -1652,7 +1652,7 @@ extern "C" int tgkt_solve(const void* A, const void* B, int64_t l, int64_t m, in
 template <typename T>
 static int nested_tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_t n, int64_t p,
                             const std::vector<double>& bounds, int kmax, int kinit, T* X, int* k_out, double* resid_out,
-                            int* status_out, hipStream_t s) {
+                            int* status_out, hipStream_t s, TikArgs* tik = nullptr) {
   typedef cplx<T> zt;
   const int64_t F = n / 2 + 1;
   const double tol = 64.0 * (sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.960464477539063e-08);
@@ -1724,6 +1724,30 @@ static int nested_tgkb_impl(const T* A, const T* B, int64_t l, int64_t m, int64_
     }
   }
   RT_ALLOC(Xh, zt, F * m * p, sc);
+  if (tik) {
+    // nested_tGKT_p: mu per slice by bisection on the nested space, X = W_k y (complex y)
+    RT_ALLOC(ytik, zd, F * p * kmax, sc);
+    RT_ALLOC(tfail, int, 1, sc);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, tfail, 0);
+    RT_LAUNCH_OK();
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(TIK_MAX_THREADS, (150 * 1024) / (40 * (int64_t)kmax)));
+    const size_t lds = (size_t)nt * 5 * kmax * sizeof(double);
+    if (lds > 65536)
+      RT_CHECK_HIP(hipFuncSetAttribute((const void*)k_nest_tik_mu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_nest_tik_mu, dim3((unsigned)p), dim3(nt), lds, s, (const double*)rho_h, (const double*)s_h,
+                       (const double*)alpha_h, (const zd*)phi_h, (const double*)res, (const int*)kin, kmax, (int)p,
+                       (int)F, (int)n, (const double*)bnd, tik->mu_lo, tik->mu_hi, tik->mu_out, tik->res_out, ytik,
+                       tfail);
+    RT_LAUNCH_OK();
+    hipLaunchKernelGGL((k_nest_tik_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), 0, s, (const zt*)Wb, ldw,
+                       (int)m, (const int*)kin, kmax, (int)p, (const zd*)ytik, Xh);
+    RT_LAUNCH_OK();
+    RT_TRY((launch_irfft<T, T>(Xh, m * p, m * p, (int)n, X, s)));
+    hipLaunchKernelGGL(k_nest_tik_finish, dim3(1), dim3(256), 0, s, (const int*)kin, (const int*)st,
+                       (const int*)tfail, (int)p, k_out, status_out);
+    RT_LAUNCH_OK();
+    return 0;
+  }
   hipLaunchKernelGGL((k_nest_solution<T>), dim3((unsigned)p, (unsigned)F), dim3(256), (size_t)kmax * sizeof(zd), s, Wb,
                      ldw, (int)m, kin, kmax, (int)p, rho_h, s_h, alpha_h, (const zd*)phi_h, Xh);
   RT_LAUNCH_OK();
@@ -1762,6 +1786,33 @@ extern "C" int nested_tgkb_solve(const void* A, const void* B, int64_t l, int64_
     return nested_tgkb_impl<float>((const float*)A, (const float*)B, l, m, n, p, bounds, k_max, kin, (float*)X, k_out,
                                    resid_out, status_out, s);
   return fail(RTSVD_E_ARG, "nested_tgkb_solve: bad dtype");
+}
+
+extern "C" int nested_tgkt_solve(const void* A, const void* B, int64_t l, int64_t m, int64_t n, int64_t p, int dtype,
+                                 const double* delta, int32_t n_delta, double eta_dp, int32_t k_max, int32_t k_init,
+                                 double mu_lo, double mu_hi, void* X, int32_t* k_out, double* mu_out,
+                                 double* resid_out, int32_t* status_out, void* stream) {
+  g_last_error.clear();
+  if (!A || !B || !X || !delta || !k_out || !mu_out) return fail(RTSVD_E_ARG, "nested_tgkt_solve: null argument");
+  if (l < 1 || m < 1 || n < 1 || p < 1 || l < m)
+    return fail(RTSVD_E_ARG, "nested_tgkt_solve: need l >= m >= 1, n >= 1, p >= 1");
+  if (k_max < 1 || k_max > m) return fail(RTSVD_E_ARG, "nested_tgkt_solve: need 1 <= k_max <= m");
+  if (k_init < 1) return fail(RTSVD_E_ARG, "nested_tgkt_solve: need k_init >= 1");
+  if (!(mu_lo > 0.0) || !(mu_hi > mu_lo) || !std::isfinite(mu_hi))
+    return fail(RTSVD_E_ARG, "nested_tgkt_solve: need 0 < mu_lo < mu_hi < inf");
+  if (l > 8192) return fail(RTSVD_E_UNSUPPORTED, "nested_tgkt_solve: l must be <= 8192");
+  std::vector<double> bounds;
+  RT_TRY(krylov_bounds("nested_tgkt_solve", delta, n_delta, p, eta_dp, bounds));
+  hipStream_t s = (hipStream_t)stream;
+  TikArgs tik{mu_lo, mu_hi, mu_out, resid_out, nullptr, nullptr};
+  const int kinit = std::min<int>(k_init, k_max);
+  if (dtype == RTSVD_F64)
+    return nested_tgkb_impl<double>((const double*)A, (const double*)B, l, m, n, p, bounds, k_max, kinit, (double*)X,
+                                    k_out, nullptr, status_out, s, &tik);
+  if (dtype == RTSVD_F32)
+    return nested_tgkb_impl<float>((const float*)A, (const float*)B, l, m, n, p, bounds, k_max, kinit, (float*)X,
+                                   k_out, nullptr, status_out, s, &tik);
+  return fail(RTSVD_E_ARG, "nested_tgkt_solve: bad dtype");
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -567,7 +567,7 @@ __device__ __forceinline__ void tik_band(const double* __restrict__ ha, const do
   }
 }
 
-// ||R y - f||^2 (+ nothing else) of one face at lam, y left in ys.  M = R^T R + lam I:
+// ||R y - f||^2 (+ nothing else) of one face at lam, y left in ys; f_i = fv[i fs].  M = R^T R + lam I:
 //   M(i, i)   = d0_i^2 + d1_{i-1}^2 + d2_{i-2}^2 + lam
 //   M(i+1, i) = d1_i d0_i + d2_{i-1} d1_{i-1},   M(i+2, i) = d2_i d0_i
 // L L^T = M with L(i, i) = g_i, L(i+1, i) = u_i, L(i+2, i) = v_i:
@@ -575,14 +575,14 @@ __device__ __forceinline__ void tik_band(const double* __restrict__ ha, const do
 //   g_i = sqrt(M(i, i) - u_{i-1}^2 - v_{i-2}^2); forward then backward substitution of R^T f.
 template <bool LANCZOS>
 __device__ double tik_face(const double* __restrict__ ha, const double* __restrict__ hb, const double* __restrict__ hc,
-                           const double* __restrict__ fv, int k, double lam, double* __restrict__ g,
+                           const double* __restrict__ fv, int fs, int k, double lam, double* __restrict__ g,
                            double* __restrict__ u, double* __restrict__ v, double* __restrict__ ys) {
   double d1m1 = 0.0, d2m1 = 0.0, d2m2 = 0.0;   // d1_{i-1}, d2_{i-1}, d2_{i-2}
   double fm1 = 0.0, fm2 = 0.0;                 // f_{i-1}, f_{i-2}
   for (int i = 0; i < k; ++i) {
     double d0, d1, d2;
     tik_band<LANCZOS>(ha, hb, hc, i, k, d0, d1, d2);
-    const double fi = fv[i];
+    const double fi = fv[(int64_t)i * fs];
     const double um1 = i >= 1 ? u[i - 1] : 0.0, vm2 = i >= 2 ? v[i - 2] : 0.0, vm1 = i >= 1 ? v[i - 1] : 0.0;
     const double mii = fma(d0, d0, fma(d1m1, d1m1, fma(d2m2, d2m2, lam)));
     const double gi = sqrt(fmax(mii - um1 * um1 - vm2 * vm2, 0.0));
@@ -616,7 +616,7 @@ __device__ double tik_face(const double* __restrict__ ha, const double* __restri
   for (int i = 0; i < k; ++i) {
     double d0, d1, d2;
     tik_band<LANCZOS>(ha, hb, hc, i, k, d0, d1, d2);
-    double e = d0 * ys[i] - fv[i];
+    double e = d0 * ys[i] - fv[(int64_t)i * fs];
     if (i + 1 < k) e = fma(d1, ys[i + 1], e);
     if (i + 2 < k) e = fma(d2, ys[i + 2], e);
     rr = fma(e, e, rr);
@@ -653,7 +653,7 @@ k_tik_mu(const double* __restrict__ ha, const double* __restrict__ hb, const dou
       for (int i = 0; i < k; ++i) ff = fma(fv[i], fv[i], ff);
       const double bt = beta[idx];
       const double pb2 = fmax(bt * bt - ff, 0.0);          // phi-bar_{k+1}^2
-      const double rr = tik_face<LANCZOS>(fa, fb, fc, fv, k, lam, g, u, v, ys);
+      const double rr = tik_face<LANCZOS>(fa, fb, fc, fv, 1, k, lam, g, u, v, ys);
       const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
       acc = fma(w, rr + pb2, acc);
       if (keep)
@@ -848,6 +848,104 @@ k_nest_solution(const cplx<T>* __restrict__ Wb, int64_t ld_basis, int m, const i
     for (int t = 0; t < k; ++t) acc = cadd(acc, cmul(ld<double>(W[(int64_t)t * m + r]), y[t]));
     Xh[(int64_t)f * m * p + (int64_t)j * m + r] = mk((T)acc.re, (T)acc.im);
   }
+}
+
+// nested_tGKT_p: Tikhonov on the nested space.  Slice j keeps, per face, the basis' Givens QR
+// (R: diagonal rho_t, superdiagonal s_t alpha_{t+1}, real) and its own rotated right-hand side
+// (phi_1 .. phi_k complex, phi-bar_{k+1}); for y = y_re + i y_im,
+//     ||P-bar_k y - g_j||^2 = ||R y_re - Re phi||^2 + ||R y_im - Im phi||^2 + |phi-bar_{k+1}|^2,
+// so the Tikhonov solution is two real banded solves with one matrix (tik_face on the real and
+// the imaginary parts), and the weighted face sum of |phi-bar_{k+1}|^2 over n is the square of the
+// projected residual k_nest_dp recorded at k_j.  mu by the bisection of k_tik_mu for
+// (1/n) sum_f w_f (||R y - phi||^2) + res_j(k_j)^2 = bound_j^2.  One workgroup per slice, threads
+// over the faces (5 k_max doubles of LDS per thread).  y_out: complex, per (face, slice).
+__global__ void __launch_bounds__(TIK_MAX_THREADS)
+k_nest_tik_mu(const double* __restrict__ rho_h, const double* __restrict__ s_h, const double* __restrict__ alpha_h,
+              const zd* __restrict__ phi_h, const double* __restrict__ res, const int* __restrict__ kin, int kmax,
+              int p, int F, int n, const double* __restrict__ bound, double mu_lo, double mu_hi,
+              double* __restrict__ mu_out, double* __restrict__ res_out, zd* __restrict__ y_out,
+              int* __restrict__ fail) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[TIK_MAX_THREADS];
+  __shared__ double sh_res;
+  const int c = blockIdx.x, tid = threadIdx.x, nt = (int)blockDim.x;
+  double* base = reinterpret_cast<double*>(smem_raw) + (size_t)tid * 5 * kmax;
+  double *g = base, *u = base + kmax, *v = base + 2 * kmax, *yr = base + 3 * kmax, *yi = base + 4 * kmax;
+  const int k = kin[c] > 0 ? kin[c] : kmax;
+  const double b2 = bound[c] * bound[c];
+  const double floor2 = res[(int64_t)c * kmax + k - 1] * res[(int64_t)c * kmax + k - 1];
+  auto residual2 = [&](double lam, bool keep) -> double {
+    double acc = 0.0;
+    for (int f = tid; f < F; f += nt) {
+      const double* fa = rho_h + (int64_t)f * kmax;
+      const double* fb = s_h + (int64_t)f * kmax;
+      const double* fc = alpha_h + (int64_t)f * kmax;
+      const double* fv = reinterpret_cast<const double*>(phi_h + ((int64_t)f * p + c) * kmax);
+      const double rr = tik_face<false>(fa, fb, fc, fv, 2, k, lam, g, u, v, yr) +
+                        tik_face<false>(fa, fb, fc, fv + 1, 2, k, lam, g, u, v, yi);
+      const double w = (f == 0 || 2 * f == n) ? 1.0 : 2.0;
+      acc = fma(w, rr, acc);
+      if (keep) {
+        zd* yo = y_out + ((int64_t)f * p + c) * kmax;
+        for (int i = 0; i < kmax; ++i) yo[i] = i < k ? mk(yr[i], yi[i]) : mk(0.0, 0.0);
+      }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int i = 0; i < nt; ++i) t += red[i];
+      sh_res = t / (double)n + floor2;
+    }
+    __syncthreads();
+    return sh_res;
+  };
+  double mu;
+  int failed = 0;
+  if (residual2(1.0 / mu_hi, false) > b2) {
+    mu = mu_hi;
+    failed = 1;
+  } else if (residual2(1.0 / mu_lo, false) <= b2) {
+    mu = mu_lo;
+  } else {
+    double lo = log(mu_lo), hi = log(mu_hi);
+    for (int it = 0; it < TIK_STEPS; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (residual2(exp(-mid), false) > b2) lo = mid;
+      else hi = mid;
+    }
+    mu = exp(hi);
+  }
+  const double r2 = residual2(1.0 / mu, true);
+  if (tid == 0) {
+    mu_out[c] = mu;
+    if (res_out) res_out[c] = sqrt(r2);
+    if (failed) atomicOr(fail, 1);
+  }
+}
+
+// X-hat(:, j) on face f = W_k y (the nested basis, complex y of k_nest_tik_mu); one block per (j, f)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_nest_tik_solution(const cplx<T>* __restrict__ Wb, int64_t ld_basis, int m, const int* __restrict__ kin, int kmax,
+                    int p, const zd* __restrict__ y_in, cplx<T>* __restrict__ Xh) {
+  const int j = blockIdx.x, f = blockIdx.y;
+  const int k = kin[j] > 0 ? kin[j] : kmax;
+  const cplx<T>* W = Wb + (int64_t)f * ld_basis;
+  const zd* y = y_in + ((int64_t)f * p + j) * kmax;
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    zd acc = mk(0.0, 0.0);
+    for (int t = 0; t < k; ++t) acc = cadd(acc, cmul(ld<double>(W[(int64_t)t * m + r]), y[t]));
+    Xh[(int64_t)f * m * p + (int64_t)j * m + r] = mk((T)acc.re, (T)acc.im);
+  }
+}
+
+// k_out and status of nested_tGKT_p: not met when a slice reached k_max unmet or mu_hi could not
+// bring a residual down to its bound
+__global__ void k_nest_tik_finish(const int* __restrict__ kin, const int* __restrict__ st, const int* __restrict__ fail,
+                                  int p, int* __restrict__ kout, int* __restrict__ status) {
+  for (int j = threadIdx.x; j < p; j += blockDim.x) kout[j] = kin[j];
+  if (threadIdx.x == 0 && status) *status = (st[2] || *fail) ? RTSVD_W_DP_NOT_MET : RTSVD_OK;
 }
 
 __global__ void k_nest_finish(const int* __restrict__ kin, const int* __restrict__ st, int p, int* __restrict__ kout,

@@ -26,7 +26,7 @@ PRECISIONS = {"fp64": P_FP64, "fp32": P_FP32, "bf16": P_BF16, "mixed": P_BF16}
 EXPORTS = ["rtsvd_factor", "ttsvd_factor", "rtsvd_factor_info", "rtsvd_factor_destroy", "rtsvd_solve",
            "tprod", "tprod_adjoint", "tgkb_solve", "nested_tgkb_solve", "ttevd_factor", "tlanczos_solve", "rtsvd_status_string", "rtsvd_last_error",
            "rtsvd_timer_enable", "rtsvd_timer_read", "rtsvd_solve_vjp", "rtsvd_trim", "rtsvd_gaussian",
-           "rtsvd_solve_noalloc", "tgkt_solve", "tlanczos_tik_solve"]
+           "rtsvd_solve_noalloc", "tgkt_solve", "tlanczos_tik_solve", "nested_tgkt_solve"]
 
 
 class RtsvdError(RuntimeError):
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                vp, vp]
     lib.tlanczos_tik_solve.argtypes = [vp, vp, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, dbl, dbl, vp, vp, vp,
                                        vp, vp, vp]
+    lib.nested_tgkt_solve.argtypes = [vp, vp, i64, i64, i64, i64, ctypes.c_int, pdbl, i32, dbl, i32, i32, dbl, dbl, vp,
+                                      vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -413,6 +415,30 @@ def nested_tgkb_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max
                                  k_init, X.data_ptr(), k.data_ptr(), resid.data_ptr(), status.data_ptr(), _stream()),
            "nested_tgkb_solve")
     return X, k, resid, status
+
+
+def nested_tgkt_solve(A: torch.Tensor, B: torch.Tensor, delta, eta: float, k_max: int, k_init: int = 2,
+                      mu_lo: float = 1e1, mu_hi: float = 1e7):
+    """nested_tGKT_p restoration (Tikhonov on the nested space of nested_tGKB_p, mu by bisection on
+    [mu_lo, mu_hi]); returns (X, k (device int32 [p]), mu (device [p]), projected residual at mu
+    (device [p]), status)."""
+    lib = load()
+    A, B = _dev(A, "A"), _dev(B, "B")
+    n, m, l = A.shape
+    n2, p, l2 = B.shape
+    if (n2, l2) != (n, l) or B.dtype != A.dtype or B.device != A.device:
+        raise ValueError("B must have storage shape (n, p, l) of A, A's dtype and device")
+    deltas = [float(d) for d in (delta if hasattr(delta, "__len__") else [delta])]
+    arr = (ctypes.c_double * len(deltas))(*deltas)
+    X = torch.empty((n, p, m), dtype=A.dtype, device=A.device)
+    k = torch.empty(p, dtype=torch.int32, device=A.device)
+    mu = torch.empty(p, dtype=torch.float64, device=A.device)
+    resid = torch.empty(p, dtype=torch.float64, device=A.device)
+    status = torch.empty(1, dtype=torch.int32, device=A.device)
+    _check(lib.nested_tgkt_solve(A.data_ptr(), B.data_ptr(), l, m, n, p, _dtype_code(A), arr, len(deltas), eta, k_max,
+                                 k_init, mu_lo, mu_hi, X.data_ptr(), k.data_ptr(), mu.data_ptr(), resid.data_ptr(),
+                                 status.data_ptr(), _stream()), "nested_tgkt_solve")
+    return X, k, mu, resid, status
 
 
 def solve_vjp(A: torch.Tensor, dA, B: torch.Tensor, omega: torch.Tensor, gX: torch.Tensor, k: int, oversample: int):

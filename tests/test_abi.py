@@ -84,6 +84,18 @@ def test_argument_errors_of_the_krylov_and_symmetric_entry_points():
     assert f(p16, p16, 8, 4, 4, 1, 0, neg, 1, 1.1, 2, 2, p16, k, None, None, None) == rt.E_ARG      # delta < 0
     assert f(p16, p16, 9000, 4, 4, 1, 0, one, 1, 1.1, 2, 2, p16, k, None, None, None) == rt.E_UNSUPPORTED
     assert b"nested_tgkb_solve" in lib.rtsvd_last_error()
+    # nested_tgkt_solve(A, B, l, m, n, p, dtype, delta, n_delta, eta, k_max, k_init, mu_lo, mu_hi, X, k, mu,
+    #                   resid, status, stream): the nested checks, then the mu interval
+    mu = (ctypes.c_double * 4)()
+    nt = lib.nested_tgkt_solve
+    assert nt(p16, p16, 8, 4, 4, 1, 0, one, 1, 1.1, 2, 2, 1e1, 1e7, p16, k, None, None, None, None) == rt.E_ARG  # mu_out
+    assert nt(p16, p16, 3, 4, 4, 1, 0, one, 1, 1.1, 2, 2, 1e1, 1e7, p16, k, mu, None, None, None) == rt.E_ARG    # l < m
+    assert nt(p16, p16, 8, 4, 4, 1, 0, one, 1, 1.1, 2, 0, 1e1, 1e7, p16, k, mu, None, None, None) == rt.E_ARG    # k_init
+    assert nt(p16, p16, 8, 4, 4, 1, 0, one, 1, 1.1, 2, 2, 1e7, 1e1, p16, k, mu, None, None, None) == rt.E_ARG    # mu_lo >= mu_hi
+    assert nt(p16, p16, 8, 4, 4, 1, 0, one, 1, 1.1, 2, 2, 0.0, 1e1, p16, k, mu, None, None, None) == rt.E_ARG    # mu_lo <= 0
+    assert nt(p16, p16, 8, 4, 4, 1, 0, one, 1, 1.0, 2, 2, 1e1, 1e7, p16, k, mu, None, None, None) == rt.E_ARG    # eta <= 1
+    assert nt(p16, p16, 9000, 4, 4, 1, 0, one, 1, 1.1, 2, 2, 1e1, 1e7, p16, k, mu, None, None, None) == rt.E_UNSUPPORTED
+    assert b"nested_tgkt_solve" in lib.rtsvd_last_error()
     # tlanczos_solve(A, B, m, n, p, dtype, delta, n_delta, eta, k_max, X, k, resid, status, stream)
     g = lib.tlanczos_solve
     assert g(None, p16, 4, 4, 1, 0, one, 1, 1.1, 2, p16, k, None, None, None) == rt.E_ARG

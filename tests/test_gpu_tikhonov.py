@@ -1,6 +1,7 @@
 """GPU: the Tikhonov variants (tGKT_p on the tGKB space, t-LanczosTik_p on the t-Lanczos space,
-mu by bisection for the discrepancy equation) against the FP64 oracle: k, mu, X, the residual at
-mu and the status, including an interval that cannot meet the bound."""
+nested_tGKT_p on the nested space of nested_tGKB_p, mu by bisection for the discrepancy equation)
+against the FP64 oracle: k, mu, X, the residual at mu and the status, including intervals that
+cannot meet the bound."""
 import numpy as np
 import pytest
 
@@ -85,3 +86,35 @@ def test_tgkt_256_fp32():
     orc = tk.tgkt_restore(Am, Bm, delta, w.eta, w.k_max, 1e1, 1e7)
     _check(rt.tgkt_solve(_t(A, "float32"), _t(wl.to_storage(Bm), "float32"), delta, w.eta, w.k_max, 1e1, 1e7),
            orc, 1e-5, 1e-4)
+
+
+# nested_tGKT_p: Tikhonov on the nested space of nested_tGKB_p (one basis from B_1)
+@pytest.mark.parametrize("dtype,Xtol,mutol", [("float64", 1e-10, 1e-8), ("float32", 1e-5, 1e-4)])
+def test_nested_tgkt_video_slices(dtype, Xtol, mutol):
+    from paper_2110_02485_amd import rtsvd as rt
+    A, X, B, Om, delta = blur_problem(48, 16, 2.0, 6, 4, 1e-2, 20, 0, seed=37, video=True)
+    Am, Bm, Xm = wl.to_math(A), wl.to_math(B), wl.to_math(X)
+    E = Bm - tp.tprod(Am, Xm)
+    deltas = [float(np.linalg.norm(E[:, j, :])) for j in range(4)]
+    orc = tk.nested_tgkt_restore(Am, Bm, deltas, 1.1, 20, 1e-2, 1e7)
+    _check(rt.nested_tgkt_solve(_t(A, dtype), _t(B, dtype), deltas, 1.1, 20, 2, 1e-2, 1e7), orc, Xtol, mutol)
+
+
+def test_nested_tgkt_ragged_k_init_and_unmet_interval():
+    # 5 slices of a random problem with odd n and k_init = 1, then an interval of tiny mu: slice 1
+    # (which started the basis) cannot reach its bound (mu_hi, DP_NOT_MET); for some of the others
+    # even y = 0 leaves a projected residual ||Q_{k+1}^T * B_j|| below the bound (mu_lo)
+    from paper_2110_02485_amd import rtsvd as rt
+    rng = np.random.default_rng(39)
+    l, m, n, p = 21, 17, 7, 5
+    A = rng.standard_normal((n, m, l))
+    B = rng.standard_normal((n, p, l))
+    Am, Bm = wl.to_math(A), wl.to_math(B)
+    deltas = [fr * float(np.linalg.norm(Bm[:, j, :])) for j, fr in enumerate([0.45, 0.6, 0.5, 0.55, 0.65])]
+    orc = tk.nested_tgkt_restore(Am, Bm, deltas, 1.05, 12, 1e-3, 1e5, k_init=1)
+    _check(rt.nested_tgkt_solve(_t(A, "float64"), _t(B, "float64"), deltas, 1.05, 12, 1, 1e-3, 1e5), orc, 1e-10,
+           1e-8)
+    orc2 = tk.nested_tgkt_restore(Am, Bm, deltas, 1.05, 12, 1e-9, 1e-7, k_init=1)
+    assert orc2["status"] == tk.DP_NOT_MET and orc2["mu"][0] == 1e-7 and set(orc2["mu"]) == {1e-7, 1e-9}
+    _check(rt.nested_tgkt_solve(_t(A, "float64"), _t(B, "float64"), deltas, 1.05, 12, 1, 1e-9, 1e-7), orc2, 1e-10,
+           1e-12)
