@@ -84,8 +84,8 @@ TRAFFIC = {
                          "sha256": "0f263c4a58d3d8eeff383dfae4dcad517867cd4708c34282cd3781b1e25bd07f",
                          "bytes_per_launch": 681669192},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
-                        "sha256": "3123ec9af2958fd33f0593ec2c55eac4f6ac81b95e04e0ff6c8b14746769f10b",
-                        "bytes_per_launch": 34664265},
+                        "sha256": "1ad8a927bda34b444a4c3900b90c5e221b995f6eba32da024d338d725d8c351b",
+                        "bytes_per_launch": 27977053},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
                         "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
                         "bytes_per_launch": 76505536},
