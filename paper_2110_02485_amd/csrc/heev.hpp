@@ -424,12 +424,15 @@ constexpr int HEEV_UREG = 16;   // rows per lane of the register-resident back-t
 // the tridiagonal (zs, stride r + 1) were computed by k_tri_stein; the kernel starts at the
 // re-orthogonalization of clusters.  MODES 2 and 3 stop before the back-transformation, which
 // k_heev_backtr does; MODE 3 runs from G (as MODE 0) and writes lamout and the reflector scalars
-// (taus_out, F x r) for it.
+// (taus_out, F x r) for it.  MODE 4 only tridiagonalizes: d and e go to tri_out (as `tri` above),
+// the reflector scalars to taus_out, the reflectors stay in gpk (the global working matrix).
 template <bool IN_LDS, int MODE = 0>
 __global__ void __launch_bounds__(HEEV_THREADS)
 k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restrict__ lamout,
        zd* __restrict__ gpk, double* __restrict__ zs, double* __restrict__ lu,
-       const double* __restrict__ tri, const zd* __restrict__ taus, zd* __restrict__ taus_out) {
+       const double* __restrict__ tri, const zd* __restrict__ taus, zd* __restrict__ taus_out,
+       double* __restrict__ tri_out) {
+  static_assert(MODE != 4 || !IN_LDS, "the tridiagonalize-only mode keeps the reflectors in global memory");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   HeevLds& L = *reinterpret_cast<HeevLds*>(smem_raw);
   const int f = blockIdx.x;
@@ -540,6 +543,14 @@ k_heev(const zd* __restrict__ Gin, int r, zd* __restrict__ Uout, double* __restr
     L.e[r - 1] = 0.0;
   }
   __syncthreads();
+  if constexpr (MODE == 4) {
+    for (int j = tid; j < r; j += blockDim.x) {
+      tri_out[(int64_t)f * 2 * r + j] = L.d[j];
+      tri_out[(int64_t)f * 2 * r + r + j] = L.e[j];
+      taus_out[(int64_t)f * r + j] = L.tau[j];
+    }
+    return;
+  }
   }  // !FROM_TRI
   for (int i = tid; i < r; i += blockDim.x) L.e2[i] = L.e[i] * L.e[i];
   __syncthreads();

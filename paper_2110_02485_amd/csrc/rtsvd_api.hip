@@ -281,6 +281,8 @@ static int max_lds_per_block() {
   return cached[dev];
 }
 
+static int orthonormalize_tri_vectors(double* zs, int r, int64_t F, Scratch& sc, hipStream_t s);
+
 static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratch& sc, hipStream_t s) {
   const size_t full = heev_lds_bytes(r, true);
   const bool in_lds = (int64_t)full <= (int64_t)max_lds_per_block();
@@ -304,9 +306,33 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
     auto kern = in_lds ? k_heev<true, 2> : k_heev<false, 2>;
     if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
-                       (const double*)tri, (const zd*)taus, (zd*)nullptr);
+                       (const double*)tri, (const zd*)taus, (zd*)nullptr, (double*)nullptr);
     RT_LAUNCH_OK();
     hipLaunchKernelGGL((k_heev_backtr<HEEV_UREG, BT_CH>), dim3((unsigned)ceil_div(r, BT_COLS), (unsigned)F),
+                       dim3(BT_THREADS), 0, s, (const zd*)gpk, (const zd*)taus, (const double*)zs, r, U);
+    RT_LAUNCH_OK();
+    return 0;
+  }
+  if (r <= 8 * BT_UREG_WIDE && !in_lds) {
+    // tridiagonalization in the one-workgroup kernel (global working matrix), eigenvalues and
+    // inverse iteration spread over many workgroups (k_tri_stein), the eigenvectors of T made
+    // orthonormal by CholeskyQR2 on FP64 MFMA (Q = Z R^{-1}: the Q of modified Gram-Schmidt over
+    // all r columns, which takes the place of Gram-Schmidt inside clusters), then the register-
+    // resident back-transformation
+    zd* taus = sc.get<zd>(F * (int64_t)r);
+    double* tri = sc.get<double>(F * 2 * (int64_t)r);
+    if (!taus || !tri) return fail(RTSVD_E_NOMEM, "device allocation failed: heev tridiagonal");
+    hipLaunchKernelGGL((k_heev<false, 4>), dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
+                       (const double*)nullptr, (const zd*)nullptr, taus, tri);
+    RT_LAUNCH_OK();
+    const size_t sb = stein_lds_bytes(r);
+    if (sb > 65536)
+      RT_CHECK_HIP(hipFuncSetAttribute((const void*)k_tri_stein, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sb));
+    hipLaunchKernelGGL(k_tri_stein, dim3((unsigned)ceil_div(r, STEIN_EPB), (unsigned)F), dim3(STEIN_THREADS), sb, s,
+                       (const double*)tri, r, lam, zs);
+    RT_LAUNCH_OK();
+    RT_TRY(orthonormalize_tri_vectors(zs, r, F, sc, s));
+    hipLaunchKernelGGL((k_heev_backtr<BT_UREG_WIDE, BT_CH_WIDE>), dim3((unsigned)ceil_div(r, BT_COLS), (unsigned)F),
                        dim3(BT_THREADS), 0, s, (const zd*)gpk, (const zd*)taus, (const double*)zs, r, U);
     RT_LAUNCH_OK();
     return 0;
@@ -318,7 +344,7 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
     auto kern = in_lds ? k_heev<true, 3> : k_heev<false, 3>;
     if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
-                       (const double*)nullptr, (const zd*)nullptr, taus);
+                       (const double*)nullptr, (const zd*)nullptr, taus, (double*)nullptr);
     RT_LAUNCH_OK();
     hipLaunchKernelGGL((k_heev_backtr<BT_UREG_WIDE, BT_CH_WIDE>), dim3((unsigned)ceil_div(r, BT_COLS), (unsigned)F),
                        dim3(BT_THREADS), 0, s, (const zd*)gpk, (const zd*)taus, (const double*)zs, r, U);
@@ -328,7 +354,7 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
   auto kern = in_lds ? k_heev<true> : k_heev<false>;
   if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
-                     (const double*)nullptr, (const zd*)nullptr, (zd*)nullptr);
+                     (const double*)nullptr, (const zd*)nullptr, (zd*)nullptr, (double*)nullptr);
   RT_LAUNCH_OK();
   return 0;
 }
@@ -411,6 +437,47 @@ static int orthonormalize(TY*& Y, int64_t rows, int64_t r, int64_t F, int passes
     RT_TRY((skinny<TY, zd, TY>(false, rows, r, r, Y, rows, rows * r, Rinv, r, r * r, tmp, rows, rows * r, F, sc, s, 0, 1)));
     std::swap(Y, tmp);
   }
+  return 0;
+}
+
+// real eigenvectors of the tridiagonal (zs: F x r columns of stride r + 1) <-> complex r x r panels
+__global__ void k_tri_vectors_to_panel(const double* __restrict__ zs, int r, int64_t F, zd* __restrict__ Z) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= F * r * r) return;
+  const int64_t f = idx / ((int64_t)r * r);
+  const int64_t rem = idx - f * r * r;
+  const int j = (int)(rem / r), i = (int)(rem - (int64_t)j * r);
+  Z[idx] = mk(zs[(f * r + j) * (r + 1) + i], 0.0);
+}
+__global__ void k_panel_to_tri_vectors(const zd* __restrict__ Z, int r, int64_t F, double* __restrict__ zs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= F * r * r) return;
+  const int64_t f = idx / ((int64_t)r * r);
+  const int64_t rem = idx - f * r * r;
+  const int j = (int)(rem / r), i = (int)(rem - (int64_t)j * r);
+  zs[(f * r + j) * (r + 1) + i] = Z[idx].re;
+}
+
+// The eigenvectors of T from inverse iteration, made orthonormal in their order by CholeskyQR2
+// (FP64 Gram, Cholesky inverse, Z R^{-1} on MFMA, twice): for the nearly orthonormal Z this is the
+// modified Gram-Schmidt result; the imaginary parts stay zero.
+static int orthonormalize_tri_vectors(double* zs, int r, int64_t F, Scratch& sc, hipStream_t s) {
+  const int64_t n = F * r * (int64_t)r;
+  zd* Z = sc.get<zd>(n);
+  zd* tmp = sc.get<zd>(n);
+  zd* G = sc.get<zd>(n);
+  zd* Rinv = sc.get<zd>(n);
+  int* flags = sc.get<int>(1);
+  if (!Z || !tmp || !G || !Rinv || !flags) return fail(RTSVD_E_NOMEM, "device allocation failed: eigenvector QR");
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, flags, 0);
+  RT_LAUNCH_OK();
+  hipLaunchKernelGGL(k_tri_vectors_to_panel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, (const double*)zs, r,
+                     F, Z);
+  RT_LAUNCH_OK();
+  RT_TRY((orthonormalize<zd>(Z, r, r, F, 2, G, Rinv, tmp, flags, sc, s)));
+  hipLaunchKernelGGL(k_panel_to_tri_vectors, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, (const zd*)Z, r, F,
+                     zs);
+  RT_LAUNCH_OK();
   return 0;
 }
 
