@@ -82,13 +82,13 @@ def stage_model(w, precision):
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
                          "sha256": "0f263c4a58d3d8eeff383dfae4dcad517867cd4708c34282cd3781b1e25bd07f",
-                         "bytes_per_launch": 681669192},
+                         "bytes_per_launch": 681676768},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
-                        "sha256": "1ad8a927bda34b444a4c3900b90c5e221b995f6eba32da024d338d725d8c351b",
-                        "bytes_per_launch": 27977053},
+                        "sha256": "125c971e9987ee3c004fedd99f93357e4f191310104170f2610f9ca2cbc1c353",
+                        "bytes_per_launch": 27996304},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
                         "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
-                        "bytes_per_launch": 76505536},
+                        "bytes_per_launch": 76507073},
 }
 
 
