@@ -290,8 +290,14 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
   zd* gpk = sc.get<zd>(F * packed_size(r));
   if (!gpk) return fail(RTSVD_E_NOMEM, "device allocation failed: heev packed scratch");
   double* zs = sc.get<double>(F * r * (int64_t)(r + 1));
-  double* lu = sc.get<double>(F * r * 5 * (int64_t)r);
-  if (!zs || !lu) return fail(RTSVD_E_NOMEM, "device allocation failed: heev scratch");
+  if (!zs) return fail(RTSVD_E_NOMEM, "device allocation failed: heev scratch");
+  // LU factors of T - lambda I in global memory: only the one-kernel solver's inverse iteration
+  // (modes 0 and 3) uses them; k_tri_stein keeps its own in LDS
+  double* lu = nullptr;
+  auto need_lu = [&]() -> int {
+    lu = sc.get<double>(F * r * 5 * (int64_t)r);
+    return lu ? 0 : fail(RTSVD_E_NOMEM, "device allocation failed: heev LU scratch");
+  };
   if (r <= TRD_R) {
     // tridiagonal form from the register-resident kernel, then eigenvalues / vectors
     double* tri = sc.get<double>(F * 2 * (int64_t)r);
@@ -341,6 +347,7 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
     // the whole solver but the back-transformation, then the register-resident back-transformation
     zd* taus = sc.get<zd>(F * (int64_t)r);
     if (!taus) return fail(RTSVD_E_NOMEM, "device allocation failed: heev reflector scalars");
+    RT_TRY(need_lu());
     auto kern = in_lds ? k_heev<true, 3> : k_heev<false, 3>;
     if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
@@ -351,6 +358,7 @@ static int launch_heev(const zd* G, int r, int64_t F, zd* U, double* lam, Scratc
     RT_LAUNCH_OK();
     return 0;
   }
+  RT_TRY(need_lu());
   auto kern = in_lds ? k_heev<true> : k_heev<false>;
   if (bytes > 65536) RT_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   hipLaunchKernelGGL(kern, dim3((unsigned)F), dim3(HEEV_THREADS), bytes, s, G, r, U, lam, gpk, zs, lu,
