@@ -1307,26 +1307,27 @@ k_cholinv(const zd* __restrict__ Gin, int r, zd* __restrict__ Rinv, double tol_r
 // Register-resident Householder tridiagonalization for r <= TRD_R (one 512-thread block per face)
 // -------------------------------------------------------------------------------------------
 // The (zero-padded) 128 x 128 Hermitian matrix lives in registers, full storage: thread
-// (wave w, lane l) owns the 4 x 8 block at rows 4a.., columns 8b.. with a = 4w + l/16, b = l%16
-// (two waves per SIMD, 32 complex entries per lane).  Per reflector k (x = A(k+1:, k)):
+// (wave w, lane l) owns rows 4a.. 4a+3 at the eight columns b, b+16, ..., b+112, with a = 4w + l/16,
+// b = l%16 (two waves per SIMD, 32 complex entries per lane).  Every lane thus holds one column of
+// each 16-column block, so a block whose columns are all eliminated is skipped by a wave-uniform
+// branch.  Per reflector k (x = A(k+1:, k)):
 //   (1) the owners of column k put it in LDS; barrier;
 //   (2) every wave forms H = I - tau v v^H with H^H x = beta e_1 from it (the same arithmetic in
 //       every wave) and keeps v in a wave-private LDS row;
 //   (3) p = tau A v: 4 x 8 block products, summed over the 16 lanes of a row group by a
 //       reduce-scatter, p^H v summed per wave; barrier;
 //   (4) w = p - (tau p^H v / 2) v, A -= v w^H + w v^H on the owned block.
-// Waves whose 16 rows are all eliminated skip (3) and (4).  FP64 throughput of the vector ALUs
-// bounds the kernel (12 FMAs per stored entry and reflector).  Output: d, e (real tridiagonal,
+// Waves whose 16 rows are all eliminated skip (3) and (4), and the others skip the column blocks
+// left of column k + 1 (v and w vanish there).  FP64 throughput of the vector ALUs bounds the
+// kernel (12 FMAs per stored entry and reflector).  Output: d, e (real tridiagonal,
 // e_k = beta_k), tau, and v_k (rows k+1..r-1, v_k(k+1) = 1) in the packed layout of k_heev.
 constexpr int TRD_R = 128;
 constexpr int TRD_THREADS = 512;
 constexpr int TRD_WAVES = TRD_THREADS / 64;
-// LDS vectors are stored with one padding entry after every 8 (index t -> t + t/8): the 16 lanes
-// of a row group read 8 consecutive entries each, 128 bytes apart without padding, which puts all
-// of them on the same banks; with the padding their 16-byte reads start 144 bytes apart and fall on
-// distinct banks.
-constexpr int TRD_RP = TRD_R + TRD_R / 8;
-__device__ __forceinline__ int trd_p(int t) { return t + (t >> 3); }
+// LDS vectors are stored unpadded: the 16 lanes of a row group read 16 consecutive entries (one
+// per column block), the four row groups of a wave read the same or neighbouring ones.
+constexpr int TRD_RP = TRD_R;
+__device__ __forceinline__ int trd_p(int t) { return t; }
 
 __device__ __forceinline__ zd shfl_xor_z(zd v, int o) { return mk(__shfl_xor(v.re, o, 64), __shfl_xor(v.im, o, 64)); }
 
@@ -1341,7 +1342,7 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
   const int f = blockIdx.x;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int a = 4 * w + (l >> 4), b = l & 15;
-  const int r0 = 4 * a, c0 = 8 * b;
+  const int r0 = 4 * a;
   const zd* __restrict__ G = Gin + (int64_t)f * r * r;
   zd* __restrict__ S = gpk + (int64_t)f * packed_size(r);
   double* __restrict__ dout = tri + (int64_t)f * 2 * r;
@@ -1352,7 +1353,7 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
   for (int ii = 0; ii < 4; ++ii)
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
-      const int i = r0 + ii, j = c0 + jj;
+      const int i = r0 + ii, j = 16 * jj + b;
       zd v = mk(0.0, 0.0);
       if (i < r && j < r) v = i >= j ? G[i + (int64_t)j * r] : cconj(G[j + (int64_t)i * r]);
       A[ii][jj] = v;
@@ -1363,8 +1364,8 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
     const int par = k & 1;
     // (1) column k into LDS (entries 0..127; the diagonal entry gives d_k).  k is uniform, so the
     // column is picked by a uniform branch, not by per-lane selects.
-    if (b == (k >> 3)) {
-      const int jk = k & 7;
+    if (b == (k & 15)) {
+      const int jk = k >> 4;
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj)
         if (jk == jj) {
@@ -1416,17 +1417,20 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
     }
     if (!active) continue;           // uniform: H = I, nothing to update
     const bool wave_on = 16 * w + 15 > k;
+    // first column block with a column right of k (uniform)
+    const int jb0 = (k + 1) >> 4;
     if (wave_on) {
       // (3) p = tau A v over the owned block, reduce-scatter over the 16-lane row group
       zd sp[4];
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) sp[ii] = mk(0.0, 0.0);
 #pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        const zd vj = vp[trd_p(c0 + jj)];
+      for (int jj = 0; jj < 8; ++jj)
+        if (jj >= jb0) {
+          const zd vj = vp[trd_p(16 * jj + b)];
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii) sp[ii] = zfma(A[ii][jj], vj, sp[ii]);
-      }
+          for (int ii = 0; ii < 4; ++ii) sp[ii] = zfma(A[ii][jj], vj, sp[ii]);
+        }
       // partners: lane ^ 8 (row rotate by 8), then lane 7 - lane within 8 (half mirror, opposite
       // bit 2), then full sums over quads
       zd k0 = zsel(b3, sp[2], sp[0]), k1 = zsel(b3, sp[3], sp[1]);
@@ -1465,25 +1469,27 @@ k_hetrd_reg(const zd* __restrict__ Gin, int r, double* __restrict__ tri, zd* __r
         wi[ii] = cadd(xsh[par][trd_p(r0 + ii)], cmul(a2, vi[ii]));
       }
 #pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        const zd vj = vp[trd_p(c0 + jj)];
-        const zd vcc = cconj(vj);
-        const zd xj = xsh[par][trd_p(c0 + jj)];
-        const zd wcc = cconj(cadd(zsel(c0 + jj > k, xj, mk(0.0, 0.0)), cmul(a2, vj)));
+      for (int jj = 0; jj < 8; ++jj)
+        if (jj >= jb0) {
+          const int cj = 16 * jj + b;
+          const zd vj = vp[trd_p(cj)];
+          const zd vcc = cconj(vj);
+          const zd xj = xsh[par][trd_p(cj)];
+          const zd wcc = cconj(cadd(zsel(cj > k, xj, mk(0.0, 0.0)), cmul(a2, vj)));
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii) A[ii][jj] = zfms(wi[ii], vcc, zfms(vi[ii], wcc, A[ii][jj]));
-      }
+          for (int ii = 0; ii < 4; ++ii) A[ii][jj] = zfms(wi[ii], vcc, zfms(vi[ii], wcc, A[ii][jj]));
+        }
     }
   }
   // last diagonal entry
   {
     const int t = r - 1;
-    if (a == (t >> 2) && b == (t >> 3)) {
+    if (a == (t >> 2) && b == (t & 15)) {
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii)
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj)
-          if ((t & 3) == ii && (t & 7) == jj) {
+          if ((t & 3) == ii && (t >> 4) == jj) {
             dout[t] = A[ii][jj].re;
             eout[t] = 0.0;
           }
