@@ -24,6 +24,7 @@
 // row 4*(l/16) + v; f64 accumulators row (l/16) + 4*v.
 #pragma once
 #include "common.hpp"
+#include <algorithm>
 #include <type_traits>
 
 namespace rt {
@@ -132,34 +133,46 @@ template <class P, bool CN, typename TA> constexpr int lds_bytes(int NB, int BM)
 // One thread per PV = 16 / sizeof(E) consecutive kl of one column: one 16-byte store per plane
 // (Xp 16-byte aligned; KSL is a multiple of PV).
 template <typename E> constexpr int pack_vec() { return 16 / (int)sizeof(E); }
+// Grid: x over one face's slab chunks (32-bit index, decoded without 64-bit divisions), y = face.
+// vec: the host has checked that X, ldx and sX allow loads of PV consecutive elements at once.
 template <typename TX, typename E, int KSL>
 __global__ void k_pack_slabs(const TX* __restrict__ X, int64_t ldx, int64_t sX, int K, int N, E* __restrict__ Xp,
-                             int KP, int NP, int ntiles, int batch) {
+                             int KP, int NP, int ntiles, int vec) {
   constexpr int PV = pack_vec<E>(), KV = KSL / PV;
   static_assert(KSL % PV == 0, "a slab row holds whole 16-byte vectors");
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   const int nsl = KP / KSL;
-  const int64_t total = (int64_t)batch * ntiles * nsl * NP * KV;
-  if (idx >= total) return;
-  const int kv = (int)(idx % KV);
-  int64_t t1 = idx / KV;
-  const int nl = (int)(t1 % NP);
+  if (idx >= ntiles * nsl * NP * KV) return;
+  const int64_t f = blockIdx.y;
+  const int kv = idx % KV;
+  int t1 = idx / KV;
+  const int nl = t1 % NP;
   t1 /= NP;
-  const int sl = (int)(t1 % nsl);
-  t1 /= nsl;
-  const int nt = (int)(t1 % ntiles);
-  const int64_t f = t1 / ntiles;
+  const int sl = t1 % nsl;
+  const int nt = t1 / nsl;
   const int k0 = sl * KSL + kv * PV, n = nt * NP + nl;
   E re[PV], im[PV];
+  const TX* src = X + f * sX + k0 + (int64_t)n * ldx;
+  if (vec && n < N && k0 + PV <= K) {
+    TX v[PV];
+    vload<TX, PV>(src, v);
 #pragma unroll
-  for (int e = 0; e < PV; ++e) {
-    double vr = 0.0, vi = 0.0;
-    if (n < N && k0 + e < K) {
-      const cplx<double> v = ld<double>(X[f * sX + k0 + e + (int64_t)n * ldx]);
-      vr = v.re; vi = v.im;
+    for (int e = 0; e < PV; ++e) {
+      const cplx<double> z = ld<double>(v[e]);
+      re[e] = cvt_e<E>(z.re);
+      im[e] = cvt_e<E>(z.im);
     }
-    re[e] = cvt_e<E>(vr);
-    im[e] = cvt_e<E>(vi);
+  } else {
+#pragma unroll
+    for (int e = 0; e < PV; ++e) {
+      double vr = 0.0, vi = 0.0;
+      if (n < N && k0 + e < K) {
+        const cplx<double> v = ld<double>(src[e]);
+        vr = v.re; vi = v.im;
+      }
+      re[e] = cvt_e<E>(vr);
+      im[e] = cvt_e<E>(vi);
+    }
   }
   E* out = Xp + (((f * ntiles + nt) * nsl + sl) * 2 * NP + nl) * KSL + kv * PV;
   vstore<E, PV>(out, re);
@@ -665,11 +678,19 @@ static int skinny_pack(int N, int K, const TX* X, int64_t ldx, int64_t sX, int b
   const int KP = packed_kp<P>(K);
   const int NPt = (int)(ceil_div(N, NP) * NP);
   constexpr int KSL = kslab<P>();
-  const int64_t total = (int64_t)NPt * KP * batch;
-  hipLaunchKernelGGL((k_pack_slabs<TX, E, KSL>), dim3((unsigned)ceil_div(total / pack_vec<E>(), 256)), dim3(256), 0, s,
-                     X, ldx, sX, K, N,
-                     static_cast<E*>(ws), KP, NP, NPt / NP, batch);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  constexpr int PV = pack_vec<E>();
+  const int64_t per_face = (int64_t)NPt * KP / PV;
+  if (per_face >= (1LL << 31)) return -1;
+  const int vec = aligned_elems(X, ldx, sX, 0, sizeof(TX), (int64_t)sizeof(TX) * PV) ? 1 : 0;
+  // faces in chunks of at most 65535 (grid y)
+  for (int f0 = 0; f0 < batch; f0 += 65535) {
+    const int fb = std::min(batch - f0, 65535);
+    hipLaunchKernelGGL((k_pack_slabs<TX, E, KSL>), dim3((unsigned)ceil_div(per_face, 256), (unsigned)fb), dim3(256), 0, s,
+                       X + (int64_t)f0 * sX, ldx, sX, K, N, static_cast<E*>(ws) + (int64_t)f0 * 2 * NPt * KP, KP, NP,
+                       NPt / NP, vec);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  return 0;
 }
 
 template <typename TA, typename TC, class P = typename PrecOf<TA>::P>
