@@ -59,7 +59,7 @@ def stage_model(w, precision):
         "fft_omega": (0.0, m * r * n * s_in + F * m * r * cw, "hbm", None),
         "sketch": (big, F * l * m * ca + F * (m + l) * r * cw, None, gp),
         "power": (big, F * l * m * ca + F * (m + l) * r * cw, None, gp),
-        "project": (big, F * l * m * ca + F * l * r * cw + F * m * r * 16, None, gp),
+        "project": (big, F * l * m * ca + F * l * r * cw + F * m * r * cw, None, gp),
         "W": (big, F * l * m * cw + F * m * r * 16 + F * l * r * cw, None, "fp64" if precision == "fp64" else "fp32"),
         "W_mma": (big, F * l * m * cw + F * m * r * 16 + F * l * r * cw, None,
                   "fp64" if precision == "fp64" else "fp32"),
@@ -67,7 +67,7 @@ def stage_model(w, precision):
         "chol": (F * (8.0 / 3.0) * r ** 3, F * 2 * r * r * 16, "alu", "fp64"),
         "qmul": (4.0 * l * r * r * F, 2 * F * l * r * cw + F * r * r * 16, None, "fp64" if precision == "fp64" else "fp32"),
         "heev": (F * (16.0 / 3.0 + 8.0) * r ** 3, F * 2 * r * r * 16, "alu", "fp64"),
-        "svd_aux": (F * (4.0 * m * r * r + 8.0 * m * r * r), F * m * r * 16 * 3, None, "fp64"),
+        "svd_aux": (F * (4.0 * m * r * r + 8.0 * m * r * r), F * m * r * (2 * cw + 16), None, "fp64"),
         "solve": (8.0 * F * (2 * l * r * p + m * r * p + r * r * p + l * r * p),
                   l * p * n * s_in + F * l * p * cw + F * (2 * l * r + m * r) * cw + m * p * n * s_in, "hbm", None),
     }

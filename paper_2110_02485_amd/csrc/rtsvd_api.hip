@@ -568,7 +568,9 @@ struct FaceBufs {
   cplx<Tw>* Z;
   zd* G;           // r x r per face
   zd* Rinv;
-  zd* Ch;          // m x r per face
+  cplx<Tw>* Ch;    // m x r per face, in the work type: the projection accumulates in the MFMA's
+                   // own precision (FP32 for the FP32 and bf16 passes), so its values are
+                   // exactly representable there, and the FP64 Gram and V products read half the bytes
   zd* Ub;
   zd* Ubs;
   double* lam;
@@ -631,17 +633,17 @@ struct QcGroup {
       }
       return orthonormalize<zw>(Y, l, r, Fg, it == q - 1 ? 2 : 1, G, Rinv, tmp, fb->flags, *sc, s);
     }
-    zd* Ch = fb->Ch + f0 * m * r;
+    zw* Ch = fb->Ch + f0 * m * r;
     {
       RT_TIMED(RTSVD_T_PROJECT);
       const zw* Ah = fb->Ah + f0 * l * m;
       const zb* Ah16 = fb->Ah16 ? fb->Ah16 + f0 * l * m : nullptr;
-      if (bf16) RT_TRY((big_gemm<zb, zw, zd>(true, Ah16, l, m, Y, r, Ch, Fg, *sc, s)));
-      else RT_TRY((big_gemm<zw, zw, zd>(true, Ah, l, m, Y, r, Ch, Fg, *sc, s)));
+      if (bf16) RT_TRY((big_gemm<zb, zw, zw>(true, Ah16, l, m, Y, r, Ch, Fg, *sc, s)));
+      else RT_TRY((big_gemm<zw, zw, zw>(true, Ah, l, m, Y, r, Ch, Fg, *sc, s)));
     }
     RT_TIMED(RTSVD_T_SVDAUX);
     // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
-    return gram<zd>(Ch, m, r, Fg, G, *sc, s);
+    return gram<zw>(Ch, m, r, Fg, G, *sc, s);
   }
 };
 
@@ -658,7 +660,7 @@ static int rtsvd_faces_svd(const FaceBufs<Tw>& fb, int64_t l, int64_t m, int64_t
   zd* Ubs = fb.Ubs + f0 * rk * rk;
   double* lam = fb.lam + f0 * rk;
   double* sigma = fb.sigma + f0 * rk;
-  const zd* Ch = fb.Ch + f0 * m * r;
+  const zw* Ch = fb.Ch + f0 * m * r;
   zd* V = fb.V + f0 * m * rk;
   zw* W = fb.W + f0 * l * rk;
   const zw* Ah = fb.Ah + f0 * l * m;
@@ -676,7 +678,8 @@ static int rtsvd_faces_svd(const FaceBufs<Tw>& fb, int64_t l, int64_t m, int64_t
     hipLaunchKernelGGL((k_scale_cols<zd, zd>), dim3(nblocks(Fg * rk * rk)), dim3(256), 0, s, (const zd*)Ub, Ubs,
                        (const double*)sigma, (int)rk, (int)rk, (int)Fg);
     RT_LAUNCH_OK();
-    RT_TRY((skinny<zd, zd, zd>(false, m, rk, rk, Ch, m, m * r, Ubs, rk, rk * rk, V, m, m * rk, Fg, sc, s)));
+    RT_TRY((skinny<zw, zd, zd, Scratch, sk::F64>(false, m, rk, rk, Ch, m, m * r, Ubs, rk, rk * rk, V, m, m * rk, Fg, sc,
+                                                 s)));
   }
   // W = A-hat V: exact residuals of the discrepancy principle
   if (phase < 0 || phase == 2) {
@@ -842,7 +845,7 @@ static int factor_impl(const Tin* A, const Tin* omega, uint64_t seed, int64_t l,
     RT_ALLOC(Y, zw, F * l * r, sc);     // per-face stride l*r (l >= m) in the three work buffers,
     RT_ALLOC(tmp, zw, F * l * r, sc);   // so that face groups own disjoint regions
     RT_ALLOC(Zb, zw, F * l * r, sc);
-    RT_ALLOC(Ch, zd, F * m * r, sc);    // C^H = A-hat^H Q, m x r per face (C = Q^H A-hat)
+    RT_ALLOC(Ch, zw, F * m * r, sc);    // C^H = A-hat^H Q, m x r per face (C = Q^H A-hat)
     RT_ALLOC(Ubs, zd, F * r * r, sc);
     if (groups == 1) {
       RT_TIMED(RTSVD_T_FFT_OMEGA);
