@@ -104,7 +104,7 @@ k_gemv_cn(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA
   cplx<Acc> acc[NP];
 #pragma unroll
   for (int c = 0; c < NP; ++c) acc[c] = mk((Acc)0, (Acc)0);
-#pragma unroll 4
+#pragma unroll 16
   for (int k = lane; k < K; k += 64) {
     const cplx<Acc> av = ld<Acc>(a[k]);
 #pragma unroll

@@ -15,6 +15,7 @@ namespace rt {
 
 constexpr int DP_ROWS = 64;        // rows per block (one wave) of the residual pass
 constexpr int DP_KCH = 64;         // residual orders per transposition chunk
+constexpr int DP_WU = 32;          // columns of W loaded at once by the residual pass
 constexpr int DP_SEL_THREADS = 1024;
 constexpr int HEEV_RMAX_SOLVE = 256;  // largest r (the eigensolver's limit)
 
@@ -71,18 +72,27 @@ k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __r
   double* __restrict__ out = partial + (((int64_t)f * tiles + tile) * pg + g) * kcap;
   for (int k0 = 0; k0 < kcap; k0 += DP_KCH) {
     const int kn = min(DP_KCH, kcap - k0);
-#pragma unroll 4
-    for (int kk = 0; kk < kn; ++kk) {
-      const int k = k0 + kk;                       // order k+1 uses column k
-      const zd wk = ld<double>(wf[(int64_t)k * l]);
-      double acc = 0.0;
+    // DP_WU columns of W are loaded at once (all in flight: a wave per 64 rows has little other
+    // work to cover the memory latency with), then applied in order
+    for (int kb = 0; kb < kn; kb += DP_WU) {
+      TW wv[DP_WU];
 #pragma unroll
-      for (int j = 0; j < CPB; ++j) {
-        const zd t = (c0 + j < p) ? tf[(int64_t)(c0 + j) * r + k] : mk(0.0, 0.0);
-        R[j] = csub(R[j], cmul(wk, t));
-        acc += cabs2(R[j]);
+      for (int u = 0; u < DP_WU; ++u) wv[u] = wf[(int64_t)min(k0 + kb + u, kcap - 1) * l];
+#pragma unroll
+      for (int u = 0; u < DP_WU; ++u) {
+        const int kk = kb + u;
+        if (kk >= kn) break;                       // uniform
+        const int k = k0 + kk;                     // order k+1 uses column k
+        const zd wk = ld<double>(wv[u]);
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPB; ++j) {
+          const zd t = (c0 + j < p) ? tf[(int64_t)(c0 + j) * r + k] : mk(0.0, 0.0);
+          R[j] = csub(R[j], cmul(wk, t));
+          acc += cabs2(R[j]);
+        }
+        sq[kk][lane] = on ? acc : 0.0;
       }
-      sq[kk][lane] = on ? acc : 0.0;
     }
     __syncthreads();
     if (lane < kn) {
