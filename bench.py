@@ -81,14 +81,14 @@ def stage_model(w, precision):
 # calibration 1 GiB -> FETCH_SIZE 524302.3 KiB (factor 1.99995), WRITE_SIZE 1048576 KiB (factor 1.0).
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
-                         "sha256": "0f263c4a58d3d8eeff383dfae4dcad517867cd4708c34282cd3781b1e25bd07f",
-                         "bytes_per_launch": 681676768},
+                         "sha256": "6f44c72ca41dc9c99e3b5b4d7e99613209af795d81ab46db378a446ca6747bfc",
+                         "bytes_per_launch": 681675368},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
-                        "sha256": "125c971e9987ee3c004fedd99f93357e4f191310104170f2610f9ca2cbc1c353",
-                        "bytes_per_launch": 27996304},
+                        "sha256": "57ad03baf9b86cfe4024bd60339516d6ec6238d30ef0b3415c15968780859eb5",
+                        "bytes_per_launch": 27982968},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
                         "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
-                        "bytes_per_launch": 76507073},
+                        "bytes_per_launch": 76505484},
 }
 
 
