@@ -185,14 +185,25 @@ def tuned_split(torch, prob, w, precision, enabled):
     from paper_2110_02485_amd import tune
     A, B, Om = operands(prob, precision)
     t = tune.tune(A, B, Om, w.k_max, w.oversample, w.power_iters, precision, prob["delta"], w.eta)
-    print(f"[bench] tuned {precision}: groups {t['face_groups']}, tiles {t['sketch_tile']} "
+    print(f"[bench] tuned {precision}: groups {t['face_groups']}, tiles {t['sketch_tile']}, "
+          f"{t['in_flight']} in flight "
           f"({t['ms_per_step']:.3f} ms; {t['table']})", file=sys.stderr, flush=True)
     if not t["identical"]:
         # the work split must not change the result; if it did, time the automatic split and say so
         print("[bench] autotuner: candidates disagreed bit for bit; using the automatic split",
               file=sys.stderr, flush=True)
-        return {**t, "face_groups": 0, "sketch_tile": 0}
+        return {**t, "face_groups": 0, "sketch_tile": 0, "in_flight": 1}
     return t
+
+
+def one_in_flight(t):
+    """The tuner's fastest candidate with a single restoration in flight (None without tuning)."""
+    if not t:
+        return None
+    rows = {k: v for k, v in t["table"].items() if k.endswith("_inflight1")}
+    best = min(rows, key=rows.get)
+    g, tl = best.split("_")[0][6:], best.split("_")[1][4:]
+    return {"face_groups": int(g), "sketch_tile": int(tl), "in_flight": 1}
 
 
 def time_fixed_precision(torch, rt, prob, w, precision, steps, eps):
@@ -215,9 +226,18 @@ def time_fixed_precision(torch, rt, prob, w, precision, steps, eps):
 
 
 def time_steps(torch, rt, prob, w, precision, steps, warmup, timers=False, split=None):
+    """K restorations timed between two events on the current stream, issued round robin on
+    split["in_flight"] caller streams (one with the stage timers, whose events belong to one call's
+    stream), with the split's face groups and tile count."""
+    from paper_2110_02485_amd import tune
     lib = rt.load()
-    for _ in range(warmup):
-        f, res = run_once(rt, prob, w, precision, split)
+    A, B, Om = operands(prob, precision)
+    split = split or {}
+    groups, tile = split.get("face_groups", 0), split.get("sketch_tile", 0)
+    in_flight = 1 if timers else split.get("in_flight", 1)
+    args = (A, B, Om, w.k_max, w.oversample, w.power_iters, precision, prob["delta"], w.eta, groups, tile, in_flight)
+    if warmup > 0:
+        f, _ = tune.restorations(*args, max(warmup, in_flight))
         f.close()
     torch.cuda.synchronize()
     if timers:
@@ -226,18 +246,15 @@ def time_steps(torch, rt, prob, w, precision, steps, warmup, timers=False, split
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record()
-    last = None
-    for i in range(steps):
-        f, res = run_once(rt, prob, w, precision, split)
-        if last is not None:
-            last.close()
-        last = f
-        print(f"[bench] {precision} step {i + 1}/{steps} issued", file=sys.stderr, flush=True)
+    last, results = tune.restorations(*args, steps, start)
     end.record()
+    print(f"[bench] {precision}: {steps} steps issued ({in_flight} in flight)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = start.elapsed_time(end)
-    out = {"X": res.X, "k": int(res.k[0]), "status": int(res.status[0])}
+    res = results[-1]
+    same = all(torch.equal(r_.X, res.X) for r_ in results)
+    out = {"X": res.X, "k": int(res.k[0]), "status": int(res.status[0]), "identical_steps": same}
     last.close()
     if timers:
         out["stages"] = read_stages(lib, steps, w, precision)
@@ -474,7 +491,7 @@ def time_video_512(torch, rt, wl, steps, tune_enabled=True):
     p = Bd.shape[1]
     print("[bench] 512-wide video restoration", file=sys.stderr, flush=True)
     tuned = tuned_split(torch, prob, w, "fp32", tune_enabled)
-    split = tuned or {}
+    split = one_in_flight(tuned) or {}     # one restoration at a time here (eager and graph replay)
     groups, tile = split.get("face_groups", 0), split.get("sketch_tile", 0)
 
     def make_restore(state):
@@ -792,6 +809,12 @@ def main():
     # carries no event records (the library runs one face group while its timers are on)
     _, _, out_st = time_steps(torch, rt, prob, w, precision, args.steps, 1, timers=True, split=tuned)
     out["stages"] = out_st.get("stages", {})
+    # latency of one restoration alone (the tuner's best schedule with a single one in flight)
+    if tuned and tuned.get("in_flight", 1) > 1:
+        split1 = one_in_flight(tuned)
+        ms1, _, _ = time_steps(torch, rt, prob, w, precision, args.steps, 1, split=split1)
+    else:
+        split1, ms1 = tuned, ms
     x_true = prob["X64"]
     err = float(torch.linalg.norm(out["X"].double() - x_true) / torch.linalg.norm(x_true))
     result = {
@@ -804,9 +827,17 @@ def main():
                    "k_max": w.k_max, "oversample": w.oversample, "r": w.r, "power_iters": w.power_iters,
                    "precision": precision, "noise": w.noise, "eta": w.eta},
         "k": out["k"], "dp_status": out["status"], "rel_error": err,
+        "identical_steps": out["identical_steps"],
+        "schedule": {"in_flight": tuned.get("in_flight", 1) if tuned else 1,
+                     "what": "independent restorations issued round robin on that many caller streams; "
+                             "every step is a whole restoration (factor + solve) of the same input",
+                     "ms_per_restoration_one_in_flight": ms1,
+                     "one_in_flight_split": ({"face_groups": split1["face_groups"],
+                                              "sketch_tile": split1["sketch_tile"]} if split1 else "automatic")},
         "tuning": ({"face_groups": tuned["face_groups"], "sketch_tile": tuned["sketch_tile"],
-                    "identical_results": tuned["identical"], "candidates_ms": tuned["table"]}
-                   if tuned else "automatic (face_groups 0, sketch_tile 0)"),
+                    "in_flight": tuned["in_flight"], "identical_results": tuned["identical"],
+                    "candidates_ms": tuned["table"]}
+                   if tuned else "automatic (face_groups 0, sketch_tile 0, one in flight)"),
     }
     stages = out.get("stages", {})
     if stages:
@@ -822,7 +853,8 @@ def main():
                           "mixed_vs_fp64_rel_diff": diff,
                           "matched": abs(err - err64) <= 0.01 * err64,
                           "speedup_mixed_over_fp64": ms64 / ms,
-                          "tuning": ({"face_groups": tuned64["face_groups"], "sketch_tile": tuned64["sketch_tile"]}
+                          "tuning": ({"face_groups": tuned64["face_groups"], "sketch_tile": tuned64["sketch_tile"],
+                                      "in_flight": tuned64["in_flight"]}
                                      if tuned64 else "automatic")}
     if not args.no_fixed_precision:
         # eps from the fixed-r factor's error indicator: eps^2 just above eta^[k_max], so Alg. 6

@@ -285,6 +285,47 @@ def test_face_groups_give_identical_factors(precision):
         assert np.array_equal(eta_, outs[0][2]) and np.array_equal(sig_, outs[0][3])
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_restorations_in_flight_on_several_streams_match_sequential(precision):
+    # independent restorations (three different problems, twice each) issued round robin on three
+    # caller streams, one face group each, give the bits of the same restorations issued one after
+    # another on one stream: a call's work and scratch stay on its own stream
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    from paper_2110_02485_amd import tune
+    dt = "float64" if precision == "fp64" else "float32"
+    probs = []
+    for seed, noise in ((81, 1e-2), (82, 1e-3), (83, 3e-2)):
+        A, X, B, Om, delta = blur_problem(128, 16, 2.0, 8, 1, noise, 20, 10, seed=seed)
+        probs.append((_t(A, dt), _t(B, dt), _t(Om, dt), delta))
+    torch.cuda.synchronize()
+
+    def run(nstreams):
+        streams = [torch.cuda.current_stream()] if nstreams == 1 else tune.caller_streams(nstreams)
+        fs, outs = [], []
+        for rep in range(2):
+            for i, (At, Bt, Omt, delta) in enumerate(probs):
+                with torch.cuda.stream(streams[(3 * rep + i) % nstreams]):
+                    f = rt.factor(At, 20, 10, 1, precision, Omt, face_groups=1)
+                    outs.append(f.solve(Bt, delta, 1.01, 1))
+                fs.append(f)
+        torch.cuda.synchronize()
+        got = [(_np(o.X), int(o.k[0]), _np(o.resid)) for o in outs]
+        for f in fs:
+            f.close()
+        return got
+
+    print(f"[in flight] {precision}", flush=True)
+    seq = run(1)
+    par = run(3)
+    for (X0, k0, r0), (X1, k1, r1) in zip(seq, par):
+        assert k0 == k1
+        assert np.array_equal(X0, X1) and np.array_equal(r0, r1)
+    # the two repetitions of a problem agree as well
+    for i in range(3):
+        assert np.array_equal(seq[i][0], seq[i + 3][0])
+
+
 @pytest.mark.parametrize("precision,r_cols", [("mixed", 30), ("mixed", 120), ("fp32", 120), ("fp64", 30)])
 def test_sketch_tiles_give_identical_factors(precision, r_cols):
     # 1, 2, 4 or 8 sixteen-column MFMA tiles per workgroup in the factor's A-hat products: only the
