@@ -96,6 +96,11 @@ typedef struct {
  * this call.  The per-face work may be issued on up to three streams of the library's own
  * (default priority, see rtsvd_opts.face_groups), forked from and joined back into `stream`
  * with events: all of the call's work is complete when `stream` reaches the end of the call.
+ * With face_groups = 1 every launch of the call, and every scratch buffer it takes from the
+ * library's cache, stays on `stream`: calls (factor and solve) issued on different streams are
+ * then independent and may run concurrently, which overlaps one call's latency-bound small-matrix
+ * kernels with another's passes over A-hat.  With more groups, calls on different streams share
+ * the library's group streams (correct, but serialized per group).
  * Errors: RTSVD_E_ARG (l < m, n < 1, k_max < 1, k_max > m, oversample < 0,
  * power_iters < 0, bad precision, face_groups outside 0..3, sketch_tile not 0, 1, 2, 4 or 8,
  * null A/opts/out),
