@@ -122,8 +122,10 @@ def roofline_of(name, ms, launches, w, precision):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    # with several restorations in flight the first and last steps fill and drain the pipeline:
+    # 40 steps (about 0.1 s of device time) keep that under a few percent
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="blur1024")
     ap.add_argument("--precision", default=None, help="override the workload precision (fp64/fp32/mixed)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the plain FP64 comparison")
