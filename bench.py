@@ -509,6 +509,17 @@ def time_video_512(torch, rt, wl, steps, tune_enabled=True):
     res = state["res"]
     k, status = int(res.k[0]), int(res.status[0])
     X_eager = res.X.clone()
+    # throughput with the tuned number of restorations in flight (independent restorations on
+    # separate caller streams), when the tuner picked more than one
+    in_flight = None
+    if tuned and tuned.get("in_flight", 1) > 1:
+        fargs = (At, Bd, Omt, w.k_max, w.oversample, 0, "fp32", delta, w.eta, tuned["face_groups"],
+                 tuned["sketch_tile"], tuned["in_flight"])
+        ms_if, res_if = _in_flight_ms(torch, fargs, max(steps, 4 * tuned["in_flight"]))
+        in_flight = {"in_flight": tuned["in_flight"], "face_groups": tuned["face_groups"],
+                     "sketch_tile": tuned["sketch_tile"], "ms_per_restoration": ms_if,
+                     "restorations_per_s": 1000.0 / ms_if, "frames_per_s": p * 1000.0 / ms_if,
+                     "identical_to_eager": all(bool(torch.equal(r_.X, X_eager)) for r_ in res_if)}
     # one restoration replayed from a graph captured on a stream of its own; the captured factor
     # handle stays alive and is rewritten by every replay
     gstate = {}
@@ -549,6 +560,7 @@ def time_video_512(torch, rt, wl, steps, tune_enabled=True):
                         if tuned else "automatic"),
              "value": 1000.0 / best, "unit": "restorations/s", "frames_per_s": p * 1000.0 / best,
              "ms_restoration_eager": ms_eager, "ms_restoration_graph": ms_graph, "graph": graph_note,
+             "in_flight": in_flight if in_flight else "one restoration at a time (tuner's choice)",
              "graph_identical_to_eager": graph_identical,
              "ms_solve_cached_factor_eager": ms_solve, "ms_solve_cached_factor_graph": ms_solve_graph,
              "solves_per_s_cached_factor": 1000.0 / best_solve, "frames_per_s_cached_factor": p * 1000.0 / best_solve,
@@ -557,6 +569,23 @@ def time_video_512(torch, rt, wl, steps, tune_enabled=True):
              "stages": {kk: {a: (round(b, 4) if isinstance(b, float) else b) for a, b in v.items()}
                         for kk, v in stages.items()}}
     return entry, {"rtsvd": (X_eager.double().cpu().numpy(), k)}
+
+
+def _in_flight_ms(torch, fargs, steps):
+    """ms per restoration of `steps` restorations issued with tune.restorations(*fargs, ...) between
+    two events on the current stream (after one warm-up round), and the results."""
+    from paper_2110_02485_amd import tune
+    f, _ = tune.restorations(*fargs, fargs[-1])
+    f.close()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    f, res = tune.restorations(*fargs, steps, start)
+    end.record()
+    torch.cuda.synchronize()
+    f.close()
+    return start.elapsed_time(end) / steps, res
 
 
 def time_video_240(torch, rt, wl, steps):
