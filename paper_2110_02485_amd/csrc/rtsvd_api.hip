@@ -409,18 +409,23 @@ static int gram(const TY* Y, int64_t rows, int64_t r, int64_t F, zd* G, Scratch&
 template <typename TA, typename TX, typename TC, typename SC = Scratch, class P = typename sk::PrecOf<TA>::P>
 static int skinny(bool conjA, int64_t M, int64_t N, int64_t K, const TA* A, int64_t lda, int64_t sA, const TX* X,
                   int64_t ldx, int64_t sX, TC* C, int64_t ldc, int64_t sC, int64_t F, SC& sc, hipStream_t s,
-                  int ktag = 0, int utri = 0) {
+                  int ktag = 0, int utri = 0, sk::PackOut cpk = sk::PackOut(), const void* prepacked = nullptr) {
   if (M <= 0 || N <= 0 || F <= 0) return 0;
   if (K <= 0) return fail(RTSVD_E_ARG, "skinny product: K must be positive");
-  unsigned char* ws = sc.template get<unsigned char>(sk::skinny_ws_bytes<TA, P>((int)K, (int)N, (int)F));
-  if (!ws) return fail(RTSVD_E_NOMEM, "device allocation failed: packed operand");
-  if (sk::skinny_pack<TA, TX, P>((int)N, (int)K, X, ldx, sX, (int)F, ws, s))
-    return fail(RTSVD_E_HIP, "skinny pack launch");
+  // prepacked: X already in the packed layout (written by the product that formed it)
+  const void* ws = prepacked;
+  if (!ws) {
+    unsigned char* w = sc.template get<unsigned char>(sk::skinny_ws_bytes<TA, P>((int)K, (int)N, (int)F));
+    if (!w) return fail(RTSVD_E_NOMEM, "device allocation failed: packed operand");
+    if (sk::skinny_pack<TA, TX, P>((int)N, (int)K, X, ldx, sX, (int)F, w, s))
+      return fail(RTSVD_E_HIP, "skinny pack launch");
+    ws = w;
+  }
   if (ktag) {
     RT_TIMED(ktag);
-    return sk::skinny_run<TA, TC, P>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri);
+    return sk::skinny_run<TA, TC, P>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri, cpk);
   }
-  return sk::skinny_run<TA, TC, P>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri);
+  return sk::skinny_run<TA, TC, P>(conjA, (int)M, (int)N, (int)K, A, lda, sA, C, ldc, sC, (int)F, ws, s, utri, cpk);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -428,9 +433,13 @@ static int skinny(bool conjA, int64_t M, int64_t N, int64_t K, const TA* A, int6
 // times (2 = CholeskyQR2, orthonormal to working precision).  The product is written to `tmp` and
 // the two buffers are exchanged, so Y names the result on return.
 // ---------------------------------------------------------------------------------------------
+// qpack (FP32 Y only, may be null): the last pass also writes Q as the packed bf16 X operand of
+// the following bf16 pass over A-hat, when the row count allows it (*packed says whether it did).
 template <typename TY>
 static int orthonormalize(TY*& Y, int64_t rows, int64_t r, int64_t F, int passes, zd* G, zd* Rinv, TY*& tmp,
-                          int* flags, Scratch& sc, hipStream_t s) {
+                          int* flags, Scratch& sc, hipStream_t s, uint16_t* qpack = nullptr,
+                          bool* packed = nullptr) {
+  if (packed) *packed = false;
   for (int pass = 0; pass < passes; ++pass) {
     {
       RT_TIMED(RTSVD_T_GRAM);
@@ -441,8 +450,20 @@ static int orthonormalize(TY*& Y, int64_t rows, int64_t r, int64_t F, int passes
       RT_TRY(launch_cholinv(G, (int)r, F, Rinv, flags, sc, s));
     }
     RT_TIMED(RTSVD_T_QMUL);
+    sk::PackOut cpk;
+    if constexpr (std::is_same<TY, zf>::value) {
+      if (qpack && pass == passes - 1) {
+        const sk::PackPlan pl = sk::bf16_pack_plan((int)r, (int)rows, (int)F);
+        if (pl.ok) {
+          cpk = pl.out;
+          cpk.p = qpack;
+          if (packed) *packed = true;
+        }
+      }
+    }
     // R^{-1} is upper triangular
-    RT_TRY((skinny<TY, zd, TY>(false, rows, r, r, Y, rows, rows * r, Rinv, r, r * r, tmp, rows, rows * r, F, sc, s, 0, 1)));
+    RT_TRY((skinny<TY, zd, TY>(false, rows, r, r, Y, rows, rows * r, Rinv, r, r * r, tmp, rows, rows * r, F, sc, s, 0, 1,
+                               cpk)));
     std::swap(Y, tmp);
   }
   return 0;
@@ -490,11 +511,21 @@ static int orthonormalize_tri_vectors(double* zs, int r, int64_t F, Scratch& sc,
 }
 
 // products over A-hat: Y = A-hat X (conjA = false, Y is l x r) or Y = A-hat^H X (Y is m x r)
+// The packed bf16 copies of Q and Z are written by the products that form them unless the
+// environment variable RTSVD_PACK_FUSION is "0" (then every pass packs its X; the results are the
+// same bits either way, the variable exists to compare the two).
+static bool pack_fusion_enabled() {
+  const char* e = std::getenv("RTSVD_PACK_FUSION");
+  return !(e && std::strcmp(e, "0") == 0);
+}
+
+// xpk: X already packed (see orthonormalize), or null
 template <typename TA, typename TX, typename TY>
 static int big_gemm(bool conjA, const TA* Ah, int64_t l, int64_t m, const TX* X, int64_t r, TY* Y, int64_t F,
-                    Scratch& sc, hipStream_t s, int ktag = 0) {
-  if (!conjA) return skinny<TA, TX, TY>(false, l, r, m, Ah, l, l * m, X, m, m * r, Y, l, l * r, F, sc, s, ktag);
-  return skinny<TA, TX, TY>(true, m, r, l, Ah, l, l * m, X, l, l * r, Y, m, m * r, F, sc, s, ktag);
+                    Scratch& sc, hipStream_t s, int ktag = 0, const void* xpk = nullptr) {
+  if (!conjA)
+    return skinny<TA, TX, TY>(false, l, r, m, Ah, l, l * m, X, m, m * r, Y, l, l * r, F, sc, s, ktag, 0, sk::PackOut(), xpk);
+  return skinny<TA, TX, TY>(true, m, r, l, Ah, l, l * m, X, l, l * r, Y, m, m * r, F, sc, s, ktag, 0, sk::PackOut(), xpk);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -568,6 +599,7 @@ struct FaceBufs {
   cplx<Tw>* Z;
   zd* G;           // r x r per face
   zd* Rinv;
+  uint16_t* Xpk;   // packed bf16 Q or Z for the next pass over A-hat (null: each pass packs its X)
   cplx<Tw>* Ch;    // m x r per face, in the work type: the projection accumulates in the MFMA's
                    // own precision (FP32 for the FP32 and bf16 passes), so its values are
                    // exactly representable there, and the FP64 Gram and V products read half the bytes
@@ -596,16 +628,28 @@ struct QcGroup {
   hipStream_t s;
   hipEvent_t mark;
   zw *Y, *tmp, *Z;
+  uint16_t* xpk = nullptr;   // this group's part of fb->Xpk
+  bool packed = false;       // xpk holds the X of the next pass over A-hat
   int phases() const { return 2 + 4 * q + 1; }
   void init() {
     Y = fb->Y + f0 * l * r;
     tmp = fb->tmp + f0 * l * r;
     Z = fb->Z + f0 * l * r;
+    if (fb->Xpk) xpk = fb->Xpk + f0 * sk::bf16_pack_plan((int)r, (int)l, 1).out.sf;
   }
-  int product(bool conjA, const zw* X, zw* Out) {
+  int qr(zw*& W, int64_t rows, int passes, zd* G, zd* Rinv) {
+    return orthonormalize<zw>(W, rows, r, Fg, passes, G, Rinv, tmp, fb->flags, *sc, s, bf16 ? xpk : nullptr, &packed);
+  }
+  // X's packed copy is used (and consumed) when the QR that formed X wrote one
+  const void* take_packed() {
+    const void* p = packed ? (const void*)xpk : nullptr;
+    packed = false;
+    return p;
+  }
+  int product(bool conjA, const zw* X, zw* Out, const void* xp = nullptr) {
     const zw* Ah = fb->Ah + f0 * l * m;
     const zb* Ah16 = fb->Ah16 ? fb->Ah16 + f0 * l * m : nullptr;
-    if (bf16) return big_gemm<zb, zw, zw>(conjA, Ah16, l, m, X, r, Out, Fg, *sc, s);
+    if (bf16) return big_gemm<zb, zw, zw>(conjA, Ah16, l, m, X, r, Out, Fg, *sc, s, 0, xp);
     return big_gemm<zw, zw, zw>(conjA, Ah, l, m, X, r, Out, Fg, *sc, s);
   }
   int run(int ph) {
@@ -619,27 +663,24 @@ struct QcGroup {
       if (mark) RT_CHECK_HIP(hipEventRecord(mark, s));
       return 0;
     }
-    if (ph == 1) return orthonormalize<zw>(Y, l, r, Fg, q == 0 ? 2 : 1, G, Rinv, tmp, fb->flags, *sc, s);
+    if (ph == 1) return qr(Y, l, q == 0 ? 2 : 1, G, Rinv);
     if (ph < 2 + 4 * q) {
       const int it = (ph - 2) / 4, k = (ph - 2) % 4;
       if (k == 0) {
         RT_TIMED(RTSVD_T_POWER);
-        return product(true, Y, Z);
+        return product(true, Y, Z, take_packed());
       }
-      if (k == 1) return orthonormalize<zw>(Z, m, r, Fg, 1, G, Rinv, tmp, fb->flags, *sc, s);
+      if (k == 1) return qr(Z, m, 1, G, Rinv);
       if (k == 2) {
         RT_TIMED(RTSVD_T_SKETCH);
-        return product(false, Z, Y);
+        return product(false, Z, Y, take_packed());
       }
-      return orthonormalize<zw>(Y, l, r, Fg, it == q - 1 ? 2 : 1, G, Rinv, tmp, fb->flags, *sc, s);
+      return qr(Y, l, it == q - 1 ? 2 : 1, G, Rinv);
     }
     zw* Ch = fb->Ch + f0 * m * r;
     {
       RT_TIMED(RTSVD_T_PROJECT);
-      const zw* Ah = fb->Ah + f0 * l * m;
-      const zb* Ah16 = fb->Ah16 ? fb->Ah16 + f0 * l * m : nullptr;
-      if (bf16) RT_TRY((big_gemm<zb, zw, zw>(true, Ah16, l, m, Y, r, Ch, Fg, *sc, s)));
-      else RT_TRY((big_gemm<zw, zw, zw>(true, Ah, l, m, Y, r, Ch, Fg, *sc, s)));
+      RT_TRY(product(true, Y, Ch, take_packed()));
     }
     RT_TIMED(RTSVD_T_SVDAUX);
     // small SVD of C through G = C C^H = U-breve diag(sigma^2) U-breve^H (FP64)
@@ -852,7 +893,14 @@ static int factor_impl(const Tin* A, const Tin* omega, uint64_t seed, int64_t l,
       if (omg) RT_TRY(launch_gaussian<Tin>(seed, m * r * n, omg, s));
       RT_TRY((launch_rfft<Tin, Tw>(omega, m * r, (int)n, Omh, m * r, (zb*)nullptr, (double*)nullptr, nullptr, s)));
     }
-    FaceBufs<Tw> fb{Ah, Ah16, Omh, Y, tmp, Zb, G, Rinv, Ch, Ub, Ubs, lam, sigma, V, Wo, flags};
+    // packed bf16 copies of Q and Z written by the products that form them (mixed precision,
+    // l and m multiples of 128): per face the slab size of an l-row operand
+    uint16_t* Xpk = nullptr;
+    if (bf16 && pack_fusion_enabled() && sk::bf16_pack_plan((int)r, (int)l, 1).ok) {
+      Xpk = sc.get<uint16_t>(F * sk::bf16_pack_plan((int)r, (int)l, 1).out.sf);
+      if (!Xpk) return fail(RTSVD_E_NOMEM, "device allocation failed: packed operand of the passes");
+    }
+    FaceBufs<Tw> fb{Ah, Ah16, Omh, Y, tmp, Zb, G, Rinv, Xpk, Ch, Ub, Ubs, lam, sigma, V, Wo, flags};
     if (groups == 1) {
       QcGroup<Tw> qg{&fb, l, m, r, 0, F, q, bf16, &sc, s, nullptr};
       qg.init();

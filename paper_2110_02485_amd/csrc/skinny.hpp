@@ -190,13 +190,24 @@ __global__ void k_pack_slabs(const TX* __restrict__ X, int64_t ldx, int64_t sX, 
 // waves per SIMD the register allocation must allow: four (two workgroups per CU, so one
 // workgroup's MFMAs run while the other waits at its k-group barrier) for the unchecked FP32
 // products, two for the others
+// Optional second output of an FP32 product: C as the packed bf16 X operand of a following bf16
+// pass over A-hat (slab-major, the layout k_pack_slabs writes with 32 k per slab: k = row of C,
+// n = column of C, block columns of NP = 16 NB), so that pass needs no packing kernel.  p == null:
+// none.  sf: elements per face; nsl: slabs per block column (rows of C / 32, rows a multiple of 128
+// so there are no padding rows).  Columns past N are written too: their values are zero.
+struct PackOut {
+  uint16_t* p = nullptr;
+  int64_t sf = 0;
+  int nsl = 0;
+};
+
 template <class P, bool SAFE> constexpr int sk_min_waves() { return (std::is_same<P, F32>::value && !SAFE) ? 4 : 2; }
 
 template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, bool UTRI, typename TA, typename TX, typename TC, int NB>
 __global__ void __launch_bounds__(SK_THREADS, (sk_min_waves<P, SAFE>()))
 k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA, const void* __restrict__ Xv,
          int64_t ldx, int64_t sX, TC* __restrict__ C, int64_t ldc, int64_t sC, int batch, int mtiles, int ntiles,
-         int kchunk, int64_t sCsplit, int vec_c) {
+         int kchunk, int64_t sCsplit, int vec_c, PackOut cpk) {
   typedef typename P::E E;
   typedef typename P::V V;
   typedef typename P::Acc Acc;
@@ -541,8 +552,6 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
   for (int c = 0; c < NT; ++c) {
     if (LOWER && n0 + cw + 16 * c > wmax) continue;
     const int col = n0 + cw + 16 * c + rho;
-    if (col >= N) continue;
-    TC* cp = C + (int64_t)col * ldc;
     if constexpr (RT == 2) {
       const int rb = mw + 8 * g;   // rows rb .. rb+7: element v of tile tt is row rb + 2 v + tt
       TC vals[8];
@@ -550,6 +559,24 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int tt = 0; tt < 2; ++tt) st(vals[2 * v + tt], mk((double)accr[tt][c][v], (double)acci[tt][c][v]));
+      if (cpk.p && rb < M) {
+        // the packed bf16 copy: rows rb .. rb+7 are eight consecutive k of one slab row (the same
+        // rounding as k_pack_slabs applies to the stored value; M is a multiple of 128, so a tile
+        // row past M starts past it by whole slabs and is skipped)
+        uint16_t pre[8], pim[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const cplx<double> z = ld<double>(vals[j]);
+          pre[j] = cvt_e<uint16_t>(z.re);
+          pim[j] = cvt_e<uint16_t>(z.im);
+        }
+        uint16_t* o = cpk.p + (int64_t)f * cpk.sf +
+                      (((int64_t)nt * cpk.nsl + rb / 32) * 2 * NP + (cw + 16 * c + rho)) * 32 + (rb % 32);
+        vstore<uint16_t, 8>(o, pre);
+        vstore<uint16_t, 8>(o + NP * 32, pim);
+      }
+      if (col >= N) continue;
+      TC* cp = C + (int64_t)col * ldc;
       if (vec_c && rb + 8 <= M) {
         vstore<TC, 8>(cp + rb, vals);
       } else {
@@ -558,6 +585,8 @@ k_skinny(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
           if (rb + j < M) cp[rb + j] = vals[j];
       }
     } else {
+      if (col >= N) continue;
+      TC* cp = C + (int64_t)col * ldc;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = mw + g + 4 * v;
@@ -593,7 +622,7 @@ template <class P> static inline int nt_for(int N) {
 template <class P, bool CN, bool PACKED, bool SAFE, bool LOWER, bool UTRI, typename TA, typename TX, typename TC, int NT>
 static int sk_launch_nt(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const void* X, int64_t ldx,
                         int64_t sX, TC* C, int64_t ldc, int64_t sC, int batch, int ksplit, int64_t sCsplit,
-                        hipStream_t s) {
+                        hipStream_t s, PackOut cpk = PackOut()) {
   constexpr int BM = Shape<NT>::WR * 16 * P::RT, NP = 16 * NT, KS = kgroup<P>();
   static_assert(NP > 0 && BM > 0, "shape");
   const int mtiles = (int)ceil_div(M, BM), ntiles = (int)ceil_div(N, NP);
@@ -612,14 +641,15 @@ static int sk_launch_nt(int M, int N, int K, const TA* A, int64_t lda, int64_t s
   }
   const bool vec_c = aligned_elems(C, ldc, sC, sCsplit, sizeof(TC), 16);
   hipLaunchKernelGGL(kern, dim3((unsigned)nblk, (unsigned)ksplit), dim3(SK_THREADS), bytes, s, M, N, K, A, lda, sA, X, ldx,
-                     sX, C, ldc, sC, batch, mtiles, ntiles, kchunk, sCsplit, (int)vec_c);
+                     sX, C, ldc, sC, batch, mtiles, ntiles, kchunk, sCsplit, (int)vec_c, cpk);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // picks the column-tile count by N and the unchecked (vector) path when shapes and alignment allow
 template <class P, bool CN, bool PACKED, bool LOWER, typename TA, typename TX, typename TC, bool UTRI = false>
 static int sk_launch(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, const void* X, int64_t ldx, int64_t sX,
-                     TC* C, int64_t ldc, int64_t sC, int batch, int ksplit, int64_t sCsplit, hipStream_t s) {
+                     TC* C, int64_t ldc, int64_t sC, int batch, int ksplit, int64_t sCsplit, hipStream_t s,
+                     PackOut cpk = PackOut()) {
   constexpr int KS = 4 * P::KL;
   constexpr int CK = 16 / (int)sizeof(typename P::E);
   // NN loads RT neighbouring rows per k, CN loads KL consecutive k (in 16-byte pieces)
@@ -636,9 +666,9 @@ static int sk_launch(int M, int N, int K, const TA* A, int64_t lda, int64_t sA, 
   const bool fast = vec_a && vec_x && small_off && M % BM == 0 && (K % KS == 0 || (UTRI && !CN));
 #define RT_SK_NT(NTV)                                                                                          \
   (fast ? sk_launch_nt<P, CN, PACKED, false, LOWER, UTRI, TA, TX, TC, NTV>(M, N, K, A, lda, sA, X, ldx, sX, C, ldc, sC, \
-                                                                    batch, ksplit, sCsplit, s)                 \
+                                                                    batch, ksplit, sCsplit, s, cpk)            \
         : sk_launch_nt<P, CN, PACKED, true, LOWER, UTRI, TA, TX, TC, NTV>(M, N, K, A, lda, sA, X, ldx, sX, C, ldc, sC,  \
-                                                                   batch, ksplit, sCsplit, s))
+                                                                   batch, ksplit, sCsplit, s, cpk))
   if (nt == 1) return RT_SK_NT(1);
   if (nt == 2) return RT_SK_NT(2);
   if (nt == 4) return RT_SK_NT(4);
@@ -695,7 +725,7 @@ static int skinny_pack(int N, int K, const TX* X, int64_t ldx, int64_t sX, int b
 
 template <typename TA, typename TC, class P = typename PrecOf<TA>::P>
 static int skinny_run(bool conjA, int M, int N, int K, const TA* A, int64_t lda, int64_t sA, TC* C, int64_t ldc,
-                      int64_t sC, int batch, const void* ws, hipStream_t s, int utri = 0) {
+                      int64_t sC, int batch, const void* ws, hipStream_t s, int utri = 0, PackOut cpk = PackOut()) {
   typedef typename P::E E;
   const int NP = 16 * nt_for<P>(N);
   const int KP = packed_kp<P>(K);
@@ -705,8 +735,27 @@ static int skinny_run(bool conjA, int M, int N, int K, const TA* A, int64_t lda,
   // packed X: the raw type parameter is unused, fixed to zd to share instantiations
   if (conjA) return sk_launch<P, true, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
   if (utri)
-    return sk_launch<P, false, true, false, TA, zd, TC, true>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
+    return sk_launch<P, false, true, false, TA, zd, TC, true>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s,
+                                                              cpk);
   return sk_launch<P, false, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
+}
+
+// The packed bf16 copy that an FP32 product C (rows x N per face) can write for a following bf16
+// pass with X = C (K = rows): only when rows is a multiple of 128, so that the slabs have no
+// padding rows (ok = false otherwise: that pass packs C itself).
+struct PackPlan {
+  bool ok = false;
+  PackOut out;
+  int64_t elems = 0;   // bf16 elements of the whole batch
+};
+inline PackPlan bf16_pack_plan(int N, int rows, int batch) {
+  PackPlan pl;
+  if (rows <= 0 || rows % 128 != 0 || packed_kp<B16>(rows) != rows) return pl;
+  pl.ok = true;
+  pl.out.sf = packed_elems<B16>(rows, N, 1);
+  pl.out.nsl = rows / kslab<B16>();
+  pl.elems = pl.out.sf * batch;
+  return pl;
 }
 
 }  // namespace sk

@@ -285,6 +285,33 @@ def test_face_groups_give_identical_factors(precision):
         assert np.array_equal(eta_, outs[0][2]) and np.array_equal(sig_, outs[0][3])
 
 
+@pytest.mark.parametrize("size,n,r_cols,q", [(256, 16, 120, 1), (128, 32, 40, 1), (256, 8, 30, 0), (384, 4, 72, 2)])
+def test_fused_packing_matches_separate_packing(size, n, r_cols, q, monkeypatch):
+    # mixed precision: Q = Y R^{-1} also writes Q (and Z) as the packed bf16 operand of the next
+    # pass over A-hat; with RTSVD_PACK_FUSION=0 every pass packs its operand itself.  The packed
+    # values are the same bf16 roundings, so factor and solution agree bit for bit.
+    import torch
+    from paper_2110_02485_amd import rtsvd as rt
+    k_max = r_cols - 10
+    A, X, B, Om, delta = blur_problem(size, n, 2.0, 8, 1, 1e-2, k_max, 10, seed=73)
+    At, Bt, Omt = _t(A, "float32"), _t(B, "float32"), _t(Om, "float32")
+    outs = []
+    for mode in ("0", "1"):
+        print(f"[pack fusion] {mode} size={size} n={n} r={r_cols} q={q}", flush=True)
+        monkeypatch.setenv("RTSVD_PACK_FUSION", mode)
+        for groups in (1, 3):
+            f = rt.factor(At, k_max, 10, q, "mixed", Omt, face_groups=groups)
+            res = f.solve(Bt, delta, 1.01, 1)
+            torch.cuda.synchronize()
+            info = f.info()
+            outs.append((_np(res.X), int(res.k[0]), info[2], info[4]))
+            f.close()
+    for X_, k_, eta_, sig_ in outs[1:]:
+        assert k_ == outs[0][1]
+        assert np.array_equal(X_, outs[0][0])
+        assert np.array_equal(eta_, outs[0][2]) and np.array_equal(sig_, outs[0][3])
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_restorations_in_flight_on_several_streams_match_sequential(precision):
     # independent restorations (three different problems, twice each) issued round robin on three
