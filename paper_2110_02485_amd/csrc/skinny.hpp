@@ -733,11 +733,12 @@ static int skinny_run(bool conjA, int M, int N, int K, const TA* A, int64_t lda,
   const E* Xp = static_cast<const E*>(ws);
   const int64_t sXp = 2 * (int64_t)NPt * KP;
   // packed X: the raw type parameter is unused, fixed to zd to share instantiations
-  if (conjA) return sk_launch<P, true, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
+  if (conjA)
+    return sk_launch<P, true, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s, cpk);
   if (utri)
     return sk_launch<P, false, true, false, TA, zd, TC, true>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s,
                                                               cpk);
-  return sk_launch<P, false, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s);
+  return sk_launch<P, false, true, false, TA, zd, TC>(M, N, K, A, lda, sA, Xp, KP, sXp, C, ldc, sC, batch, 1, 0, s, cpk);
 }
 
 // The packed bf16 copy that an FP32 product C (rows x N per face) can write for a following bf16
