@@ -81,8 +81,8 @@ def stage_model(w, precision):
 # calibration 1 GiB -> FETCH_SIZE 524302.3 KiB (factor 1.99995), WRITE_SIZE 1048576 KiB (factor 1.0).
 TRAFFIC = {
     ("W_mma", "mixed"): {"source": "paper_2110_02485_amd/csrc/skinny.hpp",
-                         "sha256": "9e0d2dfb466bb8c883bd2804477eadfc9b26c36d8ac40be2d6dae133c320f3aa",
-                         "bytes_per_launch": 677422690},
+                         "sha256": "2220cf6d2c32c75ea3ac5faa141456cb9a6dbaad7fa7a5c01d3e957a2154b24f",
+                         "bytes_per_launch": 677422818},
     ("chol", "mixed"): {"source": "paper_2110_02485_amd/csrc/heev.hpp",
                         "sha256": "57ad03baf9b86cfe4024bd60339516d6ec6238d30ef0b3415c15968780859eb5",
                         "bytes_per_launch": 27982968},
