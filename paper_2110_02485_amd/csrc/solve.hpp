@@ -14,8 +14,10 @@
 namespace rt {
 
 constexpr int DP_ROWS = 64;        // rows per block (one wave) of the residual pass
-constexpr int DP_KCH = 64;         // residual orders per transposition chunk
-constexpr int DP_WU = 32;          // columns of W loaded at once by the residual pass
+// residual orders per chunk of the residual pass (columns of W loaded at once, rows of the LDS
+// transposition): two chunks of W in registers stay within 256 VGPRs, and the 16.6 KB (FP32 W) /
+// 8.3 KB (FP64 W) of LDS let one round of waves cover 65 faces x 16 row tiles
+template <typename TW> constexpr int dp_kch() { return sizeof(TW) <= 8 ? 32 : 16; }
 constexpr int DP_SEL_THREADS = 1024;
 constexpr int HEEV_RMAX_SOLVE = 256;  // largest r (the eigensolver's limit)
 
@@ -47,19 +49,21 @@ __global__ void __launch_bounds__(256) k_scale_rows(zd* __restrict__ T, const do
 // |B-hat - W[:, :k] T[:k, c]|^2, FP64.  Block = one wave = one 64-row tile of one column group.
 // The residuals are updated one rank-1 term at a time (each W entry is loaded once for the CPB
 // columns); the 64 row values of each order k are summed through an LDS transposition (lane kk
-// sums row kk of a 64 x 64 chunk), so there is no per-order cross-lane reduction chain.  CPB = 1
-// keeps one column per partial (per-slice discrepancy principle); a joint principle sums every
-// column and may take CPB = 8.
+// sums row kk of a KCH x 64 chunk), so there is no per-order cross-lane reduction chain.  The W
+// columns of the next chunk are loaded while the current chunk is applied.  CPB = 1 keeps one
+// column per partial (per-slice discrepancy principle); a joint principle sums every column and
+// may take CPB = 8.
 template <int CPB, typename TBh, typename TW>
 __global__ void __launch_bounds__(DP_ROWS)
 k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __restrict__ T,
              int l, int p, int r, int kcap, double* __restrict__ partial) {
+  constexpr int KCH = dp_kch<TW>();
   const int tile = blockIdx.x, g = blockIdx.y, f = blockIdx.z;
   const int tiles = gridDim.x, pg = gridDim.y;
   const int lane = threadIdx.x;
   const int row = tile * DP_ROWS + lane;
   const int c0 = g * CPB;
-  __shared__ double sq[DP_KCH][DP_ROWS + 1];
+  __shared__ double sq[KCH][DP_ROWS + 1];
   const bool on = row < l;
   zd R[CPB];
 #pragma unroll
@@ -70,20 +74,20 @@ k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __r
   const TW* __restrict__ wf = W + (int64_t)f * l * r + (on ? row : 0);
   const zd* __restrict__ tf = T + (int64_t)f * r * p;
   double* __restrict__ out = partial + (((int64_t)f * tiles + tile) * pg + g) * kcap;
-  for (int k0 = 0; k0 < kcap; k0 += DP_KCH) {
-    const int kn = min(DP_KCH, kcap - k0);
-    // DP_WU columns of W are loaded at once (all in flight: a wave per 64 rows has little other
-    // work to cover the memory latency with), then applied in order
-    for (int kb = 0; kb < kn; kb += DP_WU) {
-      TW wv[DP_WU];
+  // two register chunks of W, used in turn: the next chunk's loads are issued before the current
+  // chunk is applied (column indices clamp to kcap - 1: loads past the last order are re-reads
+  // that are never applied)
+  auto load = [&](TW (&w)[KCH], int kb) {
 #pragma unroll
-      for (int u = 0; u < DP_WU; ++u) wv[u] = wf[(int64_t)min(k0 + kb + u, kcap - 1) * l];
+    for (int u = 0; u < KCH; ++u) w[u] = wf[(int64_t)min(kb + u, kcap - 1) * l];
+  };
+  auto apply = [&](const TW (&w)[KCH], int k0) {
+    const int kn = min(KCH, kcap - k0);
 #pragma unroll
-      for (int u = 0; u < DP_WU; ++u) {
-        const int kk = kb + u;
-        if (kk >= kn) break;                       // uniform
-        const int k = k0 + kk;                     // order k+1 uses column k
-        const zd wk = ld<double>(wv[u]);
+    for (int u = 0; u < KCH; ++u) {
+      if (u < kn) {                                // uniform
+        const int k = k0 + u;                      // order k+1 uses column k
+        const zd wk = ld<double>(w[u]);
         double acc = 0.0;
 #pragma unroll
         for (int j = 0; j < CPB; ++j) {
@@ -91,7 +95,7 @@ k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __r
           R[j] = csub(R[j], cmul(wk, t));
           acc += cabs2(R[j]);
         }
-        sq[kk][lane] = on ? acc : 0.0;
+        sq[u][lane] = on ? acc : 0.0;
       }
     }
     __syncthreads();
@@ -102,6 +106,15 @@ k_dp_partial(const TBh* __restrict__ Bh, const TW* __restrict__ W, const zd* __r
       out[k0 + lane] = s;
     }
     __syncthreads();
+  };
+  TW wa[KCH], wb[KCH];
+  load(wa, 0);
+  for (int k0 = 0; k0 < kcap; k0 += 2 * KCH) {
+    if (k0 + KCH < kcap) load(wb, k0 + KCH);
+    apply(wa, k0);
+    if (k0 + KCH >= kcap) break;
+    if (k0 + 2 * KCH < kcap) load(wa, k0 + 2 * KCH);
+    apply(wb, k0 + KCH);
   }
 }
 
