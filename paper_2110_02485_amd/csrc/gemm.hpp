@@ -87,15 +87,16 @@ k_cgemm(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
 
 // Few right-hand sides (N <= GEMV_NP, op(B) = B): matrix-vector products, bound by the one pass
 // over A.  A^H X: one wave per output row (a stored column of A, read contiguously by the lanes),
-// reduced across the wave.  A X: one lane per output row, the K range split over the 4 waves of
-// the block and reduced in LDS.
+// reduced across the wave; with 8-byte elements (FP32 complex) on both sides and 16-byte aligned
+// columns (vec, checked by the host) each lane reads two consecutive elements per 16-byte load.
+// A X: one lane per output row, the K range split over the 4 waves of the block and reduced in LDS.
 constexpr int GEMV_NP = 4;
 
 template <typename TA, typename TB, typename TC, typename Acc, int NP>
 __global__ void __launch_bounds__(256)
 k_gemv_cn(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA,
           const TB* __restrict__ B, int64_t ldb, int64_t sB, TC* __restrict__ C, int64_t ldc, int64_t sC,
-          Acc alpha, int accumulate) {
+          Acc alpha, int accumulate, int vec) {
   const int f = blockIdx.y;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (i >= M) return;
@@ -104,8 +105,27 @@ k_gemv_cn(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA
   cplx<Acc> acc[NP];
 #pragma unroll
   for (int c = 0; c < NP; ++c) acc[c] = mk((Acc)0, (Acc)0);
+  int k = lane;
+  if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8) {
+    if (vec) {
+      // pairs (2 j, 2 j + 1), j = lane, lane + 64, ...: whole pairs below K2, the rest below
+      const int K2 = K & ~1;
+#pragma unroll 8
+      for (int k2 = 2 * lane; k2 < K2; k2 += 128) {
+        const float4 av = *reinterpret_cast<const float4*>(a + k2);
+#pragma unroll
+        for (int c = 0; c < NP; ++c)
+          if (c < N) {
+            const float4 bv = *reinterpret_cast<const float4*>(b + k2 + c * ldb);
+            acc[c] = cadd(acc[c], cmulc(mk((Acc)av.x, (Acc)av.y), mk((Acc)bv.x, (Acc)bv.y)));
+            acc[c] = cadd(acc[c], cmulc(mk((Acc)av.z, (Acc)av.w), mk((Acc)bv.z, (Acc)bv.w)));
+          }
+      }
+      k = K2 + lane;
+    }
+  }
 #pragma unroll 16
-  for (int k = lane; k < K; k += 64) {
+  for (; k < K; k += 64) {
     const cplx<Acc> av = ld<Acc>(a[k]);
 #pragma unroll
     for (int c = 0; c < NP; ++c)
@@ -113,10 +133,11 @@ k_gemv_cn(int M, int N, int K, const TA* __restrict__ A, int64_t lda, int64_t sA
   }
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
+    if (c >= N) break;
     cplx<Acc> v = acc[c];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) { v.re += __shfl_xor(v.re, o, 64); v.im += __shfl_xor(v.im, o, 64); }
-    if (lane == 0 && c < N) {
+    if (lane == 0) {
       v = cscale(v, alpha);
       TC& dst = C[f * sC + i + (int64_t)c * ldc];
       if (accumulate) v = cadd(v, ld<Acc>(dst));
@@ -172,10 +193,14 @@ int cgemm(bool conjA, bool conjB, int M, int N, int K, const TA* A, int64_t lda,
           Acc alpha, bool accumulate, hipStream_t s) {
   if (M <= 0 || N <= 0 || batch <= 0) return 0;
   if (N <= GEMV_NP && !conjB && K > 0) {
-    if (conjA)
+    if (conjA) {
+      // 16-byte pair loads: both operands FP32 complex, every column start 16-byte aligned
+      const bool vec = sizeof(TA) == 8 && sizeof(TB) == 8 && (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 &&
+                       lda % 2 == 0 && sA % 2 == 0 && ldb % 2 == 0 && sB % 2 == 0;
       hipLaunchKernelGGL((k_gemv_cn<TA, TB, TC, Acc, GEMV_NP>), dim3((unsigned)ceil_div(M, 4), (unsigned)batch),
-                         dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate);
-    else
+                         dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate,
+                         (int)vec);
+    } else
       hipLaunchKernelGGL((k_gemv_nn<TA, TB, TC, Acc, GEMV_NP>), dim3((unsigned)ceil_div(M, 64), (unsigned)batch),
                          dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, (int)accumulate);
     return hipGetLastError() == hipSuccess ? 0 : -1;
