@@ -27,10 +27,11 @@ def _rel(a, b):
 
 
 # (l, m, p, n): small lateral sizes for every radix and its combinations, one length with a prime
-# factor above 13 (17, 34: direct DFT), and enough tubes at 240 / 300 / 500 that the workgroup
-# count is rounded up for the XCD spread (a ragged last group)
+# factor above 13 (17, 34: direct DFT), enough tubes at 240 / 300 / 500 that the workgroup count
+# is rounded up for the XCD spread (a ragged last group), and n = 128 (the lane-pair register
+# transform in FP32) with tube counts that leave the last workgroup partly or almost wholly empty
 CASES = [(13, 10, 3, n) for n in (3, 5, 6, 9, 11, 13, 17, 26, 34, 49, 210)] + \
-        [(61, 37, 2, 240), (61, 37, 1, 300), (40, 33, 2, 500)]
+        [(61, 37, 2, 240), (61, 37, 1, 300), (40, 33, 2, 500), (13, 10, 3, 128), (61, 37, 2, 128)]
 
 
 @pytest.mark.parametrize("l,m,p,n", CASES)
