@@ -25,8 +25,13 @@ typedef double gr_f64x4 __attribute__((ext_vector_type(4)));
 // block b to XCD b % 8; block b takes work item (b % 8) S + b / 8 (S = ceil(P batch / 8)), item
 // = face * P + tile, so each XCD works through a contiguous run of faces and reads each face's
 // panels into its own L2 once instead of every XCD fetching every face.
+// FP32 panels: eight waves per SIMD (64 VGPRs, four workgroups per CU; 65 faces x 36 tiles then
+// take three rounds instead of four), the waves hiding one another's load latency in place of the
+// one-step register prefetch, which no longer fits; FP64 panels keep the prefetch
+template <typename TY> constexpr int gram_min_waves() { return sizeof(TY) == 8 ? 8 : 1; }
+
 template <typename TY>
-__global__ void __launch_bounds__(GRAM_THREADS)
+__global__ void __launch_bounds__(GRAM_THREADS, gram_min_waves<TY>())
 k_gram_lower(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY, zd* __restrict__ G, int P,
              int batch) {
   __shared__ gr_f64x4 red[GRAM_WAVES - 1][2][64];
@@ -66,20 +71,31 @@ k_gram_lower(const TY* __restrict__ Y, int rows, int r, int64_t ldy, int64_t sY,
   if (16 * I + 16 <= r && 16 * J + 16 <= r && kfull > k0) {
     const TY* __restrict__ pa = ya + k0 + 4 * q;
     const TY* __restrict__ pb = yb + k0 + 4 * q;
-    TY na[4], nb[4];
+    if constexpr (sizeof(TY) == 8) {
+      for (; kb < kfull; kb += 16) {
+        zd a[4], bv[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) { na[s] = pa[s]; nb[s] = pb[s]; }
-    for (; kb < kfull; kb += 16) {
-      zd a[4], bv[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) { a[s] = ld<double>(na[s]); bv[s] = ld<double>(nb[s]); }
-      pa += 16;
-      pb += 16;
-      if (kb + 16 < kfull) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) { na[s] = pa[s]; nb[s] = pb[s]; }
+        for (int s = 0; s < 4; ++s) { a[s] = ld<double>(pa[s]); bv[s] = ld<double>(pb[s]); }
+        pa += 16;
+        pb += 16;
+        mfma_step(a, bv);
       }
-      mfma_step(a, bv);
+    } else {
+      TY na[4], nb[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) { na[s] = pa[s]; nb[s] = pb[s]; }
+      for (; kb < kfull; kb += 16) {
+        zd a[4], bv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) { a[s] = ld<double>(na[s]); bv[s] = ld<double>(nb[s]); }
+        pa += 16;
+        pb += 16;
+        if (kb + 16 < kfull) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) { na[s] = pa[s]; nb[s] = pb[s]; }
+        }
+        mfma_step(a, bv);
+      }
     }
   }
   // edge tiles and the last partial step: loads at clamped rows (in bounds), masked afterwards;
