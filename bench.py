@@ -87,8 +87,8 @@ TRAFFIC = {
                         "sha256": "57ad03baf9b86cfe4024bd60339516d6ec6238d30ef0b3415c15968780859eb5",
                         "bytes_per_launch": 27982968},
     ("gram", "mixed"): {"source": "paper_2110_02485_amd/csrc/gram.hpp",
-                        "sha256": "c59737f7dc9716e64669ffb6514504c94df3bd0209358e422d5fd02b243574f1",
-                        "bytes_per_launch": 76505484},
+                        "sha256": "500dcbda4221ee2af649334589f03211ec9635968110be8918579dad4f3249a2",
+                        "bytes_per_launch": 76532903},
 }
 
 
